@@ -1,0 +1,77 @@
+"""Planted mistakes: each test builds a copy of an oracle module with one
+plausible error (a flipped sign, a dropped factor, a swapped operand) and
+checks that at least one pin fails on it.  This shows the pins constrain the
+oracle's arithmetic, not just its plumbing.  Everything runs on the CPU.
+"""
+import importlib
+import os
+import sys
+import types
+
+import pytest
+
+import oracle
+import tests.test_oracle_fft as pins_fft
+import tests.test_oracle_physics as pins_phys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def mutated(modname, old, new):
+    path = os.path.join(ROOT, "oracle", modname + ".py")
+    src = open(path).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
+    src = src.replace(old, new, 1)
+    mod = types.ModuleType(f"oracle.{modname}")
+    mod.__package__ = "oracle"
+    mod.__file__ = path
+    exec(compile(src, path, "exec"), mod.__dict__)
+    return mod
+
+
+def must_fail(pin, *args):
+    with pytest.raises(AssertionError):
+        pin(*args)
+
+
+QG_MUTATIONS = [
+    ("beta sign", "- p.beta * 1j * g.kx * psih", "+ p.beta * 1j * g.kx * psih",
+     lambda: pins_phys.test_single_shell_rk4_exact("none", 0.0)),
+    ("jacobian sign", "J = u * wx + v * wy", "J = u * wx - v * wy",
+     pins_phys.test_jacobian_two_modes_closed_form),
+    ("strain factor", "4.0 * pxy ** 2 + pd ** 2", "2.0 * pxy ** 2 + pd ** 2",
+     pins_phys.test_poisson_and_second_derivatives_closed_form),
+    ("test ratio power", "power = 2 if kind == \"dsmag\" else 3",
+     "power = 3 if kind == \"dsmag\" else 2",
+     lambda: pins_phys.test_dynamic_coefficient_inside_test_filter("dsmag", 2)),
+    ("penalization operands", "m.Ex * v - m.Ey * u", "m.Ex * u - m.Ey * v",
+     pins_phys.test_island_interior_decay_and_inflow_vorticity),
+    ("rk4 weight", "k1 + 2.0 * k2 + 2.0 * k3 + k4", "k1 + k2 + 2.0 * k3 + k4",
+     lambda: pins_phys.test_single_shell_rk4_exact("none", 0.0)),
+    ("divergence index", "1j * g.kx * hxh + 1j * g.ky * hyh", "1j * g.kx * hxh + 1j * g.kx * hyh",
+     lambda: pins_phys.test_eddy_viscosity_dissipates_enstrophy_exactly("smag")),
+    ("dropped test filter", "- g.T * Jh", "- Jh",
+     lambda: pins_phys.test_dynamic_coefficient_inside_test_filter("dleith", 3)),
+    ("viscosity sign", "- (g.k2 * m.inv_re + p.mu) * wh", "+ (g.k2 * m.inv_re + p.mu) * wh",
+     lambda: pins_phys.test_single_shell_rk4_exact("none", 0.0)),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", QG_MUTATIONS, ids=[m[0] for m in QG_MUTATIONS])
+def test_qg_mutation_is_caught(monkeypatch, name, old, new, pin):
+    mod = mutated("qg", old, new)
+    monkeypatch.setattr(pins_phys, "qg", mod)
+    must_fail(pin)
+
+
+def test_fft_twiddle_sign_is_caught(monkeypatch):
+    mod = mutated("fft", "ang = sign * 2.0 * np.pi * k / (2 * L)",
+                  "ang = -sign * 2.0 * np.pi * k / (2 * L)")
+    monkeypatch.setattr(pins_fft, "F", mod)
+    must_fail(pins_fft.test_1d_against_definition, 8)
+
+
+def test_fft_hermitian_weight_is_caught(monkeypatch):
+    mod = mutated("fft", "full[..., 0] = cols[..., 0].real", "full[..., 0] = 2 * cols[..., 0].real")
+    monkeypatch.setattr(pins_fft, "F", mod)
+    must_fail(pins_fft.test_irfft2_against_definition, 8, 8)
