@@ -1,0 +1,160 @@
+/*
+ * qg.h -- C ABI of the MI355X (gfx950) pseudo-spectral QG time step.
+ *
+ * One step advances the non-dimensional beta-plane quasi-geostrophic
+ * vorticity equation (Sec. II-A, Eq. 1)
+ *     d omega/dt + J(psi, omega) = (1/Re) lap omega - mu omega - beta psi_x
+ *                                  + Pi + F_obs + F_sponge,   omega = lap psi,
+ * on a doubly periodic nx-by-ny grid with a Fourier pseudo-spectral method
+ * and 2/3 de-aliasing (Sec. II-C).  Pi = div(nu_e grad omega) is the
+ * eddy-viscosity closure (Eq. 8): Smagorinsky (Eq. 9), Leith (Eq. 12) or
+ * their dynamic variants with the Germano identity and Lilly's least
+ * squares (Eqs. 10-11, 13).  F_obs is Brinkman volume penalization with
+ * porosity eta and mask chi_obs (Sec. II-B, Eq. 2); F_sponge relaxes omega
+ * with rate sigma = 1/eta_sponge on the ramp chi_sponge (Sec. II-D, Eq. 3);
+ * a uniform inflow (u_in, v_in) is added to the zeroth Fourier mode of the
+ * velocity (Sec. II-D).
+ *
+ * Time step (splitting of Sec. II-E): classical RK4 over advection, beta,
+ * viscosity and closure, then an exactly integrated sub-step applying the
+ * penalization (curl of u <- exp(-dt chi/eta) u, product rule) and then the
+ * sponge (omega <- exp(-dt sigma chi_s) omega), evaluated pointwise in
+ * physical space and projected back onto the 2/3 set.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Fields are row-major (ny, nx), x contiguous, element type float when
+ *    precision == 32 and double when precision == 64.  Members of a batch
+ *    are concatenated in the order given to qg_init.
+ *  - All device pointers are owned by the caller.  The library keeps the
+ *    workspace pointer from qg_init until qg_destroy and never frees it; it
+ *    keeps no other caller pointer beyond the call.
+ *  - Calls enqueue work on the given HIP stream (hipStream_t passed as
+ *    void*, NULL = default stream) and return without synchronising, except
+ *    qg_init and qg_autotune, which synchronise their stream.
+ *  - Return codes are QG_* below; no C++ exception crosses this boundary.
+ *    On failure qg_last_error() returns a message (thread-local).
+ *  - One host thread at a time per handle.
+ */
+#ifndef QG_H
+#define QG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QG_OK = 0,
+    QG_EINVAL = 1,        /* bad argument or parameter value                  */
+    QG_EUNSUPPORTED = 2,  /* valid but not implemented (sizes, clip_mode...)  */
+    QG_EWORKSPACE = 3,    /* workspace missing, misaligned or too small       */
+    QG_EHIP = 4,          /* a HIP runtime call failed (message has details)  */
+    QG_ESTATE = 5         /* call not valid in the handle's current state     */
+};
+
+enum {
+    QG_CLOSURE_NONE = 0,
+    QG_CLOSURE_SMAG = 1,   /* nu_e = (c Delta)^2 |S|,  Eq. 9                   */
+    QG_CLOSURE_LEITH = 2,  /* nu_e = (c Delta)^3 |grad omega|, Eq. 12          */
+    QG_CLOSURE_DSMAG = 3,  /* dynamic Smagorinsky, Eqs. 10-11                  */
+    QG_CLOSURE_DLEITH = 4  /* dynamic Leith, Eq. 13                            */
+};
+
+/* Parameters of one member (Sec. II-A..E, III-A).
+ *  nx, ny       grid, powers of two in [32, 4096]; dx = lx/nx must equal
+ *               dy = ly/ny to 1e-12 relative (Delta = dx, Eq. 9)
+ *  lx, ly       domain size
+ *  beta, re, mu beta-plane gradient, Reynolds number (re <= 0 or inf means
+ *               no molecular viscosity), bottom friction (Eq. 1)
+ *  u_in, v_in   uniform inflow added to the zeroth velocity mode
+ *  eta          Brinkman porosity (Eq. 2); eta <= 0 or inf disables it
+ *  sponge_sigma 1/eta_sponge (Eq. 3); 0 disables the sponge
+ *  dt           time step
+ *  c            static c_S or c_L (ignored by the dynamic closures)
+ *  closure      QG_CLOSURE_*
+ *  precision    32 or 64: arithmetic and storage type of the step
+ *  test_ratio   Delta~/Delta of the test filter, integer in {2, 3, 4};
+ *               the test filter keeps |k| <= k_max / test_ratio with k_max
+ *               the largest retained wavenumber (Sec. III-A, dynamic models)
+ *  clip_mode    0: C = max(<HM>, 0)/<M^2>.  1 (pointwise H+) is not
+ *               implemented on the GPU and returns QG_EUNSUPPORTED.
+ *  fp64_lowk    in 32-bit runs, modes with |k| <= fp64_lowk invert the
+ *               Poisson equation in double precision                       */
+typedef struct {
+    int32_t nx, ny;
+    double lx, ly, beta, re, mu, u_in, v_in, eta, sponge_sigma, dt, c;
+    int32_t closure;
+    int32_t precision;
+    double test_ratio;
+    int32_t clip_mode;
+    int32_t fp64_lowk;
+} qg_params;
+
+typedef struct qg_handle qg_handle;
+
+/* Bytes of device workspace needed for n_members members (params[i] each)
+ * and adjoint segments of up to adj_segment_k steps (0: no adjoint).
+ * Writes *bytes.  Validates the parameters as qg_init does. */
+int qg_workspace_bytes(const qg_params* params, int32_t n_members,
+                       int32_t adj_segment_k, size_t* bytes);
+
+/* Build a handle for n_members members.
+ *  chi_obs[i], chi_sponge[i]: device pointers to member i's masks (Eq. 2 and
+ *      Eq. 3), (ny, nx) of the member's precision; copied into the workspace.
+ *  workspace, ws_bytes: caller-owned device buffer, 256-byte aligned, at
+ *      least qg_workspace_bytes(...) bytes (same adj_segment_k).
+ * Precomputes the penalization tables E = exp(-dt chi/eta), E_x, E_y (from
+ * the spectral gradient of chi) and S = exp(-dt sigma chi_sponge) on the
+ * GPU.  Synchronises hip_stream.  Members may differ in every parameter;
+ * members of equal (nx, ny, precision, closure) are launched together. */
+int qg_init(const qg_params* params, int32_t n_members,
+            const void* const* chi_obs, const void* const* chi_sponge,
+            void* workspace, size_t ws_bytes, int32_t adj_segment_k,
+            void* hip_stream, qg_handle** out);
+
+/* Advance every member nsteps steps in place.  omega: flat device buffer of
+ * all members.  On entry omega is projected onto the 2/3 set with its mean
+ * removed; the state stays spectral inside the call.  If save_every > 0,
+ * omega is written to ckpt_out (n_saves x all members, flat) after every
+ * save_every steps, and the run continues from that written field, so a run
+ * restarted from a checkpoint repeats the original bit for bit.
+ * use_graph != 0 replays a captured hipGraph of the step sequence. */
+int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
+            void* ckpt_out, int32_t use_graph, void* hip_stream);
+
+/* Discrete adjoint of qg_step over one segment (static closures only).
+ * omega_ckpt: omega at the segment start (as saved by qg_step);
+ * lambda: on entry dL/d omega at the segment end, on return dL/d omega at
+ * the segment start (both physical, same layout as omega);
+ * grad_c_dev: n_members doubles on the device; dL/dc of each member is
+ * ADDED to it.  nsteps <= adj_segment_k given to qg_init. */
+int qg_adjoint_step(qg_handle* h, const void* omega_ckpt, void* lambda,
+                    int64_t nsteps, double* grad_c_dev, void* hip_stream);
+
+/* Diagnostics at omega: for each member 8 doubles
+ *   [energy 1/2<|grad psi|^2>, enstrophy 1/2<omega^2>, C, nu_min, nu_mean,
+ *    nu_max, CFL = max(|u|+|v|) dt/Delta, nonfinite flag]
+ * into out_dev (device, n_members x 8).  nu_e_out (nullable): the eddy
+ * viscosity field nu_e = C base, flat like omega. */
+int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
+            void* hip_stream);
+
+/* Time candidate FFT tilings for every size group on hip_stream and keep
+ * the fastest; results are cached in the JSON file at cache_path (nullable:
+ * no file).  Synchronises hip_stream. */
+int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
+
+/* Number of members, total grid points, and the tiling chosen per member. */
+int qg_info(const qg_handle* h, int32_t* n_members, int64_t* total_points,
+            int32_t* col_width_out /* n_members, nullable */);
+
+void qg_destroy(qg_handle* h);
+const char* qg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QG_H */

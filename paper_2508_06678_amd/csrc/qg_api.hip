@@ -1,0 +1,735 @@
+// Host runtime of the QG step: parameter validation, per-size plans, the
+// workspace layout, the phase sequences of a step / the adjoint / the
+// diagnostics, hipGraph capture and replay, and the C ABI of include/qg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "qg_internal.hpp"
+#include "../../include/qg.h"
+
+namespace qg {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define QG_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(QG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+static int ilog2(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------ validation
+static int validate(const qg_params& p, int idx) {
+  auto bad = [&](int code, const char* what) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "member %d: %s", idx, what);
+    return fail(code, buf);
+  };
+  if (p.nx <= 0 || p.ny <= 0) return bad(QG_EINVAL, "grid sizes must be positive");
+  if (!is_pow2(p.nx) || !is_pow2(p.ny) || p.nx < 32 || p.ny < 32 || p.nx > 4096 || p.ny > 4096)
+    return bad(QG_EUNSUPPORTED, "nx and ny must be powers of two in [32, 4096]");
+  if (!(p.lx > 0) || !(p.ly > 0)) return bad(QG_EINVAL, "lx and ly must be positive");
+  const double dx = p.lx / p.nx, dy = p.ly / p.ny;
+  if (std::fabs(dx - dy) > 1e-12 * dx) return bad(QG_EUNSUPPORTED, "dx must equal dy");
+  if (!(p.dt > 0) || !std::isfinite(p.dt)) return bad(QG_EINVAL, "dt must be positive and finite");
+  if (p.closure < 0 || p.closure > 4) return bad(QG_EINVAL, "unknown closure");
+  if (p.precision != 32 && p.precision != 64) return bad(QG_EINVAL, "precision must be 32 or 64");
+  if (p.clip_mode == 1) return bad(QG_EUNSUPPORTED, "pointwise clipping (clip_mode 1) is not implemented");
+  if (p.clip_mode != 0) return bad(QG_EINVAL, "clip_mode must be 0 or 1");
+  if (p.closure >= 3) {
+    const double r = p.test_ratio;
+    if (!(r == 2.0 || r == 3.0 || r == 4.0)) return bad(QG_EUNSUPPORTED, "test_ratio must be 2, 3 or 4");
+  }
+  if (!std::isfinite(p.beta) || !std::isfinite(p.mu) || !std::isfinite(p.u_in) || !std::isfinite(p.v_in) ||
+      !std::isfinite(p.c) || !(p.sponge_sigma >= 0) || !std::isfinite(p.sponge_sigma))
+    return bad(QG_EINVAL, "non-finite or negative parameter");
+  if (p.eta == 0.0 || std::isnan(p.eta)) return bad(QG_EINVAL, "eta must be positive (or inf to disable)");
+  if (p.eta < 0) return bad(QG_EINVAL, "eta must be positive (or inf to disable)");
+  if (p.fp64_lowk < 0) return bad(QG_EINVAL, "fp64_lowk must be >= 0");
+  return QG_OK;
+}
+
+// ------------------------------------------------------------ plans
+struct Group {
+  int nx, ny, lognx, logny, closure;
+  bool dbl;
+  int kxn, myh, kyn, W, logW, kxp, RP, logRP;
+  int kxn_f, myh_f, kyn_f, kxp_f;
+  int nstrips, nstrips_f, nrow, nspec;
+  int m0, count;                 // slice of the device member table
+  std::vector<int> users;        // caller indices of the members
+  RegionLayout L;
+  long long region_bytes;
+  char* region0;                 // first member region
+  void* twx;
+  void* twy;
+  long long o_twx, o_twy;        // offsets in the global area
+};
+
+static void plan_sizes(Group& g, int adjK) {
+  const int cs = g.dbl ? 16 : 8, rs = g.dbl ? 8 : 4;
+  g.lognx = ilog2(g.nx);
+  g.logny = ilog2(g.ny);
+  g.kxn = (g.nx - 1) / 3 + 1;
+  g.myh = (g.ny - 1) / 3;
+  g.kyn = 2 * g.myh + 1;
+  g.kxn_f = g.nx / 2;
+  g.myh_f = g.ny / 2 - 1;
+  g.kyn_f = g.ny - 1;
+  // 64 KiB of LDS per column tile when the device allows more than that per
+  // block (gfx950: 160 KiB), else 32 KiB.
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    lds_limit = v;
+  }
+  const int tile_bytes = lds_limit >= 65536 + 1024 ? 65536 : 32768;
+  const int tile_elems = tile_bytes / (g.dbl ? 16 : 8);
+  int W = std::min(g.dbl ? 8 : 16, tile_elems / g.ny);
+  if (W < 1) W = 1;
+  g.W = W;
+  g.logW = ilog2(W);
+  g.kxp = (g.kxn + W - 1) / W * W;
+  g.kxp_f = (g.kxn_f + W - 1) / W * W;
+  g.RP = std::max(1, std::min(2048 / g.nx, g.ny / 2));
+  g.logRP = ilog2(g.RP);
+  g.nstrips = (g.kxn + W - 1) / W;
+  g.nstrips_f = (g.kxn_f + W - 1) / W;
+  g.nrow = g.ny / (2 * g.RP);
+  g.nspec = (g.kxn * g.kyn + 255) / 256;
+
+  const int cl = g.closure;
+  int F = std::max({rhs_fields(cl), 3, 1});
+  int Pn = std::max({rhs_products(cl), 3, 1});
+  if (adjK > 0) {
+    F = std::max(F, (smag_family(cl) ? 6 : 4) + 3);
+    Pn = std::max(Pn, smag_family(cl) ? 6 : 4);
+  }
+  const long long spec = (long long)g.kxn * g.kyn * cs;
+  const long long mf = std::max((long long)F * g.ny * g.kxp, 2LL * g.ny * g.kxp_f) * cs;
+  const long long mp = std::max((long long)Pn * g.ny * g.kxp, 1LL * g.ny * g.kxp_f) * cs;
+  long long o = 0;
+  auto take = [&](long long b) { long long r = o; o += align256(b); return r; };
+  RegionLayout& L = g.L;
+  L.wn = take(spec);
+  L.acc = take(spec);
+  L.x = take(spec);
+  L.jsp = take(spec);
+  L.qsp = take(spec);
+  L.chih = take((long long)g.kxn_f * g.kyn_f * cs);
+  L.mf = take(mf);
+  L.mp = take(mp);
+  L.phys = take(6LL * g.nx * g.ny * rs);
+  L.part = take((long long)std::max(g.nstrips, g.nstrips_f) * 2 * 8);
+  L.coef = take(32 * 8);
+  L.dpart = take((long long)(5 * g.nrow + 2 * g.nspec + 8) * 8);
+  if (adjK > 0) {
+    L.adj_lam = take(spec);
+    L.adj_lacc = take(spec);   // LW
+    L.adj_lk = take(spec);     // LK
+    L.adj_store = take((long long)align256(spec) * (4LL * adjK + 1));  // LS, then 4 stage inputs per step
+  } else {
+    L.adj_lam = L.adj_lacc = L.adj_lk = L.adj_store = -1;
+  }
+  L.total = o;
+  g.region_bytes = o;
+}
+
+struct Handle {
+  std::vector<qg_params> params;
+  std::vector<Group> groups;
+  std::vector<int> member_group;   // caller index -> group
+  std::vector<long long> omega_off;
+  long long total_points = 0;
+  long long total_bytes = 0;       // bytes of one flat field of all members
+  int adjK = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  MemberDev* mem_dev = nullptr;
+  std::map<int, hipGraphExec_t> graphs;   // steps per replay -> executable graph
+  hipStream_t graph_stream = nullptr;      // capture/replay stream (the caller's may be the null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+static bool same_group(const qg_params& a, const qg_params& b) {
+  return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.closure == b.closure;
+}
+
+// Everything qg_workspace_bytes and qg_init share: grouping, layout.
+static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
+  if (!params || n <= 0) return fail(QG_EINVAL, "need at least one member");
+  if (adjK < 0) return fail(QG_EINVAL, "adj_segment_k must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(params[i], i);
+    if (rc) return rc;
+  }
+  h.params.assign(params, params + n);
+  h.adjK = adjK;
+  h.member_group.assign(n, -1);
+  h.omega_off.assign(n, 0);
+  long long off = 0;
+  for (int i = 0; i < n; ++i) {
+    h.omega_off[i] = off;
+    off += (long long)params[i].nx * params[i].ny * (params[i].precision == 64 ? 8 : 4);
+    h.total_points += (long long)params[i].nx * params[i].ny;
+  }
+  h.total_bytes = off;
+  for (int i = 0; i < n; ++i) {
+    int gi = -1;
+    for (size_t k = 0; k < h.groups.size(); ++k)
+      if (same_group(params[h.groups[k].users[0]], params[i])) gi = (int)k;
+    if (gi < 0) {
+      Group g{};
+      g.nx = params[i].nx;
+      g.ny = params[i].ny;
+      g.closure = params[i].closure;
+      g.dbl = params[i].precision == 64;
+      plan_sizes(g, adjK);
+      h.groups.push_back(g);
+      gi = (int)h.groups.size() - 1;
+    }
+    h.groups[gi].users.push_back(i);
+    h.member_group[i] = gi;
+  }
+  // global area: member table, twiddles; then group regions
+  long long o = align256((long long)n * sizeof(MemberDev));
+  for (auto& g : h.groups) {
+    const int cs = g.dbl ? 16 : 8;
+    g.o_twx = o; o += align256((long long)g.nx * cs);
+    g.o_twy = o; o += align256((long long)g.ny * cs);
+  }
+  int m0 = 0;
+  for (auto& g : h.groups) {
+    g.m0 = m0;
+    g.count = (int)g.users.size();
+    m0 += g.count;
+    g.region0 = reinterpret_cast<char*>(o);   // offset for now
+    o += g.region_bytes * g.count;
+  }
+  h.ws_bytes = (size_t)o;
+  return QG_OK;
+}
+
+// Twiddles exp(-2 pi i m / n), m in [0, n), from the octant-reduced angle in
+// long double so that every entry is correctly rounded or nearly so.
+static void twiddles(int n, std::vector<long double>& re, std::vector<long double>& im) {
+  re.resize(n);
+  im.resize(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int m = 0; m < n; ++m) {
+    // reduce m/n to [0, 1/8] with symmetries of cos/sin
+    long long a = (long long)m * 8;           // angle in units of 2 pi / (8 n)
+    long long oct = a / n;                    // octant 0..7
+    long long r = a - oct * n;                // remainder in [0, n)
+    long double t = (long double)r / (long double)n;   // fraction of the octant
+    long double c, s;
+    // angle within octant: theta = (oct + t) * pi / 4
+    long double th = t * pi / 4.0L;
+    long double ct = cosl(th), st = sinl(th);
+    long double cq = cosl(pi / 4.0L - th), sq = sinl(pi / 4.0L - th);
+    switch (oct) {
+      case 0: c = ct; s = st; break;
+      case 1: c = sq; s = cq; break;
+      case 2: c = -st; s = ct; break;
+      case 3: c = -cq; s = sq; break;
+      case 4: c = -ct; s = -st; break;
+      case 5: c = -sq; s = -cq; break;
+      case 6: c = st; s = -ct; break;
+      default: c = cq; s = -sq; break;
+    }
+    re[m] = c;
+    im[m] = -s;   // exp(-i theta)
+  }
+}
+
+// ------------------------------------------------------------ phases
+static Phase base_phase(const Handle& h, const Group& g) {
+  Phase P{};
+  P.mem = h.mem_dev;
+  P.m0 = g.m0;
+  P.nx = g.nx; P.ny = g.ny; P.lognx = g.lognx; P.logny = g.logny;
+  P.kxn = g.kxn; P.myh = g.myh; P.kyn = g.kyn; P.kxp = g.kxp;
+  P.W = g.W; P.logW = g.logW; P.RP = g.RP; P.logRP = g.logRP;
+  P.nf = 1;
+  P.stage = 0;
+  P.nparts = g.nstrips;
+  P.o_mf = g.L.mf; P.o_mp = g.L.mp; P.o_phys = g.L.phys;
+  P.o_part = g.L.part; P.o_coef = g.L.coef; P.o_dpart = g.L.dpart;
+  P.twx = g.twx; P.twy = g.twy;
+  return P;
+}
+
+static Phase full_set(Phase P, const Group& g) {
+  P.kxn = g.kxn_f; P.myh = g.myh_f; P.kyn = g.kyn_f; P.kxp = g.kxp_f;
+  P.nparts = g.nstrips_f;
+  return P;
+}
+
+#define QG_LAUNCH(call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(QG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_));   \
+  } while (0)
+
+static int run_entry(const Handle& h, const Group& g, const void* src, long long o_out, hipStream_t s) {
+  Phase P = base_phase(h, g);
+  P.user_in = src;
+  P.o_out = o_out;
+  QG_LAUNCH(launch_row(g.dbl, OP_ENTRY, 0, P, g.count, s));
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_ENTRY, 0, P, g.count, s));
+  return QG_OK;
+}
+
+static int run_exit(const Handle& h, const Group& g, long long o_in, void* dst, hipStream_t s) {
+  Phase P = base_phase(h, g);
+  P.o_in = o_in;
+  P.nf = 1;
+  P.user = dst;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_EXIT, 0, P, g.count, s));
+  QG_LAUNCH(launch_row(g.dbl, OP_EXIT, 0, P, g.count, s));
+  return QG_OK;
+}
+
+// One RK4 stage (s = 1..4): colinv -> row -> colfwd (-> combine for dynamic).
+static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st) {
+  Phase P = base_phase(h, g);
+  const int cl = g.closure;
+  P.stage = s;
+  P.nf = rhs_fields(cl);
+  P.o_in = s == 1 ? g.L.wn : g.L.x;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+  if (!dynamic_closure(cl)) {
+    P.o_in = g.L.x;
+    P.o_in2 = g.L.wn;
+    P.o_aux = g.L.acc;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+  } else {
+    P.o_out = g.L.jsp;
+    P.o_aux = g.L.qsp;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    Phase Q = base_phase(h, g);
+    Q.stage = s;
+    Q.o_in = g.L.x;
+    Q.o_in2 = g.L.wn;
+    Q.o_out = g.L.jsp;
+    Q.o_aux = g.L.qsp;
+    Q.o_mp = g.L.acc;
+    QG_LAUNCH(launch_combine(g.dbl, OP_RHS, Q, g.count, st));
+  }
+  return QG_OK;
+}
+
+static int run_b(const Handle& h, const Group& g, hipStream_t st) {
+  Phase P = base_phase(h, g);
+  P.o_in = g.L.x;
+  P.nf = 3;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_B, 0, P, g.count, st));
+  P.o_out = g.L.wn;
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, P, g.count, st));
+  return QG_OK;
+}
+
+static int run_step(const Handle& h, const Group& g, hipStream_t st) {
+  for (int s = 1; s <= 4; ++s) {
+    int rc = run_stage(h, g, s, st);
+    if (rc) return rc;
+  }
+  return run_b(h, g, st);
+}
+
+static int run_steps_eager(const Handle& h, int n, hipStream_t st) {
+  for (int k = 0; k < n; ++k)
+    for (const auto& g : h.groups) {
+      int rc = run_step(h, g, st);
+      if (rc) return rc;
+    }
+  return QG_OK;
+}
+
+static int get_graph(Handle& h, int nsteps, hipStream_t st, hipGraphExec_t* out) {
+  auto it = h.graphs.find(nsteps);
+  if (it != h.graphs.end()) { *out = it->second; return QG_OK; }
+  hipGraph_t graph;
+  QG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = run_steps_eager(h, nsteps, st);
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc) { if (e == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
+  if (e != hipSuccess) return fail(QG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(QG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  h.graphs[nsteps] = exec;
+  *out = exec;
+  return QG_OK;
+}
+
+constexpr int GRAPH_STEPS = 10;
+
+static int run_steps(Handle& h, long long n, bool use_graph, hipStream_t st) {
+  if (!use_graph) return run_steps_eager(h, (int)n, st);
+  if (!h.graph_stream) {
+    QG_HIP(hipStreamCreateWithFlags(&h.graph_stream, hipStreamNonBlocking));
+    QG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
+    QG_HIP(hipEventCreateWithFlags(&h.ev_out, hipEventDisableTiming));
+  }
+  hipStream_t gs = h.graph_stream;
+  QG_HIP(hipEventRecord(h.ev_in, st));
+  QG_HIP(hipStreamWaitEvent(gs, h.ev_in, 0));
+  while (n > 0) {
+    const int k = n >= GRAPH_STEPS ? GRAPH_STEPS : 1;
+    hipGraphExec_t ex;
+    int rc = get_graph(h, k, gs, &ex);
+    if (rc) return rc;
+    QG_HIP(hipGraphLaunch(ex, gs));
+    n -= k;
+  }
+  QG_HIP(hipEventRecord(h.ev_out, gs));
+  QG_HIP(hipStreamWaitEvent(st, h.ev_out, 0));
+  return QG_OK;
+}
+
+static int mask_precompute(const Handle& h, const Group& g, hipStream_t st) {
+  Phase P = full_set(base_phase(h, g), g);
+  QG_LAUNCH(launch_row(g.dbl, OP_MASKFWD, 0, P, g.count, st));
+  P.o_out = g.L.chih;
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_MASKFWD, 0, P, g.count, st));
+  P.o_in = g.L.chih;
+  P.nf = 2;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_MASKGRAD, 0, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_MASKGRAD, 0, P, g.count, st));
+  return QG_OK;
+}
+
+static MemberDev make_member(const qg_params& p, char* base, long long omega_off, int user) {
+  MemberDev m{};
+  m.base = base;
+  m.omega_off = omega_off;
+  m.user_index = user;
+  const double pi = 3.14159265358979323846;
+  m.two_pi_lx = 2.0 * pi / p.lx;
+  m.two_pi_ly = 2.0 * pi / p.ly;
+  m.dt = p.dt;
+  m.beta = p.beta;
+  m.inv_re = (p.re > 0 && std::isfinite(p.re)) ? 1.0 / p.re : 0.0;
+  m.mu = p.mu;
+  m.u_in = p.u_in;
+  m.v_in = p.v_in;
+  const double delta = p.lx / p.nx;
+  m.inv_delta = 1.0 / delta;
+  m.closure = p.closure;
+  if (p.closure == 1) { m.coef_static = (p.c * delta) * (p.c * delta); m.dcoef_dc = 2.0 * p.c * delta * delta; }
+  else if (p.closure == 2) { m.coef_static = std::pow(p.c * delta, 3); m.dcoef_dc = 3.0 * p.c * p.c * delta * delta * delta; }
+  const int tr = (int)std::lround(p.test_ratio > 0 ? p.test_ratio : 2.0);
+  m.r_test = p.closure == 3 ? (double)tr * tr : (double)tr * tr * tr;
+  m.test_r2 = tr * tr;
+  const long long Mx = (p.nx - 1) / 3, My = (p.ny - 1) / 3;
+  const long long lim = std::min(Mx * p.ny, My * p.nx);
+  m.test_lim = lim * lim;
+  m.lowk2 = (double)p.fp64_lowk * p.fp64_lowk;
+  m.pen_a = (p.eta > 0 && std::isfinite(p.eta)) ? p.dt / p.eta : 0.0;
+  m.sponge_a = p.dt * p.sponge_sigma;
+  m.inv_n = 1.0 / ((double)p.nx * p.ny);
+  return m;
+}
+
+}  // namespace qg
+
+// ================================================================ C ABI
+using namespace qg;
+
+struct qg_handle {
+  Handle h;
+};
+
+extern "C" {
+
+const char* qg_last_error(void) { return g_err.c_str(); }
+
+int qg_workspace_bytes(const qg_params* params, int32_t n, int32_t adjK, size_t* bytes) {
+  if (!bytes) return fail(QG_EINVAL, "bytes is NULL");
+  try {
+    Handle h;
+    int rc = build_layout(params, n, adjK, h);
+    if (rc) return rc;
+    *bytes = h.ws_bytes;
+    return QG_OK;
+  } catch (...) {
+    return fail(QG_EINVAL, "internal error while sizing the workspace");
+  }
+}
+
+int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, const void* const* chi_sponge,
+            void* workspace, size_t ws_bytes, int32_t adjK, void* hip_stream, qg_handle** out) {
+  if (!out) return fail(QG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!chi_obs || !chi_sponge) return fail(QG_EINVAL, "mask arrays are NULL");
+  qg_handle* H = nullptr;
+  try {
+    H = new qg_handle();
+  } catch (...) {
+    return fail(QG_EINVAL, "out of host memory");
+  }
+  Handle& h = H->h;
+  int rc = build_layout(params, n, adjK, h);
+  if (rc) { delete H; return rc; }
+  if (!workspace) { delete H; return fail(QG_EWORKSPACE, "workspace is NULL"); }
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) { delete H; return fail(QG_EWORKSPACE, "workspace must be 256-byte aligned"); }
+  if (ws_bytes < h.ws_bytes) {
+    delete H;
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", ws_bytes, h.ws_bytes);
+    return fail(QG_EWORKSPACE, buf);
+  }
+  for (int i = 0; i < n; ++i)
+    if (!chi_obs[i] || !chi_sponge[i]) { delete H; return fail(QG_EINVAL, "a mask pointer is NULL"); }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  h.ws = reinterpret_cast<char*>(workspace);
+  h.mem_dev = reinterpret_cast<MemberDev*>(h.ws);
+  auto cleanup = [&](int code) { delete H; return code; };
+  if (launch_fill_zero(h.ws, h.ws_bytes, st) != hipSuccess) return cleanup(fail(QG_EHIP, "workspace clear failed"));
+  std::vector<MemberDev> table(n);
+  std::vector<char> host_tw;
+  for (auto& g : h.groups) {
+    g.region0 = h.ws + reinterpret_cast<long long>(g.region0);
+    g.twx = h.ws + g.o_twx;
+    g.twy = h.ws + g.o_twy;
+    for (int k = 0; k < g.count; ++k) {
+      const int u = g.users[k];
+      table[g.m0 + k] = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
+    }
+    for (int axis = 0; axis < 2; ++axis) {
+      const int len = axis == 0 ? g.nx : g.ny;
+      std::vector<long double> re, im;
+      twiddles(len, re, im);
+      void* dst = axis == 0 ? g.twx : g.twy;
+      if (g.dbl) {
+        std::vector<double> t(2 * len);
+        for (int m = 0; m < len; ++m) { t[2 * m] = (double)re[m]; t[2 * m + 1] = (double)im[m]; }
+        if (hipMemcpyAsync(dst, t.data(), t.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return cleanup(fail(QG_EHIP, "twiddle upload failed"));
+      } else {
+        std::vector<float> t(2 * len);
+        for (int m = 0; m < len; ++m) { t[2 * m] = (float)re[m]; t[2 * m + 1] = (float)im[m]; }
+        if (hipMemcpyAsync(dst, t.data(), t.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return cleanup(fail(QG_EHIP, "twiddle upload failed"));
+      }
+    }
+  }
+  if (hipMemcpyAsync(h.mem_dev, table.data(), n * sizeof(MemberDev), hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(QG_EHIP, "member table upload failed"));
+  for (auto& g : h.groups) {
+    const int rs = g.dbl ? 8 : 4;
+    const size_t fb = (size_t)g.nx * g.ny * rs;
+    for (int k = 0; k < g.count; ++k) {
+      char* phys = g.region0 + (long long)k * g.region_bytes + g.L.phys;
+      const int u = g.users[k];
+      if (hipMemcpyAsync(phys + 4 * fb, chi_obs[u], fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(phys + 5 * fb, chi_sponge[u], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return cleanup(fail(QG_EHIP, "mask copy failed"));
+    }
+    int r2 = mask_precompute(h, g, st);
+    if (r2) return cleanup(r2);
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return cleanup(fail(QG_EHIP, std::string("init: ") + hipGetErrorString(e)));
+  *out = H;
+  return QG_OK;
+}
+
+void qg_destroy(qg_handle* H) {
+  if (!H) return;
+  for (auto& kv : H->h.graphs) (void)hipGraphExecDestroy(kv.second);
+  if (H->h.graph_stream) {
+    (void)hipStreamSynchronize(H->h.graph_stream);
+    (void)hipStreamDestroy(H->h.graph_stream);
+  }
+  if (H->h.ev_in) (void)hipEventDestroy(H->h.ev_in);
+  if (H->h.ev_out) (void)hipEventDestroy(H->h.ev_out);
+  delete H;
+}
+
+int qg_info(const qg_handle* H, int32_t* n_members, int64_t* total_points, int32_t* col_width) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  const Handle& h = H->h;
+  if (n_members) *n_members = (int32_t)h.params.size();
+  if (total_points) *total_points = h.total_points;
+  if (col_width)
+    for (size_t i = 0; i < h.params.size(); ++i) col_width[i] = h.groups[h.member_group[i]].W;
+  return QG_OK;
+}
+
+int qg_step(qg_handle* H, void* omega, int64_t nsteps, int32_t save_every, void* ckpt_out, int32_t use_graph,
+            void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega) return fail(QG_EINVAL, "omega is NULL");
+  if (nsteps < 0) return fail(QG_EINVAL, "nsteps must be >= 0");
+  if (save_every < 0) return fail(QG_EINVAL, "save_every must be >= 0");
+  if (save_every > 0 && !ckpt_out) return fail(QG_EINVAL, "ckpt_out is NULL with save_every > 0");
+  Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  try {
+    for (const auto& g : h.groups) {
+      int rc = run_entry(h, g, omega, g.L.wn, st);
+      if (rc) return rc;
+    }
+    long long done = 0;
+    int save_idx = 0;
+    while (done < nsteps) {
+      long long chunk = nsteps - done;
+      if (save_every > 0) chunk = std::min<long long>(chunk, save_every - done % save_every);
+      int rc = run_steps(h, chunk, use_graph != 0, st);
+      if (rc) return rc;
+      done += chunk;
+      if (save_every > 0 && done % save_every == 0) {
+        char* dst = reinterpret_cast<char*>(ckpt_out) + (long long)save_idx * h.total_bytes;
+        for (const auto& g : h.groups) {
+          rc = run_exit(h, g, g.L.wn, dst, st);
+          if (rc) return rc;
+        }
+        for (const auto& g : h.groups) {
+          rc = run_entry(h, g, dst, g.L.wn, st);
+          if (rc) return rc;
+        }
+        ++save_idx;
+      }
+    }
+    for (const auto& g : h.groups) {
+      int rc = run_exit(h, g, g.L.wn, omega, st);
+      if (rc) return rc;
+    }
+  } catch (...) {
+    return fail(QG_EINVAL, "internal error in qg_step");
+  }
+  return QG_OK;
+}
+
+int qg_diag(qg_handle* H, const void* omega, double* out_dev, void* nu_e_out, void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega || !out_dev) return fail(QG_EINVAL, "omega or out_dev is NULL");
+  Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (const auto& g : h.groups) {
+    int rc = run_entry(h, g, omega, g.L.wn, st);
+    if (rc) return rc;
+    Phase P = base_phase(h, g);
+    const int cl = g.closure;
+    if (dynamic_closure(cl)) {
+      P.nf = rhs_fields(cl);
+      P.o_in = g.L.wn;
+      QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
+      QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+      P.o_out = g.L.jsp;
+      P.o_aux = g.L.qsp;
+      QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+      QG_LAUNCH(launch_dyn_coef(P, g.count, 0, st));
+    }
+    Phase D = base_phase(h, g);
+    D.nf = smag_family(cl) ? 6 : 4;
+    D.o_in = g.L.wn;
+    D.user = nu_e_out;
+    QG_LAUNCH(launch_colinv(g.dbl, OP_DIAG, cl, D, g.count, st));
+    QG_LAUNCH(launch_row(g.dbl, OP_DIAG, cl, D, g.count, st));
+    D.o_aux = g.L.dpart + 5LL * g.nrow * 8;
+    QG_LAUNCH(launch_diag_spectral(g.dbl, D, g.count, st));
+    QG_LAUNCH(launch_diag_final(D, g.count, g.nrow, g.nspec, out_dev, 0, st));
+  }
+  return QG_OK;
+}
+
+int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t nsteps, double* grad_c,
+                    void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  Handle& h = H->h;
+  if (!omega_ckpt || !lambda || !grad_c) return fail(QG_EINVAL, "NULL argument");
+  if (h.adjK <= 0) return fail(QG_ESTATE, "handle was built without adjoint storage (adj_segment_k = 0)");
+  if (nsteps < 1 || nsteps > h.adjK) return fail(QG_EINVAL, "nsteps must be in [1, adj_segment_k]");
+  for (const auto& g : h.groups)
+    if (dynamic_closure(g.closure))
+      return fail(QG_EUNSUPPORTED, "the adjoint covers the static closures only");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (const auto& g : h.groups) {
+    const long long spec = (long long)g.kxn * g.kyn * (g.dbl ? 16 : 8);
+    const long long LS = g.L.adj_store;
+    auto slot = [&](long long n, int s) { return g.L.adj_store + (1 + 4 * n + s) * (long long)align256((size_t)spec); };
+    // forward recompute of the segment, storing the stage inputs
+    int rc = run_entry(h, g, omega_ckpt, g.L.wn, st);
+    if (rc) return rc;
+    Phase C = base_phase(h, g);
+    for (long long n = 0; n < nsteps; ++n) {
+      QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, 0), g.L.wn, st));
+      for (int s = 1; s <= 4; ++s) {
+        rc = run_stage(h, g, s, st);
+        if (rc) return rc;
+        if (s < 4) QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, s), g.L.x, st));
+      }
+      rc = run_b(h, g, st);
+      if (rc) return rc;
+    }
+    // adjoint of the exit transform: LAM = D FFT(lambda), mean removed
+    rc = run_entry(h, g, lambda, g.L.adj_lam, st);
+    if (rc) return rc;
+    const int cl = g.closure;
+    const int nb = smag_family(cl) ? 6 : 4;
+    for (long long n = nsteps - 1; n >= 0; --n) {
+      Phase B = base_phase(h, g);
+      B.o_in = g.L.adj_lam;
+      B.nf = 1;
+      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+      B.o_out = LS;
+      B.o_aux = g.L.adj_lacc;
+      B.o_in = g.L.adj_lk;
+      QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+      for (int s = 4; s >= 1; --s) {
+        Phase A = base_phase(h, g);
+        A.stage = s;
+        A.o_in = slot(n, s - 1);
+        A.o_in2 = g.L.adj_lk;
+        A.nf = nb + (cl == 0 ? 1 : 3);
+        QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+        QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+        if (cl != 0) QG_LAUNCH(launch_adj_grad_c(A, g.count, g.nrow, grad_c, 0, st));
+        A.o_out = LS;
+        A.o_aux = g.L.adj_lacc;
+        QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+      }
+      QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, g.L.adj_lam, g.L.adj_lacc, st));
+    }
+    // adjoint of the entry transform: lambda = c2r(D LAM), mean removed
+    rc = run_exit(h, g, g.L.adj_lam, lambda, st);
+    if (rc) return rc;
+  }
+  return QG_OK;
+}
+
+int qg_autotune(qg_handle* H, const char*, void*) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  return QG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Batched complex FFTs staged in LDS for gfx950.
+//
+// The pseudo-spectral method evaluates derivatives in Fourier space and
+// products in physical space (Sec. II-C), so every right-hand-side
+// evaluation is a sequence of 2-D transforms.  They are split into a column
+// pass (complex, along y, over the retained kx modes only) and a row pass
+// (real <-> half spectrum along x, two rows packed as one complex row).
+// Both passes use the routine below: a self-sorting Stockham transform of
+// power-of-two length N, mixed radix 8 / 4 / 2, in place in LDS, for a
+// batch of nb independent vectors whose element n of vector b sits at
+// buf[n * es + b * bs].
+//
+// Forward transforms use exp(-2 pi i m n / N) and are unnormalised; inverse
+// transforms use the conjugate twiddles and are also unnormalised (callers
+// fold 1/(nx ny) into the spectral data).  Twiddles come from a table
+// tw[m] = exp(-2 pi i m / N), m in [0, N), computed on the host in extended
+// precision and rounded once.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace qg {
+
+template <typename T> struct cpx_of;
+template <> struct cpx_of<float> { using type = float2; };
+template <> struct cpx_of<double> { using type = double2; };
+template <typename T> using cpx = typename cpx_of<T>::type;
+
+template <typename V> __device__ __forceinline__ V cmake(decltype(V{}.x) a, decltype(V{}.x) b) {
+  V r; r.x = a; r.y = b; return r;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return cmake<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return cmake<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return cmake<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return cmake<V>(a.x, -a.y); }
+template <typename V> __device__ __forceinline__ V cscale(V a, decltype(V{}.x) s) { return cmake<V>(a.x * s, a.y * s); }
+// multiplication by +i and by -i
+template <typename V> __device__ __forceinline__ V cmul_i(V a) { return cmake<V>(-a.y, a.x); }
+template <typename V> __device__ __forceinline__ V cmul_mi(V a) { return cmake<V>(a.y, -a.x); }
+
+// Radix-2/4/8 DFT kernels in registers.  INV selects exp(+2 pi i / R).
+template <typename V, bool INV> __device__ __forceinline__ void dft2(V* v) {
+  V a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename V, bool INV> __device__ __forceinline__ void dft4(V& v0, V& v1, V& v2, V& v3) {
+  V a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = csub(v1, v3);
+  a3 = INV ? cmul_i(a3) : cmul_mi(a3);
+  v0 = cadd(a0, a2);
+  v2 = csub(a0, a2);
+  v1 = cadd(a1, a3);
+  v3 = csub(a1, a3);
+}
+
+template <typename V, bool INV> __device__ __forceinline__ void dft4(V* v) { dft4<V, INV>(v[0], v[1], v[2], v[3]); }
+
+// Length-8 DFT as one radix-2 split (decimation in frequency) into two
+// length-4 DFTs: a_t = v_t + v_{t+4} gives the even outputs, (v_t - v_{t+4})
+// times w8^t gives the odd outputs, w8 = exp(-+ 2 pi i / 8).
+template <typename V, bool INV> __device__ __forceinline__ void dft8(V* v) {
+  using T = decltype(V{}.x);
+  const T h = T(0.70710678118654752440084436210485);
+  V a0 = cadd(v[0], v[4]), a1 = cadd(v[1], v[5]), a2 = cadd(v[2], v[6]), a3 = cadd(v[3], v[7]);
+  V b0 = csub(v[0], v[4]), b1 = csub(v[1], v[5]), b2 = csub(v[2], v[6]), b3 = csub(v[3], v[7]);
+  if (!INV) {
+    b1 = cmake<V>((b1.x + b1.y) * h, (b1.y - b1.x) * h);     // * (1 - i)/sqrt2
+    b2 = cmul_mi(b2);                                        // * -i
+    b3 = cmake<V>((b3.y - b3.x) * h, -(b3.x + b3.y) * h);    // * (-1 - i)/sqrt2
+  } else {
+    b1 = cmake<V>((b1.x - b1.y) * h, (b1.y + b1.x) * h);     // * (1 + i)/sqrt2
+    b2 = cmul_i(b2);                                         // * i
+    b3 = cmake<V>(-(b3.x + b3.y) * h, (b3.x - b3.y) * h);    // * (-1 + i)/sqrt2
+  }
+  dft4<V, INV>(a0, a1, a2, a3);
+  dft4<V, INV>(b0, b1, b2, b3);
+  v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+  v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+}
+
+template <typename V, int R, bool INV> __device__ __forceinline__ void dftR(V* v) {
+  if constexpr (R == 8) dft8<V, INV>(v);
+  else if constexpr (R == 4) dft4<V, INV>(v);
+  else dft2<V, INV>(v);
+}
+
+// Geometry of one batched transform inside a workgroup.
+struct FftShape {
+  int logN;       // transform length 2^logN
+  int es, bs;     // element stride and batch stride in LDS (in elements)
+  int lognb;      // 2^lognb vectors
+  bool batch_fast;  // consecutive threads walk the batch index first
+};
+
+// One Stockham pass of radix R with sub-transform length Ns = 2^logNs:
+// butterfly j reads elements j + t N/R, multiplies element t by
+// w_{Ns R}^{t (j mod Ns)}, transforms, and writes them to
+// (j / Ns) Ns R + (j mod Ns) + t Ns.  In place: all reads, barrier, writes.
+template <typename V, int R, bool INV, int MAXB>
+__device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __restrict__ tw,
+                                              const FftShape& s, int logNs) {
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  const int logNR = s.logN - logR;
+  const int total = 1 << (s.lognb + logNR);
+  const int nt = blockDim.x;
+  const int twshift = s.logN - logNs - logR;
+  V v[MAXB][R];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int q = threadIdx.x + i * nt;
+    if (q < total) {
+      int b, j;
+      if (s.batch_fast) { b = q & ((1 << s.lognb) - 1); j = q >> s.lognb; }
+      else { j = q & ((1 << logNR) - 1); b = q >> logNR; }
+      const int k = j & ((1 << logNs) - 1);
+      const V* src = buf + b * s.bs;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[i][t] = src[(j + (t << logNR)) * s.es];
+      if (logNs > 0) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          V w = tw[(t * k) << twshift];
+          if (INV) w = cconj(w);
+          v[i][t] = cmul(v[i][t], w);
+        }
+      }
+      dftR<V, R, INV>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int q = threadIdx.x + i * nt;
+    if (q < total) {
+      int b, j;
+      if (s.batch_fast) { b = q & ((1 << s.lognb) - 1); j = q >> s.lognb; }
+      else { j = q & ((1 << logNR) - 1); b = q >> logNR; }
+      const int k = j & ((1 << logNs) - 1);
+      const int base = ((j >> logNs) << (logNs + logR)) + k;
+      V* dst = buf + b * s.bs;
+#pragma unroll
+      for (int t = 0; t < R; ++t) dst[(base + (t << logNs)) * s.es] = v[i][t];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform: radix-8 passes, then one radix-4 or radix-2 pass.
+// EPT bounds the elements per thread: nb * N <= EPT * blockDim.x.
+template <typename V, bool INV, int EPT>
+__device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s) {
+  int logNs = 0;
+  int rem = s.logN;
+  while (rem >= 3) {
+    stockham_pass<V, 8, INV, EPT / 8>(buf, tw, s, logNs);
+    logNs += 3;
+    rem -= 3;
+  }
+  if (rem == 2) stockham_pass<V, 4, INV, EPT / 4>(buf, tw, s, logNs);
+  else if (rem == 1) stockham_pass<V, 2, INV, EPT / 2>(buf, tw, s, logNs);
+}
+
+}  // namespace qg

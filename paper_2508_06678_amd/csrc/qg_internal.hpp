@@ -1,0 +1,101 @@
+// Internal structures shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qg {
+
+// Phase operations.  A right-hand-side evaluation, the B sub-step, the
+// entry/exit transforms, the mask precompute, the diagnostics and the
+// adjoint are all sequences of three kernel kinds: a column-inverse pass
+// (spectral fields -> mixed (y, kx) layout), a row pass (c2r, pointwise
+// physics, r2c) and a column-forward pass (mixed -> spectral, combine).
+enum Op : int {
+  OP_RHS = 0,       // A sub-step right-hand side (per closure)
+  OP_B = 1,         // penalization + sponge sub-step
+  OP_ENTRY = 2,     // physical omega -> projected spectral state
+  OP_EXIT = 3,      // spectral state -> physical omega
+  OP_MASKFWD = 4,   // chi -> half spectrum (full set minus Nyquist lines)
+  OP_MASKGRAD = 5,  // spectral gradient of chi -> E, E_x, E_y, S tables
+  OP_DIAG = 6,      // diagnostics at the state
+  OP_ADJ_RHS = 7,   // adjoint of the right-hand side (static closures)
+  OP_ADJ_B = 8,     // adjoint of the B sub-step
+  OP_ADJ_EXIT = 9,  // adjoint of the exit transform (physical -> spectral)
+  OP_ADJ_ENTRY = 10 // adjoint of the entry transform (spectral -> physical)
+};
+
+// Per-member constants, resident on the device.
+struct MemberDev {
+  char* base;            // start of the member's workspace region
+  long long omega_off;   // byte offset of the member in flat user fields
+  int user_index;        // position of the member in the caller's order
+  double two_pi_lx, two_pi_ly;
+  double dt, beta, inv_re, mu, u_in, v_in;
+  double coef_static;    // (c Delta)^2 or (c Delta)^3; 0 without closure
+  double dcoef_dc;       // d coef / d c
+  double r_test;         // (Delta~/Delta)^p for the dynamic closures
+  double lowk2;          // |k|^2 bound of the double-precision Poisson inversion
+  double pen_a;          // dt / eta (0 without obstacle)
+  double sponge_a;       // dt * sigma
+  double inv_n;          // 1 / (nx ny)
+  double inv_delta;      // 1 / Delta = nx / lx
+  long long test_lim;    // min(Mx ny, My nx)^2 of the integer test-filter test
+  int test_r2;           // test_ratio^2
+  int closure;
+};
+
+// Byte offsets of the buffers inside every member region of a group
+// (members of a group share sizes, hence offsets).
+struct RegionLayout {
+  long long wn, acc, x, jsp, qsp, chih, mf, mp, phys, part, coef, dpart;
+  long long adj_lam, adj_lacc, adj_lk, adj_store;  // adjoint buffers
+  long long total;
+};
+
+// Arguments of one launch (one phase of one size group).
+struct Phase {
+  const MemberDev* mem;
+  int m0;                 // first member of the group in the member table
+  int nx, ny, lognx, logny;
+  int kxn, myh, kyn, kxp; // retained kx count, |m_y| bound, compact y count, row pitch
+  int W, logW;            // column strip width
+  int RP, logRP;          // row pairs per row block
+  int nf;                 // number of fields of a column-inverse launch
+  int stage;              // RK stage 1..4 (0: not a stage)
+  int nparts;             // partial-sum slots written by the column-forward pass
+  long long o_in, o_in2, o_out, o_aux;  // op-specific byte offsets
+  long long o_mf, o_mp, o_phys, o_part, o_coef, o_dpart;
+  const void* twx;        // twiddles exp(-2 pi i m / nx)
+  const void* twy;        // twiddles exp(-2 pi i m / ny)
+  void* user;             // user physical output (exit, diag nu_e)
+  const void* user_in;    // user physical input (entry)
+  long long user_stride;  // elements between saves (unused: 0)
+};
+
+constexpr int COL_THREADS = 256;
+constexpr int COMBINE_THREADS = 256;
+
+// Launchers (defined in qg_kernels.hip).  Each returns hipGetLastError().
+hipError_t launch_colinv(bool dbl, int op, int closure, const Phase& P, int nmem, hipStream_t s);
+hipError_t launch_row(bool dbl, int op, int closure, const Phase& P, int nmem, hipStream_t s);
+hipError_t launch_colfwd(bool dbl, int op, int closure, const Phase& P, int nmem, hipStream_t s);
+hipError_t launch_combine(bool dbl, int op, const Phase& P, int nmem, hipStream_t s);
+hipError_t launch_diag_spectral(bool dbl, const Phase& P, int nmem, hipStream_t s);
+hipError_t launch_diag_final(const Phase& P, int nmem, int nrowblocks, int nspecblocks,
+                             double* out, int out_member0, hipStream_t s);
+hipError_t launch_dyn_coef(const Phase& P, int nmem, int slot, hipStream_t s);
+hipError_t launch_adj_grad_c(const Phase& P, int nmem, int nrowblocks, double* grad_c,
+                             int member0, hipStream_t s);
+hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
+                            long long o_src, double a, int zero_first, hipStream_t s);
+hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
+                            long long o_src, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Field counts per phase and closure.
+__host__ __device__ inline int rhs_fields(int cl) { return cl == 0 || cl == 2 ? 4 : cl == 1 ? 6 : cl == 4 ? 8 : 12; }
+__host__ __device__ inline int rhs_products(int cl) { return cl == 0 ? 1 : (cl == 1 || cl == 2) ? 3 : 6; }
+__host__ __device__ inline bool smag_family(int cl) { return cl == 1 || cl == 3; }
+__host__ __device__ inline bool dynamic_closure(int cl) { return cl == 3 || cl == 4; }
+
+}  // namespace qg

@@ -1,0 +1,1152 @@
+// HIP kernels of the QG step for gfx950.
+//
+// Data layout (per member, inside the caller's workspace):
+//   spectral state   D-compact complex [kx][iy]: m_x in [0, kxn), m_y in
+//                    [-myh, myh] stored as iy = m_y (m_y >= 0) or
+//                    iy = m_y + kyn (m_y < 0), kyn = 2 myh + 1.
+//                    The 2/3 set D is kxn = (nx-1)/3 + 1, myh = (ny-1)/3.
+//   mixed fields     complex [field][y][kx], row pitch kxp >= kxn: the
+//                    output of a column-inverse pass and the input of a row
+//                    pass (MF), or the output of a row pass and the input of
+//                    a column-forward pass (MP).
+//   physical tables  real [y][x]: E, E_x, E_y, S, chi, chi_sponge.
+//
+// Kernel kinds (Sec. II-C: derivatives in Fourier space, products by
+// collocation, 2/3 de-aliasing of every product):
+//   k_colinv  one block per (kx strip, field, member): builds the field's
+//             spectral column from the state (Poisson inversion, spectral
+//             derivatives, test filter), scales by 1/(nx ny), inverse FFT
+//             along y in LDS, writes the strip of the mixed layout.
+//   k_row     one block per (group of row pairs, member): for each field,
+//             two rows packed as one complex row are taken to physical space
+//             (c2r), the pointwise physics of the phase is applied, and each
+//             product goes back to the retained half spectrum (r2c).
+//   k_colfwd  one block per (kx strip, member): forward FFT along y of each
+//             product, extraction of the retained modes, then the spectral
+//             combine of the phase (right-hand side and RK4 update, dynamic
+//             coefficient partial sums, B-step projection, adjoint sums).
+#include "qg_fft.hpp"
+#include "qg_internal.hpp"
+
+namespace qg {
+
+// ---------------------------------------------------------------- helpers
+template <typename T> __device__ __forceinline__ cpx<T>* cptr(const MemberDev& M, long long off) {
+  return reinterpret_cast<cpx<T>*>(M.base + off);
+}
+template <typename T> __device__ __forceinline__ T* rptr(const MemberDev& M, long long off) {
+  return reinterpret_cast<T*>(M.base + off);
+}
+
+// signed m_y of compact index iy
+__device__ __forceinline__ int my_of_iy(int iy, int myh, int kyn) { return iy <= myh ? iy : iy - kyn; }
+
+struct Wave {
+  double kx, ky, k2, inv_k2;
+};
+__device__ __forceinline__ Wave wave(const MemberDev& M, int mx, int my) {
+  Wave w;
+  w.kx = M.two_pi_lx * mx;
+  w.ky = M.two_pi_ly * my;
+  w.k2 = w.kx * w.kx + w.ky * w.ky;
+  w.inv_k2 = (mx == 0 && my == 0) ? 0.0 : 1.0 / w.k2;
+  return w;
+}
+
+// test filter T: test_ratio^2 (ny^2 mx^2 + nx^2 my^2) <= min(Mx ny, My nx)^2
+__device__ __forceinline__ bool in_test(const MemberDev& M, int nx, int ny, int mx, int my) {
+  long long a = (long long)ny * ny * mx * mx + (long long)nx * nx * my * my;
+  return (long long)M.test_r2 * a <= M.test_lim;
+}
+
+// psi_hat = -x / |k|^2, in double precision for the lowest modes of 32-bit runs
+template <typename T> __device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave& w) {
+  using V = cpx<T>;
+  if (sizeof(T) == 4 && w.k2 <= M.lowk2) {
+    return cmake<V>(T(-(double)x.x * w.inv_k2), T(-(double)x.y * w.inv_k2));
+  }
+  T s = T(-w.inv_k2);
+  return cmake<V>(x.x * s, x.y * s);
+}
+
+// multiply by i a (a real)
+template <typename V, typename S> __device__ __forceinline__ V mul_ia(V z, S a) {
+  return cmake<V>(-z.y * a, z.x * a);
+}
+
+// ---------------------------------------------------------------- fields
+// Spectral field f of a column-inverse launch at mode (mx, my), before the
+// 1/(nx ny) scaling.  x: state (or stage input) at the mode; l: adjoint
+// variable at the mode (adjoint ops only).
+//
+// RHS / DIAG fields, per level (grid, then test-filtered for the dynamic
+// closures): 0 u' = -i ky psi, 1 v' = i kx psi, 2 omega_x = i kx x,
+// 3 omega_y = i ky x, and for the Smagorinsky family 4 psi_xx - psi_yy =
+// (ky^2 - kx^2) psi, 5 psi_xy = -kx ky psi (Eq. 1, Eq. 9).
+template <typename T, int CL>
+__device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x, const Wave& w, bool test) {
+  using V = cpx<T>;
+  constexpr int nb = (CL == 1 || CL == 3) ? 6 : 4;
+  const int kind = f % nb;
+  if (f >= nb && !test) return cmake<V>(T(0), T(0));
+  const T kx = T(w.kx), ky = T(w.ky);
+  if (kind == 2) return mul_ia(x, kx);
+  if (kind == 3) return mul_ia(x, ky);
+  V psi = poisson<T>(M, x, w);
+  if (kind == 0) return mul_ia(psi, -ky);
+  if (kind == 1) return mul_ia(psi, kx);
+  if (kind == 4) { T a = T(w.ky * w.ky - w.kx * w.kx); return cmake<V>(psi.x * a, psi.y * a); }
+  T a = T(-w.kx * w.ky);
+  return cmake<V>(psi.x * a, psi.y * a);
+}
+
+template <typename T, int OP, int CL>
+__device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy) {
+  using V = cpx<T>;
+  const int my = my_of_iy(iy, P.myh, P.kyn);
+  const long long idx = (long long)mx * P.kyn + iy;
+  const Wave w = wave(M, mx, my);
+  const bool zero_mean = (mx == 0 && my == 0);
+  if constexpr (OP == OP_RHS || OP == OP_DIAG) {
+    V x = cptr<T>(M, P.o_in)[idx];
+    const bool test = dynamic_closure(CL) ? in_test(M, P.nx, P.ny, mx, my) : false;
+    return rhs_field<T, CL>(M, f, x, w, test);
+  } else if constexpr (OP == OP_B) {
+    V x = cptr<T>(M, P.o_in)[idx];
+    if (f == 2) return x;
+    V psi = poisson<T>(M, x, w);
+    return f == 0 ? mul_ia(psi, T(-w.ky)) : mul_ia(psi, T(w.kx));
+  } else if constexpr (OP == OP_EXIT) {
+    V x = cptr<T>(M, P.o_in)[idx];
+    return zero_mean ? cmake<V>(T(0), T(0)) : x;
+  } else if constexpr (OP == OP_MASKGRAD) {
+    V x = cptr<T>(M, P.o_in)[idx];
+    return f == 0 ? mul_ia(x, T(w.kx)) : mul_ia(x, T(w.ky));
+  } else if constexpr (OP == OP_ADJ_B) {
+    V l = cptr<T>(M, P.o_in)[idx];
+    return zero_mean ? cmake<V>(T(0), T(0)) : l;
+  } else {  // OP_ADJ_RHS: forward fields of the stage input, then -l, -i kx l, -i ky l
+    constexpr int nb = (CL == 1) ? 6 : 4;
+    if (f < nb) {
+      V x = cptr<T>(M, P.o_in)[idx];
+      return rhs_field<T, CL>(M, f, x, w, false);
+    }
+    V l = cptr<T>(M, P.o_in2)[idx];
+    if (zero_mean) return cmake<V>(T(0), T(0));
+    const int a = f - nb;
+    if (a == 0) return cmake<V>(-l.x, -l.y);
+    return mul_ia(l, a == 1 ? T(-w.kx) : T(-w.ky));
+  }
+}
+
+// ---------------------------------------------------------------- colinv
+template <typename T, int OP, int CL, int EPT>
+__global__ void __launch_bounds__(COL_THREADS) k_colinv(Phase P) {
+  using V = cpx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* tile = reinterpret_cast<V*>(smem_raw);
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int f = blockIdx.y;
+  const int kx0 = blockIdx.x * P.W;
+  const int ny = P.ny;
+  const int n = P.W * ny;
+  const T scale = T(M.inv_n);
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int w = q >> P.logny;
+    const int y = q & (ny - 1);
+    const int mx = kx0 + w;
+    const int my = y < ny / 2 ? y : y - ny;
+    V v = cmake<V>(T(0), T(0));
+    if (mx < P.kxn && my <= P.myh && -my <= P.myh) {
+      const int iy = my >= 0 ? my : my + P.kyn;
+      v = colinv_value<T, OP, CL>(M, P, f, mx, iy);
+      v = cscale(v, scale);
+    }
+    tile[y * P.W + w] = v;
+  }
+  __syncthreads();
+  FftShape s{P.logny, P.W, 1, P.logW, true};
+  fft_lds<V, true, EPT>(tile, reinterpret_cast<const V*>(P.twy), s);
+  V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + kx0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int w = q & (P.W - 1);
+    const int y = q >> P.logW;
+    out[(long long)y * P.kxp + w] = tile[y * P.W + w];
+  }
+}
+
+// ---------------------------------------------------------------- row pass
+constexpr int ROW_EPT = 8;
+
+template <typename T> struct RowCtx {
+  using V = cpx<T>;
+  V* buf;            // RP rows of nx complex
+  const V* tw;
+  int nx, lognx, RP, logRP, kxn, kxp, ny;
+  int y0;            // first row of the block
+};
+
+// c2r of field src (mixed layout [y][kx], pitch kxp) for the block's row
+// pairs; returns each thread's ROW_EPT elements: .x row 2rp, .y row 2rp+1.
+template <typename T>
+__device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __restrict__ src, cpx<T> (&out)[ROW_EPT]) {
+  using V = cpx<T>;
+  const int n = C.RP * C.nx;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int rp = q >> C.lognx;
+    const int k = q & (C.nx - 1);
+    const int ya = C.y0 + 2 * rp;
+    V z = cmake<V>(T(0), T(0));
+    if (k < C.kxn) {
+      V a = src[(long long)ya * C.kxp + k];
+      V b = src[(long long)(ya + 1) * C.kxp + k];
+      if (k == 0) { a.y = T(0); b.y = T(0); }
+      z = cmake<V>(a.x - b.y, a.y + b.x);
+    } else if (k > C.nx - C.kxn) {
+      const int kk = C.nx - k;
+      V a = src[(long long)ya * C.kxp + kk];
+      V b = src[(long long)(ya + 1) * C.kxp + kk];
+      z = cmake<V>(a.x + b.y, b.x - a.y);
+    }
+    C.buf[q] = z;
+  }
+  __syncthreads();
+  FftShape s{C.lognx, 1, C.nx, C.logRP, false};
+  fft_lds<V, true, ROW_EPT>(C.buf, C.tw, s);
+#pragma unroll
+  for (int i = 0; i < ROW_EPT; ++i) {
+    const int q = threadIdx.x + i * blockDim.x;
+    out[i] = q < n ? C.buf[q] : cmake<V>(T(0), T(0));
+  }
+  __syncthreads();
+}
+
+// r2c of the thread's ROW_EPT product values (.x row 2rp, .y row 2rp+1),
+// keeping m_x < kxn, written to dst (mixed layout).
+template <typename T>
+__device__ __forceinline__ void row_r2c(const RowCtx<T>& C, const cpx<T> (&val)[ROW_EPT], cpx<T>* __restrict__ dst) {
+  using V = cpx<T>;
+  const int n = C.RP * C.nx;
+#pragma unroll
+  for (int i = 0; i < ROW_EPT; ++i) {
+    const int q = threadIdx.x + i * blockDim.x;
+    if (q < n) C.buf[q] = val[i];
+  }
+  __syncthreads();
+  FftShape s{C.lognx, 1, C.nx, C.logRP, false};
+  fft_lds<V, false, ROW_EPT>(C.buf, C.tw, s);
+  for (int rp = 0; rp < C.RP; ++rp) {
+    const V* row = C.buf + rp * C.nx;
+    const int ya = C.y0 + 2 * rp;
+    for (int k = threadIdx.x; k < C.kxn; k += blockDim.x) {
+      V z = row[k];
+      V zm = row[(C.nx - k) & (C.nx - 1)];
+      V a = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
+      V b = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
+      dst[(long long)ya * C.kxp + k] = a;
+      dst[(long long)(ya + 1) * C.kxp + k] = b;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T> __device__ __forceinline__ cpx<T> vmul(cpx<T> a, cpx<T> b) { return cmake<cpx<T>>(a.x * b.x, a.y * b.y); }
+template <typename T> __device__ __forceinline__ cpx<T> vadd(cpx<T> a, cpx<T> b) { return cmake<cpx<T>>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cpx<T> vsub(cpx<T> a, cpx<T> b) { return cmake<cpx<T>>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cpx<T> vfma(cpx<T> a, cpx<T> b, cpx<T> c) { return cmake<cpx<T>>(a.x * b.x + c.x, a.y * b.y + c.y); }
+template <typename T> __device__ __forceinline__ T strain(T pxy, T pd) { return sqrt(T(4) * pxy * pxy + pd * pd); }
+template <typename T> __device__ __forceinline__ T gradmag(T a, T b) { return sqrt(a * a + b * b); }
+
+// block-wide fixed-order sum of a double (deterministic)
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += red[i];
+  }
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = -INFINITY;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t = fmax(t, red[i]);
+  }
+  __syncthreads();
+  return t;
+}
+
+template <typename T, int OP, int CL>
+__global__ void __launch_bounds__(512) k_row(Phase P) {
+  using V = cpx<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  RowCtx<T> C;
+  C.buf = reinterpret_cast<V*>(smem_raw);
+  C.tw = reinterpret_cast<const V*>(P.twx);
+  C.nx = P.nx; C.lognx = P.lognx; C.RP = P.RP; C.logRP = P.logRP;
+  C.kxn = P.kxn; C.kxp = P.kxp; C.ny = P.ny;
+  C.y0 = blockIdx.x * 2 * P.RP;
+  __shared__ double red[16];
+  const long long fstride = (long long)P.ny * P.kxp;
+  const V* mf = cptr<T>(M, P.o_mf);
+  V* mp = cptr<T>(M, P.o_mp);
+  const int npts = P.RP * P.nx;
+  const long long nxy = (long long)P.nx * P.ny;
+
+  // physical (x, y) of element i of this thread
+  auto phys_index = [&](int i) -> long long {
+    const int q = threadIdx.x + i * blockDim.x;
+    const int rp = q >> P.lognx;
+    const int x = q & (P.nx - 1);
+    return (long long)(C.y0 + 2 * rp) * P.nx + x;
+  };
+  auto valid = [&](int i) { return threadIdx.x + i * blockDim.x < npts; };
+
+  if constexpr (OP == OP_RHS || OP == OP_DIAG) {
+    constexpr bool smag = (CL == 1 || CL == 3);
+    constexpr bool dyn = (CL == 3 || CL == 4);
+    constexpr int nb = smag ? 6 : 4;
+    constexpr int levels = (OP == OP_RHS && dyn) ? 2 : 1;
+    const T U = T(M.u_in), Vv = T(M.v_in);
+    double nu_min = INFINITY, nu_max = -INFINITY, nu_sum = 0.0, cfl = 0.0, bad = 0.0;
+    T coef = T(0);
+    if constexpr (OP == OP_DIAG) coef = dyn ? T(rptr<double>(M, P.o_coef)[0]) : T(M.coef_static);
+#pragma unroll 1
+    for (int lev = 0; lev < levels; ++lev) {
+      const V* F = mf + (long long)lev * nb * fstride;
+      V* out = mp + (long long)lev * 3 * fstride;
+      V base[ROW_EPT], wx[ROW_EPT], wy[ROW_EPT], t0[ROW_EPT], t1[ROW_EPT];
+      if constexpr (CL != 0) {
+        if constexpr (smag) {
+          row_c2r<T>(C, F + 4 * fstride, t0);
+          row_c2r<T>(C, F + 5 * fstride, t1);
+#pragma unroll
+          for (int i = 0; i < ROW_EPT; ++i)
+            base[i] = cmake<V>(strain<T>(t1[i].x, t0[i].x), strain<T>(t1[i].y, t0[i].y));
+        }
+      }
+      row_c2r<T>(C, F + 2 * fstride, wx);
+      row_c2r<T>(C, F + 3 * fstride, wy);
+      if constexpr (CL == 2 || CL == 4) {
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i)
+          base[i] = cmake<V>(gradmag<T>(wx[i].x, wy[i].x), gradmag<T>(wx[i].y, wy[i].y));
+      }
+      if constexpr (OP == OP_RHS && CL != 0) {
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(base[i], wx[i]);
+        row_r2c<T>(C, t0, out + 1 * fstride);
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(base[i], wy[i]);
+        row_r2c<T>(C, t0, out + 2 * fstride);
+      }
+      // advection by the total velocity: J = (U + u') omega_x + (V + v') omega_y
+      row_c2r<T>(C, F + 0 * fstride, t0);
+      row_c2r<T>(C, F + 1 * fstride, t1);
+      if constexpr (OP == OP_RHS) {
+        V J[ROW_EPT];
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) {
+          V u = cmake<V>(U + t0[i].x, U + t0[i].y);
+          V v = cmake<V>(Vv + t1[i].x, Vv + t1[i].y);
+          J[i] = vadd<T>(vmul<T>(u, wx[i]), vmul<T>(v, wy[i]));
+        }
+        row_r2c<T>(C, J, out);
+      } else {
+        // diagnostics: nu_e = C base, CFL, non-finite flag
+        T* nu_out = P.user ? reinterpret_cast<T*>(reinterpret_cast<char*>(P.user) + M.omega_off) : nullptr;
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) {
+          if (!valid(i)) continue;
+          const long long pi = phys_index(i);
+          T u0 = U + t0[i].x, u1 = U + t0[i].y, v0 = Vv + t1[i].x, v1 = Vv + t1[i].y;
+          T b0 = CL != 0 ? base[i].x : T(0), b1 = CL != 0 ? base[i].y : T(0);
+          T n0 = coef * b0, n1 = coef * b1;
+          if (nu_out) {
+            nu_out[pi] = n0;
+            nu_out[pi + P.nx] = n1;
+          }
+          nu_min = fmin(nu_min, fmin((double)n0, (double)n1));
+          nu_max = fmax(nu_max, fmax((double)n0, (double)n1));
+          nu_sum += (double)n0 + (double)n1;
+          cfl = fmax(cfl, fmax((double)(fabs(u0) + fabs(v0)), (double)(fabs(u1) + fabs(v1))));
+          const bool fin = isfinite(u0) && isfinite(u1) && isfinite(v0) && isfinite(v1) &&
+                           isfinite(wx[i].x) && isfinite(wx[i].y) && isfinite(wy[i].x) && isfinite(wy[i].y);
+          if (!fin) bad = 1.0;
+        }
+      }
+    }
+    if constexpr (OP == OP_DIAG) {
+      double s0 = block_sum(nu_sum, red);
+      double mn = -block_max(-nu_min, red);
+      double mx = block_max(nu_max, red);
+      double cf = block_max(cfl, red);
+      double bd = block_max(bad, red);
+      if (threadIdx.x == 0) {
+        double* d = rptr<double>(M, P.o_dpart) + 5 * blockIdx.x;
+        d[0] = s0; d[1] = mn; d[2] = mx; d[3] = cf; d[4] = bd;
+      }
+    }
+  } else if constexpr (OP == OP_B) {
+    // omega' = E omega + E_x v - E_y u (total velocity), omega'' = S omega'
+    V u[ROW_EPT], v[ROW_EPT], w[ROW_EPT];
+    row_c2r<T>(C, mf + 0 * fstride, u);
+    row_c2r<T>(C, mf + 1 * fstride, v);
+    row_c2r<T>(C, mf + 2 * fstride, w);
+    const T* E = rptr<T>(M, P.o_phys);
+    const T* Ex = E + nxy;
+    const T* Ey = E + 2 * nxy;
+    const T* S = E + 3 * nxy;
+    const T U = T(M.u_in), Vv = T(M.v_in);
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      if (!valid(i)) continue;
+      const long long a = phys_index(i), b = a + P.nx;
+      T w0 = E[a] * w[i].x + Ex[a] * (Vv + v[i].x) - Ey[a] * (U + u[i].x);
+      T w1 = E[b] * w[i].y + Ex[b] * (Vv + v[i].y) - Ey[b] * (U + u[i].y);
+      w[i] = cmake<V>(S[a] * w0, S[b] * w1);
+    }
+    row_r2c<T>(C, w, mp);
+  } else if constexpr (OP == OP_ENTRY || OP == OP_MASKFWD) {
+    const T* src = OP == OP_ENTRY
+        ? reinterpret_cast<const T*>(reinterpret_cast<const char*>(P.user_in) + M.omega_off)
+        : rptr<T>(M, P.o_phys) + 4 * nxy;
+    V w[ROW_EPT];
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      if (!valid(i)) { w[i] = cmake<V>(T(0), T(0)); continue; }
+      const long long a = phys_index(i);
+      w[i] = cmake<V>(src[a], src[a + P.nx]);
+    }
+    row_r2c<T>(C, w, mp);
+  } else if constexpr (OP == OP_EXIT) {
+    V w[ROW_EPT];
+    row_c2r<T>(C, mf, w);
+    T* dst = reinterpret_cast<T*>(reinterpret_cast<char*>(P.user) + M.omega_off);
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      if (!valid(i)) continue;
+      const long long a = phys_index(i);
+      dst[a] = w[i].x;
+      dst[a + P.nx] = w[i].y;
+    }
+  } else if constexpr (OP == OP_MASKGRAD) {
+    V cx[ROW_EPT], cy[ROW_EPT];
+    row_c2r<T>(C, mf + 0 * fstride, cx);
+    row_c2r<T>(C, mf + 1 * fstride, cy);
+    T* E = rptr<T>(M, P.o_phys);
+    const T* chi = E + 4 * nxy;
+    const T* chs = E + 5 * nxy;
+    const double a = M.pen_a, sa = M.sponge_a;
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      if (!valid(i)) continue;
+      const long long p0 = phys_index(i);
+      for (int r = 0; r < 2; ++r) {
+        const long long p = p0 + r * P.nx;
+        const double gx = r ? (double)cx[i].y : (double)cx[i].x;
+        const double gy = r ? (double)cy[i].y : (double)cy[i].x;
+        const double e = exp(-a * (double)chi[p]);
+        E[p] = T(e);
+        E[p + nxy] = T(-a * gx * e);
+        E[p + 2 * nxy] = T(-a * gy * e);
+        E[p + 3 * nxy] = T(exp(-sa * (double)chs[p]));
+      }
+    }
+  } else if constexpr (OP == OP_ADJ_B) {
+    // lambda'' = c2r(lambda); lambda' = S lambda''; products:
+    // 0: E lambda' (omega), 1: -E_y lambda' (u), 2: E_x lambda' (v)
+    V l[ROW_EPT], a0[ROW_EPT], a1[ROW_EPT];
+    row_c2r<T>(C, mf, l);
+    const T* E = rptr<T>(M, P.o_phys);
+    const T* Ex = E + nxy;
+    const T* Ey = E + 2 * nxy;
+    const T* S = E + 3 * nxy;
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      if (!valid(i)) { l[i] = a0[i] = a1[i] = cmake<V>(T(0), T(0)); continue; }
+      const long long a = phys_index(i), b = a + P.nx;
+      T s0 = S[a] * l[i].x, s1 = S[b] * l[i].y;
+      l[i] = cmake<V>(E[a] * s0, E[b] * s1);
+      a0[i] = cmake<V>(-Ey[a] * s0, -Ey[b] * s1);
+      a1[i] = cmake<V>(Ex[a] * s0, Ex[b] * s1);
+    }
+    row_r2c<T>(C, l, mp);
+    row_r2c<T>(C, a0, mp + fstride);
+    row_r2c<T>(C, a1, mp + 2 * fstride);
+  } else if constexpr (OP == OP_ADJ_RHS) {
+    // Adjoint of J = u omega_x + v omega_y, h = base grad omega, base(.)
+    constexpr bool smag = (CL == 1);
+    constexpr int nb = smag ? 6 : 4;
+    const T U = T(M.u_in), Vv = T(M.v_in);
+    const T coef = T(M.coef_static);
+    V wx[ROW_EPT], wy[ROW_EPT], lJ[ROW_EPT], t0[ROW_EPT], t1[ROW_EPT];
+    row_c2r<T>(C, mf + 2 * fstride, wx);
+    row_c2r<T>(C, mf + 3 * fstride, wy);
+    row_c2r<T>(C, mf + (long long)nb * fstride, lJ);
+    // lambda_u = lambda_J omega_x, lambda_v = lambda_J omega_y
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(lJ[i], wx[i]);
+    row_r2c<T>(C, t0, mp + 0 * fstride);
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(lJ[i], wy[i]);
+    row_r2c<T>(C, t0, mp + 1 * fstride);
+    V lwx[ROW_EPT], lwy[ROW_EPT];
+    row_c2r<T>(C, mf + 0 * fstride, t0);   // u'
+    row_c2r<T>(C, mf + 1 * fstride, t1);   // v'
+#pragma unroll
+    for (int i = 0; i < ROW_EPT; ++i) {
+      lwx[i] = cmake<V>(lJ[i].x * (U + t0[i].x), lJ[i].y * (U + t0[i].y));
+      lwy[i] = cmake<V>(lJ[i].x * (Vv + t1[i].x), lJ[i].y * (Vv + t1[i].y));
+    }
+    double dc = 0.0;
+    if constexpr (CL != 0) {
+      V gx[ROW_EPT], gy[ROW_EPT], base[ROW_EPT], lb[ROW_EPT];
+      row_c2r<T>(C, mf + (long long)(nb + 1) * fstride, gx);
+      row_c2r<T>(C, mf + (long long)(nb + 2) * fstride, gy);
+      if constexpr (smag) {
+        row_c2r<T>(C, mf + 4 * fstride, t0);   // psi_xx - psi_yy
+        row_c2r<T>(C, mf + 5 * fstride, t1);   // psi_xy
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i)
+          base[i] = cmake<V>(strain<T>(t1[i].x, t0[i].x), strain<T>(t1[i].y, t0[i].y));
+      } else {
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i)
+          base[i] = cmake<V>(gradmag<T>(wx[i].x, wy[i].x), gradmag<T>(wx[i].y, wy[i].y));
+      }
+#pragma unroll
+      for (int i = 0; i < ROW_EPT; ++i) {
+        if (valid(i)) {
+          dc += (double)(gx[i].x * base[i].x * wx[i].x + gy[i].x * base[i].x * wy[i].x);
+          dc += (double)(gx[i].y * base[i].y * wx[i].y + gy[i].y * base[i].y * wy[i].y);
+        }
+        V lhx = cmake<V>(coef * gx[i].x, coef * gx[i].y);
+        V lhy = cmake<V>(coef * gy[i].x, coef * gy[i].y);
+        lwx[i] = vfma<T>(lhx, base[i], lwx[i]);
+        lwy[i] = vfma<T>(lhy, base[i], lwy[i]);
+        lb[i] = vadd<T>(vmul<T>(lhx, wx[i]), vmul<T>(lhy, wy[i]));
+      }
+      if constexpr (smag) {
+        // lambda_pd = pd/base lambda_b, lambda_pxy = 4 pxy/base lambda_b
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) {
+          T r0 = base[i].x > T(0) ? lb[i].x / base[i].x : T(0);
+          T r1 = base[i].y > T(0) ? lb[i].y / base[i].y : T(0);
+          gx[i] = cmake<V>(t0[i].x * r0, t0[i].y * r1);
+          gy[i] = cmake<V>(T(4) * t1[i].x * r0, T(4) * t1[i].y * r1);
+        }
+        row_r2c<T>(C, gx, mp + 4 * fstride);
+        row_r2c<T>(C, gy, mp + 5 * fstride);
+      } else {
+#pragma unroll
+        for (int i = 0; i < ROW_EPT; ++i) {
+          T r0 = base[i].x > T(0) ? lb[i].x / base[i].x : T(0);
+          T r1 = base[i].y > T(0) ? lb[i].y / base[i].y : T(0);
+          lwx[i] = cmake<V>(lwx[i].x + wx[i].x * r0, lwx[i].y + wx[i].y * r1);
+          lwy[i] = cmake<V>(lwy[i].x + wy[i].x * r0, lwy[i].y + wy[i].y * r1);
+        }
+      }
+    }
+    row_r2c<T>(C, lwx, mp + 2 * fstride);
+    row_r2c<T>(C, lwy, mp + 3 * fstride);
+    double s = block_sum(dc, red);
+    if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = s * M.dcoef_dc;
+  }
+}
+
+// ---------------------------------------------------------------- colfwd
+// Forward FFT along y of product p's strip into the LDS tile.
+template <typename T, int EPT>
+__device__ __forceinline__ void colfwd_load_fft(const Phase& P, const MemberDev& M, cpx<T>* tile, int p, int kx0) {
+  using V = cpx<T>;
+  const int n = P.W * P.ny;
+  const V* src = cptr<T>(M, P.o_mp) + (long long)p * P.ny * P.kxp + kx0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int w = q & (P.W - 1);
+    const int y = q >> P.logW;
+    tile[y * P.W + w] = src[(long long)y * P.kxp + w];
+  }
+  __syncthreads();
+  FftShape s{P.logny, P.W, 1, P.logW, true};
+  fft_lds<V, false, EPT>(tile, reinterpret_cast<const V*>(P.twy), s);
+}
+
+template <typename T, int OP, int CL, int EPT>
+__global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
+  using V = cpx<T>;
+  constexpr int MAXM = EPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* tile = reinterpret_cast<V*>(smem_raw);
+  __shared__ double red[16];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int kx0 = blockIdx.x * P.W;
+  const int nmodes = P.W * P.kyn;
+  // owned modes, packed as (m_x << 16) | iy; m_x = kxn marks "not owned"
+  int own[MAXM];
+#pragma unroll
+  for (int i = 0; i < MAXM; ++i) {
+    const int q = threadIdx.x + i * blockDim.x;
+    const int w = q / P.kyn;
+    const int mx = (q < nmodes) ? kx0 + w : P.kxn;
+    own[i] = ((mx < P.kxn ? mx : P.kxn) << 16) | (q - w * P.kyn);
+  }
+#define mxs_(i) (own[i] >> 16)
+#define iys_(i) (own[i] & 0xffff)
+  auto tile_at = [&](int i) -> V {
+    const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+    const int y = my >= 0 ? my : my + P.ny;
+    return tile[y * P.W + (mxs_(i) - kx0)];
+  };
+  auto owned = [&](int i) { return mxs_(i) < P.kxn; };
+  auto sidx = [&](int i) { return (long long)mxs_(i) * P.kyn + iys_(i); };
+
+  if constexpr (OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
+    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+    V* out = cptr<T>(M, P.o_out);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      V v = tile_at(i);
+      if (OP != OP_MASKFWD && mxs_(i) == 0 && iys_(i) == 0) v = cmake<V>(T(0), T(0));
+      out[sidx(i)] = v;
+    }
+  } else if constexpr (OP == OP_RHS && !(CL == 3 || CL == 4)) {
+    // R = -J + C (i kx h_x + i ky h_y) - (k^2/Re + mu) x - i beta kx psi; RK4 update
+    V R[MAXM], Q[MAXM];
+    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      V j = tile_at(i);
+      R[i] = cmake<V>(-j.x, -j.y);
+    }
+    if constexpr (CL != 0) {
+      colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        Q[i] = mul_ia(tile_at(i), T(w.kx));
+      }
+      colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        Q[i] = cadd(Q[i], mul_ia(tile_at(i), T(w.ky)));
+      }
+    }
+    const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
+    const V* wn = cptr<T>(M, P.o_in2);
+    V* acc = cptr<T>(M, P.o_aux);
+    V* xout = cptr<T>(M, P.o_in);
+    const T C = T(M.coef_static);
+    const double dt = M.dt;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+      const Wave w = wave(M, mxs_(i), my);
+      const long long id = sidx(i);
+      const V x = xin[id];
+      V r = R[i];
+      const T lin = T(w.k2 * M.inv_re + M.mu);
+      r = csub(r, cscale(x, lin));
+      const V psi = poisson<T>(M, x, w);
+      r = csub(r, mul_ia(psi, T(M.beta * w.kx)));
+      if constexpr (CL != 0) r = cadd(r, cscale(Q[i], C));
+      if (mxs_(i) == 0 && my == 0) r = cmake<V>(T(0), T(0));
+      const V w0 = wn[id];
+      if (P.stage == 1) {
+        acc[id] = cadd(w0, cscale(r, T(dt / 6.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+      } else if (P.stage == 2) {
+        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+      } else if (P.stage == 3) {
+        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt)));
+      } else {
+        xout[id] = cadd(acc[id], cscale(r, T(dt / 6.0)));
+      }
+    }
+  } else if constexpr (OP == OP_RHS) {
+    // dynamic closures: J, Q = i k . h to the side buffers, partial sums of
+    // <HM> and <M^2> over the strip (Parseval, weights 1 at m_x = 0 else 2)
+    V A[MAXM], B[MAXM];
+    V* jsp = cptr<T>(M, P.o_out);
+    V* qsp = cptr<T>(M, P.o_aux);
+    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) if (owned(i)) { A[i] = tile_at(i); jsp[sidx(i)] = A[i]; }
+    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      B[i] = mul_ia(tile_at(i), T(w.kx));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      B[i] = cadd(B[i], mul_ia(tile_at(i), T(w.ky)));
+      qsp[sidx(i)] = B[i];
+    }
+    // H = FFT(J~) - T J
+    colfwd_load_fft<T, EPT>(P, M, tile, 3, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const bool t = in_test(M, P.nx, P.ny, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      V h = tile_at(i);
+      A[i] = t ? csub(h, A[i]) : h;
+    }
+    // M = r i k . g - T Q
+    V G[MAXM];
+    colfwd_load_fft<T, EPT>(P, M, tile, 4, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      G[i] = mul_ia(tile_at(i), T(w.kx));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 5, kx0);
+    double hm = 0.0, mm = 0.0;
+    const T r = T(M.r_test);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+      const Wave w = wave(M, mxs_(i), my);
+      V g = cadd(G[i], mul_ia(tile_at(i), T(w.ky)));
+      g = cscale(g, r);
+      if (in_test(M, P.nx, P.ny, mxs_(i), my)) g = csub(g, B[i]);
+      const double wt = mxs_(i) == 0 ? 1.0 : 2.0;
+      hm += wt * ((double)A[i].x * (double)g.x + (double)A[i].y * (double)g.y);
+      mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
+    }
+    double shm = block_sum(hm, red);
+    double smm = block_sum(mm, red);
+    if (threadIdx.x == 0) {
+      double* part = rptr<double>(M, P.o_part) + 2 * blockIdx.x;
+      part[0] = shm;
+      part[1] = smm;
+    }
+  } else if constexpr (OP == OP_ADJ_B) {
+    // lambda_s = FFT(lambda_w) - (1/|k|^2)(i ky FFT(lambda_u) - i kx FFT(lambda_v));
+    // writes LS (o_out), LW = LS (o_aux), LK = dt/6 LS (o_in)
+    V Lw[MAXM];
+    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) if (owned(i)) Lw[i] = tile_at(i);
+    V Lp[MAXM];
+    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      Lp[i] = mul_ia(tile_at(i), T(w.ky));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+    V* ls = cptr<T>(M, P.o_out);
+    V* lw = cptr<T>(M, P.o_aux);
+    V* lk = cptr<T>(M, P.o_in);
+    const T c6 = T(M.dt / 6.0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      V lpsi = csub(Lp[i], mul_ia(tile_at(i), T(w.kx)));
+      V l = csub(Lw[i], cscale(lpsi, T(w.inv_k2)));
+      const long long id = sidx(i);
+      ls[id] = l;
+      lw[id] = l;
+      lk[id] = cscale(l, c6);
+    }
+  } else if constexpr (OP == OP_ADJ_RHS) {
+    // lambda_psi = i beta kx l' + i ky F(l_u) - i kx F(l_v)
+    //              [+ (ky^2 - kx^2) F(l_pd) - kx ky F(l_pxy)]
+    // lambda_x = -(k^2/Re + mu) l' - i kx F(l_wx) - i ky F(l_wy) - lambda_psi/|k|^2
+    // then LW += lambda_x and LK <- c LS + d lambda_x for the previous stage.
+    constexpr bool smag = (CL == 1);
+    V Lpsi[MAXM], Lx[MAXM];
+    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      Lpsi[i] = mul_ia(tile_at(i), T(w.ky));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      Lpsi[i] = csub(Lpsi[i], mul_ia(tile_at(i), T(w.kx)));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      Lx[i] = mul_ia(tile_at(i), T(-w.kx));
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, 3, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      Lx[i] = cadd(Lx[i], mul_ia(tile_at(i), T(-w.ky)));
+    }
+    if constexpr (smag) {
+      colfwd_load_fft<T, EPT>(P, M, tile, 4, kx0);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        Lpsi[i] = cadd(Lpsi[i], cscale(tile_at(i), T(w.ky * w.ky - w.kx * w.kx)));
+      }
+      colfwd_load_fft<T, EPT>(P, M, tile, 5, kx0);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        Lpsi[i] = cadd(Lpsi[i], cscale(tile_at(i), T(-w.kx * w.ky)));
+      }
+    }
+    const V* lin = cptr<T>(M, P.o_in2);     // l = LK (stage input adjoint)
+    const V* ls = cptr<T>(M, P.o_out);      // LS
+    V* lw = cptr<T>(M, P.o_aux);            // LW
+    V* lk = cptr<T>(M, P.o_in2);
+    const double dt = M.dt;
+    const double cs = P.stage == 4 ? dt / 3.0 : P.stage == 3 ? dt / 3.0 : dt / 6.0;
+    const double ds = P.stage == 4 ? dt : dt / 2.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+      const Wave w = wave(M, mxs_(i), my);
+      const long long id = sidx(i);
+      V l = lin[id];
+      if (mxs_(i) == 0 && my == 0) l = cmake<V>(T(0), T(0));
+      V lp = cadd(Lpsi[i], mul_ia(l, T(M.beta * w.kx)));
+      V lx = csub(Lx[i], cscale(l, T(w.k2 * M.inv_re + M.mu)));
+      lx = csub(lx, cscale(lp, T(w.inv_k2)));
+      lw[id] = cadd(lw[id], lx);
+      if (P.stage > 1) lk[id] = cadd(cscale(ls[id], T(cs)), cscale(lx, T(ds)));
+    }
+  }
+}
+#undef mxs_
+#undef iys_
+
+// ---------------------------------------------------------------- combine
+// Dynamic closures: C = max(<HM>, 0)/<M^2> from the fixed-order sum of the
+// strip partials (every block sums them identically), then the RHS
+// R = -J + C Q - (k^2/Re + mu) x - i beta kx psi and the RK4 update.
+__device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, double* red, double& C,
+                                                double& hm_out, double& mm_out) {
+  double hm = 0.0, mm = 0.0;
+  if (threadIdx.x < 64) {
+    for (int i = threadIdx.x; i < nparts; i += 64) { hm += part[2 * i]; mm += part[2 * i + 1]; }
+    for (int o = 32; o > 0; o >>= 1) { hm += __shfl_xor(hm, o, 64); mm += __shfl_xor(mm, o, 64); }
+    if (threadIdx.x == 0) { red[0] = hm; red[1] = mm; }
+  }
+  __syncthreads();
+  hm = red[0];
+  mm = red[1];
+  hm_out = hm;
+  mm_out = mm;
+  C = mm > 0.0 ? fmax(hm, 0.0) / mm : 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
+  using V = cpx<T>;
+  __shared__ double red[2];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  double C, hm, mm;
+  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* c = rptr<double>(M, P.o_coef);
+    c[P.stage] = C;
+    c[8 + 2 * P.stage] = hm;
+    c[9 + 2 * P.stage] = mm;
+  }
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.kxn * P.kyn) return;
+  const int mx = q / P.kyn;
+  const int iy = q - mx * P.kyn;
+  const int my = my_of_iy(iy, P.myh, P.kyn);
+  const Wave w = wave(M, mx, my);
+  const V* jsp = cptr<T>(M, P.o_out);
+  const V* qsp = cptr<T>(M, P.o_aux);
+  const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
+  const V* wn = cptr<T>(M, P.o_in2);
+  V* acc = cptr<T>(M, P.o_mp);   // accumulator offset passed in o_mp for this kernel
+  V* xout = cptr<T>(M, P.o_in);
+  const V x = xin[q];
+  const V j = jsp[q];
+  V r = cmake<V>(-j.x, -j.y);
+  r = csub(r, cscale(x, T(w.k2 * M.inv_re + M.mu)));
+  r = csub(r, mul_ia(poisson<T>(M, x, w), T(M.beta * w.kx)));
+  r = cadd(r, cscale(qsp[q], T(C)));
+  if (mx == 0 && my == 0) r = cmake<V>(T(0), T(0));
+  const double dt = M.dt;
+  const V w0 = wn[q];
+  if (P.stage == 1) {
+    acc[q] = cadd(w0, cscale(r, T(dt / 6.0)));
+    xout[q] = cadd(w0, cscale(r, T(dt / 2.0)));
+  } else if (P.stage == 2) {
+    acc[q] = cadd(acc[q], cscale(r, T(dt / 3.0)));
+    xout[q] = cadd(w0, cscale(r, T(dt / 2.0)));
+  } else if (P.stage == 3) {
+    acc[q] = cadd(acc[q], cscale(r, T(dt / 3.0)));
+    xout[q] = cadd(w0, cscale(r, T(dt)));
+  } else {
+    xout[q] = cadd(acc[q], cscale(r, T(dt / 6.0)));
+  }
+}
+
+// C of the dynamic closures for diagnostics (slot 0 of the coef area).
+__global__ void k_dyn_coef(Phase P, int slot) {
+  __shared__ double red[2];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  double C, hm, mm;
+  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
+  if (threadIdx.x == 0) rptr<double>(M, P.o_coef)[slot] = C;
+}
+
+// ---------------------------------------------------------------- diagnostics
+// Parseval sums of energy sum w |k|^2 |psi|^2 and enstrophy sum w |omega|^2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
+  using V = cpx<T>;
+  __shared__ double red[16];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0, z = 0.0;
+  if (q < P.kxn * P.kyn) {
+    const int mx = q / P.kyn;
+    const int iy = q - mx * P.kyn;
+    const int my = my_of_iy(iy, P.myh, P.kyn);
+    const Wave w = wave(M, mx, my);
+    const V x = cptr<T>(M, P.o_in)[q];
+    const double a2 = (double)x.x * x.x + (double)x.y * x.y;
+    const double wt = mx == 0 ? 1.0 : 2.0;
+    const bool zm = (mx == 0 && my == 0);
+    z = zm ? 0.0 : wt * a2;
+    e = zm ? 0.0 : wt * a2 * w.inv_k2;   // |k|^2 |psi|^2 = |omega|^2 / |k|^2
+  }
+  double se = block_sum(e, red);
+  double sz = block_sum(z, red);
+  if (threadIdx.x == 0) {
+    double* d = rptr<double>(M, P.o_aux) + 2 * blockIdx.x;
+    d[0] = se;
+    d[1] = sz;
+  }
+}
+
+__global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
+  const MemberDev& M = P.mem[P.m0 + blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const double* rp = rptr<double>(M, P.o_dpart);
+  const double* sp = rptr<double>(M, P.o_aux);
+  double nus = 0.0, mn = INFINITY, mxv = -INFINITY, cf = 0.0, bad = 0.0;
+  for (int i = 0; i < nrow; ++i) {
+    nus += rp[5 * i]; mn = fmin(mn, rp[5 * i + 1]); mxv = fmax(mxv, rp[5 * i + 2]);
+    cf = fmax(cf, rp[5 * i + 3]); bad = fmax(bad, rp[5 * i + 4]);
+  }
+  double e = 0.0, z = 0.0;
+  for (int i = 0; i < nspec; ++i) { e += sp[2 * i]; z += sp[2 * i + 1]; }
+  const double n2 = M.inv_n * M.inv_n;
+  double* o = out + 8 * M.user_index;
+  o[0] = 0.5 * e * n2;
+  o[1] = 0.5 * z * n2;
+  o[2] = (M.closure == 3 || M.closure == 4) ? rptr<double>(M, P.o_coef)[0] : M.coef_static;
+  o[3] = mn;
+  o[4] = nus * M.inv_n;
+  o[5] = mxv;
+  o[6] = cf * M.dt * M.inv_delta;
+  o[7] = (bad > 0.0 || !isfinite(e) || !isfinite(z)) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------- adjoint misc
+__global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int) {
+  const MemberDev& M = P.mem[P.m0 + blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const double* d = rptr<double>(M, P.o_dpart);
+  double s = 0.0;
+  for (int i = 0; i < nrow; ++i) s += d[i];
+  grad_c[M.user_index] += s;
+}
+
+// dst = a * dst + src (zero_first: dst = src) over the D-compact state
+template <typename T>
+__global__ void k_spec_axpy(Phase P, long long o_dst, long long o_src, double a, int zero_first) {
+  using V = cpx<T>;
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.kxn * P.kyn) return;
+  V* d = cptr<T>(M, o_dst);
+  const V s = cptr<T>(M, o_src)[q];
+  d[q] = zero_first ? s : cadd(cscale(d[q], T(a)), s);
+}
+
+__global__ void k_fill_zero(unsigned int* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- launchers
+static size_t col_smem(bool dbl, const Phase& P) { return (size_t)P.W * P.ny * (dbl ? 16 : 8); }
+static size_t row_smem(bool dbl, const Phase& P) { return (size_t)P.RP * P.nx * (dbl ? 16 : 8); }
+static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
+
+template <typename T, int OP, int CL>
+static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
+  dim3 grid((P.kxn + P.W - 1) / P.W, P.nf, nmem);
+  constexpr int EPT = sizeof(T) == 4 ? 32 : 16;
+  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(COL_THREADS), col_smem(sizeof(T) == 8, P), s, P);
+}
+template <typename T, int OP, int CL>
+static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
+  dim3 grid(P.ny / (2 * P.RP), 1, nmem);
+  hipLaunchKernelGGL((k_row<T, OP, CL>), grid, dim3(row_threads(P)), row_smem(sizeof(T) == 8, P), s, P);
+}
+template <typename T, int OP, int CL>
+static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
+  dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
+  constexpr int EPT = sizeof(T) == 4 ? 32 : 16;
+  hipLaunchKernelGGL((k_colfwd<T, OP, CL, EPT>), grid, dim3(COL_THREADS), col_smem(sizeof(T) == 8, P), s, P);
+}
+
+#define QG_CL_SWITCH(FN, T, OP, cl, P, n, s)                 \
+  switch (cl) {                                              \
+    case 0: FN<T, OP, 0>(P, n, s); break;                    \
+    case 1: FN<T, OP, 1>(P, n, s); break;                    \
+    case 2: FN<T, OP, 2>(P, n, s); break;                    \
+    case 3: FN<T, OP, 3>(P, n, s); break;                    \
+    default: FN<T, OP, 4>(P, n, s); break;                   \
+  }
+
+#define QG_CL_SWITCH_STATIC(FN, T, OP, cl, P, n, s)          \
+  switch (cl) {                                              \
+    case 0: FN<T, OP, 0>(P, n, s); break;                    \
+    case 1: FN<T, OP, 1>(P, n, s); break;                    \
+    default: FN<T, OP, 2>(P, n, s); break;                   \
+  }
+
+template <typename T> static void colinv_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+  switch (op) {
+    case OP_RHS: QG_CL_SWITCH(launch_colinv_t, T, OP_RHS, cl, P, n, s); break;
+    case OP_DIAG: QG_CL_SWITCH(launch_colinv_t, T, OP_DIAG, cl, P, n, s); break;
+    case OP_B: launch_colinv_t<T, OP_B, 0>(P, n, s); break;
+    case OP_EXIT: case OP_ADJ_ENTRY: launch_colinv_t<T, OP_EXIT, 0>(P, n, s); break;
+    case OP_MASKGRAD: launch_colinv_t<T, OP_MASKGRAD, 0>(P, n, s); break;
+    case OP_ADJ_B: launch_colinv_t<T, OP_ADJ_B, 0>(P, n, s); break;
+    case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colinv_t, T, OP_ADJ_RHS, cl, P, n, s); break;
+    default: break;
+  }
+}
+template <typename T> static void row_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+  switch (op) {
+    case OP_RHS: QG_CL_SWITCH(launch_row_t, T, OP_RHS, cl, P, n, s); break;
+    case OP_DIAG: QG_CL_SWITCH(launch_row_t, T, OP_DIAG, cl, P, n, s); break;
+    case OP_B: launch_row_t<T, OP_B, 0>(P, n, s); break;
+    case OP_ENTRY: case OP_ADJ_EXIT: launch_row_t<T, OP_ENTRY, 0>(P, n, s); break;
+    case OP_EXIT: case OP_ADJ_ENTRY: launch_row_t<T, OP_EXIT, 0>(P, n, s); break;
+    case OP_MASKFWD: launch_row_t<T, OP_MASKFWD, 0>(P, n, s); break;
+    case OP_MASKGRAD: launch_row_t<T, OP_MASKGRAD, 0>(P, n, s); break;
+    case OP_ADJ_B: launch_row_t<T, OP_ADJ_B, 0>(P, n, s); break;
+    case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_row_t, T, OP_ADJ_RHS, cl, P, n, s); break;
+    default: break;
+  }
+}
+template <typename T> static void colfwd_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+  switch (op) {
+    case OP_RHS: QG_CL_SWITCH(launch_colfwd_t, T, OP_RHS, cl, P, n, s); break;
+    case OP_B: launch_colfwd_t<T, OP_B, 0>(P, n, s); break;
+    case OP_ENTRY: case OP_ADJ_EXIT: launch_colfwd_t<T, OP_ENTRY, 0>(P, n, s); break;
+    case OP_MASKFWD: launch_colfwd_t<T, OP_MASKFWD, 0>(P, n, s); break;
+    case OP_ADJ_B: launch_colfwd_t<T, OP_ADJ_B, 0>(P, n, s); break;
+    case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colfwd_t, T, OP_ADJ_RHS, cl, P, n, s); break;
+    default: break;
+  }
+}
+
+hipError_t launch_colinv(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
+  if (dbl) colinv_dispatch<double>(op, cl, P, n, s); else colinv_dispatch<float>(op, cl, P, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_row(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
+  if (dbl) row_dispatch<double>(op, cl, P, n, s); else row_dispatch<float>(op, cl, P, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_colfwd(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
+  if (dbl) colfwd_dispatch<double>(op, cl, P, n, s); else colfwd_dispatch<float>(op, cl, P, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_combine(bool dbl, int, const Phase& P, int n, hipStream_t s) {
+  dim3 grid((P.kxn * P.kyn + COMBINE_THREADS - 1) / COMBINE_THREADS, 1, n);
+  if (dbl) hipLaunchKernelGGL(k_combine<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  else hipLaunchKernelGGL(k_combine<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_dyn_coef(const Phase& P, int n, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_dyn_coef, dim3(1, 1, n), dim3(64), 0, s, P, slot);
+  return hipGetLastError();
+}
+hipError_t launch_diag_spectral(bool dbl, const Phase& P, int n, hipStream_t s) {
+  dim3 grid((P.kxn * P.kyn + 255) / 256, 1, n);
+  if (dbl) hipLaunchKernelGGL(k_diag_spectral<double>, grid, dim3(256), 0, s, P);
+  else hipLaunchKernelGGL(k_diag_spectral<float>, grid, dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_diag_final(const Phase& P, int n, int nrow, int nspec, double* out, int m0, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_final, dim3(n), dim3(64), 0, s, P, nrow, nspec, out, m0);
+  return hipGetLastError();
+}
+hipError_t launch_adj_grad_c(const Phase& P, int n, int nrow, double* grad_c, int m0, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_grad_c, dim3(n), dim3(64), 0, s, P, nrow, grad_c, m0);
+  return hipGetLastError();
+}
+hipError_t launch_spec_axpy(bool dbl, const Phase& P, int n, long long o_dst, long long o_src, double a,
+                            int zero_first, hipStream_t s) {
+  dim3 grid((P.kxn * P.kyn + 255) / 256, 1, n);
+  if (dbl) hipLaunchKernelGGL(k_spec_axpy<double>, grid, dim3(256), 0, s, P, o_dst, o_src, a, zero_first);
+  else hipLaunchKernelGGL(k_spec_axpy<float>, grid, dim3(256), 0, s, P, o_dst, o_src, a, zero_first);
+  return hipGetLastError();
+}
+hipError_t launch_spec_copy(bool dbl, const Phase& P, int n, long long o_dst, long long o_src, hipStream_t s) {
+  return launch_spec_axpy(dbl, P, n, o_dst, o_src, 0.0, 1, s);
+}
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  unsigned int blocks = (unsigned int)((n + 255) / 256 > 4096 ? 4096 : (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, (unsigned int*)p, n);
+  return hipGetLastError();
+}
+
+}  // namespace qg

@@ -1,0 +1,141 @@
+"""Python front end of libqg.so: device memory and streams from torch, every
+step of the computation in the HIP library.
+
+``Solver`` holds one handle for a batch of members (one or many grids).
+Fields are passed as flat device tensors (all members concatenated, each
+row-major (ny, nx)), or as lists of (ny, nx) tensors via ``pack``/``unpack``.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DTYPES = {32: torch.float32, 64: torch.float64}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """A batch of QG members on one GPU (see include/qg.h for the semantics)."""
+
+    def __init__(self, params, chi, chi_sponge, device="cuda:0", adj_segment_k=0):
+        if isinstance(params, dict):
+            params, chi, chi_sponge = [params], [chi], [chi_sponge]
+        self.L = _lib.lib()
+        self.device = torch.device(device)
+        self.params = [dict(p) for p in params]
+        precs = {int(p.get("precision", 64)) for p in self.params}
+        if len(precs) != 1:
+            raise ValueError("the Python front end takes one precision per Solver")
+        self.precision = precs.pop()
+        self.dtype = _DTYPES[self.precision]
+        self.n = len(self.params)
+        self.shapes = [(int(p["ny"]), int(p["nx"])) for p in self.params]
+        self.sizes = [a * b for a, b in self.shapes]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.total = int(self.offsets[-1])
+        arr = (_lib.QGParams * self.n)(*[_lib.make_params(p) for p in self.params])
+        self._arr = arr
+        size = ctypes.c_size_t()
+        _lib.check(self.L.qg_workspace_bytes(arr, self.n, int(adj_segment_k), ctypes.byref(size)))
+        self.ws_bytes = size.value
+        raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + size.value]
+        masks = [self._dev(c) for c in chi]
+        smasks = [self._dev(c) for c in chi_sponge]
+        cp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in masks])
+        sp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in smasks])
+        h = ctypes.c_void_p()
+        _lib.check(self.L.qg_init(arr, self.n, cp, sp, _ptr(self.ws), self.ws_bytes,
+                                  int(adj_segment_k), _stream(self.device), ctypes.byref(h)))
+        self.h = h
+        self.adj_segment_k = int(adj_segment_k)
+
+    # -------------------------------------------------------------- fields
+    def _dev(self, a):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=self.dtype).contiguous()
+        return torch.as_tensor(np.asarray(a), dtype=self.dtype, device=self.device).contiguous()
+
+    def pack(self, fields):
+        """List of (ny, nx) arrays/tensors -> flat device tensor."""
+        return torch.cat([self._dev(f).reshape(-1) for f in fields])
+
+    def unpack(self, flat):
+        return [flat[self.offsets[i]:self.offsets[i + 1]].view(*self.shapes[i]) for i in range(self.n)]
+
+    def _check_flat(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != self.dtype or t.device != self.device:
+            raise TypeError(f"{name} must be a {self.dtype} tensor on {self.device}")
+        if not t.is_contiguous() or t.numel() < self.total:
+            raise ValueError(f"{name} must be contiguous with {self.total} elements")
+
+    # -------------------------------------------------------------- calls
+    def step(self, omega, nsteps, save_every=0, ckpt=None, use_graph=True):
+        """Advance in place; returns omega.  ckpt: flat tensor of
+        (nsteps // save_every) * total elements when save_every > 0."""
+        self._check_flat(omega, "omega")
+        cptr = None
+        if save_every:
+            nsave = nsteps // save_every
+            if ckpt is None:
+                ckpt = torch.empty(max(nsave, 1) * self.total, dtype=self.dtype, device=self.device)
+            self._check_flat(ckpt, "ckpt")
+            if ckpt.numel() < nsave * self.total:
+                raise ValueError("ckpt too small")
+            cptr = _ptr(ckpt)
+        _lib.check(self.L.qg_step(self.h, _ptr(omega), int(nsteps), int(save_every), cptr,
+                                  1 if use_graph else 0, _stream(self.device)))
+        return (omega, ckpt) if save_every else omega
+
+    def adjoint_step(self, omega_ckpt, lam, nsteps, grad_c):
+        """lam: dL/d omega at the segment end -> at the segment start (in place);
+        grad_c: float64 device tensor (n,), dL/dc added."""
+        self._check_flat(omega_ckpt, "omega_ckpt")
+        self._check_flat(lam, "lambda")
+        if grad_c.dtype != torch.float64 or grad_c.device != self.device or grad_c.numel() < self.n:
+            raise TypeError("grad_c must be a float64 device tensor with one entry per member")
+        _lib.check(self.L.qg_adjoint_step(self.h, _ptr(omega_ckpt), _ptr(lam), int(nsteps),
+                                          _ptr(grad_c), _stream(self.device)))
+        return lam
+
+    def diag(self, omega, want_nu=False):
+        """Returns (n, 8) float64 [E, Z, C, nu_min, nu_mean, nu_max, CFL, nonfinite]
+        and, if asked, the flat nu_e field."""
+        self._check_flat(omega, "omega")
+        out = torch.zeros(self.n * 8, dtype=torch.float64, device=self.device)
+        nu = torch.empty(self.total, dtype=self.dtype, device=self.device) if want_nu else None
+        _lib.check(self.L.qg_diag(self.h, _ptr(omega), _ptr(out),
+                                  _ptr(nu) if nu is not None else None, _stream(self.device)))
+        return out.view(self.n, 8), nu
+
+    def autotune(self, cache_path=None):
+        _lib.check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
+                                      _stream(self.device)))
+
+    def column_widths(self):
+        w = (ctypes.c_int32 * self.n)()
+        _lib.check(self.L.qg_info(self.h, None, None, w))
+        return list(w)
+
+    def close(self):
+        if getattr(self, "h", None):
+            torch.cuda.current_stream(self.device).synchronize()
+            self.L.qg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,147 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on the same seeded inputs.
+
+Tolerances (per step, relative L2 of the physical vorticity): 1e-12 in
+FP64 and 1e-5 in FP32, as the method's accuracy targets state.  Sizes span
+several column strips and row blocks with ragged tails (kx counts that are
+not multiples of the strip width).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import qg
+from paper_2508_06678_amd import configs, inputs
+from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
+
+TOL = {64: 1e-12, 32: 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def member(nx, ny, closure, seed=3, init="band", beta=1.5, u_in=1.0, c=None):
+    lx, ly = 2 * math.pi, 2 * math.pi * ny / nx
+    if init == "band":
+        m = configs.island_member(nx, ny, precision=64, beta=beta, re=1e3, dt=1e-3, eta=5e-3,
+                                  xc=1.5, radius=0.4, closure=closure, seed=seed, rms=0.2,
+                                  lx=lx, ly=ly, u_in=u_in, c=c)
+    else:
+        m = configs.cape_member(nx, ny, precision=64, beta=beta, re=1e3, dt=1e-3, eta=5e-3,
+                                height=0.5, closure=closure, seed=seed, rms=0.2, init="spectrum",
+                                lx=lx, ly=ly, u_in=u_in, c=c)
+    return m
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("nx,ny", [(64, 32), (128, 64), (32, 256), (512, 128)])
+def test_entry_exit_projection(precision, nx, ny):
+    say("entry/exit", precision, nx, ny)
+    m = member(nx, ny, "none")
+    S = solver_for([m], precision)
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((ny, nx))
+    om = S.pack([w])
+    S.step(om, 0, use_graph=False)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    ref = qg.leave(qg.enter(w, M.g), M.g)
+    got = to_np(om).reshape(ny, nx)
+    err = rel_l2(got, ref)
+    say("  rel", err)
+    assert err < (1e-14 if precision == 64 else 3e-7)
+    S.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("closure", ["none", "smag", "leith", "dsmag", "dleith"])
+def test_one_step(precision, closure):
+    say("one step", precision, closure)
+    m = member(128, 64, closure, init="spectrum")
+    S = solver_for([m], precision)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    w0 = m.omega0
+    om = S.pack([w0])
+    S.step(om, 1, use_graph=False)
+    got = to_np(om).reshape(64, 128)
+    w_in = to_np(S.pack([w0])).reshape(64, 128)   # the input as the GPU saw it
+    ref = qg.step(w_in, M)
+    err = rel_l2(got, ref)
+    say("  rel", err)
+    assert err < TOL[precision]
+    S.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_config1_per_step(precision):
+    wl = configs.config1()
+    m = wl.members[0]
+    say("config1 per-step", precision)
+    S = solver_for([m], precision)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    worst = 0.0
+    for n in range(5):
+        w_n = to_np(om).reshape(64, 128)
+        S.step(om, 1, use_graph=False)
+        ref = qg.step(w_n, M)
+        err = rel_l2(to_np(om).reshape(64, 128), ref)
+        worst = max(worst, err)
+    say("  worst", worst)
+    assert worst < TOL[precision]
+    S.close()
+
+
+def test_graph_equals_eager_bitwise():
+    m = member(128, 64, "dleith", init="spectrum")
+    S = solver_for([m], 32)
+    a = S.pack([m.omega0])
+    b = a.clone()
+    S.step(a, 23, use_graph=False)
+    S.step(b, 23, use_graph=True)
+    assert (a == b).all().item()
+    S.close()
+
+
+def test_batched_ragged_members():
+    ms = [member(64, 32, "smag", seed=5), member(128, 64, "dleith", seed=6, init="spectrum"),
+          member(64, 32, "leith", seed=7), member(256, 128, "dsmag", seed=8, init="spectrum"),
+          member(128, 64, "none", seed=9)]
+    S = solver_for(ms, 64)
+    om = S.pack([m.omega0 for m in ms])
+    w_in = [to_np(x) for x in S.unpack(om)]
+    S.step(om, 2, use_graph=True)
+    got = [to_np(x) for x in S.unpack(om)]
+    for m, wi, g in zip(ms, w_in, got):
+        M = oracle_model(m.params, m.chi, m.chi_s)
+        ref = qg.run(wi, M, 2)
+        err = rel_l2(g, ref)
+        say("  member", m.params["nx"], m.params["ny"], m.params["closure"], err)
+        assert err < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("closure", ["smag", "dleith", "dsmag", "none"])
+def test_diag(closure):
+    m = member(128, 64, closure, init="spectrum")
+    S = solver_for([m], 64)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    out, nu = S.diag(om, want_nu=True)
+    out = out.cpu().numpy()[0]
+    w_in = to_np(om).reshape(64, 128)
+    ref, nu_ref = qg.diag(w_in, M)
+    say("diag", closure, out, ref)
+    np.testing.assert_allclose(out[:2], ref[:2], rtol=1e-12)
+    np.testing.assert_allclose(out[2], ref[2], rtol=1e-10, atol=1e-300)
+    np.testing.assert_allclose(out[3:7], ref[3:7], rtol=1e-10, atol=1e-14)
+    assert out[7] == 0.0
+    assert rel_l2(to_np(nu).reshape(64, 128), nu_ref) < 1e-10 or np.all(nu_ref == 0)
+    bad = om.clone()
+    bad[17] = float("nan")
+    out2, _ = S.diag(bad)
+    assert out2.cpu().numpy()[0][7] == 1.0
+    S.close()
