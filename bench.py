@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the QG step on one MI355X.
+
+Metric: grid-point-steps per second at 1024^2 for the coast-with-cape
+workload (dynamic Leith, RK4 + penalization/sponge sub-step), in FP32
+(``value``), FP64 and FP32 batched (8 members of 1024^2 in one graph
+launch), plus the adjoint/forward time ratio of the differentiable island
+run (512x256, static Smagorinsky, one 50-step checkpoint segment).
+
+Inputs are synthetic and seeded (masks, sponge ramps, k^-3 random-phase
+initial vorticity) and resident in HBM before timing.  Steps are timed with
+HIP events on the launch stream between synchronisations.  The roofline
+entry is for the kernel with the largest share of the step, timed live
+with HIP events on its stream; its bytes are the algorithmic bytes of one
+launch (what the method must move: mixed-layout fields at the 2/3-pruned
+width and the state on the 2/3 set).  ``cpu_baseline`` is the FP64 NumPy
+oracle (the correctness reference, not a tuned CPU code) on one step of the
+same 1024^2 workload, on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+PHASE_NAMES = ["colinv_rhs", "row_rhs", "colfwd_rhs", "combine_dyn", "colinv_b", "row_b", "colfwd_b"]
+PHASE_LAUNCHES = [4, 4, 4, 4, 1, 1, 1]
+KERNEL_NAMES = {
+    "colinv_rhs": "k_colinv<float, 0, 4, 32>",
+    "row_rhs": "k_row<float, 0, 4>",
+    "colfwd_rhs": "k_colfwd<float, 0, 4, 32>",
+    "combine_dyn": "k_combine<float>",
+    "colinv_b": "k_colinv<float, 1, 0, 32>",
+    "row_b": "k_row<float, 1, 0>",
+    "colfwd_b": "k_colfwd<float, 1, 0, 32>",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nx, ny, word, closure="dleith"):
+    """Bytes each kernel of one step must move for one member (see the
+    module docstring): F fields and P products cross HBM once in the mixed
+    layout of ny * kxn complex values; spectral quantities live on the
+    2/3 set of kxn * kyn complex values; physical tables are nx * ny reals."""
+    kxn = (nx - 1) // 3 + 1
+    kyn = 2 * ((ny - 1) // 3) + 1
+    c = 2 * word
+    nM = ny * kxn * c
+    nD = kxn * kyn * c
+    F = {"none": 4, "smag": 6, "leith": 4, "dsmag": 12, "dleith": 8}[closure]
+    P = {"none": 1, "smag": 3, "leith": 3, "dsmag": 6, "dleith": 6}[closure]
+    dyn = closure in ("dsmag", "dleith")
+    per = {
+        "colinv_rhs": nD + F * nM,
+        "row_rhs": F * nM + P * nM,
+        "colfwd_rhs": P * nM + (2 * nD if dyn else 4 * nD),
+        "combine_dyn": 6 * nD if dyn else 0,
+        "colinv_b": nD + 3 * nM,
+        "row_b": 3 * nM + 4 * nx * ny * word + nM,
+        "colfwd_b": nM + nD,
+    }
+    step = sum(per[k] * n for k, n in zip(PHASE_NAMES, PHASE_LAUNCHES))
+    return per, step
+
+
+def time_steps(S, om, steps, warmup, torch):
+    S.step(om, warmup, use_graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    S.step(om, steps, use_graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def time_phases(S, torch, reps=20):
+    """Average duration of each kernel of the step, HIP events on the stream
+    the kernels are launched on (the torch current stream)."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for ph, name in enumerate(PHASE_NAMES):
+        S.run_phase(ph, stage=2, reps=2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        S.run_phase(ph, stage=2, reps=reps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def make_solver(workload, precision, adj=0):
+    from paper_2508_06678_amd.solver import Solver
+    params, chi, chs = [], [], []
+    dt = np.float32 if precision == 32 else np.float64
+    for m in workload.members:
+        p = dict(m.params)
+        p["precision"] = precision
+        params.append(p)
+        chi.append(m.chi.astype(dt))
+        chs.append(m.chi_s.astype(dt))
+    S = Solver(params, chi, chs, adj_segment_k=adj)
+    om = S.pack([m.omega0 for m in workload.members])
+    return S, om
+
+
+def cpu_baseline(workload, nsteps):
+    from oracle import qg
+    m = workload.members[0]
+    p = {k: v for k, v in m.params.items() if k in qg.Params.__dataclass_fields__}
+    M = qg.Model(qg.Params(**p), m.chi, m.chi_s)
+    w = m.omega0
+    qg.step(w, M)  # warm-up (first-touch of the tables)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        w = qg.step(w, M)
+    dt = time.perf_counter() - t0
+    pts = m.params["nx"] * m.params["ny"]
+    return {"value": pts * nsteps / dt, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} step(s) of the {m.params['nx']}x{m.params['ny']} cape workload, "
+                      f"FP64 NumPy oracle with its own radix-2 FFT on 1 host thread "
+                      f"({os.cpu_count()} cores on the host), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,adjoint,cpu,phases")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(ensemble members shard across GPUs without communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    skip = set(s for s in args.skip.split(",") if s)
+    import torch
+    from paper_2508_06678_amd import configs
+
+    K, W = args.steps, args.warmup
+    wl = configs.config3(precision=32)
+    nx, ny = wl.members[0].params["nx"], wl.members[0].params["ny"]
+    pts = nx * ny
+
+    # ---- FP32, one 1024^2 member (value)
+    S, om = make_solver(wl, 32)
+    sec, wall = time_steps(S, om, K, W, torch)
+    value = pts * K / sec
+    log(f"fp32 1024^2 dleith: {sec / K * 1e3:.3f} ms/step, {value:.4g} pt-steps/s (wall {wall:.3f} s)")
+    per, step_bytes = algorithmic_bytes(nx, ny, 4, "dleith")
+    phases = None
+    if "phases" not in skip:
+        phases = time_phases(S, torch)
+        for name in PHASE_NAMES:
+            share = phases[name] * PHASE_LAUNCHES[PHASE_NAMES.index(name)]
+            gbs = per[name] / (phases[name] * 1e-3) / 1e9 if phases[name] > 0 else 0.0
+            log(f"  {name:12s} {phases[name] * 1e3:8.1f} us/launch x{PHASE_LAUNCHES[PHASE_NAMES.index(name)]}"
+                f"  {share * 1e3:8.1f} us/step  {gbs:7.0f} GB/s algorithmic")
+    S.close()
+    step_gbs = step_bytes / (sec / K) / 1e9
+
+    result = {
+        "metric": "grid-pt-steps/s at 1024^2: FP64 vs FP32 vs batched; adjoint/forward time ratio",
+        "value": value,
+        "unit": "grid-pt-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": sec / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded masks, sponge and k^-3 random-phase vorticity)",
+        "config": {"workload": "coast with Gaussian cape, 1024x1024, 2pi x 2pi, dynamic Leith, "
+                               "beta=5, Re=2e4, U=1, eta=1e-4, RK4 dt=2.5e-4, FP32",
+                   "grid": [ny, nx], "members": 1, "parallelism": "single GPU"},
+        "step_algorithmic_GBps": step_gbs,
+        "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
+    }
+    if phases:
+        dom = max(PHASE_NAMES, key=lambda n: phases[n] * PHASE_LAUNCHES[PHASE_NAMES.index(n)])
+        ach = per[dom] / (phases[dom] * 1e-3) / 1e9
+        result["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": ach,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                              "traffic": None, "bytes_per_launch": per[dom],
+                              "avg_launch_us": phases[dom] * 1e3}
+        result["kernels_us_per_launch"] = {k: v * 1e3 for k, v in phases.items()}
+
+    # ---- FP64, one member
+    if "fp64" not in skip:
+        S, om = make_solver(wl, 64)
+        k64 = max(10, K // 2)
+        sec64, _ = time_steps(S, om, k64, W, torch)
+        S.close()
+        _, b64 = algorithmic_bytes(nx, ny, 8, "dleith")
+        result["fp64"] = {"value": pts * k64 / sec64, "ms_per_step": sec64 / k64 * 1e3, "steps": k64,
+                          "step_roofline_frac": b64 / (sec64 / k64) / 1e9 / HBM_PEAK_GBS}
+        log(f"fp64 1024^2 dleith: {sec64 / k64 * 1e3:.3f} ms/step")
+
+    # ---- FP32 batched: 8 x 1024^2 in one graph
+    if "batched" not in skip:
+        bw = configs.batched1024(32)
+        S, om = make_solver(bw, 32)
+        kb = max(10, K // 4)
+        secb, _ = time_steps(S, om, kb, W // 2 + 1, torch)
+        S.close()
+        ptsb = bw.points
+        result["batched"] = {"value": ptsb * kb / secb, "ms_per_step": secb / kb * 1e3, "steps": kb,
+                             "members": len(bw.members),
+                             "step_roofline_frac": len(bw.members) * step_bytes / (secb / kb) / 1e9
+                             / HBM_PEAK_GBS}
+        log(f"batched 8x1024^2: {secb / kb * 1e3:.3f} ms/step, {ptsb * kb / secb:.4g} pt-steps/s")
+
+    # ---- adjoint / forward on the differentiable island run
+    if "adjoint" not in skip:
+        w5 = configs.config5(precision=64)
+        seg = w5.meta["ckpt_every"]
+        ratios = {}
+        for prec in (64, 32):
+            S, om = make_solver(w5, prec, adj=seg)
+            w0 = om.clone()
+            S.step(om, 5, use_graph=True)
+            torch.cuda.synchronize()
+            f0 = time.perf_counter()
+            S.step(om, seg, use_graph=True)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - f0
+            lam = torch.randn_like(om) * 1e-3
+            g = torch.zeros(1, dtype=torch.float64, device=om.device)
+            S.adjoint_step(w0, lam.clone(), seg, g)
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            S.adjoint_step(w0, lam, seg, g)
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - a0
+            S.close()
+            ratios[f"fp{prec}"] = ta / tf
+            log(f"adjoint/forward fp{prec}: {ta / tf:.2f} ({ta * 1e3:.1f} ms / {tf * 1e3:.1f} ms, {seg} steps)")
+        result["adjoint_forward_ratio"] = ratios
+
+    if "cpu" not in skip:
+        result["cpu_baseline"] = cpu_baseline(configs.config3(precision=64), args.cpu_steps)
+        log(f"cpu oracle: {result['cpu_baseline']['value']:.4g} pt-steps/s")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

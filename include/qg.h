@@ -147,6 +147,16 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
  * no file).  Synchronises hip_stream. */
 int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
 
+/* Profiling: launch one kernel of the step `reps` times on hip_stream, on
+ * the handle's current workspace contents (call after qg_step; the state it
+ * leaves is not meaningful).  phase: 0 column-inverse of the right-hand
+ * side, 1 row pass of the right-hand side, 2 column-forward of the
+ * right-hand side, 3 dynamic combine (dynamic closures), 4 column-inverse of
+ * the B sub-step, 5 row pass of the B sub-step, 6 column-forward of the B
+ * sub-step.  stage: RK stage 1..4 for phases 0-3.  Every size group of the
+ * handle is launched; phase 3 is skipped for static closures. */
+int qg_run_phase(qg_handle* h, int32_t phase, int32_t stage, int32_t reps, void* hip_stream);
+
 /* Number of members, total grid points, and the tiling chosen per member. */
 int qg_info(const qg_handle* h, int32_t* n_members, int64_t* total_points,
             int32_t* col_width_out /* n_members, nullable */);

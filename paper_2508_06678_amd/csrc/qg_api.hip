@@ -727,6 +727,44 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
   return QG_OK;
 }
 
+int qg_run_phase(qg_handle* H, int32_t phase, int32_t stage, int32_t reps, void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  if (phase < 0 || phase > 6) return fail(QG_EINVAL, "phase must be in [0, 6]");
+  if (stage < 1 || stage > 4) return fail(QG_EINVAL, "stage must be in [1, 4]");
+  if (reps < 0) return fail(QG_EINVAL, "reps must be >= 0");
+  Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int r = 0; r < reps; ++r) {
+    for (const auto& g : h.groups) {
+      const int cl = g.closure;
+      Phase P = base_phase(h, g);
+      P.stage = stage;
+      if (phase <= 3) {
+        P.nf = rhs_fields(cl);
+        P.o_in = stage == 1 ? g.L.wn : g.L.x;
+        if (phase == 0) QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
+        if (phase == 1) QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+        if (phase == 2) {
+          if (!dynamic_closure(cl)) { P.o_in = g.L.x; P.o_in2 = g.L.wn; P.o_aux = g.L.acc; }
+          else { P.o_out = g.L.jsp; P.o_aux = g.L.qsp; }
+          QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+        }
+        if (phase == 3 && dynamic_closure(cl)) {
+          P.o_in = g.L.x; P.o_in2 = g.L.wn; P.o_out = g.L.jsp; P.o_aux = g.L.qsp; P.o_mp = g.L.acc;
+          QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
+        }
+      } else {
+        P.o_in = g.L.x;
+        P.nf = 3;
+        if (phase == 4) QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, P, g.count, st));
+        if (phase == 5) QG_LAUNCH(launch_row(g.dbl, OP_B, 0, P, g.count, st));
+        if (phase == 6) { P.o_out = g.L.x; QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, P, g.count, st)); }
+      }
+    }
+  }
+  return QG_OK;
+}
+
 int qg_autotune(qg_handle* H, const char*, void*) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   return QG_OK;

@@ -123,6 +123,10 @@ class Solver:
         _lib.check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
                                       _stream(self.device)))
 
+    def run_phase(self, phase, stage=2, reps=1):
+        """Launch one kernel of the step reps times (profiling only)."""
+        _lib.check(self.L.qg_run_phase(self.h, int(phase), int(stage), int(reps), _stream(self.device)))
+
     def column_widths(self):
         w = (ctypes.c_int32 * self.n)()
         _lib.check(self.L.qg_info(self.h, None, None, w))

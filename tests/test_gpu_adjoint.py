@@ -1,0 +1,78 @@
+"""GPU discrete adjoint (qg_adjoint_step) against the oracle's adjoint and
+against central finite differences of the GPU forward step, in FP64."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import qg
+from paper_2508_06678_amd import configs, inputs
+from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def island(nx, ny, closure, seed=4):
+    return configs.island_member(nx, ny, precision=64, beta=1.5, re=500.0, dt=2e-3, eta=5e-3,
+                                 xc=1.5, radius=0.5, closure=closure, seed=seed, rms=0.3,
+                                 lx=2 * math.pi, ly=2 * math.pi * ny / nx)
+
+
+@pytest.mark.parametrize("closure", ["none", "smag", "leith"])
+@pytest.mark.parametrize("nx,ny", [(64, 32), (128, 64)])
+def test_adjoint_matches_oracle(closure, nx, ny):
+    say("adjoint vs oracle", closure, nx, ny)
+    import torch
+    m = island(nx, ny, closure)
+    nsteps = 3
+    S = solver_for([m], 64, adj_segment_k=nsteps)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    w0 = to_np(om).reshape(ny, nx)
+    rng = np.random.default_rng(9)
+    lamT = rng.standard_normal((ny, nx))
+    lam = S.pack([lamT])
+    g = torch.zeros(1, dtype=torch.float64, device=om.device)
+    S.adjoint_step(om, lam, nsteps, g)
+    ref_l, ref_c = oadj.run_adjoint(w0, lamT, M, nsteps)
+    err = rel_l2(to_np(lam).reshape(ny, nx), ref_l)
+    say("  lambda rel", err, "dc", g.item(), ref_c)
+    assert err < 1e-11
+    if closure != "none":
+        assert abs(g.item() - ref_c) <= 1e-10 * abs(ref_c)
+    else:
+        assert g.item() == 0.0
+    S.close()
+
+
+def test_adjoint_central_fd_on_gpu():
+    import torch
+    nx, ny = 128, 64
+    m = island(nx, ny, "smag")
+    nsteps = 4
+    S = solver_for([m], 64, adj_segment_k=nsteps)
+    om0 = S.pack([m.omega0])
+    tgt = S.pack([inputs.bandpass_noise(nx, ny, 2 * math.pi, math.pi, 11, 2, 8, 0.3)])
+
+    def loss(om):
+        x = om.clone()
+        S.step(x, nsteps, use_graph=False)
+        return torch.mean((x - tgt) ** 2).item(), x
+
+    L0, wT = loss(om0)
+    lam = 2.0 * (wT - tgt) / wT.numel()
+    g = torch.zeros(1, dtype=torch.float64, device=om0.device)
+    S.adjoint_step(om0, lam, nsteps, g)
+    h = 1e-4
+    for d in inputs.random_directions((ny, nx), 3, 5):
+        dd = S.pack([d])
+        fd = (loss(om0 + h * dd)[0] - loss(om0 - h * dd)[0]) / (2 * h)
+        ad = torch.sum(lam * dd).item()
+        say("  fd", fd, "adjoint", ad)
+        assert ad == pytest.approx(fd, rel=1e-6)
+    S.close()
