@@ -105,7 +105,7 @@ def time_phases(S, torch, reps=20):
     return out
 
 
-def make_solver(workload, precision, adj=0):
+def make_solver(workload, precision, adj=0, tune=True):
     from paper_2508_06678_amd.solver import Solver
     params, chi, chs = [], [], []
     dt = np.float32 if precision == 32 else np.float64
@@ -116,6 +116,9 @@ def make_solver(workload, precision, adj=0):
         chi.append(m.chi.astype(dt))
         chs.append(m.chi_s.astype(dt))
     S = Solver(params, chi, chs, adj_segment_k=adj)
+    if tune:
+        S.autotune()
+        log(f"  strip widths {sorted(set(S.column_widths()))}")
     om = S.pack([m.omega0 for m in workload.members])
     return S, om
 

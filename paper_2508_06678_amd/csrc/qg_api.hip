@@ -82,6 +82,29 @@ struct Group {
   long long o_twx, o_twy;        // offsets in the global area
 };
 
+// Strip width W of the column passes: W * ny <= one tile, at least 64
+// threads per block.  Changes the launch geometry only (the workspace is
+// sized for any W <= 16).
+static int max_width(const Group& g) { return std::max(1, std::min(16, col_tile_elems(g.dbl) / g.ny)); }
+static int min_width(const Group& g) { return std::max(1, std::min(max_width(g), 512 / g.ny)); }
+
+static void set_width(Group& g, int W) {
+  g.W = W;
+  g.logW = ilog2(W);
+  g.kxp = (g.kxn + W - 1) / W * W;
+  g.kxp_f = (g.kxn_f + W - 1) / W * W;
+  g.nstrips = (g.kxn + W - 1) / W;
+  g.nstrips_f = (g.kxn_f + W - 1) / W;
+}
+
+// Default: the widest strip that still gives every size group at least 512
+// column blocks (a 1024^2 member alone gets W = 1; eight get W = 4).
+static int default_width(const Group& g, int count) {
+  int W = max_width(g);
+  while (W > min_width(g) && (long long)((g.kxn + W - 1) / W) * count < 512) W >>= 1;
+  return W;
+}
+
 static void plan_sizes(Group& g, int adjK) {
   const int cs = g.dbl ? 16 : 8, rs = g.dbl ? 8 : 4;
   g.lognx = ilog2(g.nx);
@@ -92,28 +115,10 @@ static void plan_sizes(Group& g, int adjK) {
   g.kxn_f = g.nx / 2;
   g.myh_f = g.ny / 2 - 1;
   g.kyn_f = g.ny - 1;
-  // 64 KiB of LDS per column tile when the device allows more than that per
-  // block (gfx950: 160 KiB), else 32 KiB.
-  static int lds_limit = -1;
-  if (lds_limit < 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      v = 65536;
-    lds_limit = v;
-  }
-  const int tile_bytes = lds_limit >= 65536 + 1024 ? 65536 : 32768;
-  const int tile_elems = tile_bytes / (g.dbl ? 16 : 8);
-  int W = std::min(g.dbl ? 8 : 16, tile_elems / g.ny);
-  if (W < 1) W = 1;
-  g.W = W;
-  g.logW = ilog2(W);
-  g.kxp = (g.kxn + W - 1) / W * W;
-  g.kxp_f = (g.kxn_f + W - 1) / W * W;
+  set_width(g, max_width(g));
+  const int kxp16 = (g.kxn + 15) / 16 * 16, kxpf16 = (g.kxn_f + 15) / 16 * 16;
   g.RP = std::max(1, std::min(2048 / g.nx, g.ny / 2));
   g.logRP = ilog2(g.RP);
-  g.nstrips = (g.kxn + W - 1) / W;
-  g.nstrips_f = (g.kxn_f + W - 1) / W;
   g.nrow = g.ny / (2 * g.RP);
   g.nspec = (g.kxn * g.kyn + 255) / 256;
 
@@ -125,8 +130,8 @@ static void plan_sizes(Group& g, int adjK) {
     Pn = std::max(Pn, smag_family(cl) ? 6 : 4);
   }
   const long long spec = (long long)g.kxn * g.kyn * cs;
-  const long long mf = std::max((long long)F * g.ny * g.kxp, 2LL * g.ny * g.kxp_f) * cs;
-  const long long mp = std::max((long long)Pn * g.ny * g.kxp, 1LL * g.ny * g.kxp_f) * cs;
+  const long long mf = std::max((long long)F * g.ny * kxp16, 2LL * g.ny * kxpf16) * cs;
+  const long long mp = std::max((long long)Pn * g.ny * kxp16, 1LL * g.ny * kxpf16) * cs;
   long long o = 0;
   auto take = [&](long long b) { long long r = o; o += align256(b); return r; };
   RegionLayout& L = g.L;
@@ -139,7 +144,7 @@ static void plan_sizes(Group& g, int adjK) {
   L.mf = take(mf);
   L.mp = take(mp);
   L.phys = take(6LL * g.nx * g.ny * rs);
-  L.part = take((long long)std::max(g.nstrips, g.nstrips_f) * 2 * 8);
+  L.part = take((long long)std::max(g.kxn, g.kxn_f) * 2 * 8);   // one slot per strip at W = 1
   L.coef = take(32 * 8);
   L.dpart = take((long long)(5 * g.nrow + 2 * g.nspec + 8) * 8);
   if (adjK > 0) {
@@ -210,6 +215,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     h.groups[gi].users.push_back(i);
     h.member_group[i] = gi;
   }
+  for (auto& g : h.groups) set_width(g, default_width(g, (int)g.users.size()));
   // global area: member table, twiddles; then group regions
   long long o = align256((long long)n * sizeof(MemberDev));
   for (auto& g : h.groups) {
@@ -453,6 +459,55 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   m.sponge_a = p.dt * p.sponge_sigma;
   m.inv_n = 1.0 / ((double)p.nx * p.ny);
   return m;
+}
+
+// ------------------------------------------------------------ tuning cache
+// A flat JSON object {"<key>": W, ...}; keys name the device architecture,
+// grid, precision, closure and member count of a size group.
+static std::string group_key(const Group& g) {
+  char arch[64] = "gpu";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c) if (*c == ':') { *c = 0; break; }
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/%dx%d/fp%d/closure%d/members%d", arch, g.nx, g.ny, g.dbl ? 64 : 32,
+           g.closure, g.count);
+  return buf;
+}
+
+static void read_width_cache(const char* path, std::map<std::string, int>& out) {
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  size_t pos = 0;
+  while ((pos = txt.find('"', pos)) != std::string::npos) {
+    size_t end = txt.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    std::string key = txt.substr(pos + 1, end - pos - 1);
+    size_t colon = txt.find(':', end);
+    if (colon == std::string::npos) break;
+    out[key] = atoi(txt.c_str() + colon + 1);
+    pos = colon + 1;
+  }
+}
+
+static void write_width_cache(const char* path, const std::map<std::string, int>& m) {
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
 }
 
 }  // namespace qg
@@ -765,8 +820,50 @@ int qg_run_phase(qg_handle* H, int32_t phase, int32_t stage, int32_t reps, void*
   return QG_OK;
 }
 
-int qg_autotune(qg_handle* H, const char*, void*) {
+int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
+  Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  std::map<std::string, int> cache;
+  if (cache_path) read_width_cache(cache_path, cache);
+  hipEvent_t e0, e1;
+  QG_HIP(hipEventCreate(&e0));
+  QG_HIP(hipEventCreate(&e1));
+  int rc = QG_OK;
+  bool changed = false;
+  for (auto& g : h.groups) {
+    const std::string key = group_key(g);
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second >= min_width(g) && it->second <= max_width(g) &&
+        is_pow2(it->second)) {
+      set_width(g, it->second);
+      continue;
+    }
+    float best = 1e30f;
+    int bestW = g.W;
+    for (int W = min_width(g); W <= max_width(g) && rc == QG_OK; W *= 2) {
+      set_width(g, W);
+      for (int k = 0; k < 2 && rc == QG_OK; ++k) rc = run_step(h, g, st);
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(QG_EHIP, "event record"); break; }
+      for (int k = 0; k < 4 && rc == QG_OK; ++k) rc = run_step(h, g, st);
+      if (rc) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(QG_EHIP, "event timing"); break; }
+      if (ms < best) { best = ms; bestW = W; }
+    }
+    set_width(g, bestW);
+    cache[key] = bestW;
+    changed = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  for (auto& kv : h.graphs) (void)hipGraphExecDestroy(kv.second);
+  h.graphs.clear();
+  if (changed && cache_path) write_width_cache(cache_path, cache);
+  QG_HIP(hipStreamSynchronize(st));
   return QG_OK;
 }
 

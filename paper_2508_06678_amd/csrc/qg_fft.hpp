@@ -12,9 +12,9 @@
 //
 // Forward transforms use exp(-2 pi i m n / N) and are unnormalised; inverse
 // transforms use the conjugate twiddles and are also unnormalised (callers
-// fold 1/(nx ny) into the spectral data).  Twiddles come from a table
-// tw[m] = exp(-2 pi i m / N), m in [0, N), computed on the host in extended
-// precision and rounded once.
+// fold 1/(nx ny) into the spectral data).  Twiddles come from a half table
+// tw[m] = exp(-2 pi i m / N), m in [0, N/2), staged in LDS (computed on the
+// host in extended precision and rounded once); tw[m + N/2] = -tw[m].
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -94,22 +94,30 @@ struct FftShape {
   bool batch_fast;  // consecutive threads walk the batch index first
 };
 
+// Thread group that runs one batched transform: threads [0, nt) of the
+// group (tid = rank in the group).  Inactive groups still reach every
+// barrier, so several groups of a block can transform different vectors
+// concurrently in lock-step.
+struct FftGroup {
+  int tid, nt;
+  bool active;
+};
+
 // One Stockham pass of radix R with sub-transform length Ns = 2^logNs:
 // butterfly j reads elements j + t N/R, multiplies element t by
 // w_{Ns R}^{t (j mod Ns)}, transforms, and writes them to
 // (j / Ns) Ns R + (j mod Ns) + t Ns.  In place: all reads, barrier, writes.
 template <typename V, int R, bool INV, int MAXB>
 __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __restrict__ tw,
-                                              const FftShape& s, int logNs) {
+                                              const FftShape& s, int logNs, const FftGroup& g) {
   constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
   const int logNR = s.logN - logR;
-  const int total = 1 << (s.lognb + logNR);
-  const int nt = blockDim.x;
+  const int total = g.active ? 1 << (s.lognb + logNR) : 0;
   const int twshift = s.logN - logNs - logR;
   V v[MAXB][R];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int q = threadIdx.x + i * nt;
+    const int q = g.tid + i * g.nt;
     if (q < total) {
       int b, j;
       if (s.batch_fast) { b = q & ((1 << s.lognb) - 1); j = q >> s.lognb; }
@@ -119,9 +127,12 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = src[(j + (t << logNR)) * s.es];
       if (logNs > 0) {
+        const int half = 1 << (s.logN - 1);
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          V w = tw[(t * k) << twshift];
+          const int idx = (t * k) << twshift;
+          V w = tw[idx & (half - 1)];
+          if (idx & half) w = cmake<V>(-w.x, -w.y);
           if (INV) w = cconj(w);
           v[i][t] = cmul(v[i][t], w);
         }
@@ -132,7 +143,7 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int q = threadIdx.x + i * nt;
+    const int q = g.tid + i * g.nt;
     if (q < total) {
       int b, j;
       if (s.batch_fast) { b = q & ((1 << s.lognb) - 1); j = q >> s.lognb; }
@@ -147,19 +158,34 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
   __syncthreads();
 }
 
+// Copy the half twiddle table of length-N transforms from global memory to
+// LDS (callers synchronise before the first pass).
+template <typename V>
+__device__ __forceinline__ void stage_twiddles(V* __restrict__ dst, const V* __restrict__ src, int logN) {
+  const int half = 1 << (logN - 1);
+  for (int m = threadIdx.x; m < half; m += blockDim.x) dst[m] = src[m];
+}
+
 // Full transform: radix-8 passes, then one radix-4 or radix-2 pass.
-// EPT bounds the elements per thread: nb * N <= EPT * blockDim.x.
+// EPT bounds the elements per thread: nb * N <= EPT * g.nt.
 template <typename V, bool INV, int EPT>
-__device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s) {
+__device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s,
+                                        const FftGroup& g) {
   int logNs = 0;
   int rem = s.logN;
   while (rem >= 3) {
-    stockham_pass<V, 8, INV, EPT / 8>(buf, tw, s, logNs);
+    stockham_pass<V, 8, INV, EPT / 8>(buf, tw, s, logNs, g);
     logNs += 3;
     rem -= 3;
   }
-  if (rem == 2) stockham_pass<V, 4, INV, EPT / 4>(buf, tw, s, logNs);
-  else if (rem == 1) stockham_pass<V, 2, INV, EPT / 2>(buf, tw, s, logNs);
+  if (rem == 2) stockham_pass<V, 4, INV, EPT / 4>(buf, tw, s, logNs, g);
+  else if (rem == 1) stockham_pass<V, 2, INV, EPT / 2>(buf, tw, s, logNs, g);
+}
+
+// The whole block as one group.
+template <typename V, bool INV, int EPT>
+__device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s) {
+  fft_lds<V, INV, EPT>(buf, tw, s, FftGroup{(int)threadIdx.x, (int)blockDim.x, true});
 }
 
 }  // namespace qg

@@ -72,7 +72,12 @@ struct Phase {
   long long user_stride;  // elements between saves (unused: 0)
 };
 
-constexpr int COL_THREADS = 256;
+// Column passes: a strip tile of W * ny elements (4096 float2 or 2048
+// double2, 32 KiB, unless one column is longer) with 8 elements per thread,
+// i.e. W * ny / 8 threads (at most 512).
+constexpr int COL_EPT = 8;
+constexpr int COL_MAX_THREADS = 512;
+__host__ __device__ constexpr int col_tile_elems(bool dbl) { return dbl ? 2048 : 4096; }
 constexpr int COMBINE_THREADS = 256;
 
 // Launchers (defined in qg_kernels.hip).  Each returns hipGetLastError().

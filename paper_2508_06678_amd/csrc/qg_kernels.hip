@@ -5,10 +5,13 @@
 //                    [-myh, myh] stored as iy = m_y (m_y >= 0) or
 //                    iy = m_y + kyn (m_y < 0), kyn = 2 myh + 1.
 //                    The 2/3 set D is kxn = (nx-1)/3 + 1, myh = (ny-1)/3.
-//   mixed fields     complex [field][y][kx], row pitch kxp >= kxn: the
-//                    output of a column-inverse pass and the input of a row
-//                    pass (MF), or the output of a row pass and the input of
-//                    a column-forward pass (MP).
+//   mixed fields     complex [field][strip][y][w], kx = strip * W + w, strips
+//                    of W columns stored contiguously (kxp = strips * W >=
+//                    kxn): the output of a column-inverse pass and the input
+//                    of a row pass (MF), or the output of a row pass and the
+//                    input of a column-forward pass (MP).  A column pass
+//                    moves one contiguous strip; a row pass touches, per
+//                    strip, a contiguous run of (rows per block) * W values.
 //   physical tables  real [y][x]: E, E_x, E_y, S, chi, chi_sponge.
 //
 // Kernel kinds (Sec. II-C: derivatives in Fourier space, products by
@@ -41,15 +44,18 @@ template <typename T> __device__ __forceinline__ T* rptr(const MemberDev& M, lon
 // signed m_y of compact index iy
 __device__ __forceinline__ int my_of_iy(int iy, int myh, int kyn) { return iy <= myh ? iy : iy - kyn; }
 
-struct Wave {
-  double kx, ky, k2, inv_k2;
+// Wavenumbers of mode (mx, my), in the arithmetic type of the run.  The
+// double-precision 1/|k|^2 of the lowest modes (Poisson inversion of 32-bit
+// runs) is formed separately in poisson().
+template <typename T> struct Wave {
+  T kx, ky, k2, inv_k2;
 };
-__device__ __forceinline__ Wave wave(const MemberDev& M, int mx, int my) {
-  Wave w;
-  w.kx = M.two_pi_lx * mx;
-  w.ky = M.two_pi_ly * my;
+template <typename T> __device__ __forceinline__ Wave<T> wave(const MemberDev& M, int mx, int my) {
+  Wave<T> w;
+  w.kx = T(M.two_pi_lx) * T(mx);
+  w.ky = T(M.two_pi_ly) * T(my);
   w.k2 = w.kx * w.kx + w.ky * w.ky;
-  w.inv_k2 = (mx == 0 && my == 0) ? 0.0 : 1.0 / w.k2;
+  w.inv_k2 = (mx == 0 && my == 0) ? T(0) : T(1) / w.k2;
   return w;
 }
 
@@ -60,12 +66,15 @@ __device__ __forceinline__ bool in_test(const MemberDev& M, int nx, int ny, int 
 }
 
 // psi_hat = -x / |k|^2, in double precision for the lowest modes of 32-bit runs
-template <typename T> __device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave& w) {
+template <typename T>
+__device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave<T>& w, int mx, int my) {
   using V = cpx<T>;
-  if (sizeof(T) == 4 && w.k2 <= M.lowk2) {
-    return cmake<V>(T(-(double)x.x * w.inv_k2), T(-(double)x.y * w.inv_k2));
+  if (sizeof(T) == 4 && (double)w.k2 <= M.lowk2 && (mx | my) != 0) {
+    const double kx = M.two_pi_lx * mx, ky = M.two_pi_ly * my;
+    const double ik2 = 1.0 / (kx * kx + ky * ky);
+    return cmake<V>(T(-(double)x.x * ik2), T(-(double)x.y * ik2));
   }
-  T s = T(-w.inv_k2);
+  const T s = -w.inv_k2;
   return cmake<V>(x.x * s, x.y * s);
 }
 
@@ -84,7 +93,8 @@ template <typename V, typename S> __device__ __forceinline__ V mul_ia(V z, S a) 
 // 3 omega_y = i ky x, and for the Smagorinsky family 4 psi_xx - psi_yy =
 // (ky^2 - kx^2) psi, 5 psi_xy = -kx ky psi (Eq. 1, Eq. 9).
 template <typename T, int CL>
-__device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x, const Wave& w, bool test) {
+__device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x, const Wave<T>& w, int mx, int my,
+                                            bool test) {
   using V = cpx<T>;
   constexpr int nb = (CL == 1 || CL == 3) ? 6 : 4;
   const int kind = f % nb;
@@ -92,7 +102,7 @@ __device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x,
   const T kx = T(w.kx), ky = T(w.ky);
   if (kind == 2) return mul_ia(x, kx);
   if (kind == 3) return mul_ia(x, ky);
-  V psi = poisson<T>(M, x, w);
+  V psi = poisson<T>(M, x, w, mx, my);
   if (kind == 0) return mul_ia(psi, -ky);
   if (kind == 1) return mul_ia(psi, kx);
   if (kind == 4) { T a = T(w.ky * w.ky - w.kx * w.kx); return cmake<V>(psi.x * a, psi.y * a); }
@@ -105,16 +115,16 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
   using V = cpx<T>;
   const int my = my_of_iy(iy, P.myh, P.kyn);
   const long long idx = (long long)mx * P.kyn + iy;
-  const Wave w = wave(M, mx, my);
+  const Wave<T> w = wave<T>(M, mx, my);
   const bool zero_mean = (mx == 0 && my == 0);
   if constexpr (OP == OP_RHS || OP == OP_DIAG) {
     V x = cptr<T>(M, P.o_in)[idx];
     const bool test = dynamic_closure(CL) ? in_test(M, P.nx, P.ny, mx, my) : false;
-    return rhs_field<T, CL>(M, f, x, w, test);
+    return rhs_field<T, CL>(M, f, x, w, mx, my, test);
   } else if constexpr (OP == OP_B) {
     V x = cptr<T>(M, P.o_in)[idx];
     if (f == 2) return x;
-    V psi = poisson<T>(M, x, w);
+    V psi = poisson<T>(M, x, w, mx, my);
     return f == 0 ? mul_ia(psi, T(-w.ky)) : mul_ia(psi, T(w.kx));
   } else if constexpr (OP == OP_EXIT) {
     V x = cptr<T>(M, P.o_in)[idx];
@@ -129,7 +139,7 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     constexpr int nb = (CL == 1) ? 6 : 4;
     if (f < nb) {
       V x = cptr<T>(M, P.o_in)[idx];
-      return rhs_field<T, CL>(M, f, x, w, false);
+      return rhs_field<T, CL>(M, f, x, w, mx, my, false);
     }
     V l = cptr<T>(M, P.o_in2)[idx];
     if (zero_mean) return cmake<V>(T(0), T(0));
@@ -141,15 +151,17 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
 
 // ---------------------------------------------------------------- colinv
 template <typename T, int OP, int CL, int EPT>
-__global__ void __launch_bounds__(COL_THREADS) k_colinv(Phase P) {
+__global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
+  V* twl = tile + P.W * P.ny;
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int f = blockIdx.y;
   const int kx0 = blockIdx.x * P.W;
   const int ny = P.ny;
   const int n = P.W * ny;
+  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   const T scale = T(M.inv_n);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const int w = q >> P.logny;
@@ -166,13 +178,9 @@ __global__ void __launch_bounds__(COL_THREADS) k_colinv(Phase P) {
   }
   __syncthreads();
   FftShape s{P.logny, P.W, 1, P.logW, true};
-  fft_lds<V, true, EPT>(tile, reinterpret_cast<const V*>(P.twy), s);
-  V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + kx0;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    const int w = q & (P.W - 1);
-    const int y = q >> P.logW;
-    out[(long long)y * P.kxp + w] = tile[y * P.W + w];
-  }
+  fft_lds<V, true, EPT>(tile, twl, s);
+  V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + (long long)kx0 * ny;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) out[q] = tile[q];
 }
 
 // ---------------------------------------------------------------- row pass
@@ -182,11 +190,16 @@ template <typename T> struct RowCtx {
   using V = cpx<T>;
   V* buf;            // RP rows of nx complex
   const V* tw;
-  int nx, lognx, RP, logRP, kxn, kxp, ny;
+  int nx, lognx, RP, logRP, kxn, kxp, ny, logW;
   int y0;            // first row of the block
 };
 
-// c2r of field src (mixed layout [y][kx], pitch kxp) for the block's row
+// position of (y, kx) in a strip-major mixed field
+template <typename T> __device__ __forceinline__ long long mix_at(const RowCtx<T>& C, int y, int k) {
+  return (((long long)(k >> C.logW) * C.ny + y) << C.logW) + (k & ((1 << C.logW) - 1));
+}
+
+// c2r of field src (strip-major mixed layout) for the block's row
 // pairs; returns each thread's ROW_EPT elements: .x row 2rp, .y row 2rp+1.
 template <typename T>
 __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __restrict__ src, cpx<T> (&out)[ROW_EPT]) {
@@ -198,14 +211,16 @@ __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __rest
     const int ya = C.y0 + 2 * rp;
     V z = cmake<V>(T(0), T(0));
     if (k < C.kxn) {
-      V a = src[(long long)ya * C.kxp + k];
-      V b = src[(long long)(ya + 1) * C.kxp + k];
+      const long long o = mix_at(C, ya, k);
+      V a = src[o];
+      V b = src[o + (1 << C.logW)];
       if (k == 0) { a.y = T(0); b.y = T(0); }
       z = cmake<V>(a.x - b.y, a.y + b.x);
     } else if (k > C.nx - C.kxn) {
       const int kk = C.nx - k;
-      V a = src[(long long)ya * C.kxp + kk];
-      V b = src[(long long)(ya + 1) * C.kxp + kk];
+      const long long o = mix_at(C, ya, kk);
+      V a = src[o];
+      V b = src[o + (1 << C.logW)];
       z = cmake<V>(a.x + b.y, b.x - a.y);
     }
     C.buf[q] = z;
@@ -243,8 +258,9 @@ __device__ __forceinline__ void row_r2c(const RowCtx<T>& C, const cpx<T> (&val)[
       V zm = row[(C.nx - k) & (C.nx - 1)];
       V a = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
       V b = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
-      dst[(long long)ya * C.kxp + k] = a;
-      dst[(long long)(ya + 1) * C.kxp + k] = b;
+      const long long o = mix_at(C, ya, k);
+      dst[o] = a;
+      dst[o + (1 << C.logW)] = b;
     }
   }
   __syncthreads();
@@ -291,16 +307,25 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 }
 
 template <typename T, int OP, int CL>
-__global__ void __launch_bounds__(512) k_row(Phase P) {
+__global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 : 2)) k_row(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   RowCtx<T> C;
   C.buf = reinterpret_cast<V*>(smem_raw);
-  C.tw = reinterpret_cast<const V*>(P.twx);
+  {
+    V* twl = C.buf + P.RP * P.nx;
+    stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
+    C.tw = twl;
+  }
   C.nx = P.nx; C.lognx = P.lognx; C.RP = P.RP; C.logRP = P.logRP;
-  C.kxn = P.kxn; C.kxp = P.kxp; C.ny = P.ny;
-  C.y0 = blockIdx.x * 2 * P.RP;
+  C.kxn = P.kxn; C.kxp = P.kxp; C.ny = P.ny; C.logW = P.logW;
+  // XCD-aware order: the hardware deals blocks to the 8 XCDs round-robin;
+  // give each XCD a contiguous range of rows so mixed-layout lines shared by
+  // neighbouring row blocks meet in the same L2.
+  int rb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  C.y0 = rb * 2 * P.RP;
   __shared__ double red[16];
   const long long fstride = (long long)P.ny * P.kxp;
   const V* mf = cptr<T>(M, P.o_mf);
@@ -570,34 +595,139 @@ __global__ void __launch_bounds__(512) k_row(Phase P) {
   }
 }
 
+// ---------------------------------------------------------------- row pass, field-parallel
+// Right-hand side and B sub-step: one block per row pair.  The nb fields of
+// a level (4, or 6 for the Smagorinsky family; u', v', omega for the B
+// sub-step) are taken to physical space at the same time by nb groups of
+// nx/8 threads, the products are formed point by point in LDS (J, h_x, h_y;
+// or the penalized and sponged vorticity), and transformed back by the
+// first groups.  Used whenever nb * nx / 8 <= 1024 threads and the nb rows
+// fit in LDS.
+template <typename T, int OP, int CL>
+__global__ void __launch_bounds__(1024) k_rowp(Phase P) {
+  using V = cpx<T>;
+  constexpr bool smag = (CL == 1 || CL == 3);
+  constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
+  constexpr int nb = OP == OP_B ? 3 : smag ? 6 : 4;
+  constexpr int levels = dyn ? 2 : 1;
+  constexpr int np = (OP == OP_B || CL == 0) ? 1 : 3;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int nx = P.nx;
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  V* twl = buf + nb * nx;
+  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
+  const int lg = P.lognx - 3;              // log2 of the group size nx/8
+  const int grp = threadIdx.x >> lg;
+  const int lt = threadIdx.x & ((1 << lg) - 1);
+  const int gsz = 1 << lg;
+  int rb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int ya = 2 * rb;
+  RowCtx<T> C;
+  C.ny = P.ny; C.logW = P.logW;
+  const long long fstride = (long long)P.ny * P.kxp;
+  const V* mf = cptr<T>(M, P.o_mf);
+  V* mp = cptr<T>(M, P.o_mp);
+  const T U = T(M.u_in), Vv = T(M.v_in);
+  const FftShape sh{P.lognx, 1, nx, 0, false};
+  V* mybuf = buf + grp * nx;
+#pragma unroll 1
+  for (int lev = 0; lev < levels; ++lev) {
+    // c2r of field lev * nb + grp
+    {
+      const V* src = mf + (long long)(lev * nb + grp) * fstride;
+      for (int k = lt; k < nx; k += gsz) {
+        V z = cmake<V>(T(0), T(0));
+        if (k < P.kxn) {
+          const long long o = mix_at(C, ya, k);
+          V a = src[o];
+          V b = src[o + (1 << C.logW)];
+          if (k == 0) { a.y = T(0); b.y = T(0); }
+          z = cmake<V>(a.x - b.y, a.y + b.x);
+        } else if (k > nx - P.kxn) {
+          const long long o = mix_at(C, ya, nx - k);
+          V a = src[o];
+          V b = src[o + (1 << C.logW)];
+          z = cmake<V>(a.x + b.y, b.x - a.y);
+        }
+        mybuf[k] = z;
+      }
+    }
+    __syncthreads();
+    fft_lds<V, true, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, true});
+    // products at each point (.x row ya, .y row ya + 1)
+    if constexpr (OP == OP_B) {
+      // omega'' = S (E omega + E_x v - E_y u), total velocity
+      const long long nxy = (long long)nx * P.ny;
+      const T* E = rptr<T>(M, P.o_phys);
+      for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+        const V u = buf[q], v = buf[nx + q], w = buf[2 * nx + q];
+        const long long a = (long long)ya * nx + q, b = a + nx;
+        const T w0 = E[a] * w.x + E[nxy + a] * (Vv + v.x) - E[2 * nxy + a] * (U + u.x);
+        const T w1 = E[b] * w.y + E[nxy + b] * (Vv + v.y) - E[2 * nxy + b] * (U + u.y);
+        buf[q] = cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
+      }
+    } else
+    for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+      const V u = buf[q], v = buf[nx + q], wx = buf[2 * nx + q], wy = buf[3 * nx + q];
+      const V J = vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + v.x, Vv + v.y), wy));
+      if constexpr (CL != 0) {
+        V base;
+        if constexpr (smag) {
+          const V pd = buf[4 * nx + q], pxy = buf[5 * nx + q];
+          base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+        } else {
+          base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+        }
+        buf[nx + q] = vmul<T>(base, wx);
+        buf[2 * nx + q] = vmul<T>(base, wy);
+      }
+      buf[q] = J;
+    }
+    __syncthreads();
+    fft_lds<V, false, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, grp < np});
+    if (grp < np) {
+      V* dst = mp + (long long)(lev * 3 + grp) * fstride;
+      for (int k = lt; k < P.kxn; k += gsz) {
+        const V z = mybuf[k];
+        const V zm = mybuf[(nx - k) & (nx - 1)];
+        const long long o = mix_at(C, ya, k);
+        dst[o] = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
+        dst[o + (1 << C.logW)] = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- colfwd
 // Forward FFT along y of product p's strip into the LDS tile.
 template <typename T, int EPT>
-__device__ __forceinline__ void colfwd_load_fft(const Phase& P, const MemberDev& M, cpx<T>* tile, int p, int kx0) {
+__device__ __forceinline__ void colfwd_load_fft(const Phase& P, const MemberDev& M, cpx<T>* tile,
+                                                const cpx<T>* twl, int p, int kx0) {
   using V = cpx<T>;
   const int n = P.W * P.ny;
-  const V* src = cptr<T>(M, P.o_mp) + (long long)p * P.ny * P.kxp + kx0;
+  const V* src = cptr<T>(M, P.o_mp) + (long long)p * P.ny * P.kxp + (long long)kx0 * P.ny;
   __syncthreads();
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    const int w = q & (P.W - 1);
-    const int y = q >> P.logW;
-    tile[y * P.W + w] = src[(long long)y * P.kxp + w];
-  }
+  for (int q = threadIdx.x; q < n; q += blockDim.x) tile[q] = src[q];
   __syncthreads();
   FftShape s{P.logny, P.W, 1, P.logW, true};
-  fft_lds<V, false, EPT>(tile, reinterpret_cast<const V*>(P.twy), s);
+  fft_lds<V, false, EPT>(tile, twl, s);
 }
 
 template <typename T, int OP, int CL, int EPT>
-__global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
+__global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_colfwd(Phase P) {
   using V = cpx<T>;
   constexpr int MAXM = EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
+  V* twl = tile + P.W * P.ny;
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int kx0 = blockIdx.x * P.W;
   const int nmodes = P.W * P.kyn;
+  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   // owned modes, packed as (m_x << 16) | iy; m_x = kxn marks "not owned"
   int own[MAXM];
 #pragma unroll
@@ -618,7 +748,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
   auto sidx = [&](int i) { return (long long)mxs_(i) * P.kyn + iys_(i); };
 
   if constexpr (OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
-    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 0, kx0);
     V* out = cptr<T>(M, P.o_out);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
@@ -630,7 +760,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
   } else if constexpr (OP == OP_RHS && !(CL == 3 || CL == 4)) {
     // R = -J + C (i kx h_x + i ky h_y) - (k^2/Re + mu) x - i beta kx psi; RK4 update
     V R[MAXM], Q[MAXM];
-    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 0, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
@@ -638,18 +768,18 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
       R[i] = cmake<V>(-j.x, -j.y);
     }
     if constexpr (CL != 0) {
-      colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+      colfwd_load_fft<T, EPT>(P, M, tile, twl, 1, kx0);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (!owned(i)) continue;
-        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
         Q[i] = mul_ia(tile_at(i), T(w.kx));
       }
-      colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+      colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (!owned(i)) continue;
-        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
         Q[i] = cadd(Q[i], mul_ia(tile_at(i), T(w.ky)));
       }
     }
@@ -663,13 +793,13 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
       const int my = my_of_iy(iys_(i), P.myh, P.kyn);
-      const Wave w = wave(M, mxs_(i), my);
+      const Wave<T> w = wave<T>(M, mxs_(i), my);
       const long long id = sidx(i);
       const V x = xin[id];
       V r = R[i];
       const T lin = T(w.k2 * M.inv_re + M.mu);
       r = csub(r, cscale(x, lin));
-      const V psi = poisson<T>(M, x, w);
+      const V psi = poisson<T>(M, x, w, mxs_(i), my);
       r = csub(r, mul_ia(psi, T(M.beta * w.kx)));
       if constexpr (CL != 0) r = cadd(r, cscale(Q[i], C));
       if (mxs_(i) == 0 && my == 0) r = cmake<V>(T(0), T(0));
@@ -688,60 +818,61 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
       }
     }
   } else if constexpr (OP == OP_RHS) {
-    // dynamic closures: J, Q = i k . h to the side buffers, partial sums of
-    // <HM> and <M^2> over the strip (Parseval, weights 1 at m_x = 0 else 2)
+    // dynamic closures: Q = i k . h and J to the side buffers, then
+    // M = r i k . g - T Q and H = FFT(J~) - T J, partial sums of <HM> and
+    // <M^2> over the strip (Parseval, weights 1 at m_x = 0 else 2).
+    // Products are taken in the order h_x, h_y, g_x, g_y, J~, J so that
+    // only two per-mode accumulators are live.
     V A[MAXM], B[MAXM];
     V* jsp = cptr<T>(M, P.o_out);
     V* qsp = cptr<T>(M, P.o_aux);
-    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) if (owned(i)) { A[i] = tile_at(i); jsp[sidx(i)] = A[i]; }
-    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
-      B[i] = mul_ia(tile_at(i), T(w.kx));
-    }
-    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
-      B[i] = cadd(B[i], mul_ia(tile_at(i), T(w.ky)));
-      qsp[sidx(i)] = B[i];
-    }
-    // H = FFT(J~) - T J
-    colfwd_load_fft<T, EPT>(P, M, tile, 3, kx0);
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (!owned(i)) continue;
-      const bool t = in_test(M, P.nx, P.ny, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
-      V h = tile_at(i);
-      A[i] = t ? csub(h, A[i]) : h;
-    }
-    // M = r i k . g - T Q
-    V G[MAXM];
-    colfwd_load_fft<T, EPT>(P, M, tile, 4, kx0);
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
-      G[i] = mul_ia(tile_at(i), T(w.kx));
-    }
-    colfwd_load_fft<T, EPT>(P, M, tile, 5, kx0);
-    double hm = 0.0, mm = 0.0;
     const T r = T(M.r_test);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 1, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      A[i] = mul_ia(tile_at(i), w.kx);
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      A[i] = cadd(A[i], mul_ia(tile_at(i), w.ky));
+      qsp[sidx(i)] = A[i];
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 4, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      B[i] = mul_ia(tile_at(i), w.kx);
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 5, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
       const int my = my_of_iy(iys_(i), P.myh, P.kyn);
-      const Wave w = wave(M, mxs_(i), my);
-      V g = cadd(G[i], mul_ia(tile_at(i), T(w.ky)));
-      g = cscale(g, r);
-      if (in_test(M, P.nx, P.ny, mxs_(i), my)) g = csub(g, B[i]);
+      const Wave<T> w = wave<T>(M, mxs_(i), my);
+      V g = cscale(cadd(B[i], mul_ia(tile_at(i), w.ky)), r);
+      B[i] = in_test(M, P.nx, P.ny, mxs_(i), my) ? csub(g, A[i]) : g;
+    }
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 3, kx0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) if (owned(i)) A[i] = tile_at(i);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 0, kx0);
+    double hm = 0.0, mm = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (!owned(i)) continue;
+      const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+      const V j = tile_at(i);
+      jsp[sidx(i)] = j;
+      const V h = in_test(M, P.nx, P.ny, mxs_(i), my) ? csub(A[i], j) : A[i];
+      const V g = B[i];
       const double wt = mxs_(i) == 0 ? 1.0 : 2.0;
-      hm += wt * ((double)A[i].x * (double)g.x + (double)A[i].y * (double)g.y);
+      hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
       mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
     }
     double shm = block_sum(hm, red);
@@ -755,18 +886,18 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
     // lambda_s = FFT(lambda_w) - (1/|k|^2)(i ky FFT(lambda_u) - i kx FFT(lambda_v));
     // writes LS (o_out), LW = LS (o_aux), LK = dt/6 LS (o_in)
     V Lw[MAXM];
-    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 0, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) if (owned(i)) Lw[i] = tile_at(i);
     V Lp[MAXM];
-    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 1, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       Lp[i] = mul_ia(tile_at(i), T(w.ky));
     }
-    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
     V* ls = cptr<T>(M, P.o_out);
     V* lw = cptr<T>(M, P.o_aux);
     V* lk = cptr<T>(M, P.o_in);
@@ -774,7 +905,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       V lpsi = csub(Lp[i], mul_ia(tile_at(i), T(w.kx)));
       V l = csub(Lw[i], cscale(lpsi, T(w.inv_k2)));
       const long long id = sidx(i);
@@ -789,47 +920,47 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
     // then LW += lambda_x and LK <- c LS + d lambda_x for the previous stage.
     constexpr bool smag = (CL == 1);
     V Lpsi[MAXM], Lx[MAXM];
-    colfwd_load_fft<T, EPT>(P, M, tile, 0, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 0, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       Lpsi[i] = mul_ia(tile_at(i), T(w.ky));
     }
-    colfwd_load_fft<T, EPT>(P, M, tile, 1, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 1, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       Lpsi[i] = csub(Lpsi[i], mul_ia(tile_at(i), T(w.kx)));
     }
-    colfwd_load_fft<T, EPT>(P, M, tile, 2, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       Lx[i] = mul_ia(tile_at(i), T(-w.kx));
     }
-    colfwd_load_fft<T, EPT>(P, M, tile, 3, kx0);
+    colfwd_load_fft<T, EPT>(P, M, tile, twl, 3, kx0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
-      const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+      const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       Lx[i] = cadd(Lx[i], mul_ia(tile_at(i), T(-w.ky)));
     }
     if constexpr (smag) {
-      colfwd_load_fft<T, EPT>(P, M, tile, 4, kx0);
+      colfwd_load_fft<T, EPT>(P, M, tile, twl, 4, kx0);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (!owned(i)) continue;
-        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
         Lpsi[i] = cadd(Lpsi[i], cscale(tile_at(i), T(w.ky * w.ky - w.kx * w.kx)));
       }
-      colfwd_load_fft<T, EPT>(P, M, tile, 5, kx0);
+      colfwd_load_fft<T, EPT>(P, M, tile, twl, 5, kx0);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (!owned(i)) continue;
-        const Wave w = wave(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
+        const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
         Lpsi[i] = cadd(Lpsi[i], cscale(tile_at(i), T(-w.kx * w.ky)));
       }
     }
@@ -844,7 +975,7 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
       const int my = my_of_iy(iys_(i), P.myh, P.kyn);
-      const Wave w = wave(M, mxs_(i), my);
+      const Wave<T> w = wave<T>(M, mxs_(i), my);
       const long long id = sidx(i);
       V l = lin[id];
       if (mxs_(i) == 0 && my == 0) l = cmake<V>(T(0), T(0));
@@ -858,6 +989,109 @@ __global__ void __launch_bounds__(COL_THREADS) k_colfwd(Phase P) {
 }
 #undef mxs_
 #undef iys_
+
+// ---------------------------------------------------------------- colfwd, product-parallel
+// All np product strips of a block sit in LDS at once; np groups of
+// W ny / 8 threads transform them concurrently, then every thread combines
+// the retained modes straight from LDS.  Used when np W ny / 8 <= 1024 and
+// the strips fit in LDS (in particular W = 1 at ny <= 1024).
+template <typename T, int OP, int CL>
+__global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
+  using V = cpx<T>;
+  constexpr bool dyn = (CL == 3 || CL == 4);
+  constexpr int np = (OP == OP_RHS) ? (CL == 0 ? 1 : dyn ? 6 : 3) : 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const int n = P.W * P.ny;
+  V* tile = reinterpret_cast<V*>(smem_raw);
+  V* twl = tile + np * n;
+  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
+  const int lg = P.logW + P.logny - 3;     // log2 of the group size n/8
+  const int grp = threadIdx.x >> lg;
+  const int lt = threadIdx.x & ((1 << lg) - 1);
+  const int kx0 = blockIdx.x * P.W;
+  {
+    const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
+    V* dst = tile + grp * n;
+    for (int q = lt; q < n; q += (1 << lg)) dst[q] = src[q];
+  }
+  __syncthreads();
+  const FftShape sh{P.logny, P.W, 1, P.logW, true};
+  fft_lds<V, false, COL_EPT>(tile + grp * n, twl, sh, FftGroup{lt, 1 << lg, true});
+  // tile[p * n + y * W + w]: product p at (m_y of row y, kx0 + w)
+  auto at = [&](int p, int w, int iy) -> V {
+    const int my = my_of_iy(iy, P.myh, P.kyn);
+    const int y = my >= 0 ? my : my + P.ny;
+    return tile[p * n + y * P.W + w];
+  };
+  const int nm = P.W * P.kyn;
+  double hm = 0.0, mm = 0.0;
+  for (int q = threadIdx.x; q < nm; q += blockDim.x) {
+    const int w = q / P.kyn;
+    const int iy = q - w * P.kyn;
+    const int mx = kx0 + w;
+    if (mx >= P.kxn) continue;
+    const int my = my_of_iy(iy, P.myh, P.kyn);
+    const long long id = (long long)mx * P.kyn + iy;
+    if constexpr (OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
+      V v = at(0, w, iy);
+      if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
+      cptr<T>(M, P.o_out)[id] = v;
+    } else if constexpr (!dyn) {
+      const Wave<T> wv = wave<T>(M, mx, my);
+      const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
+      const V x = xin[id];
+      const V j = at(0, w, iy);
+      V r = cmake<V>(-j.x, -j.y);
+      r = csub(r, cscale(x, T(wv.k2 * M.inv_re + M.mu)));
+      r = csub(r, mul_ia(poisson<T>(M, x, wv, mx, my), T(M.beta * wv.kx)));
+      if constexpr (CL != 0) {
+        const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
+        r = cadd(r, cscale(Q, T(M.coef_static)));
+      }
+      if (mx == 0 && my == 0) r = cmake<V>(T(0), T(0));
+      const V w0 = cptr<T>(M, P.o_in2)[id];
+      V* acc = cptr<T>(M, P.o_aux);
+      V* xout = cptr<T>(M, P.o_in);
+      const double dt = M.dt;
+      if (P.stage == 1) {
+        acc[id] = cadd(w0, cscale(r, T(dt / 6.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+      } else if (P.stage == 2) {
+        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+      } else if (P.stage == 3) {
+        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
+        xout[id] = cadd(w0, cscale(r, T(dt)));
+      } else {
+        xout[id] = cadd(acc[id], cscale(r, T(dt / 6.0)));
+      }
+    } else {
+      const Wave<T> wv = wave<T>(M, mx, my);
+      const bool t = in_test(M, P.nx, P.ny, mx, my);
+      const V j = at(0, w, iy);
+      const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
+      cptr<T>(M, P.o_out)[id] = j;
+      cptr<T>(M, P.o_aux)[id] = Q;
+      const V h = t ? csub(at(3, w, iy), j) : at(3, w, iy);
+      V g = cscale(cadd(mul_ia(at(4, w, iy), wv.kx), mul_ia(at(5, w, iy), wv.ky)), T(M.r_test));
+      if (t) g = csub(g, Q);
+      const double wt = mx == 0 ? 1.0 : 2.0;
+      hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
+      mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
+    }
+  }
+  if constexpr (OP == OP_RHS && dyn) {
+    const double shm = block_sum(hm, red);
+    const double smm = block_sum(mm, red);
+    if (threadIdx.x == 0) {
+      double* part = rptr<double>(M, P.o_part) + 2 * blockIdx.x;
+      part[0] = shm;
+      part[1] = smm;
+    }
+  }
+}
 
 // ---------------------------------------------------------------- combine
 // Dynamic closures: C = max(<HM>, 0)/<M^2> from the fixed-order sum of the
@@ -897,7 +1131,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   const int mx = q / P.kyn;
   const int iy = q - mx * P.kyn;
   const int my = my_of_iy(iy, P.myh, P.kyn);
-  const Wave w = wave(M, mx, my);
+  const Wave<T> w = wave<T>(M, mx, my);
   const V* jsp = cptr<T>(M, P.o_out);
   const V* qsp = cptr<T>(M, P.o_aux);
   const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
@@ -908,7 +1142,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   const V j = jsp[q];
   V r = cmake<V>(-j.x, -j.y);
   r = csub(r, cscale(x, T(w.k2 * M.inv_re + M.mu)));
-  r = csub(r, mul_ia(poisson<T>(M, x, w), T(M.beta * w.kx)));
+  r = csub(r, mul_ia(poisson<T>(M, x, w, mx, my), T(M.beta * w.kx)));
   r = cadd(r, cscale(qsp[q], T(C)));
   if (mx == 0 && my == 0) r = cmake<V>(T(0), T(0));
   const double dt = M.dt;
@@ -949,7 +1183,7 @@ __global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
     const int mx = q / P.kyn;
     const int iy = q - mx * P.kyn;
     const int my = my_of_iy(iy, P.myh, P.kyn);
-    const Wave w = wave(M, mx, my);
+    const Wave<T> w = wave<T>(M, mx, my);
     const V x = cptr<T>(M, P.o_in)[q];
     const double a2 = (double)x.x * x.x + (double)x.y * x.y;
     const double wt = mx == 0 ? 1.0 : 2.0;
@@ -1019,26 +1253,63 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 }
 
 // ---------------------------------------------------------------- launchers
-static size_t col_smem(bool dbl, const Phase& P) { return (size_t)P.W * P.ny * (dbl ? 16 : 8); }
-static size_t row_smem(bool dbl, const Phase& P) { return (size_t)P.RP * P.nx * (dbl ? 16 : 8); }
+static size_t col_smem(bool dbl, const Phase& P) { return ((size_t)P.W * P.ny + P.ny / 2) * (dbl ? 16 : 8); }
+static size_t row_smem(bool dbl, const Phase& P) { return ((size_t)P.RP * P.nx + P.nx / 2) * (dbl ? 16 : 8); }
 static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
 
 template <typename T, int OP, int CL>
 static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid((P.kxn + P.W - 1) / P.W, P.nf, nmem);
-  constexpr int EPT = sizeof(T) == 4 ? 32 : 16;
-  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(COL_THREADS), col_smem(sizeof(T) == 8, P), s, P);
+  constexpr int EPT = COL_EPT;
+  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
+}
+static int rowp_fields(int op, int cl) { return op == OP_B ? 3 : (cl == 1 || cl == 3) ? 6 : 4; }
+static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
+  const int nb = rowp_fields(op, cl);
+  const size_t lds = ((size_t)nb * P.nx + P.nx / 2) * (dbl ? 16 : 8);
+  return P.nx >= 64 && nb * P.nx / 8 <= 1024 && lds <= 128 * 1024;
 }
 template <typename T, int OP, int CL>
+static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
+  const int nb = rowp_fields(OP, CL);
+  dim3 grid(P.ny / 2, 1, nmem);
+  const size_t lds = ((size_t)nb * P.nx + P.nx / 2) * sizeof(cpx<T>);
+  hipLaunchKernelGGL((k_rowp<T, OP, CL>), grid, dim3(nb * P.nx / 8), lds, s, P);
+}
+
+template <typename T, int OP, int CL>
 static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
+  if constexpr (OP == OP_RHS || OP == OP_B) {
+    if (rowp_ok(sizeof(T) == 8, OP, CL, P)) { launch_rowp_t<T, OP, CL>(P, nmem, s); return; }
+  }
   dim3 grid(P.ny / (2 * P.RP), 1, nmem);
   hipLaunchKernelGGL((k_row<T, OP, CL>), grid, dim3(row_threads(P)), row_smem(sizeof(T) == 8, P), s, P);
 }
+static int colfwdp_products(int op, int cl) {
+  if (op == OP_RHS) return cl == 0 ? 1 : (cl == 3 || cl == 4) ? 6 : 3;
+  return 1;
+}
+static bool colfwdp_ok(bool dbl, int op, int cl, const Phase& P) {
+  const int np = colfwdp_products(op, cl);
+  const size_t n = (size_t)P.W * P.ny;
+  return np * n / COL_EPT <= 1024 && (np * n + P.ny / 2) * (dbl ? 16 : 8) <= 128 * 1024;
+}
+template <typename T, int OP, int CL>
+static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
+  const int np = colfwdp_products(OP, CL);
+  dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
+  const size_t n = (size_t)P.W * P.ny;
+  hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * n / COL_EPT), (np * n + P.ny / 2) * sizeof(cpx<T>), s, P);
+}
+
 template <typename T, int OP, int CL>
 static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
+  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
+    if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) { launch_colfwdp_t<T, OP, CL>(P, nmem, s); return; }
+  }
   dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
-  constexpr int EPT = sizeof(T) == 4 ? 32 : 16;
-  hipLaunchKernelGGL((k_colfwd<T, OP, CL, EPT>), grid, dim3(COL_THREADS), col_smem(sizeof(T) == 8, P), s, P);
+  constexpr int EPT = COL_EPT;
+  hipLaunchKernelGGL((k_colfwd<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
 }
 
 #define QG_CL_SWITCH(FN, T, OP, cl, P, n, s)                 \

@@ -145,3 +145,34 @@ def test_diag(closure):
     out2, _ = S.diag(bad)
     assert out2.cpu().numpy()[0][7] == 1.0
     S.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_every_strip_width(tmp_path, precision):
+    """The column strip width W is a tuning choice only: every admissible W
+    (forced through the tuning cache) gives the same step to the tolerance."""
+    import json
+    import torch
+    nx, ny = 128, 512
+    m = member(nx, ny, "dsmag", init="spectrum")
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/{nx}x{ny}/fp{precision}/closure3/members1"
+    ref = None
+    # admissible widths: one wave at least (W ny >= 512), one tile at most
+    widths = [W for W in (1, 2, 4, 8, 16) if W * ny >= 512 and W * ny <= (2048 if precision == 64 else 4096)]
+    for W in widths:
+        cache = tmp_path / f"w{W}.json"
+        cache.write_text(json.dumps({key: W}))
+        S = solver_for([m], precision)
+        S.autotune(str(cache))
+        assert S.column_widths() == [W]
+        om = S.pack([m.omega0])
+        w_in = to_np(om).reshape(ny, nx)
+        S.step(om, 1, use_graph=False)
+        if ref is None:
+            ref = qg.step(w_in, M)
+        err = rel_l2(to_np(om).reshape(ny, nx), ref)
+        say("  W", W, err)
+        assert err < TOL[precision]
+        S.close()
