@@ -134,6 +134,12 @@ int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
 int qg_adjoint_step(qg_handle* h, const void* omega_ckpt, void* lambda,
                     int64_t nsteps, double* grad_c_dev, void* hip_stream);
 
+/* Replace the closure coefficient c of every member (c_host: n_members
+ * doubles on the host; ignored for members without a static closure).  The
+ * update is ordered on hip_stream after previously enqueued work; replays
+ * of captured graphs see the new values. */
+int qg_set_coef(qg_handle* h, const double* c_host, void* hip_stream);
+
 /* Diagnostics at omega: for each member 8 doubles
  *   [energy 1/2<|grad psi|^2>, enstrophy 1/2<omega^2>, C, nu_min, nu_mean,
  *    nu_max, CFL = max(|u|+|v|) dt/Delta, nonfinite flag]

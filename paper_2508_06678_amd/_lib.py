@@ -14,7 +14,7 @@ QG_OK, QG_EINVAL, QG_EUNSUPPORTED, QG_EWORKSPACE, QG_EHIP, QG_ESTATE = range(6)
 CLOSURES = {"none": 0, "smag": 1, "leith": 2, "dsmag": 3, "dleith": 4}
 
 EXPORTS = ["qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag",
-           "qg_autotune", "qg_run_phase", "qg_info", "qg_destroy", "qg_last_error"]
+           "qg_set_coef", "qg_autotune", "qg_run_phase", "qg_info", "qg_destroy", "qg_last_error"]
 
 
 class QGParams(ctypes.Structure):
@@ -55,6 +55,7 @@ def lib():
     L.qg_diag.argtypes = [vp, vp, vp, vp, vp]
     L.qg_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     L.qg_run_phase.argtypes = [vp, i32, i32, i32, vp]
+    L.qg_set_coef.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     L.qg_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.qg_destroy.argtypes = [vp]
     L.qg_destroy.restype = None

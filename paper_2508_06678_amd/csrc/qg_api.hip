@@ -146,7 +146,9 @@ static void plan_sizes(Group& g, int adjK) {
   L.phys = take(6LL * g.nx * g.ny * rs);
   L.part = take((long long)std::max(g.kxn, g.kxn_f) * 2 * 8);   // one slot per strip at W = 1
   L.coef = take(32 * 8);
-  L.dpart = take((long long)(5 * g.nrow + 2 * g.nspec + 8) * 8);
+  // row-block partial sums (at most ny/2 blocks, 5 values each), then the
+  // spectral partial sums of the diagnostics
+  L.dpart = take((long long)(5 * (g.ny / 2) + 2 * g.nspec + 8) * 8);
   if (adjK > 0) {
     L.adj_lam = take(spec);
     L.adj_lacc = take(spec);   // LW
@@ -171,8 +173,10 @@ struct Handle {
   size_t ws_bytes = 0;
   MemberDev* mem_dev = nullptr;
   std::map<int, hipGraphExec_t> graphs;   // steps per replay -> executable graph
+  std::map<int, hipGraphExec_t> adj_graphs;  // adjoint segment length -> executable graph
   hipStream_t graph_stream = nullptr;      // capture/replay stream (the caller's may be the null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<MemberDev> table;            // host copy of the device member table
 };
 
 static bool same_group(const qg_params& a, const qg_params& b) {
@@ -461,6 +465,59 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   return m;
 }
 
+// ------------------------------------------------------------ adjoint sweep
+// Recompute one segment from the state in wn, storing every stage input,
+// then run the adjoint steps in reverse (B-step transpose, stages 4..1),
+// starting from adj_lam and leaving dL/d state at the segment start in
+// adj_lam; dL/dc is accumulated in the workspace.  Workspace-only pointers,
+// so the whole sweep can be captured in a graph.
+static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipStream_t st) {
+  const long long spec = (long long)g.kxn * g.kyn * (g.dbl ? 16 : 8);
+  const long long slot_bytes = (long long)align256((size_t)spec);
+  const long long LS = g.L.adj_store;
+  auto slot = [&](long long n, int s) { return g.L.adj_store + (1 + 4 * n + s) * slot_bytes; };
+  Phase C = base_phase(h, g);
+  for (long long n = 0; n < nsteps; ++n) {
+    QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, 0), g.L.wn, st));
+    for (int s = 1; s <= 4; ++s) {
+      int rc = run_stage(h, g, s, st);
+      if (rc) return rc;
+      if (s < 4) QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, s), g.L.x, st));
+    }
+    int rc = run_b(h, g, st);
+    if (rc) return rc;
+  }
+  const int cl = g.closure;
+  const int nb = smag_family(cl) ? 6 : 4;
+  for (long long n = nsteps - 1; n >= 0; --n) {
+    Phase B = base_phase(h, g);
+    B.o_in = g.L.adj_lam;
+    B.nf = 1;
+    QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+    QG_LAUNCH(launch_row(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+    B.o_out = LS;
+    B.o_aux = g.L.adj_lacc;
+    B.o_in = g.L.adj_lk;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_B, 0, B, g.count, st));
+    for (int s = 4; s >= 1; --s) {
+      Phase A = base_phase(h, g);
+      A.stage = s;
+      A.o_in = slot(n, s - 1);
+      A.o_in2 = g.L.adj_lk;
+      A.nf = nb + (cl == 0 ? 1 : 3);
+      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+      if (cl != 0)
+        QG_LAUNCH(launch_adj_grad_c(A, g.count, row_launch_blocks(g.dbl, OP_ADJ_RHS, cl, A), nullptr, 0, st));
+      A.o_out = LS;
+      A.o_aux = g.L.adj_lacc;
+      QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+    }
+    QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, g.L.adj_lam, g.L.adj_lacc, st));
+  }
+  return QG_OK;
+}
+
 // ------------------------------------------------------------ tuning cache
 // A flat JSON object {"<key>": W, ...}; keys name the device architecture,
 // grid, precision, closure and member count of a size group.
@@ -597,6 +654,7 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
   }
   if (hipMemcpyAsync(h.mem_dev, table.data(), n * sizeof(MemberDev), hipMemcpyHostToDevice, st) != hipSuccess)
     return cleanup(fail(QG_EHIP, "member table upload failed"));
+  h.table = table;
   for (auto& g : h.groups) {
     const int rs = g.dbl ? 8 : 4;
     const size_t fb = (size_t)g.nx * g.ny * rs;
@@ -619,6 +677,7 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
 void qg_destroy(qg_handle* H) {
   if (!H) return;
   for (auto& kv : H->h.graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : H->h.adj_graphs) (void)hipGraphExecDestroy(kv.second);
   if (H->h.graph_stream) {
     (void)hipStreamSynchronize(H->h.graph_stream);
     (void)hipStreamDestroy(H->h.graph_stream);
@@ -666,10 +725,11 @@ int qg_step(qg_handle* H, void* omega, int64_t nsteps, int32_t save_every, void*
           rc = run_exit(h, g, g.L.wn, dst, st);
           if (rc) return rc;
         }
-        for (const auto& g : h.groups) {
-          rc = run_entry(h, g, dst, g.L.wn, st);
-          if (rc) return rc;
-        }
+        if (done < nsteps)
+          for (const auto& g : h.groups) {
+            rc = run_entry(h, g, dst, g.L.wn, st);
+            if (rc) return rc;
+          }
         ++save_idx;
       }
     }
@@ -709,9 +769,9 @@ int qg_diag(qg_handle* H, const void* omega, double* out_dev, void* nu_e_out, vo
     D.user = nu_e_out;
     QG_LAUNCH(launch_colinv(g.dbl, OP_DIAG, cl, D, g.count, st));
     QG_LAUNCH(launch_row(g.dbl, OP_DIAG, cl, D, g.count, st));
-    D.o_aux = g.L.dpart + 5LL * g.nrow * 8;
+    D.o_aux = g.L.dpart + 5LL * (g.ny / 2) * 8;
     QG_LAUNCH(launch_diag_spectral(g.dbl, D, g.count, st));
-    QG_LAUNCH(launch_diag_final(D, g.count, g.nrow, g.nspec, out_dev, 0, st));
+    QG_LAUNCH(launch_diag_final(D, g.count, row_launch_blocks(g.dbl, OP_DIAG, cl, D), g.nspec, out_dev, 0, st));
   }
   return QG_OK;
 }
@@ -727,58 +787,71 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
     if (dynamic_closure(g.closure))
       return fail(QG_EUNSUPPORTED, "the adjoint covers the static closures only");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // outside the graph: the caller's fields in, the dL/dc slots cleared
   for (const auto& g : h.groups) {
-    const long long spec = (long long)g.kxn * g.kyn * (g.dbl ? 16 : 8);
-    const long long LS = g.L.adj_store;
-    auto slot = [&](long long n, int s) { return g.L.adj_store + (1 + 4 * n + s) * (long long)align256((size_t)spec); };
-    // forward recompute of the segment, storing the stage inputs
-    int rc = run_entry(h, g, omega_ckpt, g.L.wn, st);
+    int rc = run_entry(h, g, omega_ckpt, g.L.wn, st);          // state at the segment start
     if (rc) return rc;
-    Phase C = base_phase(h, g);
-    for (long long n = 0; n < nsteps; ++n) {
-      QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, 0), g.L.wn, st));
-      for (int s = 1; s <= 4; ++s) {
-        rc = run_stage(h, g, s, st);
-        if (rc) return rc;
-        if (s < 4) QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, s), g.L.x, st));
-      }
-      rc = run_b(h, g, st);
-      if (rc) return rc;
-    }
-    // adjoint of the exit transform: LAM = D FFT(lambda), mean removed
-    rc = run_entry(h, g, lambda, g.L.adj_lam, st);
+    rc = run_entry(h, g, lambda, g.L.adj_lam, st);              // adjoint of the exit transform
     if (rc) return rc;
-    const int cl = g.closure;
-    const int nb = smag_family(cl) ? 6 : 4;
-    for (long long n = nsteps - 1; n >= 0; --n) {
-      Phase B = base_phase(h, g);
-      B.o_in = g.L.adj_lam;
-      B.nf = 1;
-      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_B, 0, B, g.count, st));
-      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_B, 0, B, g.count, st));
-      B.o_out = LS;
-      B.o_aux = g.L.adj_lacc;
-      B.o_in = g.L.adj_lk;
-      QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_B, 0, B, g.count, st));
-      for (int s = 4; s >= 1; --s) {
-        Phase A = base_phase(h, g);
-        A.stage = s;
-        A.o_in = slot(n, s - 1);
-        A.o_in2 = g.L.adj_lk;
-        A.nf = nb + (cl == 0 ? 1 : 3);
-        QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
-        QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
-        if (cl != 0) QG_LAUNCH(launch_adj_grad_c(A, g.count, g.nrow, grad_c, 0, st));
-        A.o_out = LS;
-        A.o_aux = g.L.adj_lacc;
-        QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
-      }
-      QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, g.L.adj_lam, g.L.adj_lacc, st));
-    }
-    // adjoint of the entry transform: lambda = c2r(D LAM), mean removed
-    rc = run_exit(h, g, g.L.adj_lam, lambda, st);
-    if (rc) return rc;
+    QG_LAUNCH(launch_adj_grad_c(base_phase(h, g), g.count, 0, nullptr, 1, st));
   }
+  // recompute + reverse sweep: one graph per segment length
+  if (!h.graph_stream) {
+    QG_HIP(hipStreamCreateWithFlags(&h.graph_stream, hipStreamNonBlocking));
+    QG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
+    QG_HIP(hipEventCreateWithFlags(&h.ev_out, hipEventDisableTiming));
+  }
+  hipStream_t gs = h.graph_stream;
+  hipGraphExec_t ex = nullptr;
+  auto it = h.adj_graphs.find((int)nsteps);
+  if (it != h.adj_graphs.end()) {
+    ex = it->second;
+  } else {
+    hipGraph_t graph;
+    QG_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    int rc = QG_OK;
+    for (const auto& g : h.groups) {
+      rc = adjoint_sweep(h, g, nsteps, gs);
+      if (rc) break;
+    }
+    hipError_t e = hipStreamEndCapture(gs, &graph);
+    if (rc) { if (e == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return fail(QG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(QG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h.adj_graphs[(int)nsteps] = ex;
+  }
+  QG_HIP(hipEventRecord(h.ev_in, st));
+  QG_HIP(hipStreamWaitEvent(gs, h.ev_in, 0));
+  QG_HIP(hipGraphLaunch(ex, gs));
+  QG_HIP(hipEventRecord(h.ev_out, gs));
+  QG_HIP(hipStreamWaitEvent(st, h.ev_out, 0));
+  // outside the graph: the caller's fields out
+  for (const auto& g : h.groups) {
+    int rc = run_exit(h, g, g.L.adj_lam, lambda, st);           // adjoint of the entry transform
+    if (rc) return rc;
+    QG_LAUNCH(launch_adj_grad_c(base_phase(h, g), g.count, 0, grad_c, 2, st));
+  }
+  return QG_OK;
+}
+
+int qg_set_coef(qg_handle* H, const double* c, void* hip_stream) {
+  if (!H || !c) return fail(QG_EINVAL, "NULL argument");
+  Handle& h = H->h;
+  for (size_t i = 0; i < h.params.size(); ++i)
+    if (!std::isfinite(c[i])) return fail(QG_EINVAL, "non-finite closure coefficient");
+  for (const auto& g : h.groups)
+    for (int k = 0; k < g.count; ++k) {
+      const int u = g.users[k];
+      h.params[u].c = c[u];
+      MemberDev m = make_member(h.params[u], h.table[g.m0 + k].base, h.omega_off[u], u);
+      h.table[g.m0 + k] = m;
+    }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  QG_HIP(hipMemcpyAsync(h.mem_dev, h.table.data(), h.table.size() * sizeof(MemberDev),
+                        hipMemcpyHostToDevice, st));
+  QG_HIP(hipStreamSynchronize(st));
   return QG_OK;
 }
 
@@ -862,6 +935,8 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   if (rc) return rc;
   for (auto& kv : h.graphs) (void)hipGraphExecDestroy(kv.second);
   h.graphs.clear();
+  for (auto& kv : h.adj_graphs) (void)hipGraphExecDestroy(kv.second);
+  h.adj_graphs.clear();
   if (changed && cache_path) write_width_cache(cache_path, cache);
   QG_HIP(hipStreamSynchronize(st));
   return QG_OK;

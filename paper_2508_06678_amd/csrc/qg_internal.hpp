@@ -90,7 +90,8 @@ hipError_t launch_diag_final(const Phase& P, int nmem, int nrowblocks, int nspec
                              double* out, int out_member0, hipStream_t s);
 hipError_t launch_dyn_coef(const Phase& P, int nmem, int slot, hipStream_t s);
 hipError_t launch_adj_grad_c(const Phase& P, int nmem, int nrowblocks, double* grad_c,
-                             int member0, hipStream_t s);
+                             int mode, hipStream_t s);
+int row_launch_blocks(bool dbl, int op, int closure, const Phase& P);
 hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, double a, int zero_first, hipStream_t s);
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,

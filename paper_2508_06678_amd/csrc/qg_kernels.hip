@@ -608,9 +608,13 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
-  constexpr int nb = OP == OP_B ? 3 : smag ? 6 : 4;
+  constexpr int nbase = smag ? 6 : 4;
+  // fields: B sub-step u', v', omega; adjoint: the nbase forward fields of
+  // the stage input, then -l, -i kx l, -i ky l (only -l without closure)
+  constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
   constexpr int levels = dyn ? 2 : 1;
-  constexpr int np = (OP == OP_B || CL == 0) ? 1 : 3;
+  constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
+  __shared__ double red[16];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int nx = P.nx;
@@ -657,7 +661,58 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
     __syncthreads();
     fft_lds<V, true, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, true});
     // products at each point (.x row ya, .y row ya + 1)
-    if constexpr (OP == OP_B) {
+    if constexpr (OP == OP_ADJ_RHS) {
+      // adjoint of J = u omega_x + v omega_y, h = base grad omega and base(.):
+      // products l_u, l_v, l_wx, l_wy [, l_pd, l_pxy]; partial sum of
+      // <grad l-part, h> for dL/dc
+      double dc = 0.0;
+      const T coef = T(M.coef_static);
+      for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+        const V u = buf[q], v = buf[nx + q], wx = buf[2 * nx + q], wy = buf[3 * nx + q];
+        const V lJ = buf[nbase * nx + q];
+        V lu = vmul<T>(lJ, wx), lv = vmul<T>(lJ, wy);
+        V lwx = cmake<V>(lJ.x * (U + u.x), lJ.y * (U + u.y));
+        V lwy = cmake<V>(lJ.x * (Vv + v.x), lJ.y * (Vv + v.y));
+        V lpd, lpxy;
+        if constexpr (CL != 0) {
+          const V gx = buf[(nbase + 1) * nx + q], gy = buf[(nbase + 2) * nx + q];
+          V base, pd, pxy;
+          if constexpr (smag) {
+            pd = buf[4 * nx + q];
+            pxy = buf[5 * nx + q];
+            base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+          } else {
+            base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+          }
+          dc += (double)(gx.x * base.x * wx.x + gy.x * base.x * wy.x);
+          dc += (double)(gx.y * base.y * wx.y + gy.y * base.y * wy.y);
+          const V lhx = cmake<V>(coef * gx.x, coef * gx.y);
+          const V lhy = cmake<V>(coef * gy.x, coef * gy.y);
+          lwx = vfma<T>(lhx, base, lwx);
+          lwy = vfma<T>(lhy, base, lwy);
+          const V lb = vadd<T>(vmul<T>(lhx, wx), vmul<T>(lhy, wy));
+          const T r0 = base.x > T(0) ? lb.x / base.x : T(0);
+          const T r1 = base.y > T(0) ? lb.y / base.y : T(0);
+          if constexpr (smag) {
+            lpd = cmake<V>(pd.x * r0, pd.y * r1);
+            lpxy = cmake<V>(T(4) * pxy.x * r0, T(4) * pxy.y * r1);
+          } else {
+            lwx = cmake<V>(lwx.x + wx.x * r0, lwx.y + wx.y * r1);
+            lwy = cmake<V>(lwy.x + wy.x * r0, lwy.y + wy.y * r1);
+          }
+        }
+        buf[q] = lu;
+        buf[nx + q] = lv;
+        buf[2 * nx + q] = lwx;
+        buf[3 * nx + q] = lwy;
+        if constexpr (smag) {
+          buf[4 * nx + q] = lpd;
+          buf[5 * nx + q] = lpxy;
+        }
+      }
+      const double sdc = block_sum(dc, red);
+      if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
+    } else if constexpr (OP == OP_B) {
       // omega'' = S (E omega + E_x v - E_y u), total velocity
       const long long nxy = (long long)nx * P.ny;
       const T* E = rptr<T>(M, P.o_phys);
@@ -688,7 +743,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
     __syncthreads();
     fft_lds<V, false, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, grp < np});
     if (grp < np) {
-      V* dst = mp + (long long)(lev * 3 + grp) * fstride;
+      V* dst = mp + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * fstride;
       for (int k = lt; k < P.kxn; k += gsz) {
         const V z = mybuf[k];
         const V zm = mybuf[(nx - k) & (nx - 1)];
@@ -998,8 +1053,9 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
 template <typename T, int OP, int CL>
 __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   using V = cpx<T>;
-  constexpr bool dyn = (CL == 3 || CL == 4);
-  constexpr int np = (OP == OP_RHS) ? (CL == 0 ? 1 : dyn ? 6 : 3) : 1;
+  constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
+  constexpr int np = OP == OP_RHS ? (CL == 0 ? 1 : dyn ? 6 : 3)
+                   : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
@@ -1038,6 +1094,36 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       V v = at(0, w, iy);
       if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
       cptr<T>(M, P.o_out)[id] = v;
+    } else if constexpr (OP == OP_ADJ_B) {
+      // lambda_s = F(l_w) - (i ky F(l_u) - i kx F(l_v)) / |k|^2 -> LS, LW, LK = dt/6 LS
+      const Wave<T> wv = wave<T>(M, mx, my);
+      const V lpsi = csub(mul_ia(at(1, w, iy), wv.ky), mul_ia(at(2, w, iy), wv.kx));
+      const V l = csub(at(0, w, iy), cscale(lpsi, wv.inv_k2));
+      cptr<T>(M, P.o_out)[id] = l;
+      cptr<T>(M, P.o_aux)[id] = l;
+      cptr<T>(M, P.o_in)[id] = cscale(l, T(M.dt / 6.0));
+    } else if constexpr (OP == OP_ADJ_RHS) {
+      const Wave<T> wv = wave<T>(M, mx, my);
+      V lpsi = csub(mul_ia(at(0, w, iy), wv.ky), mul_ia(at(1, w, iy), wv.kx));
+      if constexpr (CL == 1) {
+        lpsi = cadd(lpsi, cscale(at(4, w, iy), wv.ky * wv.ky - wv.kx * wv.kx));
+        lpsi = cadd(lpsi, cscale(at(5, w, iy), -wv.kx * wv.ky));
+      }
+      const V Lx = cadd(mul_ia(at(2, w, iy), -wv.kx), mul_ia(at(3, w, iy), -wv.ky));
+      V* lk = cptr<T>(M, P.o_in2);
+      V l = lk[id];
+      if (mx == 0 && my == 0) l = cmake<V>(T(0), T(0));
+      const V lp = cadd(lpsi, mul_ia(l, T(M.beta * wv.kx)));
+      V lx = csub(Lx, cscale(l, T(wv.k2 * M.inv_re + M.mu)));
+      lx = csub(lx, cscale(lp, wv.inv_k2));
+      V* lw = cptr<T>(M, P.o_aux);
+      lw[id] = cadd(lw[id], lx);
+      if (P.stage > 1) {
+        const double dt = M.dt;
+        const double cs = P.stage == 4 ? dt / 3.0 : P.stage == 3 ? dt / 3.0 : dt / 6.0;
+        const double ds = P.stage == 4 ? dt : dt / 2.0;
+        lk[id] = cadd(cscale(cptr<T>(M, P.o_out)[id], T(cs)), cscale(lx, T(ds)));
+      }
     } else if constexpr (!dyn) {
       const Wave<T> wv = wave<T>(M, mx, my);
       const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
@@ -1225,13 +1311,19 @@ __global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
 }
 
 // ---------------------------------------------------------------- adjoint misc
-__global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int) {
+// dL/dc: the row blocks' partial sums of one adjoint stage, in a fixed
+// order, accumulated into coef slot 24 of the member (mode 0); mode 1 zeroes
+// the slot; mode 2 adds the slot to the caller's grad_c.
+__global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
   const MemberDev& M = P.mem[P.m0 + blockIdx.x];
   if (threadIdx.x != 0) return;
+  double* slot = rptr<double>(M, P.o_coef) + 24;
+  if (mode == 1) { *slot = 0.0; return; }
+  if (mode == 2) { grad_c[M.user_index] += *slot; return; }
   const double* d = rptr<double>(M, P.o_dpart);
   double s = 0.0;
   for (int i = 0; i < nrow; ++i) s += d[i];
-  grad_c[M.user_index] += s;
+  *slot += s;
 }
 
 // dst = a * dst + src (zero_first: dst = src) over the D-compact state
@@ -1263,7 +1355,10 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   constexpr int EPT = COL_EPT;
   hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
 }
-static int rowp_fields(int op, int cl) { return op == OP_B ? 3 : (cl == 1 || cl == 3) ? 6 : 4; }
+static int rowp_fields(int op, int cl) {
+  const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
+  return op == OP_B ? 3 : op == OP_ADJ_RHS ? nbase + (cl == 0 ? 1 : 3) : nbase;
+}
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
   const size_t lds = ((size_t)nb * P.nx + P.nx / 2) * (dbl ? 16 : 8);
@@ -1279,7 +1374,7 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
-  if constexpr (OP == OP_RHS || OP == OP_B) {
+  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ADJ_RHS) {
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) { launch_rowp_t<T, OP, CL>(P, nmem, s); return; }
   }
   dim3 grid(P.ny / (2 * P.RP), 1, nmem);
@@ -1287,6 +1382,8 @@ static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
 }
 static int colfwdp_products(int op, int cl) {
   if (op == OP_RHS) return cl == 0 ? 1 : (cl == 3 || cl == 4) ? 6 : 3;
+  if (op == OP_ADJ_B) return 3;
+  if (op == OP_ADJ_RHS) return cl == 1 ? 6 : 4;
   return 1;
 }
 static bool colfwdp_ok(bool dbl, int op, int cl, const Phase& P) {
@@ -1304,7 +1401,8 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
-  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
+  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD || OP == OP_ADJ_B ||
+                OP == OP_ADJ_RHS) {
     if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) { launch_colfwdp_t<T, OP, CL>(P, nmem, s); return; }
   }
   dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
@@ -1370,6 +1468,11 @@ hipError_t launch_colinv(bool dbl, int op, int cl, const Phase& P, int n, hipStr
   if (dbl) colinv_dispatch<double>(op, cl, P, n, s); else colinv_dispatch<float>(op, cl, P, n, s);
   return hipGetLastError();
 }
+int row_launch_blocks(bool dbl, int op, int cl, const Phase& P) {
+  const bool par = (op == OP_RHS || op == OP_B || op == OP_ADJ_RHS) && rowp_ok(dbl, op, cl, P);
+  return par ? P.ny / 2 : P.ny / (2 * P.RP);
+}
+
 hipError_t launch_row(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
   if (dbl) row_dispatch<double>(op, cl, P, n, s); else row_dispatch<float>(op, cl, P, n, s);
   return hipGetLastError();

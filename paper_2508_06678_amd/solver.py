@@ -119,6 +119,16 @@ class Solver:
                                   _ptr(nu) if nu is not None else None, _stream(self.device)))
         return out.view(self.n, 8), nu
 
+    def set_coef(self, c):
+        """Closure coefficient c per member (sequence of floats)."""
+        c = [float(x) for x in c]
+        if len(c) != self.n:
+            raise ValueError("one coefficient per member")
+        arr = (ctypes.c_double * self.n)(*c)
+        _lib.check(self.L.qg_set_coef(self.h, arr, _stream(self.device)))
+        for p, v in zip(self.params, c):
+            p["c"] = v
+
     def autotune(self, cache_path=None):
         _lib.check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
                                       _stream(self.device)))

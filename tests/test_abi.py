@@ -1,0 +1,103 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/qg.h declares, and rejects invalid parameters with the documented
+status codes (qg_workspace_bytes validates exactly as qg_init does)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2508_06678_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "qg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.lib()
+    names = declared_functions()
+    assert {"qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def good(**kw):
+    d = dict(nx=128, ny=64, lx=2 * math.pi, ly=math.pi, beta=1.0, re=1e3, mu=0.0, u_in=1.0,
+             v_in=0.0, eta=1e-3, sponge_sigma=10.0, dt=2e-3, c=0.17, closure="smag",
+             precision=64, test_ratio=2, clip_mode=0, fp64_lowk=8)
+    d.update(kw)
+    return d
+
+
+def ws(params, adj=0):
+    L = _lib.lib()
+    arr = (_lib.QGParams * len(params))(*[_lib.make_params(p) for p in params])
+    size = ctypes.c_size_t(0)
+    rc = L.qg_workspace_bytes(arr, len(params), adj, ctypes.byref(size))
+    return rc, size.value
+
+
+def test_workspace_bytes_valid_and_monotone():
+    rc, b1 = ws([good()])
+    assert rc == 0 and b1 > 0
+    rc, b2 = ws([good(), good(nx=256, ny=128, closure="dleith")])
+    assert rc == 0 and b2 > b1
+    rc, b3 = ws([good()], adj=50)
+    assert rc == 0 and b3 > b1
+    rc, b4 = ws([good(precision=32)])
+    assert rc == 0 and b4 < b1
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=96), _lib.QG_EUNSUPPORTED),
+    (dict(nx=16, ny=16, lx=2 * math.pi, ly=2 * math.pi), _lib.QG_EUNSUPPORTED),
+    (dict(ly=2.0), _lib.QG_EUNSUPPORTED),
+    (dict(dt=0.0), _lib.QG_EINVAL),
+    (dict(dt=-1.0), _lib.QG_EINVAL),
+    (dict(closure=7), _lib.QG_EINVAL),
+    (dict(precision=16), _lib.QG_EINVAL),
+    (dict(clip_mode=1), _lib.QG_EUNSUPPORTED),
+    (dict(clip_mode=2), _lib.QG_EINVAL),
+    (dict(closure="dsmag", test_ratio=2.5), _lib.QG_EUNSUPPORTED),
+    (dict(eta=0.0), _lib.QG_EINVAL),
+    (dict(eta=-1.0), _lib.QG_EINVAL),
+    (dict(beta=float("nan")), _lib.QG_EINVAL),
+    (dict(sponge_sigma=-1.0), _lib.QG_EINVAL),
+])
+def test_invalid_parameters_are_rejected(bad, code):
+    rc, _ = ws([good(**bad)])
+    assert rc == code
+    msg = _lib.lib().qg_last_error().decode()
+    assert msg.startswith("member 0")
+
+
+def test_null_arguments():
+    L = _lib.lib()
+    assert L.qg_workspace_bytes(None, 1, 0, None) == _lib.QG_EINVAL
+    rc, _ = ws([])
+    assert rc == _lib.QG_EINVAL
+    h = ctypes.c_void_p()
+    assert L.qg_init(None, 0, None, None, None, 0, 0, None, ctypes.byref(h)) == _lib.QG_EINVAL
+    assert L.qg_step(None, None, 1, 0, None, 1, None) == _lib.QG_EINVAL
+    assert L.qg_diag(None, None, None, None, None) == _lib.QG_EINVAL
+    assert L.qg_adjoint_step(None, None, None, 1, None, None) == _lib.QG_EINVAL
+    assert L.qg_run_phase(None, 0, 1, 1, None) == _lib.QG_EINVAL
+    L.qg_destroy(None)
+
+
+def test_init_rejects_small_or_missing_workspace():
+    L = _lib.lib()
+    params = [good()]
+    arr = (_lib.QGParams * 1)(*[_lib.make_params(p) for p in params])
+    dummy = (ctypes.c_void_p * 1)(ctypes.c_void_p(256))
+    h = ctypes.c_void_p()
+    assert L.qg_init(arr, 1, dummy, dummy, None, 1 << 20, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
+    assert L.qg_init(arr, 1, dummy, dummy, ctypes.c_void_p(4096), 16, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
+    assert L.qg_init(arr, 1, dummy, dummy, ctypes.c_void_p(4097), 1 << 40, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
