@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--skip", default="", help="comma list of: fp64,batched,adjoint,cpu,phases")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,6 +162,14 @@ def main():
     from paper_2508_06678_amd import configs
 
     K, W = args.steps, args.warmup
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 268435456 bytes")
+        del src, dst
     wl = configs.config3(precision=32)
     nx, ny = wl.members[0].params["nx"], wl.members[0].params["ny"]
     pts = nx * ny

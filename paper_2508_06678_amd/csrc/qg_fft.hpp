@@ -182,6 +182,83 @@ __device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict
   else if (rem == 1) stockham_pass<V, 2, INV, EPT / 2>(buf, tw, s, logNs, g);
 }
 
+// ---------------------------------------------------------------------------
+// Single-vector transform of length N = 2^logN (32 <= N <= 4096) by a group
+// of N/8 threads, one vector per group, in a padded LDS buffer: element i
+// lives at pad8(i) = i + i/8, which spreads the stride-8 stores of the first
+// Stockham pass over all banks.  The first pass takes its 8 inputs
+// x[j + t N/8] (j = rank in the group) from registers, so callers that can
+// form the input directly (c2r from the mixed layout, products formed
+// pointwise) skip one LDS round trip.  Output: natural order, padded.
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
+template <typename V, bool INV>
+__device__ __forceinline__ void fft1_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active) {
+  if (active) dftR<V, 8, INV>(v);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) buf[9 * j + t] = v[t];
+  }
+  __syncthreads();
+}
+
+template <typename V, int R, bool INV>
+__device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restrict__ tw, int logN, int logNs, int j0,
+                                          int nt, bool active) {
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  constexpr int NB = 8 / R;   // butterflies per thread
+  const int logNR = logN - logR;
+  const int twshift = logN - logNs - logR;
+  const int half = 1 << (logN - 1);
+  V v[NB][R];
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = j0 + b * nt;
+      const int k = j & ((1 << logNs) - 1);
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[b][t] = buf[pad8(j + (t << logNR))];
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        const int idx = (t * k) << twshift;
+        V w = tw[idx & (half - 1)];
+        if (idx & half) w = cmake<V>(-w.x, -w.y);
+        if (INV) w = cconj(w);
+        v[b][t] = cmul(v[b][t], w);
+      }
+      dftR<V, R, INV>(v[b]);
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = j0 + b * nt;
+      const int k = j & ((1 << logNs) - 1);
+      const int base = ((j >> logNs) << (logNs + logR)) + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[pad8(base + (t << logNs))] = v[b][t];
+    }
+  }
+  __syncthreads();
+}
+
+// Passes after the first (the first is fft1_pass0, radix 8).
+template <typename V, bool INV>
+__device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restrict__ tw, int logN, int j, bool active) {
+  const int nt = 1 << (logN - 3);
+  int logNs = 3;
+  int rem = logN - 3;
+  while (rem >= 3) {
+    fft1_pass<V, 8, INV>(buf, tw, logN, logNs, j, nt, active);
+    logNs += 3;
+    rem -= 3;
+  }
+  if (rem == 2) fft1_pass<V, 4, INV>(buf, tw, logN, logNs, j, nt, active);
+  else if (rem == 1) fft1_pass<V, 2, INV>(buf, tw, logN, logNs, j, nt, active);
+}
+
 // The whole block as one group.
 template <typename V, bool INV, int EPT>
 __device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s) {

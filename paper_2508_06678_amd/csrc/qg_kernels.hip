@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
-  V* twl = tile + P.W * P.ny;
+  V* twl = tile + P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0);
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int f = blockIdx.y;
   const int kx0 = blockIdx.x * P.W;
@@ -163,6 +163,29 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   const int n = P.W * ny;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   const T scale = T(M.inv_n);
+  if (P.W == 1) {
+    // one column: padded single-vector transform, first pass from registers
+    const int j = threadIdx.x;
+    const int n8 = ny >> 3;
+    V v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int y = j + t * n8;
+      const int my = y < ny / 2 ? y : y - ny;
+      V z = cmake<V>(T(0), T(0));
+      if (kx0 < P.kxn && my <= P.myh && -my <= P.myh) {
+        const int iy = my >= 0 ? my : my + P.kyn;
+        z = cscale(colinv_value<T, OP, CL>(M, P, f, kx0, iy), scale);
+      }
+      v[t] = z;
+    }
+    __syncthreads();   // twiddles staged
+    fft1_pass0<V, true>(v, tile, j, true);
+    fft1_rest<V, true>(tile, twl, P.logny, j, true);
+    V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + (long long)kx0 * ny;
+    for (int y = j; y < ny; y += n8) out[y] = tile[pad8(y)];
+    return;
+  }
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const int w = q >> P.logny;
     const int y = q & (ny - 1);
@@ -194,9 +217,10 @@ template <typename T> struct RowCtx {
   int y0;            // first row of the block
 };
 
-// position of (y, kx) in a strip-major mixed field
-template <typename T> __device__ __forceinline__ long long mix_at(const RowCtx<T>& C, int y, int k) {
-  return (((long long)(k >> C.logW) * C.ny + y) << C.logW) + (k & ((1 << C.logW) - 1));
+// position of (y, kx) in a strip-major mixed field (fits in 32 bits: at
+// most 4096 rows x 1366 columns per field)
+template <typename T> __device__ __forceinline__ int mix_at(const RowCtx<T>& C, int y, int k) {
+  return (((k >> C.logW) * C.ny + y) << C.logW) + (k & ((1 << C.logW) - 1));
 }
 
 // c2r of field src (strip-major mixed layout) for the block's row
@@ -211,14 +235,14 @@ __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __rest
     const int ya = C.y0 + 2 * rp;
     V z = cmake<V>(T(0), T(0));
     if (k < C.kxn) {
-      const long long o = mix_at(C, ya, k);
+      const int o = mix_at(C, ya, k);
       V a = src[o];
       V b = src[o + (1 << C.logW)];
       if (k == 0) { a.y = T(0); b.y = T(0); }
       z = cmake<V>(a.x - b.y, a.y + b.x);
     } else if (k > C.nx - C.kxn) {
       const int kk = C.nx - k;
-      const long long o = mix_at(C, ya, kk);
+      const int o = mix_at(C, ya, kk);
       V a = src[o];
       V b = src[o + (1 << C.logW)];
       z = cmake<V>(a.x + b.y, b.x - a.y);
@@ -258,7 +282,7 @@ __device__ __forceinline__ void row_r2c(const RowCtx<T>& C, const cpx<T> (&val)[
       V zm = row[(C.nx - k) & (C.nx - 1)];
       V a = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
       V b = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
-      const long long o = mix_at(C, ya, k);
+      const int o = mix_at(C, ya, k);
       dst[o] = a;
       dst[o + (1 << C.logW)] = b;
     }
@@ -596,35 +620,37 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
 }
 
 // ---------------------------------------------------------------- row pass, field-parallel
-// Right-hand side and B sub-step: one block per row pair.  The nb fields of
-// a level (4, or 6 for the Smagorinsky family; u', v', omega for the B
-// sub-step) are taken to physical space at the same time by nb groups of
-// nx/8 threads, the products are formed point by point in LDS (J, h_x, h_y;
-// or the penalized and sponged vorticity), and transformed back by the
-// first groups.  Used whenever nb * nx / 8 <= 1024 threads and the nb rows
-// fit in LDS.
+// Right-hand side, B sub-step and adjoint right-hand side: one block per row
+// pair (.x row ya, .y row ya + 1).  The nb fields are taken to physical space
+// at the same time by nb groups of nx/8 threads (padded single-vector
+// transforms whose first pass is fed from the mixed layout directly); then
+// each of the first np groups forms one product at its own points straight
+// into the registers of its forward transform, and keeps the retained half
+// spectrum.  Products: J, h_x, h_y per level (right-hand side); the
+// penalized and sponged vorticity (B sub-step); l_u, l_v, l_wx, l_wy
+// [, l_pd, l_pxy] (adjoint).  Used whenever nb * nx / 8 <= 1024 threads and
+// the nb rows fit in LDS.
 template <typename T, int OP, int CL>
 __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int nbase = smag ? 6 : 4;
-  // fields: B sub-step u', v', omega; adjoint: the nbase forward fields of
-  // the stage input, then -l, -i kx l, -i ky l (only -l without closure)
   constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
   constexpr int levels = dyn ? 2 : 1;
   constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
-  __shared__ double red[16];
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int nx = P.nx;
+  const int bstride = nx + (nx >> 3);      // padded row buffer
   V* buf = reinterpret_cast<V*>(smem_raw);
-  V* twl = buf + nb * nx;
+  V* twl = buf + nb * bstride;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
-  const int lg = P.lognx - 3;              // log2 of the group size nx/8
+  const int lg = P.lognx - 3;
   const int grp = threadIdx.x >> lg;
-  const int lt = threadIdx.x & ((1 << lg) - 1);
-  const int gsz = 1 << lg;
+  const int j = threadIdx.x & ((1 << lg) - 1);
+  const int n8 = 1 << lg;
   int rb = blockIdx.x;
   if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int ya = 2 * rb;
@@ -634,120 +660,132 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   const V* mf = cptr<T>(M, P.o_mf);
   V* mp = cptr<T>(M, P.o_mp);
   const T U = T(M.u_in), Vv = T(M.v_in);
-  const FftShape sh{P.lognx, 1, nx, 0, false};
-  V* mybuf = buf + grp * nx;
-#pragma unroll 1
-  for (int lev = 0; lev < levels; ++lev) {
-    // c2r of field lev * nb + grp
+  V* mybuf = buf + grp * bstride;
+  __syncthreads();   // twiddles staged
+  auto F = [&](int f, int q) -> V { return buf[f * bstride + pad8(q)]; };
+  // the two levels of the dynamic closures (grid and test filter) are
+  // independent: one block each (grid.y)
+  const int lev = levels > 1 ? (int)blockIdx.y : 0;
+  {
+    // ---- c2r of field lev * nb + grp
     {
       const V* src = mf + (long long)(lev * nb + grp) * fstride;
-      for (int k = lt; k < nx; k += gsz) {
+      V v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = j + t * n8;
         V z = cmake<V>(T(0), T(0));
         if (k < P.kxn) {
-          const long long o = mix_at(C, ya, k);
+          const int o = mix_at(C, ya, k);
           V a = src[o];
           V b = src[o + (1 << C.logW)];
           if (k == 0) { a.y = T(0); b.y = T(0); }
           z = cmake<V>(a.x - b.y, a.y + b.x);
         } else if (k > nx - P.kxn) {
-          const long long o = mix_at(C, ya, nx - k);
+          const int o = mix_at(C, ya, nx - k);
           V a = src[o];
           V b = src[o + (1 << C.logW)];
           z = cmake<V>(a.x + b.y, b.x - a.y);
         }
-        mybuf[k] = z;
+        v[t] = z;
+      }
+      fft1_pass0<V, true>(v, mybuf, j, true);
+      fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
+    }
+    // ---- products at this thread's points q = j + t nx/8, for product grp
+    V v[8];
+    double dc = 0.0;
+    const bool act = grp < np;
+    if (act) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = j + t * n8;
+        V out;
+        if constexpr (OP == OP_B) {
+          // omega'' = S (E omega + E_x v - E_y u), total velocity
+          const long long nxy = (long long)nx * P.ny;
+          const T* E = rptr<T>(M, P.o_phys);
+          const V u = F(0, q), vv = F(1, q), w = F(2, q);
+          const long long a = (long long)ya * nx + q, b = a + nx;
+          const T w0 = E[a] * w.x + E[nxy + a] * (Vv + vv.x) - E[2 * nxy + a] * (U + u.x);
+          const T w1 = E[b] * w.y + E[nxy + b] * (Vv + vv.y) - E[2 * nxy + b] * (U + u.y);
+          out = cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
+        } else if constexpr (OP == OP_RHS) {
+          const V wx = F(2, q), wy = F(3, q);
+          if (grp == 0) {
+            const V u = F(0, q), vv = F(1, q);
+            out = vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + vv.x, Vv + vv.y), wy));
+          } else {
+            V base;
+            if constexpr (smag) {
+              const V pd = F(4, q), pxy = F(5, q);
+              base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+            } else {
+              base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+            }
+            out = vmul<T>(base, grp == 1 ? wx : wy);
+          }
+        } else {  // OP_ADJ_RHS
+          const V u = F(0, q), vv = F(1, q), wx = F(2, q), wy = F(3, q);
+          const V lJ = F(nbase, q);
+          V lu = vmul<T>(lJ, wx), lv = vmul<T>(lJ, wy);
+          V lwx = cmake<V>(lJ.x * (U + u.x), lJ.y * (U + u.y));
+          V lwy = cmake<V>(lJ.x * (Vv + vv.x), lJ.y * (Vv + vv.y));
+          V lpd = cmake<V>(T(0), T(0)), lpxy = lpd;
+          if constexpr (CL != 0) {
+            const T coef = T(M.coef_static);
+            const V gx = F(nbase + 1, q), gy = F(nbase + 2, q);
+            V base, pd, pxy;
+            if constexpr (smag) {
+              pd = F(4, q);
+              pxy = F(5, q);
+              base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+            } else {
+              base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+            }
+            if (grp == 0) {
+              dc += (double)(gx.x * base.x * wx.x + gy.x * base.x * wy.x);
+              dc += (double)(gx.y * base.y * wx.y + gy.y * base.y * wy.y);
+            }
+            const V lhx = cmake<V>(coef * gx.x, coef * gx.y);
+            const V lhy = cmake<V>(coef * gy.x, coef * gy.y);
+            lwx = vfma<T>(lhx, base, lwx);
+            lwy = vfma<T>(lhy, base, lwy);
+            const V lb = vadd<T>(vmul<T>(lhx, wx), vmul<T>(lhy, wy));
+            const T r0 = base.x > T(0) ? lb.x / base.x : T(0);
+            const T r1 = base.y > T(0) ? lb.y / base.y : T(0);
+            if constexpr (smag) {
+              lpd = cmake<V>(pd.x * r0, pd.y * r1);
+              lpxy = cmake<V>(T(4) * pxy.x * r0, T(4) * pxy.y * r1);
+            } else {
+              lwx = cmake<V>(lwx.x + wx.x * r0, lwx.y + wx.y * r1);
+              lwy = cmake<V>(lwy.x + wy.x * r0, lwy.y + wy.y * r1);
+            }
+          }
+          if (grp == 0) out = lu;
+          else if (grp == 1) out = lv;
+          else if (grp == 2) out = lwx;
+          else if (grp == 3) out = lwy;
+          else if (grp == 4) out = lpd;
+          else out = lpxy;
+        }
+        v[t] = out;
       }
     }
-    __syncthreads();
-    fft_lds<V, true, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, true});
-    // products at each point (.x row ya, .y row ya + 1)
     if constexpr (OP == OP_ADJ_RHS) {
-      // adjoint of J = u omega_x + v omega_y, h = base grad omega and base(.):
-      // products l_u, l_v, l_wx, l_wy [, l_pd, l_pxy]; partial sum of
-      // <grad l-part, h> for dL/dc
-      double dc = 0.0;
-      const T coef = T(M.coef_static);
-      for (int q = threadIdx.x; q < nx; q += blockDim.x) {
-        const V u = buf[q], v = buf[nx + q], wx = buf[2 * nx + q], wy = buf[3 * nx + q];
-        const V lJ = buf[nbase * nx + q];
-        V lu = vmul<T>(lJ, wx), lv = vmul<T>(lJ, wy);
-        V lwx = cmake<V>(lJ.x * (U + u.x), lJ.y * (U + u.y));
-        V lwy = cmake<V>(lJ.x * (Vv + v.x), lJ.y * (Vv + v.y));
-        V lpd, lpxy;
-        if constexpr (CL != 0) {
-          const V gx = buf[(nbase + 1) * nx + q], gy = buf[(nbase + 2) * nx + q];
-          V base, pd, pxy;
-          if constexpr (smag) {
-            pd = buf[4 * nx + q];
-            pxy = buf[5 * nx + q];
-            base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
-          } else {
-            base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
-          }
-          dc += (double)(gx.x * base.x * wx.x + gy.x * base.x * wy.x);
-          dc += (double)(gx.y * base.y * wx.y + gy.y * base.y * wy.y);
-          const V lhx = cmake<V>(coef * gx.x, coef * gx.y);
-          const V lhy = cmake<V>(coef * gy.x, coef * gy.y);
-          lwx = vfma<T>(lhx, base, lwx);
-          lwy = vfma<T>(lhy, base, lwy);
-          const V lb = vadd<T>(vmul<T>(lhx, wx), vmul<T>(lhy, wy));
-          const T r0 = base.x > T(0) ? lb.x / base.x : T(0);
-          const T r1 = base.y > T(0) ? lb.y / base.y : T(0);
-          if constexpr (smag) {
-            lpd = cmake<V>(pd.x * r0, pd.y * r1);
-            lpxy = cmake<V>(T(4) * pxy.x * r0, T(4) * pxy.y * r1);
-          } else {
-            lwx = cmake<V>(lwx.x + wx.x * r0, lwx.y + wx.y * r1);
-            lwy = cmake<V>(lwy.x + wy.x * r0, lwy.y + wy.y * r1);
-          }
-        }
-        buf[q] = lu;
-        buf[nx + q] = lv;
-        buf[2 * nx + q] = lwx;
-        buf[3 * nx + q] = lwy;
-        if constexpr (smag) {
-          buf[4 * nx + q] = lpd;
-          buf[5 * nx + q] = lpxy;
-        }
-      }
       const double sdc = block_sum(dc, red);
       if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
-    } else if constexpr (OP == OP_B) {
-      // omega'' = S (E omega + E_x v - E_y u), total velocity
-      const long long nxy = (long long)nx * P.ny;
-      const T* E = rptr<T>(M, P.o_phys);
-      for (int q = threadIdx.x; q < nx; q += blockDim.x) {
-        const V u = buf[q], v = buf[nx + q], w = buf[2 * nx + q];
-        const long long a = (long long)ya * nx + q, b = a + nx;
-        const T w0 = E[a] * w.x + E[nxy + a] * (Vv + v.x) - E[2 * nxy + a] * (U + u.x);
-        const T w1 = E[b] * w.y + E[nxy + b] * (Vv + v.y) - E[2 * nxy + b] * (U + u.y);
-        buf[q] = cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
-      }
-    } else
-    for (int q = threadIdx.x; q < nx; q += blockDim.x) {
-      const V u = buf[q], v = buf[nx + q], wx = buf[2 * nx + q], wy = buf[3 * nx + q];
-      const V J = vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + v.x, Vv + v.y), wy));
-      if constexpr (CL != 0) {
-        V base;
-        if constexpr (smag) {
-          const V pd = buf[4 * nx + q], pxy = buf[5 * nx + q];
-          base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
-        } else {
-          base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
-        }
-        buf[nx + q] = vmul<T>(base, wx);
-        buf[2 * nx + q] = vmul<T>(base, wy);
-      }
-      buf[q] = J;
     }
-    __syncthreads();
-    fft_lds<V, false, ROW_EPT>(mybuf, twl, sh, FftGroup{lt, gsz, grp < np});
-    if (grp < np) {
+    (void)levels;
+    // ---- r2c of product grp, keep m_x < kxn
+    fft1_pass0<V, false>(v, mybuf, j, act);
+    fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
+    if (act) {
       V* dst = mp + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * fstride;
-      for (int k = lt; k < P.kxn; k += gsz) {
-        const V z = mybuf[k];
-        const V zm = mybuf[(nx - k) & (nx - 1)];
-        const long long o = mix_at(C, ya, k);
+      for (int k = j; k < P.kxn; k += n8) {
+        const V z = mybuf[pad8(k)];
+        const V zm = mybuf[pad8((nx - k) & (nx - 1))];
+        const int o = mix_at(C, ya, k);
         dst[o] = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
         dst[o + (1 << C.logW)] = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
       }
@@ -1059,27 +1097,35 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
-  const int n = P.W * P.ny;
+  const bool one = P.W == 1;                // padded single-vector path
+  const int n = P.W * P.ny + (one ? P.ny / 8 : 0);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + np * n;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
-  const int lg = P.logW + P.logny - 3;     // log2 of the group size n/8
+  const int lg = P.logW + P.logny - 3;     // log2 of the group size W ny/8
   const int grp = threadIdx.x >> lg;
   const int lt = threadIdx.x & ((1 << lg) - 1);
   const int kx0 = blockIdx.x * P.W;
-  {
-    const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
+  const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
+  if (one) {
+    V v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = src[lt + (t << lg)];
+    __syncthreads();   // twiddles staged
+    fft1_pass0<V, false>(v, tile + grp * n, lt, true);
+    fft1_rest<V, false>(tile + grp * n, twl, P.logny, lt, true);
+  } else {
     V* dst = tile + grp * n;
-    for (int q = lt; q < n; q += (1 << lg)) dst[q] = src[q];
+    for (int q = lt; q < P.W * P.ny; q += (1 << lg)) dst[q] = src[q];
+    __syncthreads();
+    const FftShape sh{P.logny, P.W, 1, P.logW, true};
+    fft_lds<V, false, COL_EPT>(tile + grp * n, twl, sh, FftGroup{lt, 1 << lg, true});
   }
-  __syncthreads();
-  const FftShape sh{P.logny, P.W, 1, P.logW, true};
-  fft_lds<V, false, COL_EPT>(tile + grp * n, twl, sh, FftGroup{lt, 1 << lg, true});
-  // tile[p * n + y * W + w]: product p at (m_y of row y, kx0 + w)
+  // product p at (m_y of row y, kx0 + w)
   auto at = [&](int p, int w, int iy) -> V {
     const int my = my_of_iy(iy, P.myh, P.kyn);
     const int y = my >= 0 ? my : my + P.ny;
-    return tile[p * n + y * P.W + w];
+    return one ? tile[p * n + pad8(y)] : tile[p * n + y * P.W + w];
   };
   const int nm = P.W * P.kyn;
   double hm = 0.0, mm = 0.0;
@@ -1345,7 +1391,8 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 }
 
 // ---------------------------------------------------------------- launchers
-static size_t col_smem(bool dbl, const Phase& P) { return ((size_t)P.W * P.ny + P.ny / 2) * (dbl ? 16 : 8); }
+static size_t col_tile(const Phase& P) { return (size_t)P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0); }
+static size_t col_smem(bool dbl, const Phase& P) { return (col_tile(P) + P.ny / 2) * (dbl ? 16 : 8); }
 static size_t row_smem(bool dbl, const Phase& P) { return ((size_t)P.RP * P.nx + P.nx / 2) * (dbl ? 16 : 8); }
 static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
 
@@ -1359,17 +1406,19 @@ static int rowp_fields(int op, int cl) {
   const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
   return op == OP_B ? 3 : op == OP_ADJ_RHS ? nbase + (cl == 0 ? 1 : 3) : nbase;
 }
+static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
+  return ((size_t)rowp_fields(op, cl) * (P.nx + P.nx / 8) + P.nx / 2) * (dbl ? 16 : 8);
+}
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
-  const size_t lds = ((size_t)nb * P.nx + P.nx / 2) * (dbl ? 16 : 8);
-  return P.nx >= 64 && nb * P.nx / 8 <= 1024 && lds <= 128 * 1024;
+  return P.nx >= 64 && nb * P.nx / 8 <= 1024 && rowp_lds(dbl, op, cl, P) <= 128 * 1024;
 }
 template <typename T, int OP, int CL>
 static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int nb = rowp_fields(OP, CL);
-  dim3 grid(P.ny / 2, 1, nmem);
-  const size_t lds = ((size_t)nb * P.nx + P.nx / 2) * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_rowp<T, OP, CL>), grid, dim3(nb * P.nx / 8), lds, s, P);
+  const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
+  dim3 grid(P.ny / 2, levels, nmem);
+  hipLaunchKernelGGL((k_rowp<T, OP, CL>), grid, dim3(nb * P.nx / 8), rowp_lds(sizeof(T) == 8, OP, CL, P), s, P);
 }
 
 template <typename T, int OP, int CL>
@@ -1388,15 +1437,16 @@ static int colfwdp_products(int op, int cl) {
 }
 static bool colfwdp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int np = colfwdp_products(op, cl);
-  const size_t n = (size_t)P.W * P.ny;
-  return np * n / COL_EPT <= 1024 && (np * n + P.ny / 2) * (dbl ? 16 : 8) <= 128 * 1024;
+  const size_t n = col_tile(P);
+  return np * ((size_t)P.W * P.ny) / COL_EPT <= 1024 && (np * n + P.ny / 2) * (dbl ? 16 : 8) <= 128 * 1024;
 }
 template <typename T, int OP, int CL>
 static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
   const int np = colfwdp_products(OP, CL);
   dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
-  const size_t n = (size_t)P.W * P.ny;
-  hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * n / COL_EPT), (np * n + P.ny / 2) * sizeof(cpx<T>), s, P);
+  const size_t n = col_tile(P);
+  hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * ((size_t)P.W * P.ny) / COL_EPT),
+                     (np * n + P.ny / 2) * sizeof(cpx<T>), s, P);
 }
 
 template <typename T, int OP, int CL>
