@@ -27,6 +27,7 @@ class QGRollout(torch.autograd.Function):
         ctx.segment = segment
         ctx.nseg = nseg
         ctx.c_dtype = c.dtype
+        ctx.c_device = c.device
         ctx.save_for_backward(omega0.detach().clone(), ckpt)
         return omega
 
@@ -39,4 +40,4 @@ class QGRollout(torch.autograd.Function):
         for j in range(ctx.nseg - 1, -1, -1):
             start = omega0 if j == 0 else ckpt[(j - 1) * S.total:j * S.total]
             S.adjoint_step(start.contiguous(), lam, ctx.segment, gc)
-        return lam, gc.to(ctx.c_dtype), None, None, None
+        return lam, gc.to(device=ctx.c_device, dtype=ctx.c_dtype), None, None, None

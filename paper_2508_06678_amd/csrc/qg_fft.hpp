@@ -259,6 +259,154 @@ __device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restri
   else if (rem == 1) fft1_pass<V, 2, INV>(buf, tw, logN, logNs, j, nt, active);
 }
 
+// ---------------------------------------------------------------------------
+// Radix-16 single-vector transform for N >= 256: a group of N/16 threads
+// (one wave at N = 1024), 16 elements per thread, passes 16, 16, then 16/8/4/2
+// for what remains; padded LDS (one slot per 16 elements).  The twiddles of
+// every pass after the first depend only on the thread's rank, so they are
+// read once per kernel into a Tw16 register set and reused by every
+// transform of that length in the kernel.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+// Length-16 DFT in registers as 4 x 4: inner length-4 DFTs over n1 of
+// x[4 n1 + n2], twiddles w16^(n2 k1), outer length-4 DFTs over n2; output in
+// natural order.
+template <typename V, bool INV> __device__ __forceinline__ void dft16(V* v) {
+  using T = decltype(V{}.x);
+  const T c1 = T(0.92387953251128675612818318939678828682);   // cos(pi/8)
+  const T s1 = T(0.38268343236508977172845998403039886676);   // sin(pi/8)
+  const T h = T(0.70710678118654752440084436210484903928);
+  V y[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    V a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+    dft4<V, INV>(a0, a1, a2, a3);
+    y[n2 * 4 + 0] = a0; y[n2 * 4 + 1] = a1; y[n2 * 4 + 2] = a2; y[n2 * 4 + 3] = a3;
+  }
+  // twiddles w16^(n2 k1) (forward: exp(-2 pi i m/16); inverse: conjugate)
+  const T sg = INV ? T(1) : T(-1);
+  auto tw = [&](V a, T c, T s) { return cmake<V>(a.x * c - a.y * sg * s, a.x * sg * s + a.y * c); };
+  y[1 * 4 + 1] = tw(y[5], c1, s1);          // m = 1
+  y[1 * 4 + 2] = tw(y[6], h, h);            // m = 2
+  y[1 * 4 + 3] = tw(y[7], s1, c1);          // m = 3
+  y[2 * 4 + 1] = tw(y[9], h, h);            // m = 2
+  y[2 * 4 + 2] = INV ? cmul_i(y[10]) : cmul_mi(y[10]);   // m = 4
+  y[2 * 4 + 3] = tw(y[11], -h, h);          // m = 6
+  y[3 * 4 + 1] = tw(y[13], s1, c1);         // m = 3
+  y[3 * 4 + 2] = tw(y[14], -h, h);          // m = 6
+  y[3 * 4 + 3] = tw(y[15], -c1, -s1);       // m = 9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    V b0 = y[k1], b1 = y[4 + k1], b2 = y[8 + k1], b3 = y[12 + k1];
+    dft4<V, INV>(b0, b1, b2, b3);
+    v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
+  }
+}
+
+template <typename V, int R, bool INV> __device__ __forceinline__ void dftR16(V* v) {
+  if constexpr (R == 16) dft16<V, INV>(v);
+  else dftR<V, R, INV>(v);
+}
+
+// Compile-time schedule for length 2^LOGN (LOGN >= 8): after the first
+// radix-16 pass, radix 16 while >= 4 bits remain, then one pass of 8/4/2.
+template <int LOGN> struct Sched16 {
+  static constexpr int rem(int p) { return LOGN - 4 - 4 * p; }             // bits left before pass p+1
+  static constexpr int logR(int p) { return rem(p) >= 4 ? 4 : rem(p); }
+  static constexpr int npass = (LOGN - 4 + 3) / 4;                           // passes after the first
+  static constexpr int logNs(int p) { return 4 + 4 * p; }
+};
+
+// Twiddle registers of the passes after the first: 15 per pass (radix 16:
+// one butterfly of 15 twiddles; radix R < 16: 16/R butterflies of R-1).
+template <typename V, int LOGN> struct Tw16 {
+  V w[Sched16<LOGN>::npass][15];
+};
+
+template <typename V, int LOGN>
+__device__ __forceinline__ void tw16_load(Tw16<V, LOGN>& T16, const V* __restrict__ tw, int j) {
+  using S = Sched16<LOGN>;
+  constexpr int half = 1 << (LOGN - 1);
+  constexpr int nt = 1 << (LOGN - 4);
+#pragma unroll
+  for (int p = 0; p < S::npass; ++p) {
+    const int logR = S::logR(p);
+    const int R = 1 << logR;
+    const int nb = 16 / R;
+    const int logNs = S::logNs(p);
+    const int twshift = LOGN - logNs - logR;
+#pragma unroll
+    for (int b = 0; b < nb; ++b) {
+      const int k = (j + b * nt) & ((1 << logNs) - 1);
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        const int idx = (t * k) << twshift;
+        V w = tw[idx & (half - 1)];
+        if (idx & half) w = cmake<V>(-w.x, -w.y);
+        T16.w[p][b * (R - 1) + (t - 1)] = w;
+      }
+    }
+  }
+}
+
+template <typename V, bool INV>
+__device__ __forceinline__ void fft16_pass0(V (&v)[16], V* __restrict__ buf, int j, bool active) {
+  if (active) dft16<V, INV>(v);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) buf[17 * j + t] = v[t];
+  }
+  __syncthreads();
+}
+
+template <typename V, int LOGN, int P, bool INV>
+__device__ __forceinline__ void fft16_pass(V* __restrict__ buf, const Tw16<V, LOGN>& T16, int j0, bool active) {
+  using S = Sched16<LOGN>;
+  constexpr int logR = S::logR(P);
+  constexpr int R = 1 << logR;
+  constexpr int NB = 16 / R;
+  constexpr int nt = 1 << (LOGN - 4);
+  constexpr int logNR = LOGN - logR;
+  constexpr int logNs = S::logNs(P);
+  V v[NB][R];
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = j0 + b * nt;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[b][t] = buf[pad16(j + (t << logNR))];
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        V w = T16.w[P][b * (R - 1) + (t - 1)];
+        if (INV) w = cconj(w);
+        v[b][t] = cmul(v[b][t], w);
+      }
+      dftR16<V, R, INV>(v[b]);
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = j0 + b * nt;
+      const int k = j & ((1 << logNs) - 1);
+      const int base = ((j >> logNs) << (logNs + logR)) + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[pad16(base + (t << logNs))] = v[b][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename V, int LOGN, bool INV, int P = 0>
+__device__ __forceinline__ void fft16_rest(V* __restrict__ buf, const Tw16<V, LOGN>& T16, int j, bool active) {
+  if constexpr (P < Sched16<LOGN>::npass) {
+    fft16_pass<V, LOGN, P, INV>(buf, T16, j, active);
+    fft16_rest<V, LOGN, INV, P + 1>(buf, T16, j, active);
+  }
+}
+
 // The whole block as one group.
 template <typename V, bool INV, int EPT>
 __device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict__ tw, const FftShape& s) {

@@ -622,175 +622,195 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
 // ---------------------------------------------------------------- row pass, field-parallel
 // Right-hand side, B sub-step and adjoint right-hand side: one block per row
 // pair (.x row ya, .y row ya + 1).  The nb fields are taken to physical space
-// at the same time by nb groups of nx/8 threads (padded single-vector
-// transforms whose first pass is fed from the mixed layout directly); then
-// each of the first np groups forms one product at its own points straight
-// into the registers of its forward transform, and keeps the retained half
-// spectrum.  Products: J, h_x, h_y per level (right-hand side); the
-// penalized and sponged vorticity (B sub-step); l_u, l_v, l_wx, l_wy
-// [, l_pd, l_pxy] (adjoint).  Used whenever nb * nx / 8 <= 1024 threads and
-// the nb rows fit in LDS.
-template <typename T, int OP, int CL>
-__global__ void __launch_bounds__(1024) k_rowp(Phase P) {
+// at the same time by nb groups of threads (padded single-vector transforms
+// whose first pass is fed from the mixed layout directly); then each of the
+// first np groups forms one product at its own points straight into the
+// registers of its forward transform, and keeps the retained half spectrum.
+// Products: J, h_x, h_y per level (right-hand side); the penalized and
+// sponged vorticity (B sub-step); l_u, l_v, l_wx, l_wy [, l_pd, l_pxy]
+// (adjoint).  LOGN = 0: radix-8 engine, nx/8 threads per group, any nx;
+// LOGN = log2(nx): radix-16 engine, nx/16 threads per group, twiddles in
+// registers.
+
+// one product at point q; dc accumulates the dL/dc integrand (adjoint)
+template <typename T, int OP, int CL, int PADS>
+__device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& P, const cpx<T>* buf, int bstride,
+                                               int q, int grp, int ya, double& dc) {
+  using V = cpx<T>;
+  constexpr bool smag = (CL == 1 || CL == 3);
+  constexpr int nbase = smag ? 6 : 4;
+  const int nx = P.nx;
+  const T U = T(M.u_in), Vv = T(M.v_in);
+  auto F = [&](int f) -> V { return buf[f * bstride + q + (q >> PADS)]; };
+  if constexpr (OP == OP_B) {
+    // omega'' = S (E omega + E_x v - E_y u), total velocity
+    const long long nxy = (long long)nx * P.ny;
+    const T* E = rptr<T>(M, P.o_phys);
+    const V u = F(0), vv = F(1), w = F(2);
+    const long long a = (long long)ya * nx + q, b = a + nx;
+    const T w0 = E[a] * w.x + E[nxy + a] * (Vv + vv.x) - E[2 * nxy + a] * (U + u.x);
+    const T w1 = E[b] * w.y + E[nxy + b] * (Vv + vv.y) - E[2 * nxy + b] * (U + u.y);
+    return cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
+  } else if constexpr (OP == OP_RHS) {
+    const V wx = F(2), wy = F(3);
+    if (grp == 0) {
+      const V u = F(0), vv = F(1);
+      return vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + vv.x, Vv + vv.y), wy));
+    }
+    V base;
+    if constexpr (smag) {
+      const V pd = F(4), pxy = F(5);
+      base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+    } else {
+      base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+    }
+    return vmul<T>(base, grp == 1 ? wx : wy);
+  } else {  // OP_ADJ_RHS
+    const V u = F(0), vv = F(1), wx = F(2), wy = F(3);
+    const V lJ = F(nbase);
+    if (grp == 0 && CL == 0) return vmul<T>(lJ, wx);
+    if (grp == 1 && CL == 0) return vmul<T>(lJ, wy);
+    V lwx = cmake<V>(lJ.x * (U + u.x), lJ.y * (U + u.y));
+    V lwy = cmake<V>(lJ.x * (Vv + vv.x), lJ.y * (Vv + vv.y));
+    V lpd = cmake<V>(T(0), T(0)), lpxy = lpd;
+    if constexpr (CL != 0) {
+      const T coef = T(M.coef_static);
+      const V gx = F(nbase + 1), gy = F(nbase + 2);
+      V base, pd, pxy;
+      if constexpr (smag) {
+        pd = F(4);
+        pxy = F(5);
+        base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
+      } else {
+        base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
+      }
+      if (grp == 0) {
+        dc += (double)(gx.x * base.x * wx.x + gy.x * base.x * wy.x);
+        dc += (double)(gx.y * base.y * wx.y + gy.y * base.y * wy.y);
+        return vmul<T>(lJ, wx);
+      }
+      if (grp == 1) return vmul<T>(lJ, wy);
+      const V lhx = cmake<V>(coef * gx.x, coef * gx.y);
+      const V lhy = cmake<V>(coef * gy.x, coef * gy.y);
+      lwx = vfma<T>(lhx, base, lwx);
+      lwy = vfma<T>(lhy, base, lwy);
+      const V lb = vadd<T>(vmul<T>(lhx, wx), vmul<T>(lhy, wy));
+      const T r0 = base.x > T(0) ? lb.x / base.x : T(0);
+      const T r1 = base.y > T(0) ? lb.y / base.y : T(0);
+      if constexpr (smag) {
+        lpd = cmake<V>(pd.x * r0, pd.y * r1);
+        lpxy = cmake<V>(T(4) * pxy.x * r0, T(4) * pxy.y * r1);
+      } else {
+        lwx = cmake<V>(lwx.x + wx.x * r0, lwx.y + wx.y * r1);
+        lwy = cmake<V>(lwy.x + wy.x * r0, lwy.y + wy.y * r1);
+      }
+    }
+    if (grp == 2) return lwx;
+    if (grp == 3) return lwy;
+    if (grp == 4) return lpd;
+    return lpxy;
+  }
+}
+
+// c2r input at column k of the packed row pair, from the mixed layout
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_input(const RowCtx<T>& C, const cpx<T>* src, int ya, int k, int nx, int kxn) {
+  using V = cpx<T>;
+  if (k < kxn) {
+    const int o = mix_at(C, ya, k);
+    V a = src[o];
+    V b = src[o + (1 << C.logW)];
+    if (k == 0) { a.y = T(0); b.y = T(0); }
+    return cmake<V>(a.x - b.y, a.y + b.x);
+  }
+  if (k > nx - kxn) {
+    const int o = mix_at(C, ya, nx - k);
+    const V a = src[o];
+    const V b = src[o + (1 << C.logW)];
+    return cmake<V>(a.x + b.y, b.x - a.y);
+  }
+  return cmake<V>(T(0), T(0));
+}
+
+template <typename T, int OP, int CL, int LOGN>
+__global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int nbase = smag ? 6 : 4;
   constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
-  constexpr int levels = dyn ? 2 : 1;
   constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
+  constexpr int EPT = LOGN ? 16 : 8;           // points per thread
+  constexpr int PADS = LOGN ? 4 : 3;           // one pad slot per 2^PADS
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int nx = P.nx;
-  const int bstride = nx + (nx >> 3);      // padded row buffer
+  const int bstride = nx + (nx >> PADS);
   V* buf = reinterpret_cast<V*>(smem_raw);
   V* twl = buf + nb * bstride;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
-  const int lg = P.lognx - 3;
+  const int lg = P.lognx - (LOGN ? 4 : 3);
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
-  const int n8 = 1 << lg;
+  const int ng = 1 << lg;                      // threads per group
   int rb = blockIdx.x;
   if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int ya = 2 * rb;
   RowCtx<T> C;
   C.ny = P.ny; C.logW = P.logW;
   const long long fstride = (long long)P.ny * P.kxp;
-  const V* mf = cptr<T>(M, P.o_mf);
-  V* mp = cptr<T>(M, P.o_mp);
-  const T U = T(M.u_in), Vv = T(M.v_in);
   V* mybuf = buf + grp * bstride;
-  __syncthreads();   // twiddles staged
-  auto F = [&](int f, int q) -> V { return buf[f * bstride + pad8(q)]; };
   // the two levels of the dynamic closures (grid and test filter) are
   // independent: one block each (grid.y)
-  const int lev = levels > 1 ? (int)blockIdx.y : 0;
+  const int lev = dyn ? (int)blockIdx.y : 0;
+  __syncthreads();   // twiddles staged
+  Tw16<V, (LOGN ? LOGN : 8)> T16;
+  if constexpr (LOGN != 0) tw16_load<V, LOGN>(T16, twl, j);
+  // ---- c2r of field lev * nb + grp
   {
-    // ---- c2r of field lev * nb + grp
-    {
-      const V* src = mf + (long long)(lev * nb + grp) * fstride;
-      V v[8];
+    const V* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
+    V v[EPT];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = j + t * n8;
-        V z = cmake<V>(T(0), T(0));
-        if (k < P.kxn) {
-          const int o = mix_at(C, ya, k);
-          V a = src[o];
-          V b = src[o + (1 << C.logW)];
-          if (k == 0) { a.y = T(0); b.y = T(0); }
-          z = cmake<V>(a.x - b.y, a.y + b.x);
-        } else if (k > nx - P.kxn) {
-          const int o = mix_at(C, ya, nx - k);
-          V a = src[o];
-          V b = src[o + (1 << C.logW)];
-          z = cmake<V>(a.x + b.y, b.x - a.y);
-        }
-        v[t] = z;
-      }
+    for (int t = 0; t < EPT; ++t) v[t] = c2r_input<T>(C, src, ya, j + t * ng, nx, P.kxn);
+    if constexpr (LOGN != 0) {
+      fft16_pass0<V, true>(v, mybuf, j, true);
+      fft16_rest<V, LOGN, true>(mybuf, T16, j, true);
+    } else {
       fft1_pass0<V, true>(v, mybuf, j, true);
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
     }
-    // ---- products at this thread's points q = j + t nx/8, for product grp
-    V v[8];
-    double dc = 0.0;
-    const bool act = grp < np;
-    if (act) {
+  }
+  // ---- product grp at this thread's points q = j + t ng
+  V v[EPT];
+  double dc = 0.0;
+  const bool act = grp < np;
+  if (act) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int q = j + t * n8;
-        V out;
-        if constexpr (OP == OP_B) {
-          // omega'' = S (E omega + E_x v - E_y u), total velocity
-          const long long nxy = (long long)nx * P.ny;
-          const T* E = rptr<T>(M, P.o_phys);
-          const V u = F(0, q), vv = F(1, q), w = F(2, q);
-          const long long a = (long long)ya * nx + q, b = a + nx;
-          const T w0 = E[a] * w.x + E[nxy + a] * (Vv + vv.x) - E[2 * nxy + a] * (U + u.x);
-          const T w1 = E[b] * w.y + E[nxy + b] * (Vv + vv.y) - E[2 * nxy + b] * (U + u.y);
-          out = cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
-        } else if constexpr (OP == OP_RHS) {
-          const V wx = F(2, q), wy = F(3, q);
-          if (grp == 0) {
-            const V u = F(0, q), vv = F(1, q);
-            out = vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + vv.x, Vv + vv.y), wy));
-          } else {
-            V base;
-            if constexpr (smag) {
-              const V pd = F(4, q), pxy = F(5, q);
-              base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
-            } else {
-              base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
-            }
-            out = vmul<T>(base, grp == 1 ? wx : wy);
-          }
-        } else {  // OP_ADJ_RHS
-          const V u = F(0, q), vv = F(1, q), wx = F(2, q), wy = F(3, q);
-          const V lJ = F(nbase, q);
-          V lu = vmul<T>(lJ, wx), lv = vmul<T>(lJ, wy);
-          V lwx = cmake<V>(lJ.x * (U + u.x), lJ.y * (U + u.y));
-          V lwy = cmake<V>(lJ.x * (Vv + vv.x), lJ.y * (Vv + vv.y));
-          V lpd = cmake<V>(T(0), T(0)), lpxy = lpd;
-          if constexpr (CL != 0) {
-            const T coef = T(M.coef_static);
-            const V gx = F(nbase + 1, q), gy = F(nbase + 2, q);
-            V base, pd, pxy;
-            if constexpr (smag) {
-              pd = F(4, q);
-              pxy = F(5, q);
-              base = cmake<V>(strain<T>(pxy.x, pd.x), strain<T>(pxy.y, pd.y));
-            } else {
-              base = cmake<V>(gradmag<T>(wx.x, wy.x), gradmag<T>(wx.y, wy.y));
-            }
-            if (grp == 0) {
-              dc += (double)(gx.x * base.x * wx.x + gy.x * base.x * wy.x);
-              dc += (double)(gx.y * base.y * wx.y + gy.y * base.y * wy.y);
-            }
-            const V lhx = cmake<V>(coef * gx.x, coef * gx.y);
-            const V lhy = cmake<V>(coef * gy.x, coef * gy.y);
-            lwx = vfma<T>(lhx, base, lwx);
-            lwy = vfma<T>(lhy, base, lwy);
-            const V lb = vadd<T>(vmul<T>(lhx, wx), vmul<T>(lhy, wy));
-            const T r0 = base.x > T(0) ? lb.x / base.x : T(0);
-            const T r1 = base.y > T(0) ? lb.y / base.y : T(0);
-            if constexpr (smag) {
-              lpd = cmake<V>(pd.x * r0, pd.y * r1);
-              lpxy = cmake<V>(T(4) * pxy.x * r0, T(4) * pxy.y * r1);
-            } else {
-              lwx = cmake<V>(lwx.x + wx.x * r0, lwx.y + wx.y * r1);
-              lwy = cmake<V>(lwy.x + wy.x * r0, lwy.y + wy.y * r1);
-            }
-          }
-          if (grp == 0) out = lu;
-          else if (grp == 1) out = lv;
-          else if (grp == 2) out = lwx;
-          else if (grp == 3) out = lwy;
-          else if (grp == 4) out = lpd;
-          else out = lpxy;
-        }
-        v[t] = out;
-      }
-    }
-    if constexpr (OP == OP_ADJ_RHS) {
-      const double sdc = block_sum(dc, red);
-      if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
-    }
-    (void)levels;
-    // ---- r2c of product grp, keep m_x < kxn
+    for (int t = 0; t < EPT; ++t) v[t] = rowp_product<T, OP, CL, PADS>(M, P, buf, bstride, j + t * ng, grp, ya, dc);
+  }
+  if constexpr (OP == OP_ADJ_RHS) {
+    const double sdc = block_sum(dc, red);
+    if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
+  }
+  // ---- r2c of product grp, keep m_x < kxn
+  if constexpr (LOGN != 0) {
+    fft16_pass0<V, false>(v, mybuf, j, act);
+    fft16_rest<V, LOGN, false>(mybuf, T16, j, act);
+  } else {
     fft1_pass0<V, false>(v, mybuf, j, act);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
-    if (act) {
-      V* dst = mp + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * fstride;
-      for (int k = j; k < P.kxn; k += n8) {
-        const V z = mybuf[pad8(k)];
-        const V zm = mybuf[pad8((nx - k) & (nx - 1))];
-        const int o = mix_at(C, ya, k);
-        dst[o] = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
-        dst[o + (1 << C.logW)] = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
-      }
+  }
+  if (act) {
+    V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * fstride;
+    for (int k = j; k < P.kxn; k += ng) {
+      const int a = k, b = (nx - k) & (nx - 1);
+      const V z = mybuf[a + (a >> PADS)];
+      const V zm = mybuf[b + (b >> PADS)];
+      const int o = mix_at(C, ya, k);
+      dst[o] = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
+      dst[o + (1 << C.logW)] = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
     }
-    __syncthreads();
   }
 }
 
@@ -1406,8 +1426,13 @@ static int rowp_fields(int op, int cl) {
   const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
   return op == OP_B ? 3 : op == OP_ADJ_RHS ? nbase + (cl == 0 ? 1 : 3) : nbase;
 }
+// Radix-16 row engine (16 points per thread, twiddles in registers).  It
+// needs ~160 VGPRs and measured slower than the radix-8 engine at 1024 on
+// gfx950 (3 vs 6 waves per SIMD), so it is kept selectable but not chosen.
+static int rowp_logn16(bool, const Phase&) { return 0; }
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
-  return ((size_t)rowp_fields(op, cl) * (P.nx + P.nx / 8) + P.nx / 2) * (dbl ? 16 : 8);
+  const int pads = rowp_logn16(dbl, P) ? 4 : 3;
+  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> pads)) + P.nx / 2) * (dbl ? 16 : 8);
 }
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
@@ -1418,7 +1443,13 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int nb = rowp_fields(OP, CL);
   const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
   dim3 grid(P.ny / 2, levels, nmem);
-  hipLaunchKernelGGL((k_rowp<T, OP, CL>), grid, dim3(nb * P.nx / 8), rowp_lds(sizeof(T) == 8, OP, CL, P), s, P);
+  const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
+  if (rowp_logn16(sizeof(T) == 8, P) == 10) {
+    if constexpr (sizeof(T) == 4)
+      hipLaunchKernelGGL((k_rowp<T, OP, CL, 10>), grid, dim3(nb * P.nx / 16), lds, s, P);
+    return;
+  }
+  hipLaunchKernelGGL((k_rowp<T, OP, CL, 0>), grid, dim3(nb * P.nx / 8), lds, s, P);
 }
 
 template <typename T, int OP, int CL>

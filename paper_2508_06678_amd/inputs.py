@@ -97,6 +97,12 @@ def spectrum_noise(nx, ny, lx, ly, seed, kmin=4.0, rms=0.1):
     return _rms_scaled(np.fft.irfft2(spec, s=(ny, nx)), rms)
 
 
+def smooth_directions(nx, ny, lx, ly, count, seed, kmax=32.0):
+    """Random perturbation fields of the resolved scales (1 <= |k| <= kmax)
+    with unit rms per grid point, for finite-difference checks."""
+    return [bandpass_noise(nx, ny, lx, ly, seed * 1000 + i, 1.0, kmax, 1.0) for i in range(count)]
+
+
 def random_directions(shape, count, seed):
     """Unit-norm random directions for finite-difference checks."""
     rng = np.random.default_rng(seed)
