@@ -118,7 +118,7 @@ def make_solver(workload, precision, adj=0, tune=True):
     S = Solver(params, chi, chs, adj_segment_k=adj)
     if tune:
         S.autotune()
-        log(f"  strip widths {sorted(set(S.column_widths()))}")
+        log(f"  strip widths fwd {sorted(set(S.column_widths()))} inv {sorted(set(S.inverse_widths()))}")
     om = S.pack([m.omega0 for m in workload.members])
     return S, om
 

@@ -163,9 +163,11 @@ int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
  * handle is launched; phase 3 is skipped for static closures. */
 int qg_run_phase(qg_handle* h, int32_t phase, int32_t stage, int32_t reps, void* hip_stream);
 
-/* Number of members, total grid points, and the tiling chosen per member. */
+/* Number of members, total grid points, and the tiling chosen per member:
+ * strip width of the column-forward and of the column-inverse passes
+ * (each output array nullable, n_members entries). */
 int qg_info(const qg_handle* h, int32_t* n_members, int64_t* total_points,
-            int32_t* col_width_out /* n_members, nullable */);
+            int32_t* fwd_width_out, int32_t* inv_width_out);
 
 void qg_destroy(qg_handle* h);
 const char* qg_last_error(void);

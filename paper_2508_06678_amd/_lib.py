@@ -56,7 +56,8 @@ def lib():
     L.qg_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     L.qg_run_phase.argtypes = [vp, i32, i32, i32, vp]
     L.qg_set_coef.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
-    L.qg_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.qg_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                          ctypes.POINTER(i32)]
     L.qg_destroy.argtypes = [vp]
     L.qg_destroy.restype = None
     L.qg_last_error.argtypes = []

@@ -71,6 +71,7 @@ struct Group {
   bool dbl;
   int kxn, myh, kyn, W, logW, kxp, RP, logRP;
   int kxn_f, myh_f, kyn_f, kxp_f;
+  int Wi, logWi, mfp, mfp_f;     // column-inverse strip width, MF row pitch
   int nstrips, nstrips_f, nrow, nspec;
   int m0, count;                 // slice of the device member table
   std::vector<int> users;        // caller indices of the members
@@ -88,6 +89,11 @@ struct Group {
 static int max_width(const Group& g) { return std::max(1, std::min(16, col_tile_elems(g.dbl) / g.ny)); }
 static int min_width(const Group& g) { return std::max(1, std::min(max_width(g), 512 / g.ny)); }
 
+static void set_inv_width(Group& g, int Wi) {
+  g.Wi = Wi;
+  g.logWi = ilog2(Wi);
+}
+
 static void set_width(Group& g, int W) {
   g.W = W;
   g.logW = ilog2(W);
@@ -104,6 +110,13 @@ static int default_width(const Group& g, int count) {
   while (W > min_width(g) && (long long)((g.kxn + W - 1) / W) * count < 512) W >>= 1;
   return W;
 }
+// column-inverse: one block per (strip, field), so wider strips keep enough
+// blocks; wide strips make the scattered MF row stores longer.
+static int default_inv_width(const Group& g, int count) {
+  int W = max_width(g);
+  while (W > min_width(g) && (long long)((g.kxn + W - 1) / W) * count * rhs_fields(g.closure) < 1024) W >>= 1;
+  return W;
+}
 
 static void plan_sizes(Group& g, int adjK) {
   const int cs = g.dbl ? 16 : 8, rs = g.dbl ? 8 : 4;
@@ -116,7 +129,10 @@ static void plan_sizes(Group& g, int adjK) {
   g.myh_f = g.ny / 2 - 1;
   g.kyn_f = g.ny - 1;
   set_width(g, max_width(g));
+  set_inv_width(g, max_width(g));
   const int kxp16 = (g.kxn + 15) / 16 * 16, kxpf16 = (g.kxn_f + 15) / 16 * 16;
+  g.mfp = kxp16;
+  g.mfp_f = kxpf16;
   g.RP = std::max(1, std::min(2048 / g.nx, g.ny / 2));
   g.logRP = ilog2(g.RP);
   g.nrow = g.ny / (2 * g.RP);
@@ -219,7 +235,10 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     h.groups[gi].users.push_back(i);
     h.member_group[i] = gi;
   }
-  for (auto& g : h.groups) set_width(g, default_width(g, (int)g.users.size()));
+  for (auto& g : h.groups) {
+    set_width(g, default_width(g, (int)g.users.size()));
+    set_inv_width(g, default_inv_width(g, (int)g.users.size()));
+  }
   // global area: member table, twiddles; then group regions
   long long o = align256((long long)n * sizeof(MemberDev));
   for (auto& g : h.groups) {
@@ -279,6 +298,7 @@ static Phase base_phase(const Handle& h, const Group& g) {
   P.nx = g.nx; P.ny = g.ny; P.lognx = g.lognx; P.logny = g.logny;
   P.kxn = g.kxn; P.myh = g.myh; P.kyn = g.kyn; P.kxp = g.kxp;
   P.W = g.W; P.logW = g.logW; P.RP = g.RP; P.logRP = g.logRP;
+  P.Wi = g.Wi; P.logWi = g.logWi; P.mfp = g.mfp;
   P.nf = 1;
   P.stage = 0;
   P.nparts = g.nstrips;
@@ -289,7 +309,7 @@ static Phase base_phase(const Handle& h, const Group& g) {
 }
 
 static Phase full_set(Phase P, const Group& g) {
-  P.kxn = g.kxn_f; P.myh = g.myh_f; P.kyn = g.kyn_f; P.kxp = g.kxp_f;
+  P.kxn = g.kxn_f; P.myh = g.myh_f; P.kyn = g.kyn_f; P.kxp = g.kxp_f; P.mfp = g.mfp_f;
   P.nparts = g.nstrips_f;
   return P;
 }
@@ -687,13 +707,16 @@ void qg_destroy(qg_handle* H) {
   delete H;
 }
 
-int qg_info(const qg_handle* H, int32_t* n_members, int64_t* total_points, int32_t* col_width) {
+int qg_info(const qg_handle* H, int32_t* n_members, int64_t* total_points, int32_t* fwd_width,
+            int32_t* inv_width) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   const Handle& h = H->h;
   if (n_members) *n_members = (int32_t)h.params.size();
   if (total_points) *total_points = h.total_points;
-  if (col_width)
-    for (size_t i = 0; i < h.params.size(); ++i) col_width[i] = h.groups[h.member_group[i]].W;
+  for (size_t i = 0; i < h.params.size(); ++i) {
+    if (fwd_width) fwd_width[i] = h.groups[h.member_group[i]].W;
+    if (inv_width) inv_width[i] = h.groups[h.member_group[i]].Wi;
+  }
   return QG_OK;
 }
 
@@ -904,30 +927,38 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   QG_HIP(hipEventCreate(&e1));
   int rc = QG_OK;
   bool changed = false;
+  auto time_group = [&](Group& g, float* ms) -> int {
+    for (int k = 0; k < 2; ++k) { int r = run_step(h, g, st); if (r) return r; }
+    if (hipEventRecord(e0, st) != hipSuccess) return fail(QG_EHIP, "event record");
+    for (int k = 0; k < 4; ++k) { int r = run_step(h, g, st); if (r) return r; }
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(QG_EHIP, "event timing");
+    return QG_OK;
+  };
+  auto valid = [&](const Group& g, int W) { return W >= min_width(g) && W <= max_width(g) && is_pow2(W); };
   for (auto& g : h.groups) {
     const std::string key = group_key(g);
-    auto it = cache.find(key);
-    if (it != cache.end() && it->second >= min_width(g) && it->second <= max_width(g) &&
-        is_pow2(it->second)) {
-      set_width(g, it->second);
+    auto itf = cache.find(key + "/fwd");
+    auto iti = cache.find(key + "/inv");
+    if (itf != cache.end() && iti != cache.end() && valid(g, itf->second) && valid(g, iti->second)) {
+      set_width(g, itf->second);
+      set_inv_width(g, iti->second);
       continue;
     }
-    float best = 1e30f;
-    int bestW = g.W;
-    for (int W = min_width(g); W <= max_width(g) && rc == QG_OK; W *= 2) {
-      set_width(g, W);
-      for (int k = 0; k < 2 && rc == QG_OK; ++k) rc = run_step(h, g, st);
-      if (rc) break;
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(QG_EHIP, "event record"); break; }
-      for (int k = 0; k < 4 && rc == QG_OK; ++k) rc = run_step(h, g, st);
-      if (rc) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(QG_EHIP, "event timing"); break; }
-      if (ms < best) { best = ms; bestW = W; }
+    // forward strip width first (inverse width at its default), then the inverse width
+    for (int pass = 0; pass < 2 && rc == QG_OK; ++pass) {
+      float best = 1e30f;
+      int bestW = pass == 0 ? g.W : g.Wi;
+      for (int W = min_width(g); W <= max_width(g) && rc == QG_OK; W *= 2) {
+        if (pass == 0) set_width(g, W); else set_inv_width(g, W);
+        float ms = 0.f;
+        rc = time_group(g, &ms);
+        if (rc == QG_OK && ms < best) { best = ms; bestW = W; }
+      }
+      if (pass == 0) set_width(g, bestW); else set_inv_width(g, bestW);
     }
-    set_width(g, bestW);
-    cache[key] = bestW;
+    cache[key + "/fwd"] = g.W;
+    cache[key + "/inv"] = g.Wi;
     changed = true;
   }
   (void)hipEventDestroy(e0);

@@ -58,7 +58,9 @@ struct Phase {
   int m0;                 // first member of the group in the member table
   int nx, ny, lognx, logny;
   int kxn, myh, kyn, kxp; // retained kx count, |m_y| bound, compact y count, row pitch
-  int W, logW;            // column strip width
+  int W, logW;            // strip width of the column-forward pass (and MP layout)
+  int Wi, logWi;          // strip width of the column-inverse pass
+  int mfp;                // row pitch of the row-major MF layout
   int RP, logRP;          // row pairs per row block
   int nf;                 // number of fields of a column-inverse launch
   int stage;              // RK stage 1..4 (0: not a stage)

@@ -5,13 +5,15 @@
 //                    [-myh, myh] stored as iy = m_y (m_y >= 0) or
 //                    iy = m_y + kyn (m_y < 0), kyn = 2 myh + 1.
 //                    The 2/3 set D is kxn = (nx-1)/3 + 1, myh = (ny-1)/3.
-//   mixed fields     complex [field][strip][y][w], kx = strip * W + w, strips
-//                    of W columns stored contiguously (kxp = strips * W >=
-//                    kxn): the output of a column-inverse pass and the input
-//                    of a row pass (MF), or the output of a row pass and the
-//                    input of a column-forward pass (MP).  A column pass
-//                    moves one contiguous strip; a row pass touches, per
-//                    strip, a contiguous run of (rows per block) * W values.
+//   mixed fields     the output of a column-inverse pass / input of a row
+//                    pass (MF) is row-major complex [field][y][kx] with row
+//                    pitch kxp; the output of a row pass / input of a
+//                    column-forward pass (MP) is strip-major complex
+//                    [field][strip][y][w], kx = strip * W + w.  So every read
+//                    of a mixed field is contiguous (row passes read rows,
+//                    column-forward passes read strips) and only the writes
+//                    are scattered (they do not stall the waves and merge in
+//                    L2, see the XCD-aware block order).
 //   physical tables  real [y][x]: E, E_x, E_y, S, chi, chi_sponge.
 //
 // Kernel kinds (Sec. II-C: derivatives in Fourier space, products by
@@ -39,6 +41,14 @@ template <typename T> __device__ __forceinline__ cpx<T>* cptr(const MemberDev& M
 }
 template <typename T> __device__ __forceinline__ T* rptr(const MemberDev& M, long long off) {
   return reinterpret_cast<T*>(M.base + off);
+}
+
+// XCD-aware block order: the hardware deals consecutive blocks to the 8
+// XCDs in turn; with n a multiple of 8 this gives XCD x the contiguous range
+// [x n/8, (x+1) n/8) of logical indices, so neighbouring strips (or rows)
+// that share cache lines run on the same L2.
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
 }
 
 // signed m_y of compact index iy
@@ -155,15 +165,17 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
-  V* twl = tile + P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0);
+  V* twl = tile + P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0);
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int f = blockIdx.y;
-  const int kx0 = blockIdx.x * P.W;
+  const int strip = xcd_order(blockIdx.x, gridDim.x);
+  if (strip * P.Wi >= P.kxn) return;
+  const int kx0 = strip * P.Wi;
   const int ny = P.ny;
-  const int n = P.W * ny;
+  const int n = P.Wi * ny;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   const T scale = T(M.inv_n);
-  if (P.W == 1) {
+  if (P.Wi == 1) {
     // one column: padded single-vector transform, first pass from registers
     const int j = threadIdx.x;
     const int n8 = ny >> 3;
@@ -182,8 +194,8 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     __syncthreads();   // twiddles staged
     fft1_pass0<V, true>(v, tile, j, true);
     fft1_rest<V, true>(tile, twl, P.logny, j, true);
-    V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + (long long)kx0 * ny;
-    for (int y = j; y < ny; y += n8) out[y] = tile[pad8(y)];
+    V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.mfp + kx0;
+    for (int y = j; y < ny; y += n8) out[(long long)y * P.mfp] = tile[pad8(y)];
     return;
   }
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -197,13 +209,17 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
       v = colinv_value<T, OP, CL>(M, P, f, mx, iy);
       v = cscale(v, scale);
     }
-    tile[y * P.W + w] = v;
+    tile[y * P.Wi + w] = v;
   }
   __syncthreads();
-  FftShape s{P.logny, P.W, 1, P.logW, true};
+  FftShape s{P.logny, P.Wi, 1, P.logWi, true};
   fft_lds<V, true, EPT>(tile, twl, s);
-  V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.kxp + (long long)kx0 * ny;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) out[q] = tile[q];
+  V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.mfp + kx0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int w = q & (P.Wi - 1);
+    const int y = q >> P.logWi;
+    out[(long long)y * P.mfp + w] = tile[q];
+  }
 }
 
 // ---------------------------------------------------------------- row pass
@@ -235,16 +251,16 @@ __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __rest
     const int ya = C.y0 + 2 * rp;
     V z = cmake<V>(T(0), T(0));
     if (k < C.kxn) {
-      const int o = mix_at(C, ya, k);
+      const int o = ya * C.kxp + k;
       V a = src[o];
-      V b = src[o + (1 << C.logW)];
+      V b = src[o + C.kxp];
       if (k == 0) { a.y = T(0); b.y = T(0); }
       z = cmake<V>(a.x - b.y, a.y + b.x);
     } else if (k > C.nx - C.kxn) {
       const int kk = C.nx - k;
-      const int o = mix_at(C, ya, kk);
+      const int o = ya * C.kxp + kk;
       V a = src[o];
-      V b = src[o + (1 << C.logW)];
+      V b = src[o + C.kxp];
       z = cmake<V>(a.x + b.y, b.x - a.y);
     }
     C.buf[q] = z;
@@ -343,7 +359,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     C.tw = twl;
   }
   C.nx = P.nx; C.lognx = P.lognx; C.RP = P.RP; C.logRP = P.logRP;
-  C.kxn = P.kxn; C.kxp = P.kxp; C.ny = P.ny; C.logW = P.logW;
+  C.kxn = P.kxn; C.kxp = P.mfp; C.ny = P.ny; C.logW = P.logW;
   // XCD-aware order: the hardware deals blocks to the 8 XCDs round-robin;
   // give each XCD a contiguous range of rows so mixed-layout lines shared by
   // neighbouring row blocks meet in the same L2.
@@ -351,7 +367,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
   if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   C.y0 = rb * 2 * P.RP;
   __shared__ double red[16];
-  const long long fstride = (long long)P.ny * P.kxp;
+  const long long fstride = (long long)P.ny * P.mfp;   // MF field stride
+  const long long pstride = (long long)P.ny * P.kxp;   // MP field stride
   const V* mf = cptr<T>(M, P.o_mf);
   V* mp = cptr<T>(M, P.o_mp);
   const int npts = P.RP * P.nx;
@@ -378,7 +395,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
 #pragma unroll 1
     for (int lev = 0; lev < levels; ++lev) {
       const V* F = mf + (long long)lev * nb * fstride;
-      V* out = mp + (long long)lev * 3 * fstride;
+      V* out = mp + (long long)lev * 3 * pstride;
       V base[ROW_EPT], wx[ROW_EPT], wy[ROW_EPT], t0[ROW_EPT], t1[ROW_EPT];
       if constexpr (CL != 0) {
         if constexpr (smag) {
@@ -399,10 +416,10 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
       if constexpr (OP == OP_RHS && CL != 0) {
 #pragma unroll
         for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(base[i], wx[i]);
-        row_r2c<T>(C, t0, out + 1 * fstride);
+        row_r2c<T>(C, t0, out + 1 * pstride);
 #pragma unroll
         for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(base[i], wy[i]);
-        row_r2c<T>(C, t0, out + 2 * fstride);
+        row_r2c<T>(C, t0, out + 2 * pstride);
       }
       // advection by the total velocity: J = (U + u') omega_x + (V + v') omega_y
       row_c2r<T>(C, F + 0 * fstride, t0);
@@ -536,8 +553,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
       a1[i] = cmake<V>(Ex[a] * s0, Ex[b] * s1);
     }
     row_r2c<T>(C, l, mp);
-    row_r2c<T>(C, a0, mp + fstride);
-    row_r2c<T>(C, a1, mp + 2 * fstride);
+    row_r2c<T>(C, a0, mp + pstride);
+    row_r2c<T>(C, a1, mp + 2 * pstride);
   } else if constexpr (OP == OP_ADJ_RHS) {
     // Adjoint of J = u omega_x + v omega_y, h = base grad omega, base(.)
     constexpr bool smag = (CL == 1);
@@ -551,10 +568,10 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     // lambda_u = lambda_J omega_x, lambda_v = lambda_J omega_y
 #pragma unroll
     for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(lJ[i], wx[i]);
-    row_r2c<T>(C, t0, mp + 0 * fstride);
+    row_r2c<T>(C, t0, mp + 0 * pstride);
 #pragma unroll
     for (int i = 0; i < ROW_EPT; ++i) t0[i] = vmul<T>(lJ[i], wy[i]);
-    row_r2c<T>(C, t0, mp + 1 * fstride);
+    row_r2c<T>(C, t0, mp + 1 * pstride);
     V lwx[ROW_EPT], lwy[ROW_EPT];
     row_c2r<T>(C, mf + 0 * fstride, t0);   // u'
     row_c2r<T>(C, mf + 1 * fstride, t1);   // v'
@@ -600,8 +617,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
           gx[i] = cmake<V>(t0[i].x * r0, t0[i].y * r1);
           gy[i] = cmake<V>(T(4) * t1[i].x * r0, T(4) * t1[i].y * r1);
         }
-        row_r2c<T>(C, gx, mp + 4 * fstride);
-        row_r2c<T>(C, gy, mp + 5 * fstride);
+        row_r2c<T>(C, gx, mp + 4 * pstride);
+        row_r2c<T>(C, gy, mp + 5 * pstride);
       } else {
 #pragma unroll
         for (int i = 0; i < ROW_EPT; ++i) {
@@ -612,8 +629,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
         }
       }
     }
-    row_r2c<T>(C, lwx, mp + 2 * fstride);
-    row_r2c<T>(C, lwy, mp + 3 * fstride);
+    row_r2c<T>(C, lwx, mp + 2 * pstride);
+    row_r2c<T>(C, lwy, mp + 3 * pstride);
     double s = block_sum(dc, red);
     if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = s * M.dcoef_dc;
   }
@@ -717,16 +734,16 @@ template <typename T>
 __device__ __forceinline__ cpx<T> c2r_input(const RowCtx<T>& C, const cpx<T>* src, int ya, int k, int nx, int kxn) {
   using V = cpx<T>;
   if (k < kxn) {
-    const int o = mix_at(C, ya, k);
+    const int o = ya * C.kxp + k;
     V a = src[o];
-    V b = src[o + (1 << C.logW)];
+    V b = src[o + C.kxp];
     if (k == 0) { a.y = T(0); b.y = T(0); }
     return cmake<V>(a.x - b.y, a.y + b.x);
   }
   if (k > nx - kxn) {
-    const int o = mix_at(C, ya, nx - k);
+    const int o = ya * C.kxp + (nx - k);
     const V a = src[o];
-    const V b = src[o + (1 << C.logW)];
+    const V b = src[o + C.kxp];
     return cmake<V>(a.x + b.y, b.x - a.y);
   }
   return cmake<V>(T(0), T(0));
@@ -758,8 +775,9 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
   if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int ya = 2 * rb;
   RowCtx<T> C;
-  C.ny = P.ny; C.logW = P.logW;
-  const long long fstride = (long long)P.ny * P.kxp;
+  C.ny = P.ny; C.logW = P.logW; C.kxp = P.mfp;
+  const long long fstride = (long long)P.ny * P.mfp;   // MF field stride
+  const long long pstride = (long long)P.ny * P.kxp;   // MP field stride
   V* mybuf = buf + grp * bstride;
   // the two levels of the dynamic closures (grid and test filter) are
   // independent: one block each (grid.y)
@@ -802,7 +820,7 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
   }
   if (act) {
-    V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * fstride;
+    V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
       const int a = k, b = (nx - k) & (nx - 1);
       const V z = mybuf[a + (a >> PADS)];
@@ -838,7 +856,9 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
   V* twl = tile + P.W * P.ny;
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
-  const int kx0 = blockIdx.x * P.W;
+  const int strip = xcd_order(blockIdx.x, gridDim.x);
+  if (strip * P.W >= P.kxn) return;
+  const int kx0 = strip * P.W;
   const int nmodes = P.W * P.kyn;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   // owned modes, packed as (m_x << 16) | iy; m_x = kxn marks "not owned"
@@ -991,7 +1011,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
     double shm = block_sum(hm, red);
     double smm = block_sum(mm, red);
     if (threadIdx.x == 0) {
-      double* part = rptr<double>(M, P.o_part) + 2 * blockIdx.x;
+      double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
     }
@@ -1125,7 +1145,9 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   const int lg = P.logW + P.logny - 3;     // log2 of the group size W ny/8
   const int grp = threadIdx.x >> lg;
   const int lt = threadIdx.x & ((1 << lg) - 1);
-  const int kx0 = blockIdx.x * P.W;
+  const int strip = xcd_order(blockIdx.x, gridDim.x);
+  if (strip * P.W >= P.kxn) return;
+  const int kx0 = strip * P.W;
   const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
   if (one) {
     V v[8];
@@ -1238,7 +1260,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     const double shm = block_sum(hm, red);
     const double smm = block_sum(mm, red);
     if (threadIdx.x == 0) {
-      double* part = rptr<double>(M, P.o_part) + 2 * blockIdx.x;
+      double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
     }
@@ -1411,16 +1433,22 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 }
 
 // ---------------------------------------------------------------- launchers
+// strips of a column pass, padded to a multiple of 8 (XCD-aware order)
+static unsigned col_grid(const Phase& P) { return (unsigned)(((P.kxn + P.W - 1) / P.W + 7) / 8 * 8); }
 static size_t col_tile(const Phase& P) { return (size_t)P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0); }
 static size_t col_smem(bool dbl, const Phase& P) { return (col_tile(P) + P.ny / 2) * (dbl ? 16 : 8); }
+static unsigned coli_grid(const Phase& P) { return (unsigned)(((P.kxn + P.Wi - 1) / P.Wi + 7) / 8 * 8); }
+static size_t coli_smem(bool dbl, const Phase& P) {
+  return ((size_t)P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0) + P.ny / 2) * (dbl ? 16 : 8);
+}
 static size_t row_smem(bool dbl, const Phase& P) { return ((size_t)P.RP * P.nx + P.nx / 2) * (dbl ? 16 : 8); }
 static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
 
 template <typename T, int OP, int CL>
 static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
-  dim3 grid((P.kxn + P.W - 1) / P.W, P.nf, nmem);
+  dim3 grid(coli_grid(P), P.nf, nmem);
   constexpr int EPT = COL_EPT;
-  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
+  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(P.Wi * P.ny / COL_EPT), coli_smem(sizeof(T) == 8, P), s, P);
 }
 static int rowp_fields(int op, int cl) {
   const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
@@ -1474,7 +1502,7 @@ static bool colfwdp_ok(bool dbl, int op, int cl, const Phase& P) {
 template <typename T, int OP, int CL>
 static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
   const int np = colfwdp_products(OP, CL);
-  dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
+  dim3 grid(col_grid(P), 1, nmem);
   const size_t n = col_tile(P);
   hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * ((size_t)P.W * P.ny) / COL_EPT),
                      (np * n + P.ny / 2) * sizeof(cpx<T>), s, P);
@@ -1486,7 +1514,7 @@ static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
                 OP == OP_ADJ_RHS) {
     if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) { launch_colfwdp_t<T, OP, CL>(P, nmem, s); return; }
   }
-  dim3 grid((P.kxn + P.W - 1) / P.W, 1, nmem);
+  dim3 grid(col_grid(P), 1, nmem);
   constexpr int EPT = COL_EPT;
   hipLaunchKernelGGL((k_colfwd<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
 }

@@ -138,8 +138,15 @@ class Solver:
         _lib.check(self.L.qg_run_phase(self.h, int(phase), int(stage), int(reps), _stream(self.device)))
 
     def column_widths(self):
+        """Strip width of the column-forward pass per member."""
         w = (ctypes.c_int32 * self.n)()
-        _lib.check(self.L.qg_info(self.h, None, None, w))
+        _lib.check(self.L.qg_info(self.h, None, None, w, None))
+        return list(w)
+
+    def inverse_widths(self):
+        """Strip width of the column-inverse pass per member."""
+        w = (ctypes.c_int32 * self.n)()
+        _lib.check(self.L.qg_info(self.h, None, None, None, w))
         return list(w)
 
     def close(self):

@@ -149,8 +149,9 @@ def test_diag(closure):
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_every_strip_width(tmp_path, precision):
-    """The column strip width W is a tuning choice only: every admissible W
-    (forced through the tuning cache) gives the same step to the tolerance."""
+    """The strip widths of the column passes are tuning choices only: every
+    admissible forward width W and inverse width Wi (forced through the
+    tuning cache) gives the same step to the tolerance."""
     import json
     import torch
     nx, ny = 128, 512
@@ -161,18 +162,19 @@ def test_every_strip_width(tmp_path, precision):
     ref = None
     # admissible widths: one wave at least (W ny >= 512), one tile at most
     widths = [W for W in (1, 2, 4, 8, 16) if W * ny >= 512 and W * ny <= (2048 if precision == 64 else 4096)]
-    for W in widths:
-        cache = tmp_path / f"w{W}.json"
-        cache.write_text(json.dumps({key: W}))
+    combos = [(W, widths[-1 - i % len(widths)]) for i, W in enumerate(widths)]
+    for W, Wi in combos:
+        cache = tmp_path / f"w{W}_{Wi}.json"
+        cache.write_text(json.dumps({key + "/fwd": W, key + "/inv": Wi}))
         S = solver_for([m], precision)
         S.autotune(str(cache))
-        assert S.column_widths() == [W]
+        assert S.column_widths() == [W] and S.inverse_widths() == [Wi]
         om = S.pack([m.omega0])
         w_in = to_np(om).reshape(ny, nx)
         S.step(om, 1, use_graph=False)
         if ref is None:
             ref = qg.step(w_in, M)
         err = rel_l2(to_np(om).reshape(ny, nx), ref)
-        say("  W", W, err)
+        say("  W", W, "Wi", Wi, err)
         assert err < TOL[precision]
         S.close()
