@@ -12,9 +12,9 @@
 //
 // Forward transforms use exp(-2 pi i m n / N) and are unnormalised; inverse
 // transforms use the conjugate twiddles and are also unnormalised (callers
-// fold 1/(nx ny) into the spectral data).  Twiddles come from a half table
-// tw[m] = exp(-2 pi i m / N), m in [0, N/2), staged in LDS (computed on the
-// host in extended precision and rounded once); tw[m + N/2] = -tw[m].
+// fold 1/(nx ny) into the spectral data).  Twiddles come from the table
+// tw[m] = exp(-2 pi i m / N), m in [0, N), staged in LDS (computed on the
+// host in extended precision and rounded once).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -127,12 +127,11 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = src[(j + (t << logNR)) * s.es];
       if (logNs > 0) {
-        const int half = 1 << (s.logN - 1);
+        const int step = k << twshift;
+        int idx = step;
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-          const int idx = (t * k) << twshift;
-          V w = tw[idx & (half - 1)];
-          if (idx & half) w = cmake<V>(-w.x, -w.y);
+        for (int t = 1; t < R; ++t, idx += step) {
+          V w = tw[idx];
           if (INV) w = cconj(w);
           v[i][t] = cmul(v[i][t], w);
         }
@@ -158,12 +157,12 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
   __syncthreads();
 }
 
-// Copy the half twiddle table of length-N transforms from global memory to
-// LDS (callers synchronise before the first pass).
+// Copy the twiddle table of length-N transforms from global memory to LDS
+// (callers synchronise before the first pass).
 template <typename V>
 __device__ __forceinline__ void stage_twiddles(V* __restrict__ dst, const V* __restrict__ src, int logN) {
-  const int half = 1 << (logN - 1);
-  for (int m = threadIdx.x; m < half; m += blockDim.x) dst[m] = src[m];
+  const int n = 1 << logN;
+  for (int m = threadIdx.x; m < n; m += blockDim.x) dst[m] = src[m];
 }
 
 // Full transform: radix-8 passes, then one radix-4 or radix-2 pass.
@@ -210,7 +209,6 @@ __device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restri
   constexpr int NB = 8 / R;   // butterflies per thread
   const int logNR = logN - logR;
   const int twshift = logN - logNs - logR;
-  const int half = 1 << (logN - 1);
   V v[NB][R];
   if (active) {
 #pragma unroll
@@ -219,11 +217,11 @@ __device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restri
       const int k = j & ((1 << logNs) - 1);
 #pragma unroll
       for (int t = 0; t < R; ++t) v[b][t] = buf[pad8(j + (t << logNR))];
+      const int step = k << twshift;
+      int idx = step;
 #pragma unroll
-      for (int t = 1; t < R; ++t) {
-        const int idx = (t * k) << twshift;
-        V w = tw[idx & (half - 1)];
-        if (idx & half) w = cmake<V>(-w.x, -w.y);
+      for (int t = 1; t < R; ++t, idx += step) {
+        V w = tw[idx];
         if (INV) w = cconj(w);
         v[b][t] = cmul(v[b][t], w);
       }
@@ -326,7 +324,6 @@ template <typename V, int LOGN> struct Tw16 {
 template <typename V, int LOGN>
 __device__ __forceinline__ void tw16_load(Tw16<V, LOGN>& T16, const V* __restrict__ tw, int j) {
   using S = Sched16<LOGN>;
-  constexpr int half = 1 << (LOGN - 1);
   constexpr int nt = 1 << (LOGN - 4);
 #pragma unroll
   for (int p = 0; p < S::npass; ++p) {
@@ -340,10 +337,7 @@ __device__ __forceinline__ void tw16_load(Tw16<V, LOGN>& T16, const V* __restric
       const int k = (j + b * nt) & ((1 << logNs) - 1);
 #pragma unroll
       for (int t = 1; t < R; ++t) {
-        const int idx = (t * k) << twshift;
-        V w = tw[idx & (half - 1)];
-        if (idx & half) w = cmake<V>(-w.x, -w.y);
-        T16.w[p][b * (R - 1) + (t - 1)] = w;
+        T16.w[p][b * (R - 1) + (t - 1)] = tw[(t * k) << twshift];
       }
     }
   }

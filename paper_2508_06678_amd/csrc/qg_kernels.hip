@@ -36,11 +36,35 @@
 namespace qg {
 
 // ---------------------------------------------------------------- helpers
+// Workspace pointers come from the member table, so the compiler cannot see
+// that they address global memory and would emit flat loads/stores (which
+// also hold up every LDS wait).  Hot loads and stores go through explicit
+// global-address-space pointers instead.
+__device__ __forceinline__ char* as_global(char* p) { return p; }
+template <typename S> struct nvec2;
+template <> struct nvec2<float> { typedef float __attribute__((ext_vector_type(2))) t; };
+template <> struct nvec2<double> { typedef double __attribute__((ext_vector_type(2))) t; };
+template <typename V> __device__ __forceinline__ V gld(const V* p) {
+  using N = typename nvec2<decltype(V{}.x)>::t;
+  const N v = *(const __attribute__((address_space(1))) N*)(p);
+  V r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+template <typename V> __device__ __forceinline__ void gst(V* p, const V& v) {
+  using N = typename nvec2<decltype(V{}.x)>::t;
+  N n;
+  n.x = v.x;
+  n.y = v.y;
+  *(__attribute__((address_space(1))) N*)(p) = n;
+}
+
 template <typename T> __device__ __forceinline__ cpx<T>* cptr(const MemberDev& M, long long off) {
-  return reinterpret_cast<cpx<T>*>(M.base + off);
+  return reinterpret_cast<cpx<T>*>(as_global(M.base + off));
 }
 template <typename T> __device__ __forceinline__ T* rptr(const MemberDev& M, long long off) {
-  return reinterpret_cast<T*>(M.base + off);
+  return reinterpret_cast<T*>(as_global(M.base + off));
 }
 
 // XCD-aware block order: the hardware deals consecutive blocks to the 8
@@ -128,30 +152,30 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
   const Wave<T> w = wave<T>(M, mx, my);
   const bool zero_mean = (mx == 0 && my == 0);
   if constexpr (OP == OP_RHS || OP == OP_DIAG) {
-    V x = cptr<T>(M, P.o_in)[idx];
+    V x = gld(cptr<T>(M, P.o_in) + idx);
     const bool test = dynamic_closure(CL) ? in_test(M, P.nx, P.ny, mx, my) : false;
     return rhs_field<T, CL>(M, f, x, w, mx, my, test);
   } else if constexpr (OP == OP_B) {
-    V x = cptr<T>(M, P.o_in)[idx];
+    V x = gld(cptr<T>(M, P.o_in) + idx);
     if (f == 2) return x;
     V psi = poisson<T>(M, x, w, mx, my);
     return f == 0 ? mul_ia(psi, T(-w.ky)) : mul_ia(psi, T(w.kx));
   } else if constexpr (OP == OP_EXIT) {
-    V x = cptr<T>(M, P.o_in)[idx];
+    V x = gld(cptr<T>(M, P.o_in) + idx);
     return zero_mean ? cmake<V>(T(0), T(0)) : x;
   } else if constexpr (OP == OP_MASKGRAD) {
-    V x = cptr<T>(M, P.o_in)[idx];
+    V x = gld(cptr<T>(M, P.o_in) + idx);
     return f == 0 ? mul_ia(x, T(w.kx)) : mul_ia(x, T(w.ky));
   } else if constexpr (OP == OP_ADJ_B) {
-    V l = cptr<T>(M, P.o_in)[idx];
+    V l = gld(cptr<T>(M, P.o_in) + idx);
     return zero_mean ? cmake<V>(T(0), T(0)) : l;
   } else {  // OP_ADJ_RHS: forward fields of the stage input, then -l, -i kx l, -i ky l
     constexpr int nb = (CL == 1) ? 6 : 4;
     if (f < nb) {
-      V x = cptr<T>(M, P.o_in)[idx];
+      V x = gld(cptr<T>(M, P.o_in) + idx);
       return rhs_field<T, CL>(M, f, x, w, mx, my, false);
     }
-    V l = cptr<T>(M, P.o_in2)[idx];
+    V l = gld(cptr<T>(M, P.o_in2) + idx);
     if (zero_mean) return cmake<V>(T(0), T(0));
     const int a = f - nb;
     if (a == 0) return cmake<V>(-l.x, -l.y);
@@ -195,7 +219,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     fft1_pass0<V, true>(v, tile, j, true);
     fft1_rest<V, true>(tile, twl, P.logny, j, true);
     V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.mfp + kx0;
-    for (int y = j; y < ny; y += n8) out[(long long)y * P.mfp] = tile[pad8(y)];
+    for (int y = j; y < ny; y += n8) gst(out + (long long)y * P.mfp, tile[pad8(y)]);
     return;
   }
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -218,7 +242,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const int w = q & (P.Wi - 1);
     const int y = q >> P.logWi;
-    out[(long long)y * P.mfp + w] = tile[q];
+    gst(out + (long long)y * P.mfp + w, tile[q]);
   }
 }
 
@@ -252,15 +276,15 @@ __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __rest
     V z = cmake<V>(T(0), T(0));
     if (k < C.kxn) {
       const int o = ya * C.kxp + k;
-      V a = src[o];
-      V b = src[o + C.kxp];
+      V a = gld(src + o);
+      V b = gld(src + o + C.kxp);
       if (k == 0) { a.y = T(0); b.y = T(0); }
       z = cmake<V>(a.x - b.y, a.y + b.x);
     } else if (k > C.nx - C.kxn) {
       const int kk = C.nx - k;
       const int o = ya * C.kxp + kk;
-      V a = src[o];
-      V b = src[o + C.kxp];
+      V a = gld(src + o);
+      V b = gld(src + o + C.kxp);
       z = cmake<V>(a.x + b.y, b.x - a.y);
     }
     C.buf[q] = z;
@@ -299,8 +323,8 @@ __device__ __forceinline__ void row_r2c(const RowCtx<T>& C, const cpx<T> (&val)[
       V a = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
       V b = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
       const int o = mix_at(C, ya, k);
-      dst[o] = a;
-      dst[o + (1 << C.logW)] = b;
+      gst(dst + o, a);
+      gst(dst + o + (1 << C.logW), b);
     }
   }
   __syncthreads();
@@ -310,8 +334,12 @@ template <typename T> __device__ __forceinline__ cpx<T> vmul(cpx<T> a, cpx<T> b)
 template <typename T> __device__ __forceinline__ cpx<T> vadd(cpx<T> a, cpx<T> b) { return cmake<cpx<T>>(a.x + b.x, a.y + b.y); }
 template <typename T> __device__ __forceinline__ cpx<T> vsub(cpx<T> a, cpx<T> b) { return cmake<cpx<T>>(a.x - b.x, a.y - b.y); }
 template <typename T> __device__ __forceinline__ cpx<T> vfma(cpx<T> a, cpx<T> b, cpx<T> c) { return cmake<cpx<T>>(a.x * b.x + c.x, a.y * b.y + c.y); }
-template <typename T> __device__ __forceinline__ T strain(T pxy, T pd) { return sqrt(T(4) * pxy * pxy + pd * pd); }
-template <typename T> __device__ __forceinline__ T gradmag(T a, T b) { return sqrt(a * a + b * b); }
+// square roots: the hardware instruction in 32-bit runs (about 1 ulp), the
+// correctly rounded one in 64-bit runs
+__device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T strain(T pxy, T pd) { return qsqrt(T(4) * pxy * pxy + pd * pd); }
+template <typename T> __device__ __forceinline__ T gradmag(T a, T b) { return qsqrt(a * a + b * b); }
 
 // block-wide fixed-order sum of a double (deterministic)
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -735,15 +763,15 @@ __device__ __forceinline__ cpx<T> c2r_input(const RowCtx<T>& C, const cpx<T>* sr
   using V = cpx<T>;
   if (k < kxn) {
     const int o = ya * C.kxp + k;
-    V a = src[o];
-    V b = src[o + C.kxp];
+    V a = gld(src + o);
+    V b = gld(src + o + C.kxp);
     if (k == 0) { a.y = T(0); b.y = T(0); }
     return cmake<V>(a.x - b.y, a.y + b.x);
   }
   if (k > nx - kxn) {
     const int o = ya * C.kxp + (nx - k);
-    const V a = src[o];
-    const V b = src[o + C.kxp];
+    const V a = gld(src + o);
+    const V b = gld(src + o + C.kxp);
     return cmake<V>(a.x + b.y, b.x - a.y);
   }
   return cmake<V>(T(0), T(0));
@@ -826,8 +854,8 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
       const V z = mybuf[a + (a >> PADS)];
       const V zm = mybuf[b + (b >> PADS)];
       const int o = mix_at(C, ya, k);
-      dst[o] = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));
-      dst[o + (1 << C.logW)] = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));
+      gst(dst + o, cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)));
+      gst(dst + o + (1 << C.logW), cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)));
     }
   }
 }
@@ -1152,13 +1180,13 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   if (one) {
     V v[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = src[lt + (t << lg)];
+    for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     __syncthreads();   // twiddles staged
     fft1_pass0<V, false>(v, tile + grp * n, lt, true);
     fft1_rest<V, false>(tile + grp * n, twl, P.logny, lt, true);
   } else {
     V* dst = tile + grp * n;
-    for (int q = lt; q < P.W * P.ny; q += (1 << lg)) dst[q] = src[q];
+    for (int q = lt; q < P.W * P.ny; q += (1 << lg)) dst[q] = gld(src + q);
     __syncthreads();
     const FftShape sh{P.logny, P.W, 1, P.logW, true};
     fft_lds<V, false, COL_EPT>(tile + grp * n, twl, sh, FftGroup{lt, 1 << lg, true});
@@ -1181,15 +1209,15 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     if constexpr (OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
       V v = at(0, w, iy);
       if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
-      cptr<T>(M, P.o_out)[id] = v;
+      gst(cptr<T>(M, P.o_out) + id, v);
     } else if constexpr (OP == OP_ADJ_B) {
       // lambda_s = F(l_w) - (i ky F(l_u) - i kx F(l_v)) / |k|^2 -> LS, LW, LK = dt/6 LS
       const Wave<T> wv = wave<T>(M, mx, my);
       const V lpsi = csub(mul_ia(at(1, w, iy), wv.ky), mul_ia(at(2, w, iy), wv.kx));
       const V l = csub(at(0, w, iy), cscale(lpsi, wv.inv_k2));
-      cptr<T>(M, P.o_out)[id] = l;
-      cptr<T>(M, P.o_aux)[id] = l;
-      cptr<T>(M, P.o_in)[id] = cscale(l, T(M.dt / 6.0));
+      gst(cptr<T>(M, P.o_out) + id, l);
+      gst(cptr<T>(M, P.o_aux) + id, l);
+      gst(cptr<T>(M, P.o_in) + id, cscale(l, T(M.dt / 6.0)));
     } else if constexpr (OP == OP_ADJ_RHS) {
       const Wave<T> wv = wave<T>(M, mx, my);
       V lpsi = csub(mul_ia(at(0, w, iy), wv.ky), mul_ia(at(1, w, iy), wv.kx));
@@ -1199,23 +1227,23 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       }
       const V Lx = cadd(mul_ia(at(2, w, iy), -wv.kx), mul_ia(at(3, w, iy), -wv.ky));
       V* lk = cptr<T>(M, P.o_in2);
-      V l = lk[id];
+      V l = gld(lk + id);
       if (mx == 0 && my == 0) l = cmake<V>(T(0), T(0));
       const V lp = cadd(lpsi, mul_ia(l, T(M.beta * wv.kx)));
       V lx = csub(Lx, cscale(l, T(wv.k2 * M.inv_re + M.mu)));
       lx = csub(lx, cscale(lp, wv.inv_k2));
       V* lw = cptr<T>(M, P.o_aux);
-      lw[id] = cadd(lw[id], lx);
+      gst(lw + id, cadd(gld(lw + id), lx));
       if (P.stage > 1) {
         const double dt = M.dt;
         const double cs = P.stage == 4 ? dt / 3.0 : P.stage == 3 ? dt / 3.0 : dt / 6.0;
         const double ds = P.stage == 4 ? dt : dt / 2.0;
-        lk[id] = cadd(cscale(cptr<T>(M, P.o_out)[id], T(cs)), cscale(lx, T(ds)));
+        gst(lk + id, cadd(cscale(gld(cptr<T>(M, P.o_out) + id), T(cs)), cscale(lx, T(ds))));
       }
     } else if constexpr (!dyn) {
       const Wave<T> wv = wave<T>(M, mx, my);
       const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
-      const V x = xin[id];
+      const V x = gld(xin + id);
       const V j = at(0, w, iy);
       V r = cmake<V>(-j.x, -j.y);
       r = csub(r, cscale(x, T(wv.k2 * M.inv_re + M.mu)));
@@ -1225,29 +1253,29 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
         r = cadd(r, cscale(Q, T(M.coef_static)));
       }
       if (mx == 0 && my == 0) r = cmake<V>(T(0), T(0));
-      const V w0 = cptr<T>(M, P.o_in2)[id];
+      const V w0 = gld(cptr<T>(M, P.o_in2) + id);
       V* acc = cptr<T>(M, P.o_aux);
       V* xout = cptr<T>(M, P.o_in);
       const double dt = M.dt;
       if (P.stage == 1) {
-        acc[id] = cadd(w0, cscale(r, T(dt / 6.0)));
-        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+        gst(acc + id, cadd(w0, cscale(r, T(dt / 6.0))));
+        gst(xout + id, cadd(w0, cscale(r, T(dt / 2.0))));
       } else if (P.stage == 2) {
-        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
-        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+        gst(acc + id, cadd(gld(acc + id), cscale(r, T(dt / 3.0))));
+        gst(xout + id, cadd(w0, cscale(r, T(dt / 2.0))));
       } else if (P.stage == 3) {
-        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
-        xout[id] = cadd(w0, cscale(r, T(dt)));
+        gst(acc + id, cadd(gld(acc + id), cscale(r, T(dt / 3.0))));
+        gst(xout + id, cadd(w0, cscale(r, T(dt))));
       } else {
-        xout[id] = cadd(acc[id], cscale(r, T(dt / 6.0)));
+        gst(xout + id, cadd(gld(acc + id), cscale(r, T(dt / 6.0))));
       }
     } else {
       const Wave<T> wv = wave<T>(M, mx, my);
       const bool t = in_test(M, P.nx, P.ny, mx, my);
       const V j = at(0, w, iy);
       const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
-      cptr<T>(M, P.o_out)[id] = j;
-      cptr<T>(M, P.o_aux)[id] = Q;
+      gst(cptr<T>(M, P.o_out) + id, j);
+      gst(cptr<T>(M, P.o_aux) + id, Q);
       const V h = t ? csub(at(3, w, iy), j) : at(3, w, iy);
       V g = cscale(cadd(mul_ia(at(4, w, iy), wv.kx), mul_ia(at(5, w, iy), wv.ky)), T(M.r_test));
       if (t) g = csub(g, Q);
@@ -1436,12 +1464,12 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 // strips of a column pass, padded to a multiple of 8 (XCD-aware order)
 static unsigned col_grid(const Phase& P) { return (unsigned)(((P.kxn + P.W - 1) / P.W + 7) / 8 * 8); }
 static size_t col_tile(const Phase& P) { return (size_t)P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0); }
-static size_t col_smem(bool dbl, const Phase& P) { return (col_tile(P) + P.ny / 2) * (dbl ? 16 : 8); }
+static size_t col_smem(bool dbl, const Phase& P) { return (col_tile(P) + P.ny) * (dbl ? 16 : 8); }
 static unsigned coli_grid(const Phase& P) { return (unsigned)(((P.kxn + P.Wi - 1) / P.Wi + 7) / 8 * 8); }
 static size_t coli_smem(bool dbl, const Phase& P) {
-  return ((size_t)P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0) + P.ny / 2) * (dbl ? 16 : 8);
+  return ((size_t)P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0) + P.ny) * (dbl ? 16 : 8);
 }
-static size_t row_smem(bool dbl, const Phase& P) { return ((size_t)P.RP * P.nx + P.nx / 2) * (dbl ? 16 : 8); }
+static size_t row_smem(bool dbl, const Phase& P) { return ((size_t)P.RP * P.nx + P.nx) * (dbl ? 16 : 8); }
 static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
 
 template <typename T, int OP, int CL>
@@ -1460,7 +1488,7 @@ static int rowp_fields(int op, int cl) {
 static int rowp_logn16(bool, const Phase&) { return 0; }
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
   const int pads = rowp_logn16(dbl, P) ? 4 : 3;
-  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> pads)) + P.nx / 2) * (dbl ? 16 : 8);
+  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> pads)) + P.nx) * (dbl ? 16 : 8);
 }
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
@@ -1497,7 +1525,7 @@ static int colfwdp_products(int op, int cl) {
 static bool colfwdp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int np = colfwdp_products(op, cl);
   const size_t n = col_tile(P);
-  return np * ((size_t)P.W * P.ny) / COL_EPT <= 1024 && (np * n + P.ny / 2) * (dbl ? 16 : 8) <= 128 * 1024;
+  return np * ((size_t)P.W * P.ny) / COL_EPT <= 1024 && (np * n + P.ny) * (dbl ? 16 : 8) <= 128 * 1024;
 }
 template <typename T, int OP, int CL>
 static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
@@ -1505,7 +1533,7 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(col_grid(P), 1, nmem);
   const size_t n = col_tile(P);
   hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * ((size_t)P.W * P.ny) / COL_EPT),
-                     (np * n + P.ny / 2) * sizeof(cpx<T>), s, P);
+                     (np * n + P.ny) * sizeof(cpx<T>), s, P);
 }
 
 template <typename T, int OP, int CL>
