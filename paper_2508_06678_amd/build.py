@@ -1,7 +1,7 @@
 """Build the HIP library libqg.so for gfx950 in-tree (hipcc, no JIT cache).
 
-Sources are compiled in parallel, then linked into
-paper_2508_06678_amd/libqg.so.  All device code is built with packed-FP32
+Sources are compiled in parallel (the kernel file once per slice of its
+launchers, QG_PART = 0..4), then linked into paper_2508_06678_amd/libqg.so.  All device code is built with packed-FP32
 instruction generation disabled.
 """
 import os
@@ -12,7 +12,9 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["qg_kernels.hip", "qg_api.hip"]
+# (source, extra defines, object name)
+UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}"], f"qg_kernels_{i}.o") for i in range(5)] + \
+        [("qg_api.hip", [], "qg_api.o")]
 LIB = os.path.join(PKG, "libqg.so")
 ARCH = os.environ.get("QG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -32,16 +34,18 @@ def build(verbose=False):
     os.makedirs(out_dir, exist_ok=True)
     hipcc = _hipcc()
 
-    def compile_one(src):
-        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(unit):
+        src, defs, name = unit
+        obj = os.path.join(out_dir, name)
+        cmd = [hipcc, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    workers = max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(compile_one, UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

@@ -290,6 +290,28 @@ static void twiddles(int n, std::vector<long double>& re, std::vector<long doubl
   }
 }
 
+// Per-pass table of the FFT engines: the pass with sub-transform length
+// Ns >= 8 and radix R (8 while three factors of two remain, then 4 or 2)
+// keeps exp(-2 pi i t k / (Ns R)) at (Ns - 8) + k (R - 1) + t - 1, taken
+// from the full table (index t k N / (Ns R)).  n - 8 entries; the rest of
+// the n slots is zero.
+static void pass_twiddles(int n, const std::vector<long double>& fre, const std::vector<long double>& fim,
+                          std::vector<long double>& re, std::vector<long double>& im) {
+  re.assign(n, 0.0L);
+  im.assign(n, 0.0L);
+  for (int ns = 8; ns < n; ns *= 8) {
+    const int rem = n / ns;
+    const int r = rem >= 8 ? 8 : rem;
+    const int stride = n / (ns * r);
+    for (int k = 0; k < ns; ++k)
+      for (int t = 1; t < r; ++t) {
+        const int o = (ns - 8) + k * (r - 1) + (t - 1);
+        re[o] = fre[(long long)t * k * stride];
+        im[o] = fim[(long long)t * k * stride];
+      }
+  }
+}
+
 // ------------------------------------------------------------ phases
 static Phase base_phase(const Handle& h, const Group& g) {
   Phase P{};
@@ -654,8 +676,9 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
     }
     for (int axis = 0; axis < 2; ++axis) {
       const int len = axis == 0 ? g.nx : g.ny;
-      std::vector<long double> re, im;
-      twiddles(len, re, im);
+      std::vector<long double> fre, fim, re, im;
+      twiddles(len, fre, fim);
+      pass_twiddles(len, fre, fim, re, im);
       void* dst = axis == 0 ? g.twx : g.twy;
       if (g.dbl) {
         std::vector<double> t(2 * len);

@@ -12,9 +12,17 @@
 //
 // Forward transforms use exp(-2 pi i m n / N) and are unnormalised; inverse
 // transforms use the conjugate twiddles and are also unnormalised (callers
-// fold 1/(nx ny) into the spectral data).  Twiddles come from the table
-// tw[m] = exp(-2 pi i m / N), m in [0, N), staged in LDS (computed on the
-// host in extended precision and rounded once).
+// fold 1/(nx ny) into the spectral data).
+//
+// Every engine runs the same pass schedule: radix 8 while at least three
+// factors of two remain, then one radix-4 or radix-2 pass.  Twiddles come
+// from a per-pass table staged in LDS (computed on the host in extended
+// precision and rounded once): the pass with sub-transform length Ns >= 8
+// and radix R keeps exp(-2 pi i t k / (Ns R)) at
+//     (Ns - 8) + k (R - 1) + (t - 1),   0 <= k < Ns,  1 <= t < R,
+// so a butterfly reads its R - 1 twiddles from consecutive slots; the table
+// of a length-N transform has N - 8 entries (the first pass, Ns = 1, needs
+// none).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -113,7 +121,6 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
   constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
   const int logNR = s.logN - logR;
   const int total = g.active ? 1 << (s.lognb + logNR) : 0;
-  const int twshift = s.logN - logNs - logR;
   V v[MAXB][R];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
@@ -127,14 +134,9 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
 #pragma unroll
       for (int t = 0; t < R; ++t) v[i][t] = src[(j + (t << logNR)) * s.es];
       if (logNs > 0) {
-        const int step = k << twshift;
-        int idx = step;
+        const V* w = tw + ((1 << logNs) - 8) + k * (R - 1);
 #pragma unroll
-        for (int t = 1; t < R; ++t, idx += step) {
-          V w = tw[idx];
-          if (INV) w = cconj(w);
-          v[i][t] = cmul(v[i][t], w);
-        }
+        for (int t = 1; t < R; ++t) v[i][t] = cmul(v[i][t], INV ? cconj(w[t - 1]) : w[t - 1]);
       }
       dftR<V, R, INV>(v[i]);
     }
@@ -157,11 +159,11 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
   __syncthreads();
 }
 
-// Copy the twiddle table of length-N transforms from global memory to LDS
-// (callers synchronise before the first pass).
+// Copy the per-pass twiddle table of length-N transforms from global memory
+// to LDS (callers synchronise before the first pass).
 template <typename V>
 __device__ __forceinline__ void stage_twiddles(V* __restrict__ dst, const V* __restrict__ src, int logN) {
-  const int n = 1 << logN;
+  const int n = (1 << logN) - 8;
   for (int m = threadIdx.x; m < n; m += blockDim.x) dst[m] = src[m];
 }
 
@@ -208,7 +210,6 @@ __device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restri
   constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
   constexpr int NB = 8 / R;   // butterflies per thread
   const int logNR = logN - logR;
-  const int twshift = logN - logNs - logR;
   V v[NB][R];
   if (active) {
 #pragma unroll
@@ -217,14 +218,9 @@ __device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restri
       const int k = j & ((1 << logNs) - 1);
 #pragma unroll
       for (int t = 0; t < R; ++t) v[b][t] = buf[pad8(j + (t << logNR))];
-      const int step = k << twshift;
-      int idx = step;
+      const V* w = tw + ((1 << logNs) - 8) + k * (R - 1);
 #pragma unroll
-      for (int t = 1; t < R; ++t, idx += step) {
-        V w = tw[idx];
-        if (INV) w = cconj(w);
-        v[b][t] = cmul(v[b][t], w);
-      }
+      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], INV ? cconj(w[t - 1]) : w[t - 1]);
       dftR<V, R, INV>(v[b]);
     }
   }
@@ -258,147 +254,61 @@ __device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Radix-16 single-vector transform for N >= 256: a group of N/16 threads
-// (one wave at N = 1024), 16 elements per thread, passes 16, 16, then 16/8/4/2
-// for what remains; padded LDS (one slot per 16 elements).  The twiddles of
-// every pass after the first depend only on the thread's rank, so they are
-// read once per kernel into a Tw16 register set and reused by every
-// transform of that length in the kernel.
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
-
-// Length-16 DFT in registers as 4 x 4: inner length-4 DFTs over n1 of
-// x[4 n1 + n2], twiddles w16^(n2 k1), outer length-4 DFTs over n2; output in
-// natural order.
-template <typename V, bool INV> __device__ __forceinline__ void dft16(V* v) {
-  using T = decltype(V{}.x);
-  const T c1 = T(0.92387953251128675612818318939678828682);   // cos(pi/8)
-  const T s1 = T(0.38268343236508977172845998403039886676);   // sin(pi/8)
-  const T h = T(0.70710678118654752440084436210484903928);
-  V y[16];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) {
-    V a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
-    dft4<V, INV>(a0, a1, a2, a3);
-    y[n2 * 4 + 0] = a0; y[n2 * 4 + 1] = a1; y[n2 * 4 + 2] = a2; y[n2 * 4 + 3] = a3;
-  }
-  // twiddles w16^(n2 k1) (forward: exp(-2 pi i m/16); inverse: conjugate)
-  const T sg = INV ? T(1) : T(-1);
-  auto tw = [&](V a, T c, T s) { return cmake<V>(a.x * c - a.y * sg * s, a.x * sg * s + a.y * c); };
-  y[1 * 4 + 1] = tw(y[5], c1, s1);          // m = 1
-  y[1 * 4 + 2] = tw(y[6], h, h);            // m = 2
-  y[1 * 4 + 3] = tw(y[7], s1, c1);          // m = 3
-  y[2 * 4 + 1] = tw(y[9], h, h);            // m = 2
-  y[2 * 4 + 2] = INV ? cmul_i(y[10]) : cmul_mi(y[10]);   // m = 4
-  y[2 * 4 + 3] = tw(y[11], -h, h);          // m = 6
-  y[3 * 4 + 1] = tw(y[13], s1, c1);         // m = 3
-  y[3 * 4 + 2] = tw(y[14], -h, h);          // m = 6
-  y[3 * 4 + 3] = tw(y[15], -c1, -s1);       // m = 9
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1) {
-    V b0 = y[k1], b1 = y[4 + k1], b2 = y[8 + k1], b3 = y[12 + k1];
-    dft4<V, INV>(b0, b1, b2, b3);
-    v[k1] = b0; v[k1 + 4] = b1; v[k1 + 8] = b2; v[k1 + 12] = b3;
-  }
-}
-
-template <typename V, int R, bool INV> __device__ __forceinline__ void dftR16(V* v) {
-  if constexpr (R == 16) dft16<V, INV>(v);
-  else dftR<V, R, INV>(v);
-}
-
-// Compile-time schedule for length 2^LOGN (LOGN >= 8): after the first
-// radix-16 pass, radix 16 while >= 4 bits remain, then one pass of 8/4/2.
-template <int LOGN> struct Sched16 {
-  static constexpr int rem(int p) { return LOGN - 4 - 4 * p; }             // bits left before pass p+1
-  static constexpr int logR(int p) { return rem(p) >= 4 ? 4 : rem(p); }
-  static constexpr int npass = (LOGN - 4 + 3) / 4;                           // passes after the first
-  static constexpr int logNs(int p) { return 4 + 4 * p; }
-};
-
-// Twiddle registers of the passes after the first: 15 per pass (radix 16:
-// one butterfly of 15 twiddles; radix R < 16: 16/R butterflies of R-1).
-template <typename V, int LOGN> struct Tw16 {
-  V w[Sched16<LOGN>::npass][15];
-};
-
-template <typename V, int LOGN>
-__device__ __forceinline__ void tw16_load(Tw16<V, LOGN>& T16, const V* __restrict__ tw, int j) {
-  using S = Sched16<LOGN>;
-  constexpr int nt = 1 << (LOGN - 4);
-#pragma unroll
-  for (int p = 0; p < S::npass; ++p) {
-    const int logR = S::logR(p);
-    const int R = 1 << logR;
-    const int nb = 16 / R;
-    const int logNs = S::logNs(p);
-    const int twshift = LOGN - logNs - logR;
-#pragma unroll
-    for (int b = 0; b < nb; ++b) {
-      const int k = (j + b * nt) & ((1 << logNs) - 1);
-#pragma unroll
-      for (int t = 1; t < R; ++t) {
-        T16.w[p][b * (R - 1) + (t - 1)] = tw[(t * k) << twshift];
-      }
-    }
-  }
-}
-
-template <typename V, bool INV>
-__device__ __forceinline__ void fft16_pass0(V (&v)[16], V* __restrict__ buf, int j, bool active) {
-  if (active) dft16<V, INV>(v);
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int t = 0; t < 16; ++t) buf[17 * j + t] = v[t];
-  }
-  __syncthreads();
-}
-
-template <typename V, int LOGN, int P, bool INV>
-__device__ __forceinline__ void fft16_pass(V* __restrict__ buf, const Tw16<V, LOGN>& T16, int j0, bool active) {
-  using S = Sched16<LOGN>;
-  constexpr int logR = S::logR(P);
-  constexpr int R = 1 << logR;
-  constexpr int NB = 16 / R;
-  constexpr int nt = 1 << (LOGN - 4);
-  constexpr int logNR = LOGN - logR;
-  constexpr int logNs = S::logNs(P);
+// The same single-vector transform with the length fixed at compile time
+// (64 <= N = 2^LOGN): every pass is unrolled and every LDS address is one
+// per-thread base plus constant offsets.  pad8 is additive over multiples of
+// eight (pad8(a + 8c) = pad8(a) + 9c), so the reads of all passes share the
+// base pad8(j), and the writes of a pass need one base per butterfly.
+template <typename V, int LOGN, int LOGNS, bool INV>
+__device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NS = 1 << LOGNS;
+  constexpr int REM = LOGN - LOGNS;
+  constexpr int R = REM >= 3 ? 8 : REM == 2 ? 4 : 2;
+  constexpr int logR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  constexpr int NB = 8 / R;          // butterflies per thread
+  constexpr int nt = N / 8;          // threads per transform
+  constexpr int NR = N / R;
+  static_assert(LOGN >= 6 && LOGNS >= 3, "compile-time engine: N >= 64, passes after the first");
   V v[NB][R];
   if (active) {
+    const V* rb = buf + pad8(j);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int j = j0 + b * nt;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = buf[pad16(j + (t << logNR))];
+      for (int t = 0; t < R; ++t) v[b][t] = rb[b * (nt + nt / 8) + t * (NR + NR / 8)];
+      // butterfly j + b nt; in a radix-4/2 pass (the last) it is below Ns
+      const int k = NB == 1 ? (j & (NS - 1)) : j + b * nt;
+      const V* w = tw + (NS - 8) + k * (R - 1);
 #pragma unroll
-      for (int t = 1; t < R; ++t) {
-        V w = T16.w[P][b * (R - 1) + (t - 1)];
-        if (INV) w = cconj(w);
-        v[b][t] = cmul(v[b][t], w);
-      }
-      dftR16<V, R, INV>(v[b]);
+      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], INV ? cconj(w[t - 1]) : w[t - 1]);
+      dftR<V, R, INV>(v[b]);
     }
   }
   __syncthreads();
   if (active) {
+    if constexpr (NB == 1) {
+      const int k = j & (NS - 1);
+      V* wb = buf + pad8(((j >> LOGNS) << (LOGNS + logR)) + k);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = j0 + b * nt;
-      const int k = j & ((1 << logNs) - 1);
-      const int base = ((j >> logNs) << (logNs + logR)) + k;
+      for (int t = 0; t < R; ++t) wb[t * (NS + NS / 8)] = v[0][t];
+    } else {
+      V* wb = buf + pad8(j);
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[pad16(base + (t << logNs))] = v[b][t];
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) wb[b * (nt + nt / 8) + t * (NS + NS / 8)] = v[b][t];
+      }
     }
   }
   __syncthreads();
+  if constexpr (REM > 3) fft1c_pass<V, LOGN, LOGNS + 3, INV>(buf, tw, j, active);
 }
 
-template <typename V, int LOGN, bool INV, int P = 0>
-__device__ __forceinline__ void fft16_rest(V* __restrict__ buf, const Tw16<V, LOGN>& T16, int j, bool active) {
-  if constexpr (P < Sched16<LOGN>::npass) {
-    fft16_pass<V, LOGN, P, INV>(buf, T16, j, active);
-    fft16_rest<V, LOGN, INV, P + 1>(buf, T16, j, active);
-  }
+// Passes after the first (fft1_pass0), compile-time length.
+template <typename V, int LOGN, bool INV>
+__device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
+  fft1c_pass<V, LOGN, 3, INV>(buf, tw, j, active);
 }
 
 // The whole block as one group.

@@ -33,6 +33,15 @@
 #include "qg_fft.hpp"
 #include "qg_internal.hpp"
 
+// The library compiles this file once per slice (QG_PART = 0..4): the
+// column and row launchers per precision in slices 0-3, everything else in
+// slice 4, so that the kernel instantiations build in parallel.  Without
+// QG_PART every slice is compiled.
+#ifndef QG_PART
+#define QG_PART -1
+#endif
+#define QG_HAS(p) (QG_PART < 0 || QG_PART == (p))
+
 namespace qg {
 
 // ---------------------------------------------------------------- helpers
@@ -673,9 +682,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
 // registers of its forward transform, and keeps the retained half spectrum.
 // Products: J, h_x, h_y per level (right-hand side); the penalized and
 // sponged vorticity (B sub-step); l_u, l_v, l_wx, l_wy [, l_pd, l_pxy]
-// (adjoint).  LOGN = 0: radix-8 engine, nx/8 threads per group, any nx;
-// LOGN = log2(nx): radix-16 engine, nx/16 threads per group, twiddles in
-// registers.
+// (adjoint).  nx/8 threads per group; LOGN = log2(nx) selects the
+// compile-time-length engine, LOGN = 0 the run-time one.
 
 // one product at point q; dc accumulates the dL/dc integrand (adjoint)
 template <typename T, int OP, int CL, int PADS>
@@ -778,15 +786,15 @@ __device__ __forceinline__ cpx<T> c2r_input(const RowCtx<T>& C, const cpx<T>* sr
 }
 
 template <typename T, int OP, int CL, int LOGN>
-__global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
+__global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int nbase = smag ? 6 : 4;
   constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
   constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
-  constexpr int EPT = LOGN ? 16 : 8;           // points per thread
-  constexpr int PADS = LOGN ? 4 : 3;           // one pad slot per 2^PADS
+  constexpr int EPT = 8;                       // points per thread
+  constexpr int PADS = 3;                      // one pad slot per 8
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
@@ -795,7 +803,7 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
   V* buf = reinterpret_cast<V*>(smem_raw);
   V* twl = buf + nb * bstride;
   stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
-  const int lg = P.lognx - (LOGN ? 4 : 3);
+  const int lg = P.lognx - 3;
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
   const int ng = 1 << lg;                      // threads per group
@@ -811,21 +819,15 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
   // independent: one block each (grid.y)
   const int lev = dyn ? (int)blockIdx.y : 0;
   __syncthreads();   // twiddles staged
-  Tw16<V, (LOGN ? LOGN : 8)> T16;
-  if constexpr (LOGN != 0) tw16_load<V, LOGN>(T16, twl, j);
   // ---- c2r of field lev * nb + grp
   {
     const V* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
     V v[EPT];
 #pragma unroll
     for (int t = 0; t < EPT; ++t) v[t] = c2r_input<T>(C, src, ya, j + t * ng, nx, P.kxn);
-    if constexpr (LOGN != 0) {
-      fft16_pass0<V, true>(v, mybuf, j, true);
-      fft16_rest<V, LOGN, true>(mybuf, T16, j, true);
-    } else {
-      fft1_pass0<V, true>(v, mybuf, j, true);
-      fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
-    }
+    fft1_pass0<V, true>(v, mybuf, j, true);
+    if constexpr (LOGN != 0) fft1c_rest<V, LOGN, true>(mybuf, twl, j, true);
+    else fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
   }
   // ---- product grp at this thread's points q = j + t ng
   V v[EPT];
@@ -840,13 +842,9 @@ __global__ void __launch_bounds__(LOGN ? 576 : 1024) k_rowp(Phase P) {
     if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
   }
   // ---- r2c of product grp, keep m_x < kxn
-  if constexpr (LOGN != 0) {
-    fft16_pass0<V, false>(v, mybuf, j, act);
-    fft16_rest<V, LOGN, false>(mybuf, T16, j, act);
-  } else {
-    fft1_pass0<V, false>(v, mybuf, j, act);
-    fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
-  }
+  fft1_pass0<V, false>(v, mybuf, j, act);
+  if constexpr (LOGN != 0) fft1c_rest<V, LOGN, false>(mybuf, twl, j, act);
+  else fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
   if (act) {
     V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
@@ -1364,6 +1362,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
 }
 
 // C of the dynamic closures for diagnostics (slot 0 of the coef area).
+#if QG_HAS(4)
 __global__ void k_dyn_coef(Phase P, int slot) {
   __shared__ double red[2];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
@@ -1371,6 +1370,7 @@ __global__ void k_dyn_coef(Phase P, int slot) {
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
   if (threadIdx.x == 0) rptr<double>(M, P.o_coef)[slot] = C;
 }
+#endif
 
 // ---------------------------------------------------------------- diagnostics
 // Parseval sums of energy sum w |k|^2 |psi|^2 and enstrophy sum w |omega|^2.
@@ -1402,6 +1402,7 @@ __global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
   }
 }
 
+#if QG_HAS(4)
 __global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
   const MemberDev& M = P.mem[P.m0 + blockIdx.x];
   if (threadIdx.x != 0) return;
@@ -1425,11 +1426,13 @@ __global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
   o[6] = cf * M.dt * M.inv_delta;
   o[7] = (bad > 0.0 || !isfinite(e) || !isfinite(z)) ? 1.0 : 0.0;
 }
+#endif
 
 // ---------------------------------------------------------------- adjoint misc
 // dL/dc: the row blocks' partial sums of one adjoint stage, in a fixed
 // order, accumulated into coef slot 24 of the member (mode 0); mode 1 zeroes
 // the slot; mode 2 adds the slot to the caller's grad_c.
+#if QG_HAS(4)
 __global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
   const MemberDev& M = P.mem[P.m0 + blockIdx.x];
   if (threadIdx.x != 0) return;
@@ -1441,6 +1444,7 @@ __global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
   for (int i = 0; i < nrow; ++i) s += d[i];
   *slot += s;
 }
+#endif
 
 // dst = a * dst + src (zero_first: dst = src) over the D-compact state
 template <typename T>
@@ -1454,11 +1458,13 @@ __global__ void k_spec_axpy(Phase P, long long o_dst, long long o_src, double a,
   d[q] = zero_first ? s : cadd(cscale(d[q], T(a)), s);
 }
 
+#if QG_HAS(4)
 __global__ void k_fill_zero(unsigned int* p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = 0u;
 }
+#endif
 
 // ---------------------------------------------------------------- launchers
 // strips of a column pass, padded to a multiple of 8 (XCD-aware order)
@@ -1485,10 +1491,8 @@ static int rowp_fields(int op, int cl) {
 // Radix-16 row engine (16 points per thread, twiddles in registers).  It
 // needs ~160 VGPRs and measured slower than the radix-8 engine at 1024 on
 // gfx950 (3 vs 6 waves per SIMD), so it is kept selectable but not chosen.
-static int rowp_logn16(bool, const Phase&) { return 0; }
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
-  const int pads = rowp_logn16(dbl, P) ? 4 : 3;
-  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> pads)) + P.nx) * (dbl ? 16 : 8);
+  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> 3)) + P.nx) * (dbl ? 16 : 8);
 }
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
@@ -1500,12 +1504,14 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
   dim3 grid(P.ny / 2, levels, nmem);
   const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
-  if (rowp_logn16(sizeof(T) == 8, P) == 10) {
-    if constexpr (sizeof(T) == 4)
-      hipLaunchKernelGGL((k_rowp<T, OP, CL, 10>), grid, dim3(nb * P.nx / 16), lds, s, P);
-    return;
+  const dim3 block(nb * P.nx / 8);
+  // compile-time transform lengths for the common row lengths
+  switch (P.lognx) {
+    case 8: hipLaunchKernelGGL((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P); return;
+    case 9: hipLaunchKernelGGL((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P); return;
+    case 10: hipLaunchKernelGGL((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+    default: hipLaunchKernelGGL((k_rowp<T, OP, CL, 0>), grid, block, lds, s, P); return;
   }
-  hipLaunchKernelGGL((k_rowp<T, OP, CL, 0>), grid, dim3(nb * P.nx / 8), lds, s, P);
 }
 
 template <typename T, int OP, int CL>
@@ -1563,7 +1569,7 @@ static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
     default: FN<T, OP, 2>(P, n, s); break;                   \
   }
 
-template <typename T> static void colinv_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+template <typename T> void colinv_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
   switch (op) {
     case OP_RHS: QG_CL_SWITCH(launch_colinv_t, T, OP_RHS, cl, P, n, s); break;
     case OP_DIAG: QG_CL_SWITCH(launch_colinv_t, T, OP_DIAG, cl, P, n, s); break;
@@ -1575,7 +1581,7 @@ template <typename T> static void colinv_dispatch(int op, int cl, const Phase& P
     default: break;
   }
 }
-template <typename T> static void row_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+template <typename T> void row_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
   switch (op) {
     case OP_RHS: QG_CL_SWITCH(launch_row_t, T, OP_RHS, cl, P, n, s); break;
     case OP_DIAG: QG_CL_SWITCH(launch_row_t, T, OP_DIAG, cl, P, n, s); break;
@@ -1589,7 +1595,7 @@ template <typename T> static void row_dispatch(int op, int cl, const Phase& P, i
     default: break;
   }
 }
-template <typename T> static void colfwd_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
+template <typename T> void colfwd_dispatch(int op, int cl, const Phase& P, int n, hipStream_t s) {
   switch (op) {
     case OP_RHS: QG_CL_SWITCH(launch_colfwd_t, T, OP_RHS, cl, P, n, s); break;
     case OP_B: launch_colfwd_t<T, OP_B, 0>(P, n, s); break;
@@ -1601,6 +1607,32 @@ template <typename T> static void colfwd_dispatch(int op, int cl, const Phase& P
   }
 }
 
+// slices 0-3 instantiate the column and row launchers per precision; slice
+// 4 uses them
+#if QG_HAS(0)
+template void colinv_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+template void colfwd_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+#endif
+#if QG_HAS(1)
+template void row_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+#endif
+#if QG_HAS(2)
+template void colinv_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+template void colfwd_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+#endif
+#if QG_HAS(3)
+template void row_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+#endif
+#if QG_PART == 4
+extern template void colinv_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+extern template void colfwd_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+extern template void row_dispatch<float>(int, int, const Phase&, int, hipStream_t);
+extern template void colinv_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+extern template void colfwd_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+extern template void row_dispatch<double>(int, int, const Phase&, int, hipStream_t);
+#endif
+
+#if QG_HAS(4)
 hipError_t launch_colinv(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
   if (dbl) colinv_dispatch<double>(op, cl, P, n, s); else colinv_dispatch<float>(op, cl, P, n, s);
   return hipGetLastError();
@@ -1659,5 +1691,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, (unsigned int*)p, n);
   return hipGetLastError();
 }
+#endif  // QG_HAS(4)
 
 }  // namespace qg
