@@ -68,6 +68,15 @@ template <typename V> __device__ __forceinline__ void gst(V* p, const V& v) {
   n.y = v.y;
   *(__attribute__((address_space(1))) N*)(p) = n;
 }
+template <typename S> struct nvec4;
+template <> struct nvec4<float> { typedef float __attribute__((ext_vector_type(4))) t; };
+template <> struct nvec4<double> { typedef double __attribute__((ext_vector_type(4))) t; };
+// a at p, b at p + 1 as one vector store (p aligned to two elements)
+template <typename V> __device__ __forceinline__ void gst_pair(V* p, const V& a, const V& b) {
+  using N = typename nvec4<decltype(V{}.x)>::t;
+  N n; n.x = a.x; n.y = a.y; n.z = b.x; n.w = b.y;
+  *(__attribute__((address_space(1))) N*)(p) = n;
+}
 
 template <typename T> __device__ __forceinline__ cpx<T>* cptr(const MemberDev& M, long long off) {
   return reinterpret_cast<cpx<T>*>(as_global(M.base + off));
@@ -801,8 +810,9 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   const int nx = P.nx;
   const int bstride = nx + (nx >> PADS);
   V* buf = reinterpret_cast<V*>(smem_raw);
-  V* twl = buf + nb * bstride;
-  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twx), P.lognx);
+  // twiddles straight from the (cached) global table: keeping LDS to the
+  // field buffers lets one more block share a compute unit
+  const V* twl = reinterpret_cast<const V*>(P.twx);
   const int lg = P.lognx - 3;
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
@@ -818,7 +828,6 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   // the two levels of the dynamic closures (grid and test filter) are
   // independent: one block each (grid.y)
   const int lev = dyn ? (int)blockIdx.y : 0;
-  __syncthreads();   // twiddles staged
   // ---- c2r of field lev * nb + grp
   {
     const V* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
@@ -852,8 +861,14 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
       const V z = mybuf[a + (a >> PADS)];
       const V zm = mybuf[b + (b >> PADS)];
       const int o = mix_at(C, ya, k);
-      gst(dst + o, cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)));
-      gst(dst + o + (1 << C.logW), cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)));
+      const V ra = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));     // row ya
+      const V rb = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));     // row ya + 1
+      if (C.logW == 0) {
+        gst_pair(dst + o, ra, rb);          // the two rows are adjacent
+      } else {
+        gst(dst + o, ra);
+        gst(dst + o + (1 << C.logW), rb);
+      }
     }
   }
 }
@@ -1492,7 +1507,7 @@ static int rowp_fields(int op, int cl) {
 // needs ~160 VGPRs and measured slower than the radix-8 engine at 1024 on
 // gfx950 (3 vs 6 waves per SIMD), so it is kept selectable but not chosen.
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
-  return ((size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> 3)) + P.nx) * (dbl ? 16 : 8);
+  return (size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> 3)) * (dbl ? 16 : 8);
 }
 static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
