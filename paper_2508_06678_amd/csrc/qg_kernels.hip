@@ -117,6 +117,19 @@ __device__ __forceinline__ bool in_test(const MemberDev& M, int nx, int ny, int 
   return (long long)M.test_r2 * a <= M.test_lim;
 }
 
+// The same set, column by column: the largest |m_y| that passes in column
+// m_x (-1 if none), so that in_test(mx, my) == (|my| <= test_mylim(mx)).
+__device__ __forceinline__ int test_mylim(const MemberDev& M, int nx, int ny, int mx) {
+  const long long a = (long long)M.test_r2 * ny * ny * mx * mx;
+  if (a > M.test_lim) return -1;
+  const long long den = (long long)M.test_r2 * nx * nx;
+  const long long rem = M.test_lim - a;
+  long long s = (long long)sqrt((double)rem / (double)den);
+  while (s > 0 && s * s * den > rem) --s;
+  while ((s + 1) * (s + 1) * den <= rem) ++s;
+  return (int)s;
+}
+
 // psi_hat = -x / |k|^2, in double precision for the lowest modes of 32-bit runs
 template <typename T>
 __device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave<T>& w, int mx, int my) {
@@ -162,8 +175,10 @@ __device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x,
   return cmake<V>(psi.x * a, psi.y * a);
 }
 
+// mylim: test_mylim(mx) of the dynamic closures (-2: evaluate in_test)
 template <typename T, int OP, int CL>
-__device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy) {
+__device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy,
+                                               int mylim = -2) {
   using V = cpx<T>;
   const int my = my_of_iy(iy, P.myh, P.kyn);
   const long long idx = (long long)mx * P.kyn + iy;
@@ -171,7 +186,9 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
   const bool zero_mean = (mx == 0 && my == 0);
   if constexpr (OP == OP_RHS || OP == OP_DIAG) {
     V x = gld(cptr<T>(M, P.o_in) + idx);
-    const bool test = dynamic_closure(CL) ? in_test(M, P.nx, P.ny, mx, my) : false;
+    const bool test = dynamic_closure(CL)
+                          ? (mylim >= -1 ? (my <= mylim && -my <= mylim) : in_test(M, P.nx, P.ny, mx, my))
+                          : false;
     return rhs_field<T, CL>(M, f, x, w, mx, my, test);
   } else if constexpr (OP == OP_B) {
     V x = gld(cptr<T>(M, P.o_in) + idx);
@@ -202,12 +219,17 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
 }
 
 // ---------------------------------------------------------------- colinv
-template <typename T, int OP, int CL, int EPT>
+// One block per (strip of Wi columns, field f): spectral field values of
+// the strip, inverse transform along y, rows written to the field's
+// row-major physical-y / spectral-x intermediate.  LOGN = log2(ny) selects
+// one compile-time-length transform per column (ny/8 threads each, the
+// first pass fed from registers, twiddles from the global table); LOGN = 0
+// the run-time engines.
+template <typename T, int OP, int CL, int LOGN>
 __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
-  V* twl = tile + P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0);
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   const int f = blockIdx.y;
   const int strip = xcd_order(blockIdx.x, gridDim.x);
@@ -215,8 +237,38 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   const int kx0 = strip * P.Wi;
   const int ny = P.ny;
   const int n = P.Wi * ny;
-  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   const T scale = T(M.inv_n);
+  if constexpr (LOGN != 0) {
+    constexpr int NY = 1 << LOGN, NT = NY / 8, STR = NY + NY / 8;
+    const int w = threadIdx.x >> (LOGN - 3);
+    const int j = threadIdx.x & (NT - 1);
+    const int mx = kx0 + w;
+    V* buf = tile + w * STR;
+    const int mylim = dynamic_closure(CL) && mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
+    V v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int y = j + t * NT;
+      const int my = y < NY / 2 ? y : y - NY;
+      V z = cmake<V>(T(0), T(0));
+      if (mx < P.kxn && my <= P.myh && -my <= P.myh) {
+        const int iy = my >= 0 ? my : my + P.kyn;
+        z = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, mylim), scale);
+      }
+      v[t] = z;
+    }
+    fft1_pass0<V, true>(v, buf, j, true);
+    fft1c_rest<V, LOGN, true>(buf, reinterpret_cast<const V*>(P.twy), j, true);
+    V* out = cptr<T>(M, P.o_mf) + (long long)f * NY * P.mfp + kx0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+      const int c = q & (P.Wi - 1);
+      const int y = q >> P.logWi;
+      gst(out + y * P.mfp + c, tile[c * STR + pad8(y)]);
+    }
+    return;
+  }
+  V* twl = tile + P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0);
+  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   if (P.Wi == 1) {
     // one column: padded single-vector transform, first pass from registers
     const int j = threadIdx.x;
@@ -255,7 +307,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   }
   __syncthreads();
   FftShape s{P.logny, P.Wi, 1, P.logWi, true};
-  fft_lds<V, true, EPT>(tile, twl, s);
+  fft_lds<V, true, COL_EPT>(tile, twl, s);
   V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.mfp + kx0;
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     const int w = q & (P.Wi - 1);
@@ -1169,7 +1221,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
 // W ny / 8 threads transform them concurrently, then every thread combines
 // the retained modes straight from LDS.  Used when np W ny / 8 <= 1024 and
 // the strips fit in LDS (in particular W = 1 at ny <= 1024).
-template <typename T, int OP, int CL>
+template <typename T, int OP, int CL, int LOGN>
 __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
@@ -1178,11 +1230,13 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
-  const bool one = P.W == 1;                // padded single-vector path
+  // W = 1: padded single-vector path (compile-time length if LOGN != 0,
+  // twiddles then read from the global table)
+  const bool one = LOGN != 0 || P.W == 1;
   const int n = P.W * P.ny + (one ? P.ny / 8 : 0);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + np * n;
-  stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
+  if constexpr (LOGN == 0) stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
   const int lg = P.logW + P.logny - 3;     // log2 of the group size W ny/8
   const int grp = threadIdx.x >> lg;
   const int lt = threadIdx.x & ((1 << lg) - 1);
@@ -1194,9 +1248,14 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
-    __syncthreads();   // twiddles staged
-    fft1_pass0<V, false>(v, tile + grp * n, lt, true);
-    fft1_rest<V, false>(tile + grp * n, twl, P.logny, lt, true);
+    if constexpr (LOGN != 0) {
+      fft1_pass0<V, false>(v, tile + grp * n, lt, true);
+      fft1c_rest<V, LOGN, false>(tile + grp * n, reinterpret_cast<const V*>(P.twy), lt, true);
+    } else {
+      __syncthreads();   // twiddles staged
+      fft1_pass0<V, false>(v, tile + grp * n, lt, true);
+      fft1_rest<V, false>(tile + grp * n, twl, P.logny, lt, true);
+    }
   } else {
     V* dst = tile + grp * n;
     for (int q = lt; q < P.W * P.ny; q += (1 << lg)) dst[q] = gld(src + q);
@@ -1212,8 +1271,10 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   };
   const int nm = P.W * P.kyn;
   double hm = 0.0, mm = 0.0;
+  // test filter of the dynamic closures: one column per block when W = 1
+  const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   for (int q = threadIdx.x; q < nm; q += blockDim.x) {
-    const int w = q / P.kyn;
+    const int w = one ? 0 : q / P.kyn;
     const int iy = q - w * P.kyn;
     const int mx = kx0 + w;
     if (mx >= P.kxn) continue;
@@ -1284,7 +1345,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       }
     } else {
       const Wave<T> wv = wave<T>(M, mx, my);
-      const bool t = in_test(M, P.nx, P.ny, mx, my);
+      const bool t = mylim >= -1 ? (my <= mylim && -my <= mylim) : in_test(M, P.nx, P.ny, mx, my);
       const V j = at(0, w, iy);
       const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
       gst(cptr<T>(M, P.o_out) + id, j);
@@ -1496,8 +1557,18 @@ static int row_threads(const Phase& P) { return P.RP * P.nx / ROW_EPT; }
 template <typename T, int OP, int CL>
 static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(coli_grid(P), P.nf, nmem);
-  constexpr int EPT = COL_EPT;
-  hipLaunchKernelGGL((k_colinv<T, OP, CL, EPT>), grid, dim3(P.Wi * P.ny / COL_EPT), coli_smem(sizeof(T) == 8, P), s, P);
+  const dim3 block(P.Wi * P.ny / COL_EPT);
+  if constexpr (OP == OP_RHS || OP == OP_B) {
+    // compile-time column lengths for the common sizes
+    const size_t lds = (size_t)P.Wi * (P.ny + P.ny / 8) * sizeof(cpx<T>);
+    switch (P.logny) {
+      case 8: hipLaunchKernelGGL((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
+      case 9: hipLaunchKernelGGL((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
+      case 10: hipLaunchKernelGGL((k_colinv<T, OP, CL, 10>), grid, block, lds, s, P); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL((k_colinv<T, OP, CL, 0>), grid, block, coli_smem(sizeof(T) == 8, P), s, P);
 }
 static int rowp_fields(int op, int cl) {
   const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
@@ -1553,8 +1624,18 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
   const int np = colfwdp_products(OP, CL);
   dim3 grid(col_grid(P), 1, nmem);
   const size_t n = col_tile(P);
-  hipLaunchKernelGGL((k_colfwdp<T, OP, CL>), grid, dim3(np * ((size_t)P.W * P.ny) / COL_EPT),
-                     (np * n + P.ny) * sizeof(cpx<T>), s, P);
+  const dim3 block(np * ((size_t)P.W * P.ny) / COL_EPT);
+  if constexpr (OP == OP_RHS || OP == OP_B) {
+    // compile-time column lengths for the common sizes (one column per block)
+    const size_t lds = np * n * sizeof(cpx<T>);
+    if (P.W == 1) switch (P.logny) {
+      case 8: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P); return;
+      case 9: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 9>), grid, block, lds, s, P); return;
+      case 10: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 0>), grid, block, (np * n + P.ny) * sizeof(cpx<T>), s, P);
 }
 
 template <typename T, int OP, int CL>
