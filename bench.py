@@ -114,6 +114,38 @@ def time_phases(S, torch, reps=20):
     return out
 
 
+TUNE_CACHE = None
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.json")
+
+
+def kernel_sources_digest():
+    """SHA-256 over the HIP sources, to tell whether counters taken earlier
+    still describe the kernels that run now."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2508_06678_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counters, each scaled by the factor a plain device copy of
+    known size gives; None if there are none for this kernel or the sources
+    changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel") != kernel or t.get("sources_sha256") != kernel_sources_digest():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
+
 def make_solver(workload, precision, adj=0, tune=True):
     from paper_2508_06678_amd.solver import Solver
     params, chi, chs = [], [], []
@@ -126,7 +158,7 @@ def make_solver(workload, precision, adj=0, tune=True):
         chs.append(m.chi_s.astype(dt))
     S = Solver(params, chi, chs, adj_segment_k=adj)
     if tune:
-        S.autotune()
+        S.autotune(TUNE_CACHE)
         log(f"  strip widths fwd {sorted(set(S.column_widths()))} inv {sorted(set(S.inverse_widths()))}")
     om = S.pack([m.omega0 for m in workload.members])
     return S, om
@@ -157,6 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--skip", default="", help="comma list of: fp64,batched,adjoint,cpu,phases")
+    ap.add_argument("--tune-cache", default=None,
+                    help="strip-width cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -167,6 +201,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     skip = set(s for s in args.skip.split(",") if s)
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
     import torch
     from paper_2508_06678_amd import configs
 
@@ -225,7 +261,7 @@ def main():
         ach = per[dom] / (phases[dom] * 1e-3) / 1e9
         result["roofline"] = {"bound": "hbm", "kernel": names[dom], "achieved": ach,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                              "traffic": None, "bytes_per_launch": per[dom],
+                              "traffic": measured_traffic(names[dom]), "bytes_per_launch": per[dom],
                               "avg_launch_us": phases[dom] * 1e3}
         result["kernels_us_per_launch"] = {k: v * 1e3 for k, v in phases.items()}
 
