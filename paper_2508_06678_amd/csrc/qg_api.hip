@@ -500,6 +500,11 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   const long long Mx = (p.nx - 1) / 3, My = (p.ny - 1) / 3;
   const long long lim = std::min(Mx * p.ny, My * p.nx);
   m.test_lim = lim * lim;
+  // first column with no mode in the test filter: test_r2 ny^2 mx^2 > test_lim
+  m.test_kx = 0;
+  while (m.test_kx < p.nx / 2 + 1 &&
+         (long long)m.test_r2 * p.ny * p.ny * (long long)m.test_kx * m.test_kx <= m.test_lim)
+    ++m.test_kx;
   m.lowk2 = (double)p.fp64_lowk * p.fp64_lowk;
   m.pen_a = (p.eta > 0 && std::isfinite(p.eta)) ? p.dt / p.eta : 0.0;
   m.sponge_a = p.dt * p.sponge_sigma;

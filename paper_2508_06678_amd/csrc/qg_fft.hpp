@@ -255,11 +255,30 @@ __device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restri
 
 // ---------------------------------------------------------------------------
 // The same single-vector transform with the length fixed at compile time
-// (64 <= N = 2^LOGN): every pass is unrolled and every LDS address is one
-// per-thread base plus constant offsets.  pad8 is additive over multiples of
-// eight (pad8(a + 8c) = pad8(a) + 9c), so the reads of all passes share the
-// base pad8(j), and the writes of a pass need one base per butterfly.
-template <typename V, int LOGN, int LOGNS, bool INV>
+// (N = 2^LOGN >= 8 * 2^P) and a pad slot every 2^P elements
+// (padp<P>(i) = i + i / 2^P): every pass is unrolled and every LDS address
+// is one per-thread base plus constant offsets.  padp<P> is additive over
+// multiples of 2^P, so the reads of all passes share the base padp(j); a
+// write of a pass goes to padp(base + t Ns) = padp(base) + t Ns + (t Ns)/2^P
+// (base = its butterfly's first output, whose offset below Ns is < 2^P when
+// Ns < 2^P).
+template <int P> __device__ __forceinline__ int padp(int i) { return i + (i >> P); }
+
+// First pass (radix 8) from registers: butterfly j writes x'[8 j + t].
+template <typename V, bool INV, int P>
+__device__ __forceinline__ void fft1c_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active) {
+  static_assert(P >= 3, "pad period of at least 8");
+  if (active) dftR<V, 8, INV>(v);
+  __syncthreads();
+  if (active) {
+    V* wb = buf + 8 * j + (j >> (P - 3));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) wb[t] = v[t];
+  }
+  __syncthreads();
+}
+
+template <typename V, int LOGN, int LOGNS, bool INV, int P>
 __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
   constexpr int N = 1 << LOGN;
   constexpr int NS = 1 << LOGNS;
@@ -269,14 +288,14 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
   constexpr int NB = 8 / R;          // butterflies per thread
   constexpr int nt = N / 8;          // threads per transform
   constexpr int NR = N / R;
-  static_assert(LOGN >= 6 && LOGNS >= 3, "compile-time engine: N >= 64, passes after the first");
+  static_assert(LOGN >= P + 3 && LOGNS >= 3, "compile-time engine: N >= 8 * 2^P, passes after the first");
   V v[NB][R];
   if (active) {
-    const V* rb = buf + pad8(j);
+    const V* rb = buf + padp<P>(j);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = rb[b * (nt + nt / 8) + t * (NR + NR / 8)];
+      for (int t = 0; t < R; ++t) v[b][t] = rb[b * (nt + (nt >> P)) + t * (NR + (NR >> P))];
       // butterfly j + b nt; in a radix-4/2 pass (the last) it is below Ns
       const int k = NB == 1 ? (j & (NS - 1)) : j + b * nt;
       const V* w = tw + (NS - 8) + k * (R - 1);
@@ -289,26 +308,26 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
   if (active) {
     if constexpr (NB == 1) {
       const int k = j & (NS - 1);
-      V* wb = buf + pad8(((j >> LOGNS) << (LOGNS + logR)) + k);
+      V* wb = buf + padp<P>(((j >> LOGNS) << (LOGNS + logR)) + k);
 #pragma unroll
-      for (int t = 0; t < R; ++t) wb[t * (NS + NS / 8)] = v[0][t];
+      for (int t = 0; t < R; ++t) wb[t * NS + ((t * NS) >> P)] = v[0][t];
     } else {
-      V* wb = buf + pad8(j);
+      V* wb = buf + padp<P>(j);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) wb[b * (nt + nt / 8) + t * (NS + NS / 8)] = v[b][t];
+        for (int t = 0; t < R; ++t) wb[b * (nt + (nt >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
       }
     }
   }
   __syncthreads();
-  if constexpr (REM > 3) fft1c_pass<V, LOGN, LOGNS + 3, INV>(buf, tw, j, active);
+  if constexpr (REM > 3) fft1c_pass<V, LOGN, LOGNS + 3, INV, P>(buf, tw, j, active);
 }
 
-// Passes after the first (fft1_pass0), compile-time length.
-template <typename V, int LOGN, bool INV>
+// Passes after the first (fft1c_pass0), compile-time length.
+template <typename V, int LOGN, bool INV, int P>
 __device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
-  fft1c_pass<V, LOGN, 3, INV>(buf, tw, j, active);
+  fft1c_pass<V, LOGN, 3, INV, P>(buf, tw, j, active);
 }
 
 // The whole block as one group.

@@ -41,6 +41,7 @@ struct MemberDev {
   double inv_delta;      // 1 / Delta = nx / lx
   long long test_lim;    // min(Mx ny, My nx)^2 of the integer test-filter test
   int test_r2;           // test_ratio^2
+  int test_kx;           // columns m_x < test_kx hold the test-filtered modes
   int closure;
 };
 
@@ -101,9 +102,9 @@ hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Field counts per phase and closure.
-__host__ __device__ inline int rhs_fields(int cl) { return cl == 0 || cl == 2 ? 4 : cl == 1 ? 6 : cl == 4 ? 8 : 12; }
+__host__ __device__ constexpr int rhs_fields(int cl) { return cl == 0 || cl == 2 ? 4 : cl == 1 ? 6 : cl == 4 ? 8 : 12; }
 __host__ __device__ inline int rhs_products(int cl) { return cl == 0 ? 1 : (cl == 1 || cl == 2) ? 3 : 6; }
 __host__ __device__ inline bool smag_family(int cl) { return cl == 1 || cl == 3; }
-__host__ __device__ inline bool dynamic_closure(int cl) { return cl == 3 || cl == 4; }
+__host__ __device__ constexpr bool dynamic_closure(int cl) { return cl == 3 || cl == 4; }
 
 }  // namespace qg

@@ -42,6 +42,15 @@
 #endif
 #define QG_HAS(p) (QG_PART < 0 || QG_PART == (p))
 
+// LDS pad period (one slot every 2^P elements) of the compile-time-length
+// row and column transforms
+#ifndef QG_ROW_PADS
+#define QG_ROW_PADS 4
+#endif
+#ifndef QG_COL_PADS
+#define QG_COL_PADS 4
+#endif
+
 namespace qg {
 
 // ---------------------------------------------------------------- helpers
@@ -235,11 +244,16 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   const int strip = xcd_order(blockIdx.x, gridDim.x);
   if (strip * P.Wi >= P.kxn) return;
   const int kx0 = strip * P.Wi;
+  // test-filtered fields of the dynamic closures vanish beyond column
+  // test_kx; the row pass reads no further, so nothing is written there
+  if constexpr (OP == OP_RHS && dynamic_closure(CL))
+    if (f >= rhs_fields(CL) / 2 && kx0 >= M.test_kx) return;
   const int ny = P.ny;
   const int n = P.Wi * ny;
   const T scale = T(M.inv_n);
   if constexpr (LOGN != 0) {
-    constexpr int NY = 1 << LOGN, NT = NY / 8, STR = NY + NY / 8;
+    constexpr int PD = QG_COL_PADS;
+    constexpr int NY = 1 << LOGN, NT = NY / 8, STR = NY + (NY >> PD);
     const int w = threadIdx.x >> (LOGN - 3);
     const int j = threadIdx.x & (NT - 1);
     const int mx = kx0 + w;
@@ -257,13 +271,13 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
       }
       v[t] = z;
     }
-    fft1_pass0<V, true>(v, buf, j, true);
-    fft1c_rest<V, LOGN, true>(buf, reinterpret_cast<const V*>(P.twy), j, true);
+    fft1c_pass0<V, true, PD>(v, buf, j, true);
+    fft1c_rest<V, LOGN, true, PD>(buf, reinterpret_cast<const V*>(P.twy), j, true);
     V* out = cptr<T>(M, P.o_mf) + (long long)f * NY * P.mfp + kx0;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
       const int c = q & (P.Wi - 1);
       const int y = q >> P.logWi;
-      gst(out + y * P.mfp + c, tile[c * STR + pad8(y)]);
+      gst(out + y * P.mfp + c, tile[c * STR + padp<PD>(y)]);
     }
     return;
   }
@@ -324,6 +338,7 @@ template <typename T> struct RowCtx {
   V* buf;            // RP rows of nx complex
   const V* tw;
   int nx, lognx, RP, logRP, kxn, kxp, ny, logW;
+  int kin;           // c2r input columns: m_x < kin (kin <= kxn)
   int y0;            // first row of the block
 };
 
@@ -344,13 +359,13 @@ __device__ __forceinline__ void row_c2r(const RowCtx<T>& C, const cpx<T>* __rest
     const int k = q & (C.nx - 1);
     const int ya = C.y0 + 2 * rp;
     V z = cmake<V>(T(0), T(0));
-    if (k < C.kxn) {
+    if (k < C.kin) {
       const int o = ya * C.kxp + k;
       V a = gld(src + o);
       V b = gld(src + o + C.kxp);
       if (k == 0) { a.y = T(0); b.y = T(0); }
       z = cmake<V>(a.x - b.y, a.y + b.x);
-    } else if (k > C.nx - C.kxn) {
+    } else if (k > C.nx - C.kin) {
       const int kk = C.nx - k;
       const int o = ya * C.kxp + kk;
       V a = gld(src + o);
@@ -457,7 +472,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     C.tw = twl;
   }
   C.nx = P.nx; C.lognx = P.lognx; C.RP = P.RP; C.logRP = P.logRP;
-  C.kxn = P.kxn; C.kxp = P.mfp; C.ny = P.ny; C.logW = P.logW;
+  C.kxn = P.kxn; C.kin = P.kxn; C.kxp = P.mfp; C.ny = P.ny; C.logW = P.logW;
   // XCD-aware order: the hardware deals blocks to the 8 XCDs round-robin;
   // give each XCD a contiguous range of rows so mixed-layout lines shared by
   // neighbouring row blocks meet in the same L2.
@@ -494,6 +509,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     for (int lev = 0; lev < levels; ++lev) {
       const V* F = mf + (long long)lev * nb * fstride;
       V* out = mp + (long long)lev * 3 * pstride;
+      C.kin = lev == 0 ? P.kxn : min(P.kxn, M.test_kx);   // test-filtered level: m_x < test_kx
       V base[ROW_EPT], wx[ROW_EPT], wy[ROW_EPT], t0[ROW_EPT], t1[ROW_EPT];
       if constexpr (CL != 0) {
         if constexpr (smag) {
@@ -855,7 +871,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
   constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
   constexpr int EPT = 8;                       // points per thread
-  constexpr int PADS = 3;                      // one pad slot per 8
+  constexpr int PADS = LOGN ? QG_ROW_PADS : 3;  // one pad slot per 2^PADS
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
@@ -883,12 +899,18 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   // ---- c2r of field lev * nb + grp
   {
     const V* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
+    // the test-filtered level holds no mode at m_x >= test_kx
+    const int kin = lev == 0 ? P.kxn : min(P.kxn, M.test_kx);
     V v[EPT];
 #pragma unroll
-    for (int t = 0; t < EPT; ++t) v[t] = c2r_input<T>(C, src, ya, j + t * ng, nx, P.kxn);
-    fft1_pass0<V, true>(v, mybuf, j, true);
-    if constexpr (LOGN != 0) fft1c_rest<V, LOGN, true>(mybuf, twl, j, true);
-    else fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
+    for (int t = 0; t < EPT; ++t) v[t] = c2r_input<T>(C, src, ya, j + t * ng, nx, kin);
+    if constexpr (LOGN != 0) {
+      fft1c_pass0<V, true, PADS>(v, mybuf, j, true);
+      fft1c_rest<V, LOGN, true, PADS>(mybuf, twl, j, true);
+    } else {
+      fft1_pass0<V, true>(v, mybuf, j, true);
+      fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
+    }
   }
   // ---- product grp at this thread's points q = j + t ng
   V v[EPT];
@@ -903,9 +925,13 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
     if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
   }
   // ---- r2c of product grp, keep m_x < kxn
-  fft1_pass0<V, false>(v, mybuf, j, act);
-  if constexpr (LOGN != 0) fft1c_rest<V, LOGN, false>(mybuf, twl, j, act);
-  else fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
+  if constexpr (LOGN != 0) {
+    fft1c_pass0<V, false, PADS>(v, mybuf, j, act);
+    fft1c_rest<V, LOGN, false, PADS>(mybuf, twl, j, act);
+  } else {
+    fft1_pass0<V, false>(v, mybuf, j, act);
+    fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
+  }
   if (act) {
     V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
@@ -1233,7 +1259,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   // W = 1: padded single-vector path (compile-time length if LOGN != 0,
   // twiddles then read from the global table)
   const bool one = LOGN != 0 || P.W == 1;
-  const int n = P.W * P.ny + (one ? P.ny / 8 : 0);
+  constexpr int CPD = LOGN ? QG_COL_PADS : 3;   // pad period of the single-column path
+  const int n = P.W * P.ny + (one ? P.ny >> CPD : 0);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + np * n;
   if constexpr (LOGN == 0) stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
@@ -1249,8 +1276,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     if constexpr (LOGN != 0) {
-      fft1_pass0<V, false>(v, tile + grp * n, lt, true);
-      fft1c_rest<V, LOGN, false>(tile + grp * n, reinterpret_cast<const V*>(P.twy), lt, true);
+      fft1c_pass0<V, false, CPD>(v, tile + grp * n, lt, true);
+      fft1c_rest<V, LOGN, false, CPD>(tile + grp * n, reinterpret_cast<const V*>(P.twy), lt, true);
     } else {
       __syncthreads();   // twiddles staged
       fft1_pass0<V, false>(v, tile + grp * n, lt, true);
@@ -1267,7 +1294,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   auto at = [&](int p, int w, int iy) -> V {
     const int my = my_of_iy(iy, P.myh, P.kyn);
     const int y = my >= 0 ? my : my + P.ny;
-    return one ? tile[p * n + pad8(y)] : tile[p * n + y * P.W + w];
+    return one ? tile[p * n + padp<CPD>(y)] : tile[p * n + y * P.W + w];
   };
   const int nm = P.W * P.kyn;
   double hm = 0.0, mm = 0.0;
@@ -1560,7 +1587,7 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   const dim3 block(P.Wi * P.ny / COL_EPT);
   if constexpr (OP == OP_RHS || OP == OP_B) {
     // compile-time column lengths for the common sizes
-    const size_t lds = (size_t)P.Wi * (P.ny + P.ny / 8) * sizeof(cpx<T>);
+    const size_t lds = (size_t)P.Wi * (P.ny + (P.ny >> QG_COL_PADS)) * sizeof(cpx<T>);
     switch (P.logny) {
       case 8: hipLaunchKernelGGL((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
       case 9: hipLaunchKernelGGL((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
