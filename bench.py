@@ -55,24 +55,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(nx, ny, word, closure="dleith"):
+def algorithmic_bytes(nx, ny, word, closure="dleith", test_ratio=2):
     """Bytes each kernel of one step must move for one member (see the
-    module docstring): F fields and P products cross HBM once in the mixed
-    layout of ny * kxn complex values; spectral quantities live on the
-    2/3 set of kxn * kyn complex values; physical tables are nx * ny reals."""
+    module docstring): fields and products cross HBM once in the mixed
+    layout of ny * kxn complex values (the test-filtered fields of the
+    dynamic closures only over the test_kx columns that hold their modes);
+    spectral quantities live on the 2/3 set of kxn * kyn complex values;
+    physical tables are nx * ny reals."""
     kxn = (nx - 1) // 3 + 1
     kyn = 2 * ((ny - 1) // 3) + 1
     c = 2 * word
     nM = ny * kxn * c
     nD = kxn * kyn * c
-    F = {"none": 4, "smag": 6, "leith": 4, "dsmag": 12, "dleith": 8}[closure]
-    P = {"none": 1, "smag": 3, "leith": 3, "dsmag": 6, "dleith": 6}[closure]
     dyn = closure in ("dsmag", "dleith")
+    nb = {"none": 4, "smag": 6, "leith": 4, "dsmag": 6, "dleith": 4}[closure]
+    test_kx = 0
+    if dyn:
+        lim = min(((nx - 1) // 3) * ny, ((ny - 1) // 3) * nx) ** 2
+        while test_kx <= nx // 2 and test_ratio ** 2 * ny * ny * test_kx * test_kx <= lim:
+            test_kx += 1
+    F = nb + (nb * min(test_kx, kxn) / kxn if dyn else 0)     # full-width field equivalents
+    P = {"none": 1, "smag": 3, "leith": 3, "dsmag": 6, "dleith": 6}[closure]
     per = {
         "colinv_rhs": nD + F * nM,
         "row_rhs": F * nM + P * nM,
         "colfwd_rhs": P * nM + (2 * nD if dyn else 4 * nD),
-        "combine_dyn": 6 * nD if dyn else 0,
+        "combine_dyn": 7 * nD if dyn else 0,
         "colinv_b": nD + 3 * nM,
         "row_b": 3 * nM + 4 * nx * ny * word + nM,
         "colfwd_b": nM + nD,

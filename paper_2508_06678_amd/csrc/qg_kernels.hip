@@ -1400,17 +1400,20 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 // Dynamic closures: C = max(<HM>, 0)/<M^2> from the fixed-order sum of the
 // strip partials (every block sums them identically), then the RHS
 // R = -J + C Q - (k^2/Re + mu) x - i beta kx psi and the RK4 update.
+// Every thread of the block loads its share of the partials at once; the
+// 64-lane wave sums and then the wave sums are added in a fixed order, so
+// every block of a launch forms the same C.  red: 2 doubles per wave.
 __device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, double* red, double& C,
                                                 double& hm_out, double& mm_out) {
   double hm = 0.0, mm = 0.0;
-  if (threadIdx.x < 64) {
-    for (int i = threadIdx.x; i < nparts; i += 64) { hm += part[2 * i]; mm += part[2 * i + 1]; }
-    for (int o = 32; o > 0; o >>= 1) { hm += __shfl_xor(hm, o, 64); mm += __shfl_xor(mm, o, 64); }
-    if (threadIdx.x == 0) { red[0] = hm; red[1] = mm; }
-  }
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) { hm += part[2 * i]; mm += part[2 * i + 1]; }
+  for (int o = 32; o > 0; o >>= 1) { hm += __shfl_xor(hm, o, 64); mm += __shfl_xor(mm, o, 64); }
+  const int nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = hm; red[2 * (threadIdx.x >> 6) + 1] = mm; }
   __syncthreads();
-  hm = red[0];
-  mm = red[1];
+  hm = 0.0;
+  mm = 0.0;
+  for (int w = 0; w < nw; ++w) { hm += red[2 * w]; mm += red[2 * w + 1]; }
   hm_out = hm;
   mm_out = mm;
   C = mm > 0.0 ? fmax(hm, 0.0) / mm : 0.0;
@@ -1419,7 +1422,7 @@ __device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, 
 template <typename T>
 __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   using V = cpx<T>;
-  __shared__ double red[2];
+  __shared__ double red[2 * (COMBINE_THREADS / 64)];
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   double C, hm, mm;
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
@@ -1467,7 +1470,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
 // C of the dynamic closures for diagnostics (slot 0 of the coef area).
 #if QG_HAS(4)
 __global__ void k_dyn_coef(Phase P, int slot) {
-  __shared__ double red[2];
+  __shared__ double red[2];   // one 64-thread wave
   const MemberDev& M = P.mem[P.m0 + blockIdx.z];
   double C, hm, mm;
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
