@@ -94,6 +94,18 @@ template <typename T> __device__ __forceinline__ T* rptr(const MemberDev& M, lon
   return reinterpret_cast<T*>(as_global(M.base + off));
 }
 
+// Member table entry read through the constant address space: the table is
+// written by the host only, so block-uniform reads of it become scalar
+// loads (which neither wait for nor hold back the vector-memory counter).
+__device__ __forceinline__ MemberDev member_const(const Phase& P, int m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(4))) MemberDev* CT;
+  return ((CT)(P.mem))[P.m0 + m];
+#else
+  return P.mem[P.m0 + m];   // host pass of the device code (never executed)
+#endif
+}
+
 // XCD-aware block order: the hardware deals consecutive blocks to the 8
 // XCDs in turn; with n a multiple of 8 this gives XCD x the contiguous range
 // [x n/8, (x+1) n/8) of logical indices, so neighbouring strips (or rows)
@@ -239,7 +251,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* tile = reinterpret_cast<V*>(smem_raw);
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   const int f = blockIdx.y;
   const int strip = xcd_order(blockIdx.x, gridDim.x);
   if (strip * P.Wi >= P.kxn) return;
@@ -463,7 +475,7 @@ template <typename T, int OP, int CL>
 __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 : 2)) k_row(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   RowCtx<T> C;
   C.buf = reinterpret_cast<V*>(smem_raw);
   {
@@ -763,14 +775,14 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
 // compile-time-length engine, LOGN = 0 the run-time one.
 
 // one product at point q; dc accumulates the dL/dc integrand (adjoint)
+// U, Vv: the member's inflow velocity; coef: its static closure coefficient
 template <typename T, int OP, int CL, int PADS>
 __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& P, const cpx<T>* buf, int bstride,
-                                               int q, int grp, int ya, double& dc) {
+                                               int q, int grp, int ya, double& dc, T U, T Vv, T coef) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
   constexpr int nbase = smag ? 6 : 4;
   const int nx = P.nx;
-  const T U = T(M.u_in), Vv = T(M.v_in);
   auto F = [&](int f) -> V { return buf[f * bstride + q + (q >> PADS)]; };
   if constexpr (OP == OP_B) {
     // omega'' = S (E omega + E_x v - E_y u), total velocity
@@ -804,7 +816,6 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     V lwy = cmake<V>(lJ.x * (Vv + vv.x), lJ.y * (Vv + vv.y));
     V lpd = cmake<V>(T(0), T(0)), lpxy = lpd;
     if constexpr (CL != 0) {
-      const T coef = T(M.coef_static);
       const V gx = F(nbase + 1), gy = F(nbase + 2);
       V base, pd, pxy;
       if constexpr (smag) {
@@ -842,68 +853,78 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
   }
 }
 
-// c2r input at column k of the packed row pair, from the mixed layout
+// c2r input of the packed row pair (rows ya, ya + 1) at column k: the raw
+// loads (spectral m_x = k, or its mirror nx - k), then the packing into one
+// complex row.
+template <typename T> struct RowRaw {
+  cpx<T> a[8], b[8];
+};
 template <typename T>
-__device__ __forceinline__ cpx<T> c2r_input(const RowCtx<T>& C, const cpx<T>* src, int ya, int k, int nx, int kxn) {
+__device__ __forceinline__ void c2r_load(RowRaw<T>& r, const cpx<T>* src, int pitch, int ya, int j, int ng, int nx,
+                                         int kin) {
   using V = cpx<T>;
-  if (k < kxn) {
-    const int o = ya * C.kxp + k;
-    V a = gld(src + o);
-    V b = gld(src + o + C.kxp);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int k = j + t * ng;
+    const int m = k < kin ? k : k > nx - kin ? nx - k : -1;
+    if (m >= 0) {
+      const int o = ya * pitch + m;
+      r.a[t] = gld(src + o);
+      r.b[t] = gld(src + o + pitch);
+    } else {
+      r.a[t] = r.b[t] = cmake<V>(T(0), T(0));
+    }
+  }
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_form(cpx<T> a, cpx<T> b, int k, int nx, int kin) {
+  using V = cpx<T>;
+  if (k < kin) {
     if (k == 0) { a.y = T(0); b.y = T(0); }
     return cmake<V>(a.x - b.y, a.y + b.x);
   }
-  if (k > nx - kxn) {
-    const int o = ya * C.kxp + (nx - k);
-    const V a = gld(src + o);
-    const V b = gld(src + o + C.kxp);
-    return cmake<V>(a.x + b.y, b.x - a.y);
-  }
+  if (k > nx - kin) return cmake<V>(a.x + b.y, b.x - a.y);
   return cmake<V>(T(0), T(0));
 }
 
+// Column limit of the c2r input: the test-filtered level holds no mode at
+// m_x >= test_kx.
+__device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, int lev) {
+  return lev == 0 ? P.kxn : min(P.kxn, M.test_kx);
+}
+
+// One item of the row pass: row pair rb of member mem at level lev, from
+// the packed c2r inputs vin (column j + t nx/8 of the thread's group);
+// twl: the x twiddle table (global or staged in LDS).
 template <typename T, int OP, int CL, int LOGN>
-__global__ void __launch_bounds__(1024) k_rowp(Phase P) {
+__device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int lev, const cpx<T> (&vin)[8],
+                                          cpx<T>* buf, const cpx<T>* twl, double* red, int item_slot) {
   using V = cpx<T>;
   constexpr bool smag = (CL == 1 || CL == 3);
-  constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int nbase = smag ? 6 : 4;
   constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
   constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
   constexpr int EPT = 8;                       // points per thread
   constexpr int PADS = LOGN ? QG_ROW_PADS : 3;  // one pad slot per 2^PADS
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[16];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, mem);
+  // member constants read once, not per point
+  const T U = T(M.u_in), Vv = T(M.v_in), coef = T(M.coef_static);
   const int nx = P.nx;
   const int bstride = nx + (nx >> PADS);
-  V* buf = reinterpret_cast<V*>(smem_raw);
-  // twiddles straight from the (cached) global table: keeping LDS to the
-  // field buffers lets one more block share a compute unit
-  const V* twl = reinterpret_cast<const V*>(P.twx);
   const int lg = P.lognx - 3;
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
   const int ng = 1 << lg;                      // threads per group
-  int rb = blockIdx.x;
-  if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int ya = 2 * rb;
   RowCtx<T> C;
   C.ny = P.ny; C.logW = P.logW; C.kxp = P.mfp;
-  const long long fstride = (long long)P.ny * P.mfp;   // MF field stride
   const long long pstride = (long long)P.ny * P.kxp;   // MP field stride
   V* mybuf = buf + grp * bstride;
-  // the two levels of the dynamic closures (grid and test filter) are
-  // independent: one block each (grid.y)
-  const int lev = dyn ? (int)blockIdx.y : 0;
   // ---- c2r of field lev * nb + grp
   {
-    const V* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
-    // the test-filtered level holds no mode at m_x >= test_kx
-    const int kin = lev == 0 ? P.kxn : min(P.kxn, M.test_kx);
     V v[EPT];
 #pragma unroll
-    for (int t = 0; t < EPT; ++t) v[t] = c2r_input<T>(C, src, ya, j + t * ng, nx, kin);
+    for (int t = 0; t < EPT; ++t) v[t] = vin[t];
     if constexpr (LOGN != 0) {
       fft1c_pass0<V, true, PADS>(v, mybuf, j, true);
       fft1c_rest<V, LOGN, true, PADS>(mybuf, twl, j, true);
@@ -918,11 +939,12 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   const bool act = grp < np;
   if (act) {
 #pragma unroll
-    for (int t = 0; t < EPT; ++t) v[t] = rowp_product<T, OP, CL, PADS>(M, P, buf, bstride, j + t * ng, grp, ya, dc);
+    for (int t = 0; t < EPT; ++t)
+      v[t] = rowp_product<T, OP, CL, PADS>(M, P, buf, bstride, j + t * ng, grp, ya, dc, U, Vv, coef);
   }
   if constexpr (OP == OP_ADJ_RHS) {
     const double sdc = block_sum(dc, red);
-    if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = sdc * M.dcoef_dc;
+    if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[item_slot] = sdc * M.dcoef_dc;
   }
   // ---- r2c of product grp, keep m_x < kxn
   if constexpr (LOGN != 0) {
@@ -940,15 +962,66 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
       const V zm = mybuf[b + (b >> PADS)];
       const int o = mix_at(C, ya, k);
       const V ra = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));     // row ya
-      const V rb = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));     // row ya + 1
+      const V rb2 = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));    // row ya + 1
       if (C.logW == 0) {
-        gst_pair(dst + o, ra, rb);          // the two rows are adjacent
+        gst_pair(dst + o, ra, rb2);          // the two rows are adjacent
       } else {
         gst(dst + o, ra);
-        gst(dst + o + (1 << C.logW), rb);
+        gst(dst + o + (1 << C.logW), rb2);
       }
     }
   }
+}
+
+// packed c2r inputs of the item from its loads
+template <typename T>
+__device__ __forceinline__ void rowp_form(const Phase& P, int mem, int lev, const RowRaw<T>& in, cpx<T> (&v)[8]) {
+  const MemberDev M = member_const(P, mem);
+  const int lg = P.lognx - 3;
+  const int j = threadIdx.x & ((1 << lg) - 1);
+  const int kin = rowp_kin(P, M, lev);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = c2r_form<T>(in.a[t], in.b[t], j + (t << lg), P.nx, kin);
+}
+
+// c2r loads of the item's field (row pair rb, level lev, member mem)
+template <typename T, int OP, int CL>
+__device__ __forceinline__ void rowp_load(const Phase& P, int mem, int rb, int lev, RowRaw<T>& in) {
+  constexpr bool smag = (CL == 1 || CL == 3);
+  constexpr int nbase = smag ? 6 : 4;
+  constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
+  const MemberDev M = member_const(P, mem);
+  const int lg = P.lognx - 3;
+  const int grp = threadIdx.x >> lg;
+  const int j = threadIdx.x & ((1 << lg) - 1);
+  const long long fstride = (long long)P.ny * P.mfp;   // MF field stride
+  const cpx<T>* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
+  c2r_load<T>(in, src, P.mfp, 2 * rb, j, 1 << lg, P.nx, rowp_kin(P, M, lev));
+}
+
+// Right-hand side, B sub-step and adjoint right-hand side: one block per
+// row pair (grid.x), level (grid.y) and member (grid.z).
+template <typename T, int OP, int CL, int LOGN>
+__global__ void __launch_bounds__(1024) k_rowp(Phase P) {
+  using V = cpx<T>;
+  constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  // consecutive row pairs on the same XCD: their interleaved output stores
+  // meet in one L2
+  int rb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  // the two levels of the dynamic closures (grid and test filter) are
+  // independent: one block each
+  const int lev = dyn ? (int)blockIdx.y : 0;
+  RowRaw<T> in;
+  rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
+  V vin[8];
+  rowp_form<T>(P, blockIdx.z, lev, in, vin);
+  // twiddles straight from the (cached) global table: keeping LDS to the
+  // field buffers lets one more block share a compute unit
+  rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, reinterpret_cast<const V*>(P.twx), red, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- colfwd
@@ -974,7 +1047,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + P.W * P.ny;
   __shared__ double red[16];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   const int strip = xcd_order(blockIdx.x, gridDim.x);
   if (strip * P.W >= P.kxn) return;
   const int kx0 = strip * P.W;
@@ -1255,7 +1328,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
                    : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   // W = 1: padded single-vector path (compile-time length if LOGN != 0,
   // twiddles then read from the global table)
   const bool one = LOGN != 0 || P.W == 1;
@@ -1423,7 +1496,7 @@ template <typename T>
 __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   using V = cpx<T>;
   __shared__ double red[2 * (COMBINE_THREADS / 64)];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   double C, hm, mm;
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1471,7 +1544,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
 #if QG_HAS(4)
 __global__ void k_dyn_coef(Phase P, int slot) {
   __shared__ double red[2];   // one 64-thread wave
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   double C, hm, mm;
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
   if (threadIdx.x == 0) rptr<double>(M, P.o_coef)[slot] = C;
@@ -1484,7 +1557,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
   using V = cpx<T>;
   __shared__ double red[16];
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0.0, z = 0.0;
   if (q < P.kxn * P.kyn) {
@@ -1556,7 +1629,7 @@ __global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
 template <typename T>
 __global__ void k_spec_axpy(Phase P, long long o_dst, long long o_src, double a, int zero_first) {
   using V = cpx<T>;
-  const MemberDev& M = P.mem[P.m0 + blockIdx.z];
+  const MemberDev M = member_const(P, blockIdx.z);
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.kxn * P.kyn) return;
   V* d = cptr<T>(M, o_dst);
@@ -1604,9 +1677,6 @@ static int rowp_fields(int op, int cl) {
   const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
   return op == OP_B ? 3 : op == OP_ADJ_RHS ? nbase + (cl == 0 ? 1 : 3) : nbase;
 }
-// Radix-16 row engine (16 points per thread, twiddles in registers).  It
-// needs ~160 VGPRs and measured slower than the radix-8 engine at 1024 on
-// gfx950 (3 vs 6 waves per SIMD), so it is kept selectable but not chosen.
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
   return (size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> 3)) * (dbl ? 16 : 8);
 }
@@ -1618,9 +1688,9 @@ template <typename T, int OP, int CL>
 static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int nb = rowp_fields(OP, CL);
   const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
-  dim3 grid(P.ny / 2, levels, nmem);
   const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
   const dim3 block(nb * P.nx / 8);
+  dim3 grid(P.ny / 2, levels, nmem);
   // compile-time transform lengths for the common row lengths
   switch (P.lognx) {
     case 8: hipLaunchKernelGGL((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P); return;
