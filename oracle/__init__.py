@@ -16,6 +16,8 @@ qg       -- grid, masks D (2/3 rule) and T (test filter), the right-hand side
             diagnostics.
 adjoint  -- the exact discrete adjoint of one step (static closures), and the
             gradient of the a-posteriori vorticity loss.
+ab2cn    -- the paper's own time scheme: AB2CN for the penalized equations,
+            then the AB2 sponge (Sec. II-E, Eq. 4).
 
 Every floating-point operation is in float64.  Each function cites the
 passage of the paper it follows: the QG vorticity equation (Sec. II-A,

@@ -117,6 +117,9 @@ __device__ __forceinline__ int xcd_order(int b, int n) {
 // signed m_y of compact index iy
 __device__ __forceinline__ int my_of_iy(int iy, int myh, int kyn) { return iy <= myh ? iy : iy - kyn; }
 
+__device__ __forceinline__ float qrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double qrcp(double x) { return 1.0 / x; }
+
 // Wavenumbers of mode (mx, my), in the arithmetic type of the run.  The
 // double-precision 1/|k|^2 of the lowest modes (Poisson inversion of 32-bit
 // runs) is formed separately in poisson().
@@ -128,7 +131,8 @@ template <typename T> __device__ __forceinline__ Wave<T> wave(const MemberDev& M
   w.kx = T(M.two_pi_lx) * T(mx);
   w.ky = T(M.two_pi_ly) * T(my);
   w.k2 = w.kx * w.kx + w.ky * w.ky;
-  w.inv_k2 = (mx == 0 && my == 0) ? T(0) : T(1) / w.k2;
+  // 32-bit runs: the hardware reciprocal (about 1 ulp), 64-bit runs: division
+  w.inv_k2 = (mx == 0 && my == 0) ? T(0) : qrcp(w.k2);
   return w;
 }
 
@@ -155,7 +159,7 @@ __device__ __forceinline__ int test_mylim(const MemberDev& M, int nx, int ny, in
 template <typename T>
 __device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave<T>& w, int mx, int my) {
   using V = cpx<T>;
-  if (sizeof(T) == 4 && (double)w.k2 <= M.lowk2 && (mx | my) != 0) {
+  if (sizeof(T) == 4 && w.k2 <= T(M.lowk2) && (mx | my) != 0) {
     const double kx = M.two_pi_lx * mx, ky = M.two_pi_ly * my;
     const double ik2 = 1.0 / (kx * kx + ky * ky);
     return cmake<V>(T(-(double)x.x * ik2), T(-(double)x.y * ik2));
@@ -202,7 +206,7 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
                                                int mylim = -2) {
   using V = cpx<T>;
   const int my = my_of_iy(iy, P.myh, P.kyn);
-  const long long idx = (long long)mx * P.kyn + iy;
+  const int idx = mx * P.kyn + iy;   // < 2^31 for every admissible size
   const Wave<T> w = wave<T>(M, mx, my);
   const bool zero_mean = (mx == 0 && my == 0);
   if constexpr (OP == OP_RHS || OP == OP_DIAG) {
@@ -1379,7 +1383,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     const int mx = kx0 + w;
     if (mx >= P.kxn) continue;
     const int my = my_of_iy(iy, P.myh, P.kyn);
-    const long long id = (long long)mx * P.kyn + iy;
+    const int id = mx * P.kyn + iy;
     if constexpr (OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD) {
       V v = at(0, w, iy);
       if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));

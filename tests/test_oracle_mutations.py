@@ -75,3 +75,28 @@ def test_fft_hermitian_weight_is_caught(monkeypatch):
     mod = mutated("fft", "full[..., 0] = cols[..., 0].real", "full[..., 0] = 2 * cols[..., 0].real")
     monkeypatch.setattr(pins_fft, "F", mod)
     must_fail(pins_fft.test_irfft2_against_definition, 8, 8)
+
+
+import tests.test_oracle_ab2cn as pins_ab2  # noqa: E402
+
+AB2CN_MUTATIONS = [
+    ("ab2 weights", "dt * (1.5 * N - 0.5 * Nm)", "dt * (1.0 * N - 0.0 * Nm)",
+     pins_ab2.test_ab2_advection_by_the_inflow),
+    ("crank-nicolson half", "wh * (1.0 + 0.5 * dt * L)", "wh * (1.0 + dt * L)",
+     lambda: pins_ab2.test_crank_nicolson_single_mode(50.0, 0.3, 2.0)),
+    ("penalty curl sign", "- 1j * g.ky * g.spec(m.chi * u)", "+ 1j * g.ky * g.spec(m.chi * u)",
+     pins_ab2.test_ab2_brinkman_constant_mask),
+    ("velocity history", "1.5 * u - 0.5 * um", "1.5 * u - 0.5 * u",
+     pins_ab2.test_ab2_brinkman_constant_mask),
+    ("sponge history", "(1.5 * ws - 0.5 * wss)", "(1.5 * ws - 0.5 * ws)",
+     pins_ab2.test_ab2_sponge_constant_profile),
+    ("rossby sign", "+ 1j * p.beta * g.kx * g.inv_k2", "- 1j * p.beta * g.kx * g.inv_k2",
+     pins_ab2.test_rossby_phase_and_modulus),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", AB2CN_MUTATIONS, ids=[m[0] for m in AB2CN_MUTATIONS])
+def test_ab2cn_mutation_is_caught(monkeypatch, name, old, new, pin):
+    mod = mutated("ab2cn", old, new)
+    monkeypatch.setattr(pins_ab2, "ab2cn", mod)
+    must_fail(pin)
