@@ -15,11 +15,21 @@
  * a uniform inflow (u_in, v_in) is added to the zeroth Fourier mode of the
  * velocity (Sec. II-D).
  *
- * Time step (splitting of Sec. II-E): classical RK4 over advection, beta,
- * viscosity and closure, then an exactly integrated sub-step applying the
- * penalization (curl of u <- exp(-dt chi/eta) u, product rule) and then the
- * sponge (omega <- exp(-dt sigma chi_s) omega), evaluated pointwise in
- * physical space and projected back onto the 2/3 set.
+ * Time step (splitting of Sec. II-E), selected per member by `scheme`:
+ *  QG_SCHEME_RK4: classical RK4 over advection, beta, viscosity and
+ *    closure, then an exactly integrated sub-step applying the penalization
+ *    (curl of u <- exp(-dt chi/eta) u, product rule) and then the sponge
+ *    (omega <- exp(-dt sigma chi_s) omega), evaluated pointwise in physical
+ *    space and projected back onto the 2/3 set;
+ *  QG_SCHEME_AB2CN: the paper's own scheme (Eq. 4): Crank-Nicolson on the
+ *    linear terms (viscosity, friction, beta), second-order Adams-Bashforth
+ *    on the Jacobian, the closure and the penalization curl(chi u / eta),
+ *    then the sponge by Adams-Bashforth 2 on omega* and the previous step's
+ *    omega**.  Explicit penalization needs eta > dt.  The scheme carries
+ *    history inside the handle (the previous explicit terms and omega**):
+ *    the first step after qg_init is forward Euler on the explicit parts,
+ *    and later qg_step calls continue the sequence, so the omega passed in
+ *    must be the one the previous call returned.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -56,6 +66,11 @@ enum {
 };
 
 enum {
+    QG_SCHEME_RK4 = 0,     /* RK4 + exactly integrated penalization/sponge    */
+    QG_SCHEME_AB2CN = 1    /* AB2CN + AB2 sponge, Sec. II-E, Eq. 4            */
+};
+
+enum {
     QG_CLOSURE_NONE = 0,
     QG_CLOSURE_SMAG = 1,   /* nu_e = (c Delta)^2 |S|,  Eq. 9                   */
     QG_CLOSURE_LEITH = 2,  /* nu_e = (c Delta)^3 |grad omega|, Eq. 12          */
@@ -82,7 +97,9 @@ enum {
  *  clip_mode    0: C = max(<HM>, 0)/<M^2>.  1 (pointwise H+) is not
  *               implemented on the GPU and returns QG_EUNSUPPORTED.
  *  fp64_lowk    in 32-bit runs, modes with |k| <= fp64_lowk invert the
- *               Poisson equation in double precision                       */
+ *               Poisson equation in double precision
+ *  scheme       QG_SCHEME_*.  QG_SCHEME_AB2CN needs nx >= 64 (and
+ *               nx, ny <= 2048 in 64-bit runs); it has no adjoint.        */
 typedef struct {
     int32_t nx, ny;
     double lx, ly, beta, re, mu, u_in, v_in, eta, sponge_sigma, dt, c;
@@ -91,6 +108,7 @@ typedef struct {
     double test_ratio;
     int32_t clip_mode;
     int32_t fp64_lowk;
+    int32_t scheme;
 } qg_params;
 
 typedef struct qg_handle qg_handle;
@@ -125,7 +143,8 @@ int qg_init(const qg_params* params, int32_t n_members,
 int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
             void* ckpt_out, int32_t use_graph, void* hip_stream);
 
-/* Discrete adjoint of qg_step over one segment (static closures only).
+/* Discrete adjoint of qg_step over one segment (static closures and
+ * QG_SCHEME_RK4 only).
  * omega_ckpt: omega at the segment start (as saved by qg_step);
  * lambda: on entry dL/d omega at the segment end, on return dL/d omega at
  * the segment start (both physical, same layout as omega);
@@ -150,12 +169,15 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
 
 /* Time candidate FFT tilings for every size group on hip_stream and keep
  * the fastest; results are cached in the JSON file at cache_path (nullable:
- * no file).  Synchronises hip_stream. */
+ * no file).  The timed steps run on the workspace: the spectral state is
+ * not meaningful afterwards (the next qg_step enters omega again) and the
+ * history of QG_SCHEME_AB2CN members starts again (forward-Euler first
+ * step).  Synchronises hip_stream. */
 int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
 
-/* Profiling: launch one kernel of the step `reps` times on hip_stream, on
- * the handle's current workspace contents (call after qg_step; the state it
- * leaves is not meaningful).  phase: 0 column-inverse of the right-hand
+/* Profiling: launch one kernel of the RK4 step `reps` times on hip_stream,
+ * on the handle's current workspace contents (call after qg_step; the state
+ * it leaves is not meaningful).  QG_SCHEME_AB2CN groups are skipped.  phase: 0 column-inverse of the right-hand
  * side, 1 row pass of the right-hand side, 2 column-forward of the
  * right-hand side, 3 dynamic combine (dynamic closures), 4 column-inverse of
  * the B sub-step, 5 row pass of the B sub-step, 6 column-forward of the B

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_PKG, "libqg.so")
 
 QG_OK, QG_EINVAL, QG_EUNSUPPORTED, QG_EWORKSPACE, QG_EHIP, QG_ESTATE = range(6)
 CLOSURES = {"none": 0, "smag": 1, "leith": 2, "dsmag": 3, "dleith": 4}
+SCHEMES = {"rk4": 0, "ab2cn": 1}
 
 EXPORTS = ["qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag",
            "qg_set_coef", "qg_autotune", "qg_run_phase", "qg_info", "qg_destroy", "qg_last_error"]
@@ -25,7 +26,7 @@ class QGParams(ctypes.Structure):
                 ("sponge_sigma", ctypes.c_double), ("dt", ctypes.c_double), ("c", ctypes.c_double),
                 ("closure", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("test_ratio", ctypes.c_double), ("clip_mode", ctypes.c_int32),
-                ("fp64_lowk", ctypes.c_int32)]
+                ("fp64_lowk", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class QGError(RuntimeError):
@@ -88,4 +89,6 @@ def make_params(d):
     p.test_ratio = float(d.get("test_ratio", 2))
     p.clip_mode = int(d.get("clip_mode", 0))
     p.fp64_lowk = int(d.get("fp64_lowk", 8))
+    sc = d.get("scheme", 0)
+    p.scheme = SCHEMES[sc] if isinstance(sc, str) else int(sc)
     return p

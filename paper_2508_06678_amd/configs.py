@@ -99,6 +99,16 @@ def config3(precision=32, n=1024, seed=2):
     return Workload(f"C3 cape {n}x{n} dleith", [m], 1000)
 
 
+def ab2cn_island(precision=64, nx=128, ny=64, closure="smag", dt=2e-3):
+    """The island channel of config 1 under the paper's own time scheme
+    (AB2CN + AB2 sponge, Sec. II-E): explicit penalization needs eta > dt,
+    so eta = 2.5 dt."""
+    m = island_member(nx, ny, precision=precision, beta=1.0, re=1e3, dt=dt,
+                      eta=2.5 * dt, xc=1.5, radius=0.3, closure=closure, seed=0, rms=0.1)
+    m.params["scheme"] = "ab2cn"
+    return Workload(f"AB2CN island {nx}x{ny} {closure}", [m], 200)
+
+
 def config4(precision=32, sizes=((256, 128, 32), (512, 256, 24), (1024, 512, 8))):
     """Batched ensemble of uneven grids, closures drawn uniformly, 500 steps."""
     rng = np.random.default_rng(4)

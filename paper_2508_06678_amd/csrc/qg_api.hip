@@ -62,12 +62,20 @@ static int validate(const qg_params& p, int idx) {
   if (p.eta == 0.0 || std::isnan(p.eta)) return bad(QG_EINVAL, "eta must be positive (or inf to disable)");
   if (p.eta < 0) return bad(QG_EINVAL, "eta must be positive (or inf to disable)");
   if (p.fp64_lowk < 0) return bad(QG_EINVAL, "fp64_lowk must be >= 0");
+  if (p.scheme != QG_SCHEME_RK4 && p.scheme != QG_SCHEME_AB2CN) return bad(QG_EINVAL, "unknown scheme");
+  if (p.scheme == QG_SCHEME_AB2CN) {
+    // the penalization and sponge passes run on the field-parallel kernels only
+    if (p.nx < 64) return bad(QG_EUNSUPPORTED, "the AB2CN scheme needs nx >= 64");
+    if (p.precision == 64 && (p.nx > 2048 || p.ny > 2048))
+      return bad(QG_EUNSUPPORTED, "the AB2CN scheme in 64-bit runs needs nx, ny <= 2048");
+  }
   return QG_OK;
 }
 
 // ------------------------------------------------------------ plans
 struct Group {
   int nx, ny, lognx, logny, closure;
+  int scheme;                    // QG_SCHEME_*
   bool dbl;
   int kxn, myh, kyn, W, logW, kxp, RP, logRP;
   int kxn_f, myh_f, kyn_f, kxp_f;
@@ -154,6 +162,13 @@ static void plan_sizes(Group& g, int adjK) {
   L.wn = take(spec);
   L.acc = take(spec);
   L.x = take(spec);
+  if (g.scheme == QG_SCHEME_AB2CN) {
+    L.ab_pen = take(spec);
+    L.ab_hist = take(spec);
+    L.ab_wss = take(spec);
+  } else {
+    L.ab_pen = L.ab_hist = L.ab_wss = -1;
+  }
   L.jsp = take(spec);
   L.qsp = take(spec);
   L.chih = take((long long)g.kxn_f * g.kyn_f * cs);
@@ -196,7 +211,8 @@ struct Handle {
 };
 
 static bool same_group(const qg_params& a, const qg_params& b) {
-  return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.closure == b.closure;
+  return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.closure == b.closure &&
+         a.scheme == b.scheme;
 }
 
 // Everything qg_workspace_bytes and qg_init share: grouping, layout.
@@ -227,6 +243,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
       g.nx = params[i].nx;
       g.ny = params[i].ny;
       g.closure = params[i].closure;
+      g.scheme = params[i].scheme;
       g.dbl = params[i].precision == 64;
       plan_sizes(g, adjK);
       h.groups.push_back(g);
@@ -403,7 +420,57 @@ static int run_b(const Handle& h, const Group& g, hipStream_t st) {
   return QG_OK;
 }
 
+// One step of the paper's scheme (Sec. II-E, Eq. 4) for an AB2CN group:
+// D curl(chi u^t) (penalization pass), the nonlinear terms at omega^t and
+// the AB2CN update to omega* (right-hand-side pass), the AB2 sponge from
+// omega* and omega** back to w_n (sponge pass), then omega** <- omega*.
+static int run_ab2cn_step(const Handle& h, const Group& g, hipStream_t st) {
+  const int cl = g.closure;
+  // penalization: u', v' at omega^t -> chi (U + u'), chi (V + v') -> curl
+  Phase Pp = base_phase(h, g);
+  Pp.nf = 2;
+  Pp.o_in = g.L.wn;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, Pp, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_PEN, 0, Pp, g.count, st));
+  Pp.o_out = g.L.ab_pen;
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_PEN, 0, Pp, g.count, st));
+  // nonlinear terms and the CN / AB2 update: omega^t = wn -> omega* = x
+  Phase P = base_phase(h, g);
+  P.stage = AB2CN_STAGE;
+  P.nf = rhs_fields(cl);
+  P.o_in = g.L.wn;
+  P.o_ab_pen = g.L.ab_pen;
+  P.o_ab_hist = g.L.ab_hist;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+  if (!dynamic_closure(cl)) {
+    P.o_in = g.L.x;
+    P.o_in2 = g.L.wn;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+  } else {
+    P.o_out = g.L.jsp;
+    P.o_aux = g.L.qsp;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    P.o_in = g.L.x;
+    P.o_in2 = g.L.wn;
+    QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
+  }
+  // sponge: omega*, omega** -> omega^{t+1} on D -> wn
+  Phase Ps = base_phase(h, g);
+  Ps.nf = 2;
+  Ps.o_in = g.L.x;
+  Ps.o_in2 = g.L.ab_wss;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_SPONGE, 0, Ps, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_SPONGE, 0, Ps, g.count, st));
+  Ps.o_out = g.L.wn;
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, Ps, g.count, st));
+  Ps.o_out = g.L.ab_wss;
+  QG_LAUNCH(launch_ab2cn_finish(g.dbl, Ps, g.count, st));
+  return QG_OK;
+}
+
 static int run_step(const Handle& h, const Group& g, hipStream_t st) {
+  if (g.scheme == QG_SCHEME_AB2CN) return run_ab2cn_step(h, g, st);
   for (int s = 1; s <= 4; ++s) {
     int rc = run_stage(h, g, s, st);
     if (rc) return rc;
@@ -834,9 +901,12 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
   if (!omega_ckpt || !lambda || !grad_c) return fail(QG_EINVAL, "NULL argument");
   if (h.adjK <= 0) return fail(QG_ESTATE, "handle was built without adjoint storage (adj_segment_k = 0)");
   if (nsteps < 1 || nsteps > h.adjK) return fail(QG_EINVAL, "nsteps must be in [1, adj_segment_k]");
-  for (const auto& g : h.groups)
+  for (const auto& g : h.groups) {
     if (dynamic_closure(g.closure))
       return fail(QG_EUNSUPPORTED, "the adjoint covers the static closures only");
+    if (g.scheme != QG_SCHEME_RK4)
+      return fail(QG_EUNSUPPORTED, "the adjoint covers the RK4 scheme only");
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // outside the graph: the caller's fields in, the dL/dc slots cleared
   for (const auto& g : h.groups) {
@@ -915,6 +985,7 @@ int qg_run_phase(qg_handle* H, int32_t phase, int32_t stage, int32_t reps, void*
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   for (int r = 0; r < reps; ++r) {
     for (const auto& g : h.groups) {
+      if (g.scheme != QG_SCHEME_RK4) continue;   // the phases are those of the RK4 step
       const int cl = g.closure;
       Phase P = base_phase(h, g);
       P.stage = stage;
@@ -1003,6 +1074,14 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  // the timed steps advanced the AB2CN members' history: start it again
+  for (const auto& g : h.groups) {
+    if (g.scheme != QG_SCHEME_AB2CN) continue;
+    for (int k = 0; k < g.count; ++k) {
+      char* flag = h.table[g.m0 + k].base + g.L.coef + AB2CN_FLAG_SLOT * (long long)sizeof(double);
+      QG_HIP(launch_fill_zero(flag, sizeof(double), st));
+    }
+  }
   for (auto& kv : h.graphs) (void)hipGraphExecDestroy(kv.second);
   h.graphs.clear();
   for (auto& kv : h.adj_graphs) (void)hipGraphExecDestroy(kv.second);

@@ -21,8 +21,15 @@ enum Op : int {
   OP_ADJ_RHS = 7,   // adjoint of the right-hand side (static closures)
   OP_ADJ_B = 8,     // adjoint of the B sub-step
   OP_ADJ_EXIT = 9,  // adjoint of the exit transform (physical -> spectral)
-  OP_ADJ_ENTRY = 10 // adjoint of the entry transform (spectral -> physical)
+  OP_ADJ_ENTRY = 10,// adjoint of the entry transform (spectral -> physical)
+  OP_PEN = 11,      // AB2CN: D curl(chi u) of the total velocity
+  OP_SPONGE = 12    // AB2CN: omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
 };
+
+// RK stage code of the AB2CN update in the column-forward / combine passes
+constexpr int AB2CN_STAGE = 9;
+// coefficient slot of the AB2CN history flag (0: no history yet)
+constexpr int AB2CN_FLAG_SLOT = 30;
 
 // Per-member constants, resident on the device.
 struct MemberDev {
@@ -49,6 +56,7 @@ struct MemberDev {
 // (members of a group share sizes, hence offsets).
 struct RegionLayout {
   long long wn, acc, x, jsp, qsp, chih, mf, mp, phys, part, coef, dpart;
+  long long ab_pen, ab_hist, ab_wss;               // AB2CN: D curl(chi u), explicit terms, omega**
   long long adj_lam, adj_lacc, adj_lk, adj_store;  // adjoint buffers
   long long total;
 };
@@ -67,6 +75,7 @@ struct Phase {
   int stage;              // RK stage 1..4 (0: not a stage)
   int nparts;             // partial-sum slots written by the column-forward pass
   long long o_in, o_in2, o_out, o_aux;  // op-specific byte offsets
+  long long o_ab_pen, o_ab_hist;        // AB2CN: penalization curl, explicit-term history
   long long o_mf, o_mp, o_phys, o_part, o_coef, o_dpart;
   const void* twx;        // twiddles exp(-2 pi i m / nx)
   const void* twy;        // twiddles exp(-2 pi i m / ny)
@@ -99,6 +108,7 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, double a, int zero_first, hipStream_t s);
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, hipStream_t s);
+hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int nmem, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Field counts per phase and closure.
@@ -106,5 +116,18 @@ __host__ __device__ constexpr int rhs_fields(int cl) { return cl == 0 || cl == 2
 __host__ __device__ inline int rhs_products(int cl) { return cl == 0 ? 1 : (cl == 1 || cl == 2) ? 3 : 6; }
 __host__ __device__ inline bool smag_family(int cl) { return cl == 1 || cl == 3; }
 __host__ __device__ constexpr bool dynamic_closure(int cl) { return cl == 3 || cl == 4; }
+
+// Fields (thread groups) and products of the field-parallel row pass.
+__host__ __device__ constexpr int rowp_nb(int op, int cl) {
+  return op == OP_B ? 3
+       : (op == OP_PEN || op == OP_SPONGE) ? 2
+       : op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4) + (cl == 0 ? 1 : 3)
+       : ((cl == 1 || cl == 3) ? 6 : 4);
+}
+__host__ __device__ constexpr int rowp_np(int op, int cl) {
+  return op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4)
+       : op == OP_PEN ? 2
+       : (op == OP_B || op == OP_SPONGE || cl == 0) ? 1 : 3;
+}
 
 }  // namespace qg

@@ -223,6 +223,11 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
   } else if constexpr (OP == OP_EXIT) {
     V x = gld(cptr<T>(M, P.o_in) + idx);
     return zero_mean ? cmake<V>(T(0), T(0)) : x;
+  } else if constexpr (OP == OP_SPONGE) {
+    // field 0: omega*, field 1: omega** (omega* itself before any history)
+    const bool first = rptr<double>(M, P.o_coef)[AB2CN_FLAG_SLOT] == 0.0;
+    V x = gld(cptr<T>(M, (f == 0 || first) ? P.o_in : P.o_in2) + idx);
+    return zero_mean ? cmake<V>(T(0), T(0)) : x;
   } else if constexpr (OP == OP_MASKGRAD) {
     V x = gld(cptr<T>(M, P.o_in) + idx);
     return f == 0 ? mul_ia(x, T(w.kx)) : mul_ia(x, T(w.ky));
@@ -788,7 +793,23 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
   constexpr int nbase = smag ? 6 : 4;
   const int nx = P.nx;
   auto F = [&](int f) -> V { return buf[f * bstride + q + (q >> PADS)]; };
-  if constexpr (OP == OP_B) {
+  if constexpr (OP == OP_PEN) {
+    // chi times the total velocity: product 0 chi (U + u'), 1 chi (V + v')
+    const long long a = (long long)ya * nx + q, b = a + nx;
+    const T* chi = rptr<T>(M, P.o_phys) + 4LL * nx * P.ny;
+    const V vel = F(grp);
+    const T base = grp == 0 ? U : Vv;
+    return cmake<V>(chi[a] * (base + vel.x), chi[b] * (base + vel.y));
+  } else if constexpr (OP == OP_SPONGE) {
+    // omega^{t+1} = omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
+    const long long a = (long long)ya * nx + q, b = a + nx;
+    const T* chs = rptr<T>(M, P.o_phys) + 5LL * nx * P.ny;
+    const T sa = T(M.sponge_a);
+    const V ws = F(0), wss = F(1);
+    const T r0 = ws.x - sa * chs[a] * (T(1.5) * ws.x - T(0.5) * wss.x);
+    const T r1 = ws.y - sa * chs[b] * (T(1.5) * ws.y - T(0.5) * wss.y);
+    return cmake<V>(r0, r1);
+  } else if constexpr (OP == OP_B) {
     // omega'' = S (E omega + E_x v - E_y u), total velocity
     const long long nxy = (long long)nx * P.ny;
     const T* E = rptr<T>(M, P.o_phys);
@@ -904,10 +925,7 @@ template <typename T, int OP, int CL, int LOGN>
 __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int lev, const cpx<T> (&vin)[8],
                                           cpx<T>* buf, const cpx<T>* twl, double* red, int item_slot) {
   using V = cpx<T>;
-  constexpr bool smag = (CL == 1 || CL == 3);
-  constexpr int nbase = smag ? 6 : 4;
-  constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
-  constexpr int np = OP == OP_ADJ_RHS ? nbase : (OP == OP_B || CL == 0) ? 1 : 3;
+  constexpr int np = rowp_np(OP, CL);
   constexpr int EPT = 8;                       // points per thread
   constexpr int PADS = LOGN ? QG_ROW_PADS : 3;  // one pad slot per 2^PADS
   const MemberDev M = member_const(P, mem);
@@ -991,9 +1009,7 @@ __device__ __forceinline__ void rowp_form(const Phase& P, int mem, int lev, cons
 // c2r loads of the item's field (row pair rb, level lev, member mem)
 template <typename T, int OP, int CL>
 __device__ __forceinline__ void rowp_load(const Phase& P, int mem, int rb, int lev, RowRaw<T>& in) {
-  constexpr bool smag = (CL == 1 || CL == 3);
-  constexpr int nbase = smag ? 6 : 4;
-  constexpr int nb = OP == OP_B ? 3 : OP == OP_ADJ_RHS ? nbase + (CL == 0 ? 1 : 3) : nbase;
+  constexpr int nb = rowp_nb(OP, CL);
   const MemberDev M = member_const(P, mem);
   const int lg = P.lognx - 3;
   const int grp = threadIdx.x >> lg;
@@ -1026,6 +1042,53 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   // twiddles straight from the (cached) global table: keeping LDS to the
   // field buffers lets one more block share a compute unit
   rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, reinterpret_cast<const V*>(P.twx), red, blockIdx.x);
+}
+
+// ---------------------------------------------------------------- AB2CN
+// One AB2CN step at a mode (Sec. II-E, Eq. 4), given the nonlinear terms
+// N = -J_hat + C Q_hat at omega^t: the explicit terms E = N - (1/eta) D
+// curl(chi u) (o_ab_pen) go through Adams-Bashforth 2 against the previous
+// step's (o_ab_hist; E itself before any history), the linear terms
+// L = -(|k|^2/Re + mu) + i beta kx/|k|^2 through Crank-Nicolson:
+//   omega* = (omega^t (1 + dt/2 L) + dt (3/2 E - 1/2 E_prev)) / (1 - dt/2 L).
+// omega^t from o_in2, omega* to o_in; E replaces the history.  The CN
+// factors are formed in double precision.
+template <typename T>
+__device__ __forceinline__ void ab2cn_update(const MemberDev& M, const Phase& P, int id, int mx, int my, cpx<T> N) {
+  using V = cpx<T>;
+  const double dt = M.dt;
+  const V pen = gld(cptr<T>(M, P.o_ab_pen) + id);
+  const T pa = T(M.pen_a / dt);                  // 1/eta
+  const V E = csub(N, cscale(pen, pa));
+  V* hist = cptr<T>(M, P.o_ab_hist) + id;
+  const bool first = rptr<double>(M, P.o_coef)[AB2CN_FLAG_SLOT] == 0.0;
+  const V Ep = first ? E : gld(hist);
+  gst(hist, E);
+  const V w = gld(cptr<T>(M, P.o_in2) + id);
+  V out = cmake<V>(T(0), T(0));
+  if (mx != 0 || my != 0) {
+    const double kx = M.two_pi_lx * mx, ky = M.two_pi_ly * my;
+    const double k2 = kx * kx + ky * ky;
+    const double lr = -(k2 * M.inv_re + M.mu), li = M.beta * kx / k2;
+    const double ar = 1.0 + 0.5 * dt * lr, ai = 0.5 * dt * li;     // 1 + dt/2 L
+    const double dr = 1.0 - 0.5 * dt * lr, di = -0.5 * dt * li;    // 1 - dt/2 L
+    const double nr = (double)w.x * ar - (double)w.y * ai + dt * (1.5 * (double)E.x - 0.5 * (double)Ep.x);
+    const double ni = (double)w.x * ai + (double)w.y * ar + dt * (1.5 * (double)E.y - 0.5 * (double)Ep.y);
+    const double den = dr * dr + di * di;
+    out = cmake<V>(T((nr * dr + ni * di) / den), T((ni * dr - nr * di) / den));
+  }
+  gst(cptr<T>(M, P.o_in) + id, out);
+}
+
+// End of an AB2CN step: omega* becomes the next step's omega** and the
+// history flag is set (after the sponge pass has read the old omega**).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ab2cn_finish(Phase P) {
+  using V = cpx<T>;
+  const MemberDev M = member_const(P, blockIdx.z);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < P.kxn * P.kyn) gst(cptr<T>(M, P.o_out) + q, gld(cptr<T>(M, P.o_in) + q));
+  if (blockIdx.x == 0 && threadIdx.x == 0) rptr<double>(M, P.o_coef)[AB2CN_FLAG_SLOT] = 1.0;
 }
 
 // ---------------------------------------------------------------- colfwd
@@ -1329,7 +1392,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int np = OP == OP_RHS ? (CL == 0 ? 1 : dyn ? 6 : 3)
-                   : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : 1;
+                   : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : OP == OP_PEN ? 2 : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev M = member_const(P, blockIdx.z);
@@ -1388,6 +1451,12 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       V v = at(0, w, iy);
       if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
       gst(cptr<T>(M, P.o_out) + id, v);
+    } else if constexpr (OP == OP_PEN) {
+      // D curl(chi u) = i kx F(chi v) - i ky F(chi u)
+      const Wave<T> wv = wave<T>(M, mx, my);
+      V v = csub(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(0, w, iy), wv.ky));
+      if (mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
+      gst(cptr<T>(M, P.o_out) + id, v);
     } else if constexpr (OP == OP_ADJ_B) {
       // lambda_s = F(l_w) - (i ky F(l_u) - i kx F(l_v)) / |k|^2 -> LS, LW, LK = dt/6 LS
       const Wave<T> wv = wave<T>(M, mx, my);
@@ -1420,6 +1489,16 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       }
     } else if constexpr (!dyn) {
       const Wave<T> wv = wave<T>(M, mx, my);
+      if (P.stage == AB2CN_STAGE) {
+        const V j = at(0, w, iy);
+        V N = cmake<V>(-j.x, -j.y);
+        if constexpr (CL != 0) {
+          const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
+          N = cadd(N, cscale(Q, T(M.coef_static)));
+        }
+        ab2cn_update<T>(M, P, id, mx, my, N);
+        continue;
+      }
       const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
       const V x = gld(xin + id);
       const V j = at(0, w, iy);
@@ -1517,6 +1596,11 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   const Wave<T> w = wave<T>(M, mx, my);
   const V* jsp = cptr<T>(M, P.o_out);
   const V* qsp = cptr<T>(M, P.o_aux);
+  if (P.stage == AB2CN_STAGE) {
+    const V j = jsp[q];
+    ab2cn_update<T>(M, P, q, mx, my, cadd(cmake<V>(-j.x, -j.y), cscale(qsp[q], T(C))));
+    return;
+  }
   const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
   const V* wn = cptr<T>(M, P.o_in2);
   V* acc = cptr<T>(M, P.o_mp);   // accumulator offset passed in o_mp for this kernel
@@ -1677,10 +1761,7 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   }
   hipLaunchKernelGGL((k_colinv<T, OP, CL, 0>), grid, block, coli_smem(sizeof(T) == 8, P), s, P);
 }
-static int rowp_fields(int op, int cl) {
-  const int nbase = (cl == 1 || cl == 3) ? 6 : 4;
-  return op == OP_B ? 3 : op == OP_ADJ_RHS ? nbase + (cl == 0 ? 1 : 3) : nbase;
-}
+static int rowp_fields(int op, int cl) { return rowp_nb(op, cl); }
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
   return (size_t)rowp_fields(op, cl) * (P.nx + (P.nx >> 3)) * (dbl ? 16 : 8);
 }
@@ -1706,6 +1787,11 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
+  if constexpr (OP == OP_PEN || OP == OP_SPONGE) {
+    // field-parallel kernel only (the sizes it cannot take are refused at init)
+    if (rowp_ok(sizeof(T) == 8, OP, CL, P)) launch_rowp_t<T, OP, CL>(P, nmem, s);
+    return;
+  }
   if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ADJ_RHS) {
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) { launch_rowp_t<T, OP, CL>(P, nmem, s); return; }
   }
@@ -1715,6 +1801,7 @@ static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
 static int colfwdp_products(int op, int cl) {
   if (op == OP_RHS) return cl == 0 ? 1 : (cl == 3 || cl == 4) ? 6 : 3;
   if (op == OP_ADJ_B) return 3;
+  if (op == OP_PEN) return 2;
   if (op == OP_ADJ_RHS) return cl == 1 ? 6 : 4;
   return 1;
 }
@@ -1744,6 +1831,11 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
+  if constexpr (OP == OP_PEN) {
+    // product-parallel kernel only (the sizes it cannot take are refused at init)
+    if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) launch_colfwdp_t<T, OP, CL>(P, nmem, s);
+    return;
+  }
   if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ENTRY || OP == OP_MASKFWD || OP == OP_ADJ_B ||
                 OP == OP_ADJ_RHS) {
     if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) { launch_colfwdp_t<T, OP, CL>(P, nmem, s); return; }
@@ -1776,6 +1868,7 @@ template <typename T> void colinv_dispatch(int op, int cl, const Phase& P, int n
     case OP_B: launch_colinv_t<T, OP_B, 0>(P, n, s); break;
     case OP_EXIT: case OP_ADJ_ENTRY: launch_colinv_t<T, OP_EXIT, 0>(P, n, s); break;
     case OP_MASKGRAD: launch_colinv_t<T, OP_MASKGRAD, 0>(P, n, s); break;
+    case OP_SPONGE: launch_colinv_t<T, OP_SPONGE, 0>(P, n, s); break;
     case OP_ADJ_B: launch_colinv_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colinv_t, T, OP_ADJ_RHS, cl, P, n, s); break;
     default: break;
@@ -1789,6 +1882,8 @@ template <typename T> void row_dispatch(int op, int cl, const Phase& P, int n, h
     case OP_ENTRY: case OP_ADJ_EXIT: launch_row_t<T, OP_ENTRY, 0>(P, n, s); break;
     case OP_EXIT: case OP_ADJ_ENTRY: launch_row_t<T, OP_EXIT, 0>(P, n, s); break;
     case OP_MASKFWD: launch_row_t<T, OP_MASKFWD, 0>(P, n, s); break;
+    case OP_PEN: launch_row_t<T, OP_PEN, 0>(P, n, s); break;
+    case OP_SPONGE: launch_row_t<T, OP_SPONGE, 0>(P, n, s); break;
     case OP_MASKGRAD: launch_row_t<T, OP_MASKGRAD, 0>(P, n, s); break;
     case OP_ADJ_B: launch_row_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_row_t, T, OP_ADJ_RHS, cl, P, n, s); break;
@@ -1801,6 +1896,7 @@ template <typename T> void colfwd_dispatch(int op, int cl, const Phase& P, int n
     case OP_B: launch_colfwd_t<T, OP_B, 0>(P, n, s); break;
     case OP_ENTRY: case OP_ADJ_EXIT: launch_colfwd_t<T, OP_ENTRY, 0>(P, n, s); break;
     case OP_MASKFWD: launch_colfwd_t<T, OP_MASKFWD, 0>(P, n, s); break;
+    case OP_PEN: launch_colfwd_t<T, OP_PEN, 0>(P, n, s); break;
     case OP_ADJ_B: launch_colfwd_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colfwd_t, T, OP_ADJ_RHS, cl, P, n, s); break;
     default: break;
@@ -1883,6 +1979,12 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int n, long long o_dst, lo
 }
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int n, long long o_dst, long long o_src, hipStream_t s) {
   return launch_spec_axpy(dbl, P, n, o_dst, o_src, 0.0, 1, s);
+}
+hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {
+  dim3 grid((P.kxn * P.kyn + 255) / 256, 1, n);
+  if (dbl) hipLaunchKernelGGL(k_ab2cn_finish<double>, grid, dim3(256), 0, s, P);
+  else hipLaunchKernelGGL(k_ab2cn_finish<float>, grid, dim3(256), 0, s, P);
+  return hipGetLastError();
 }
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   size_t n = bytes / 4;

@@ -44,6 +44,12 @@ def ws(params, adj=0):
     return rc, size.value
 
 
+def test_ab2cn_workspace_holds_its_history():
+    rc, b_rk4 = ws([good()])
+    rc2, b_ab = ws([good(scheme="ab2cn")])
+    assert rc == 0 and rc2 == 0 and b_ab > b_rk4
+
+
 def test_workspace_bytes_valid_and_monotone():
     rc, b1 = ws([good()])
     assert rc == 0 and b1 > 0
@@ -70,6 +76,9 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(eta=-1.0), _lib.QG_EINVAL),
     (dict(beta=float("nan")), _lib.QG_EINVAL),
     (dict(sponge_sigma=-1.0), _lib.QG_EINVAL),
+    (dict(scheme=2), _lib.QG_EINVAL),
+    (dict(scheme="ab2cn", nx=32, ny=32, lx=2 * math.pi, ly=2 * math.pi), _lib.QG_EUNSUPPORTED),
+    (dict(scheme="ab2cn", nx=4096, ny=2048, lx=2 * math.pi, ly=math.pi), _lib.QG_EUNSUPPORTED),
 ])
 def test_invalid_parameters_are_rejected(bad, code):
     rc, _ = ws([good(**bad)])

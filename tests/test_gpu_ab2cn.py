@@ -1,0 +1,100 @@
+"""GPU parity of the paper's own time scheme (AB2CN + AB2 sponge, Sec. II-E,
+Eq. 4) against the oracle (oracle/ab2cn.py), which is pinned by
+test_oracle_ab2cn.py.
+
+The scheme carries history (previous explicit terms and omega**), so the GPU
+and the oracle run the same sequence in lockstep from the same start and are
+compared after every step (relative L2 of the physical vorticity): FP64 to
+1e-12, FP32 to 1e-5 per step elapsed.
+"""
+import numpy as np
+import pytest
+
+from oracle import ab2cn, qg
+from paper_2508_06678_amd import configs
+from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def lockstep(S, m, precision, shape, nsteps, use_graph):
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    wh = qg.enter(to_np(om).reshape(shape), M.g)
+    hist = None
+    worst = 0.0
+    for n in range(1, nsteps + 1):
+        S.step(om, 1, use_graph=use_graph)
+        wh, hist = ab2cn.step_spectral(wh, hist, M)
+        err = rel_l2(to_np(om).reshape(shape), qg.leave(wh, M.g))
+        worst = max(worst, err / n)
+    return worst
+
+
+@pytest.mark.parametrize("closure", ["none", "smag", "leith", "dsmag", "dleith"])
+def test_island_fp64_every_step(closure):
+    """128x64 island channel, 20 steps, every closure."""
+    wl = configs.ab2cn_island(64, closure=closure)
+    m = wl.members[0]
+    S = solver_for([m], 64)
+    worst = lockstep(S, m, 64, (64, 128), 20, use_graph=False)
+    say("AB2CN", closure, "fp64 worst rel L2 per step", worst)
+    assert worst < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("closure", ["smag", "dleith"])
+def test_island_fp32_512(closure):
+    wl = configs.ab2cn_island(32, 512, 256, closure=closure, dt=5e-4)
+    m = wl.members[0]
+    S = solver_for([m], 32)
+    S.autotune()
+    worst = lockstep(S, m, 32, (256, 512), 4, use_graph=True)
+    say("AB2CN", closure, "fp32 512x256 worst rel L2 per step", worst)
+    assert worst < 1e-5
+    S.close()
+
+
+def test_history_carries_across_calls_and_graphs():
+    """The history lives in the handle: 2 + 4 steps in two calls continue the
+    sequence of 6 steps in one (equal up to the rounding of the exit/entry
+    transforms between the calls); graph replay == eager, bit for bit."""
+    m = configs.ab2cn_island(64, closure="dsmag").members[0]
+    outs = {}
+    for chunks, graph in (((6,), False), ((6,), True), ((2, 4), False), ((3, 3), True)):
+        S = solver_for([m], 64)
+        om = S.pack([m.omega0])
+        for k in chunks:
+            S.step(om, k, use_graph=graph)
+        outs[(chunks, graph)] = to_np(om)
+        S.close()
+    ref = outs[((6,), False)]
+    assert np.array_equal(outs[((6,), True)], ref)
+    # a restart without the history would take a forward-Euler step: O(dt^2)
+    # away, far above this bound
+    for key in (((2, 4), False), ((3, 3), True)):
+        err = rel_l2(outs[key], ref)
+        say("AB2CN chunks", key, "rel L2 vs one call", err)
+        assert err < 1e-13
+
+
+def test_mixed_schemes_in_one_handle():
+    """An RK4 and an AB2CN member launched together, each against its own oracle."""
+    a = configs.config1(64).members[0]
+    b = configs.ab2cn_island(64, closure="leith").members[0]
+    S = solver_for([a, b], 64)
+    om = S.pack([a.omega0, b.omega0])
+    w_a, w_b = (to_np(x).reshape(64, 128) for x in S.unpack(om))
+    S.step(om, 3, use_graph=True)
+    got_a, got_b = (to_np(x).reshape(64, 128) for x in S.unpack(om))
+    Ma = oracle_model(a.params, a.chi, a.chi_s)
+    Mb = oracle_model(b.params, b.chi, b.chi_s)
+    ea = rel_l2(got_a, qg.run(w_a, Ma, 3))
+    eb = rel_l2(got_b, ab2cn.run(w_b, Mb, 3)[0])
+    say("mixed handle: rk4", ea, "ab2cn", eb)
+    assert ea < 1e-12 and eb < 1e-12
+    S.close()
