@@ -4,8 +4,9 @@
 Metric: grid-point-steps per second at 1024^2 for the coast-with-cape
 workload (dynamic Leith, RK4 + penalization/sponge sub-step), in FP32
 (``value``), FP64 and FP32 batched (8 members of 1024^2 in one graph
-launch), plus the adjoint/forward time ratio of the differentiable island
-run (512x256, static Smagorinsky, one 50-step checkpoint segment).
+launch), the same step under the paper's own AB2CN scheme, plus the
+adjoint/forward time ratio of the differentiable island run (512x256,
+static Smagorinsky, one 50-step checkpoint segment).
 
 Inputs are synthetic and seeded (masks, sponge ramps, k^-3 random-phase
 initial vorticity) and resident in HBM before timing.  Steps are timed with
@@ -195,8 +196,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=1)
-    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,adjoint,cpu,phases")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,adjoint,cpu,phases")
     ap.add_argument("--tune-cache", default=None,
                     help="strip-width cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -297,6 +298,21 @@ def main():
                              "step_roofline_frac": len(bw.members) * step_bytes / (secb / kb) / 1e9
                              / HBM_PEAK_GBS}
         log(f"batched 8x1024^2: {secb / kb * 1e3:.3f} ms/step, {ptsb * kb / secb:.4g} pt-steps/s")
+
+    # ---- the paper's own scheme (AB2CN + AB2 sponge) on the same workload,
+    # with eta = 2.5 dt (explicit penalization needs eta > dt)
+    if "ab2cn" not in skip:
+        wa = configs.config3(precision=32)
+        for m in wa.members:
+            m.params["scheme"] = "ab2cn"
+            m.params["eta"] = 2.5 * m.params["dt"]
+        S, om = make_solver(wa, 32)
+        ka = max(10, K // 2)
+        seca, _ = time_steps(S, om, ka, W, torch)
+        S.close()
+        result["ab2cn"] = {"value": pts * ka / seca, "ms_per_step": seca / ka * 1e3, "steps": ka,
+                           "workload": "as value, AB2CN + AB2 sponge, eta = 2.5 dt"}
+        log(f"ab2cn 1024^2 dleith: {seca / ka * 1e3:.3f} ms/step")
 
     # ---- adjoint / forward on the differentiable island run
     if "adjoint" not in skip:
