@@ -18,6 +18,8 @@ adjoint  -- the exact discrete adjoint of one step (static closures), and the
             gradient of the a-posteriori vorticity loss.
 ab2cn    -- the paper's own time scheme: AB2CN for the penalized equations,
             then the AB2 sponge (Sec. II-E, Eq. 4).
+les      -- the filter H_full from the fully-resolved grid to the LES grid
+            (Sec. III) and the pattern correlation PCC (Sec. IV).
 
 Every floating-point operation is in float64.  Each function cites the
 passage of the paper it follows: the QG vorticity equation (Sec. II-A,

@@ -100,3 +100,24 @@ def test_ab2cn_mutation_is_caught(monkeypatch, name, old, new, pin):
     mod = mutated("ab2cn", old, new)
     monkeypatch.setattr(pins_ab2, "ab2cn", mod)
     must_fail(pin)
+
+
+import tests.test_oracle_les as pins_les  # noqa: E402
+
+LES_MUTATIONS = [
+    ("gaussian width not squared", "k2 * (delta * dfr) ** 2 / 6.0", "k2 * (delta * dfr) / 6.0",
+     lambda: pins_les.test_gaussian_equals_physical_convolution(2)),
+    ("coarse rescaling", "ch / (delta * delta)", "ch / delta",
+     pins_les.test_cutoff_edges_and_single_mode_amplitude),
+    ("cut-off radius", "kc = np.pi / (delta * dfr)", "kc = 1.1 * np.pi / (delta * dfr)",
+     pins_les.test_cutoff_edges_and_single_mode_amplitude),
+    ("pcc centring", "dy = y - y.mean()", "dy = y",
+     pins_les.test_pcc_against_numpy_and_affine),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", LES_MUTATIONS, ids=[m[0] for m in LES_MUTATIONS])
+def test_les_mutation_is_caught(monkeypatch, name, old, new, pin):
+    mod = mutated("les", old, new)
+    monkeypatch.setattr(pins_les, "les", mod)
+    must_fail(pin)
