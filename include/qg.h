@@ -153,6 +153,24 @@ int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
 int qg_adjoint_step(qg_handle* h, const void* omega_ckpt, void* lambda,
                     int64_t nsteps, double* grad_c_dev, void* hip_stream);
 
+/* The LES filter of Sec. III, H_full = interpolation onto the LES grid o
+ * cut-off at |k| > pi/Delta_FF o Gaussian exp(-k^2 (delta Delta_FR)^2 / 6),
+ * for every member pair: member i of `fr` holds the fully-resolved grid,
+ * member i of `les` the same domain coarsened by delta (a power of two
+ * >= 2, equal in x and y, same precision).  omega_fr: flat FR fields (fr's
+ * layout), projected onto the FR 2/3 set on entry; omega_ff: the filtered
+ * fields on the LES grids (les's layout; the coarse Nyquist modes are
+ * zero).  Uses both workspaces as scratch: call between qg_step calls, not
+ * during one (the handles' states live in the caller's omega). */
+int qg_filter_les(qg_handle* fr, qg_handle* les, const void* omega_fr, void* omega_ff,
+                  void* hip_stream);
+
+/* Pattern (Pearson) correlation of two fields per member (Sec. IV):
+ * out_dev[i] = <(a - <a>)(b - <b>)> / sqrt(<(a - <a>)^2> <(b - <b>)^2>) over
+ * member i's grid, <.> the grid mean, in double precision.  a, b: flat
+ * device fields in the handle's layout; out_dev: n_members doubles. */
+int qg_pcc(qg_handle* h, const void* a, const void* b, double* out_dev, void* hip_stream);
+
 /* Replace the closure coefficient c of every member (c_host: n_members
  * doubles on the host; ignored for members without a static closure).  The
  * update is ordered on hip_stream after previously enqueued work; replays

@@ -861,6 +861,79 @@ int qg_step(qg_handle* H, void* omega, int64_t nsteps, int32_t save_every, void*
   return QG_OK;
 }
 
+// Position of caller member i inside its group.
+static int group_slot(const Handle& h, int i) {
+  const Group& g = h.groups[h.member_group[i]];
+  for (int k = 0; k < g.count; ++k)
+    if (g.users[k] == i) return k;
+  return -1;
+}
+
+int qg_filter_les(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* omega_ff, void* hip_stream) {
+  if (!Fh || !Lh) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega_fr || !omega_ff) return fail(QG_EINVAL, "omega_fr or omega_ff is NULL");
+  const Handle& F = Fh->h;
+  const Handle& L = Lh->h;
+  const int n = (int)F.params.size();
+  if ((int)L.params.size() != n) return fail(QG_EINVAL, "the two handles hold different member counts");
+  for (int i = 0; i < n; ++i) {
+    const qg_params& a = F.params[i];
+    const qg_params& b = L.params[i];
+    char buf[160];
+    const int d = b.nx > 0 ? a.nx / b.nx : 0;
+    if (d < 2 || a.nx != d * b.nx || a.ny != d * b.ny || !is_pow2(d)) {
+      snprintf(buf, sizeof buf, "member %d: the LES grid must be the FR grid coarsened by a power of two >= 2", i);
+      return fail(QG_EINVAL, buf);
+    }
+    if (std::fabs(a.lx - b.lx) > 1e-12 * a.lx || std::fabs(a.ly - b.ly) > 1e-12 * a.ly || a.precision != b.precision) {
+      snprintf(buf, sizeof buf, "member %d: the two grids must share lx, ly and precision", i);
+      return fail(QG_EINVAL, buf);
+    }
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (const auto& g : F.groups) {
+    int rc = run_entry(F, g, omega_fr, g.L.wn, st);
+    if (rc) return rc;
+  }
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    const Group& gf = F.groups[F.member_group[i]];
+    const Group& gl = L.groups[L.member_group[i]];
+    const qg_params& a = F.params[i];
+    const int d = a.nx / L.params[i].nx;
+    FilterArgs A{};
+    A.src = F.table[gf.m0 + group_slot(F, i)].base + gf.L.wn;
+    A.dst = L.table[gl.m0 + group_slot(L, i)].base + gl.L.chih;
+    A.kxn_f = gf.kxn; A.kyn_f = gf.kyn; A.myh_f = gf.myh;
+    A.kxn_c = gl.kxn_f; A.kyn_c = gl.kyn_f; A.myh_c = gl.myh_f;
+    A.two_pi_lx = 2.0 * pi / a.lx;
+    A.two_pi_ly = 2.0 * pi / a.ly;
+    const double dfr = a.lx / a.nx;
+    A.width2 = (d * dfr) * (d * dfr);
+    A.kc2 = (pi / (d * dfr)) * (pi / (d * dfr));
+    A.inv_d2 = 1.0 / ((double)d * d);
+    QG_LAUNCH(launch_filter_les(gf.dbl, A, st));
+  }
+  for (const auto& g : L.groups) {
+    Phase P = full_set(base_phase(L, g), g);
+    P.o_in = g.L.chih;
+    P.nf = 1;
+    P.user = omega_ff;
+    QG_LAUNCH(launch_colinv(g.dbl, OP_EXIT, 0, P, g.count, st));
+    QG_LAUNCH(launch_row(g.dbl, OP_EXIT, 0, P, g.count, st));
+  }
+  return QG_OK;
+}
+
+int qg_pcc(qg_handle* H, const void* a, const void* b, double* out_dev, void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  if (!a || !b || !out_dev) return fail(QG_EINVAL, "a, b or out_dev is NULL");
+  Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (const auto& g : h.groups) QG_LAUNCH(launch_pcc(g.dbl, base_phase(h, g), g.count, a, b, out_dev, st));
+  return QG_OK;
+}
+
 int qg_diag(qg_handle* H, const void* omega, double* out_dev, void* nu_e_out, void* hip_stream) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   if (!omega || !out_dev) return fail(QG_EINVAL, "omega or out_dev is NULL");

@@ -109,6 +109,22 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, hipStream_t s);
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int nmem, hipStream_t s);
+
+// One member pair of the LES filter: FR D-compact spectrum -> coarse
+// full-set compact spectrum.
+struct FilterArgs {
+  const void* src;             // FR state of the member
+  void* dst;                   // coarse full-set spectrum of the member
+  int kxn_f, kyn_f, myh_f;     // FR 2/3 set
+  int kxn_c, kyn_c, myh_c;     // coarse full set (Nyquist lines excluded)
+  double two_pi_lx, two_pi_ly;
+  double width2;               // (delta Delta_FR)^2
+  double kc2;                  // (pi / Delta_FF)^2
+  double inv_d2;               // 1 / delta^2
+};
+hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s);
+hipError_t launch_pcc(bool dbl, const Phase& P, int nmem, const void* a, const void* b, double* out,
+                      hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Field counts per phase and closure.

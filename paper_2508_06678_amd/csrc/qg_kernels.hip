@@ -1628,6 +1628,64 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   }
 }
 
+// ---------------------------------------------------------------- LES filter
+// H_full of Sec. III on one member pair: the fully-resolved state (FR
+// D-compact spectrum) times exp(-k^2 (delta Delta_FR)^2 / 6), cut off at
+// |k| > pi / Delta_FF, rescaled by 1/delta^2 onto the coarse grid's
+// full-set compact spectrum (Nyquist lines excluded).  Every retained mode
+// lies inside the FR 2/3 set (delta >= 2).
+template <typename T>
+__global__ void __launch_bounds__(256) k_filter_les(FilterArgs A) {
+  using V = cpx<T>;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.kxn_c * A.kyn_c) return;
+  const int mx = q / A.kyn_c;
+  const int iyc = q - mx * A.kyn_c;
+  const int my = my_of_iy(iyc, A.myh_c, A.kyn_c);
+  V v = cmake<V>(T(0), T(0));
+  const double kx = A.two_pi_lx * mx, ky = A.two_pi_ly * my;
+  const double k2 = kx * kx + ky * ky;
+  if (k2 <= A.kc2 && mx < A.kxn_f && my <= A.myh_f && -my <= A.myh_f) {
+    const int iyf = my >= 0 ? my : my + A.kyn_f;
+    const V w = gld(reinterpret_cast<const V*>(A.src) + (mx * A.kyn_f + iyf));
+    const double h = exp(-k2 * A.width2 / 6.0) * A.inv_d2;
+    v = cmake<V>(T((double)w.x * h), T((double)w.y * h));
+  }
+  gst(reinterpret_cast<V*>(A.dst) + q, v);
+}
+
+// ---------------------------------------------------------------- PCC
+// Pattern correlation of two fields per member (one block per member):
+// means first, then the centred sums, in double precision with a fixed
+// summation order.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pcc(Phase P, const void* a, const void* b, double* out) {
+  __shared__ double red[16];
+  const MemberDev M = member_const(P, blockIdx.x);
+  const long long n = (long long)P.nx * P.ny;
+  const T* x = reinterpret_cast<const T*>(reinterpret_cast<const char*>(a) + M.omega_off);
+  const T* y = reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + M.omega_off);
+  double sx = 0.0, sy = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) { sx += (double)x[i]; sy += (double)y[i]; }
+  sx = block_sum(sx, red);
+  sy = block_sum(sy, red);
+  __shared__ double mean[2];
+  if (threadIdx.x == 0) { mean[0] = sx / (double)n; mean[1] = sy / (double)n; }
+  __syncthreads();
+  const double mx = mean[0], my = mean[1];
+  double sxy = 0.0, sxx = 0.0, syy = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double dx = (double)x[i] - mx, dy = (double)y[i] - my;
+    sxy += dx * dy;
+    sxx += dx * dx;
+    syy += dy * dy;
+  }
+  sxy = block_sum(sxy, red);
+  sxx = block_sum(sxx, red);
+  syy = block_sum(syy, red);
+  if (threadIdx.x == 0) out[M.user_index] = sxy / sqrt(sxx * syy);
+}
+
 // C of the dynamic closures for diagnostics (slot 0 of the coef area).
 #if QG_HAS(4)
 __global__ void k_dyn_coef(Phase P, int slot) {
@@ -1979,6 +2037,17 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int n, long long o_dst, lo
 }
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int n, long long o_dst, long long o_src, hipStream_t s) {
   return launch_spec_axpy(dbl, P, n, o_dst, o_src, 0.0, 1, s);
+}
+hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s) {
+  dim3 grid((A.kxn_c * A.kyn_c + 255) / 256);
+  if (dbl) hipLaunchKernelGGL(k_filter_les<double>, grid, dim3(256), 0, s, A);
+  else hipLaunchKernelGGL(k_filter_les<float>, grid, dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_pcc(bool dbl, const Phase& P, int n, const void* a, const void* b, double* out, hipStream_t s) {
+  if (dbl) hipLaunchKernelGGL(k_pcc<double>, dim3(n), dim3(1024), 0, s, P, a, b, out);
+  else hipLaunchKernelGGL(k_pcc<float>, dim3(n), dim3(1024), 0, s, P, a, b, out);
+  return hipGetLastError();
 }
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {
   dim3 grid((P.kxn * P.kyn + 255) / 256, 1, n);

@@ -119,6 +119,23 @@ class Solver:
                                   _ptr(nu) if nu is not None else None, _stream(self.device)))
         return out.view(self.n, 8), nu
 
+    def filter_les(self, les, omega_fr):
+        """H_full of every member's fully-resolved field onto the grids of
+        the solver `les` (same members, coarsened grids).  Returns the flat
+        filtered fields in `les`'s layout."""
+        self._check_flat(omega_fr, "omega_fr")
+        out = torch.empty(les.total, dtype=les.dtype, device=les.device)
+        _lib.check(self.L.qg_filter_les(self.h, les.h, _ptr(omega_fr), _ptr(out), _stream(self.device)))
+        return out
+
+    def pcc(self, a, b):
+        """Pattern correlation of two flat fields, one float64 per member."""
+        self._check_flat(a, "a")
+        self._check_flat(b, "b")
+        out = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        _lib.check(self.L.qg_pcc(self.h, _ptr(a), _ptr(b), _ptr(out), _stream(self.device)))
+        return out
+
     def set_coef(self, c):
         """Closure coefficient c per member (sequence of floats)."""
         c = [float(x) for x in c]

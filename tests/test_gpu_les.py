@@ -1,0 +1,94 @@
+"""GPU parity of the LES filter H_full and of the pattern correlation
+(qg_filter_les, qg_pcc) against the oracle (oracle/les.py, pinned by
+test_oracle_les.py), and the a-posteriori vorticity comparison of the paper
+(an FR run and an LES run from its filtered start, PCC(omega_LES, omega_FF))
+against the same pipeline in the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import les as oles
+from oracle import qg
+from paper_2508_06678_amd import configs, inputs
+from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def island(nx, ny, closure, seed=0):
+    return configs.island_member(nx, ny, precision=64, beta=1.0, re=1e3, dt=2e-3, eta=1e-3, xc=1.5,
+                                 radius=0.3, closure=closure, seed=seed, rms=0.1)
+
+
+@pytest.mark.parametrize("precision,nx,ny,delta", [(64, 256, 128, 2), (64, 256, 128, 4), (32, 1024, 512, 2)])
+def test_filter_matches_oracle(precision, nx, ny, delta):
+    fr_members = [island(nx, ny, "none", seed=s) for s in (3, 4)]
+    for m in fr_members:   # richer small scales than the default band
+        m.omega0 = inputs.spectrum_noise(nx, ny, 2 * math.pi, math.pi, m.meta["seed"], 2.0, 0.1)
+    les_members = [island(nx // delta, ny // delta, "smag", seed=s) for s in (3, 4)]
+    F = solver_for(fr_members, precision)
+    L = solver_for(les_members, precision)
+    om = F.pack([m.omega0 for m in fr_members])
+    got = L.unpack(F.filter_les(L, om))
+    tol = 1e-12 if precision == 64 else 1e-5
+    for g, m in zip(got, fr_members):
+        w = to_np(F.unpack(om)[fr_members.index(m)]).reshape(ny, nx)
+        ref = oles.filter_to(qg.leave(qg.enter(w, qg.Grid(nx, ny, 2 * math.pi, math.pi)),
+                                      qg.Grid(nx, ny, 2 * math.pi, math.pi)), 2 * math.pi, math.pi, delta)
+        err = rel_l2(to_np(g).reshape(ny // delta, nx // delta), ref)
+        say("filter", precision, nx, ny, delta, err)
+        assert err < tol
+    F.close()
+    L.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_pcc_matches_oracle(precision):
+    ms = [island(256, 128, "smag", seed=s) for s in (5, 6, 7)]
+    S = solver_for(ms, precision)
+    a = S.pack([m.omega0 for m in ms])
+    b = S.pack([0.4 * m.omega0 + inputs.bandpass_noise(256, 128, 2 * math.pi, math.pi, 40 + i, 2, 8, 0.1)
+                for i, m in enumerate(ms)])
+    got = S.pcc(a, b).cpu().numpy()
+    for i, (x, y) in enumerate(zip(S.unpack(a), S.unpack(b))):
+        ref = oles.pcc(to_np(x), to_np(y))
+        say("pcc", precision, got[i], ref)
+        assert abs(got[i] - ref) < (1e-13 if precision == 64 else 1e-6)
+    S.close()
+
+
+def test_a_posteriori_vorticity_correlation():
+    """FR 256x128 (no closure) and LES 128x64 (Smagorinsky) from the filtered
+    FR start, 10 steps each; PCC(omega_LES, H_full(omega_FR))."""
+    nsteps = 10
+    fr = island(256, 128, "none", seed=9)
+    fr.params["dt"] = 1e-3
+    le = island(128, 64, "smag", seed=9)
+    le.params["dt"] = 1e-3
+    F = solver_for([fr], 64)
+    L = solver_for([le], 64)
+    w_fr = F.pack([fr.omega0])
+    w_les = F.filter_les(L, w_fr)
+    w_les0 = to_np(w_les).reshape(64, 128)
+    F.step(w_fr, nsteps)
+    L.step(w_les, nsteps)
+    w_ff = F.filter_les(L, w_fr)
+    got = L.pcc(w_les, w_ff).item()
+    # the same pipeline in the oracle
+    Mf = oracle_model(fr.params, fr.chi, fr.chi_s)
+    Ml = oracle_model(le.params, le.chi, le.chi_s)
+    f0 = qg.leave(qg.enter(fr.omega0, Mf.g), Mf.g)
+    l0 = oles.filter_to(f0, 2 * math.pi, math.pi, 2)
+    assert rel_l2(w_les0, l0) < 1e-12
+    fT = qg.run(f0, Mf, nsteps)
+    lT = qg.run(l0, Ml, nsteps)
+    ref = oles.pcc(lT, oles.filter_to(fT, 2 * math.pi, math.pi, 2))
+    say("a posteriori PCC", got, ref)
+    assert abs(got - ref) < 1e-10
+    F.close()
+    L.close()
