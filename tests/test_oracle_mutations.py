@@ -113,6 +113,19 @@ LES_MUTATIONS = [
      pins_les.test_cutoff_edges_and_single_mode_amplitude),
     ("pcc centring", "dy = y - y.mean()", "dy = y",
      pins_les.test_pcc_against_numpy_and_affine),
+    ("penalty forcing sign", "G = G + (1.0 / p.eta)", "G = G - (1.0 / p.eta)",
+     pins_les.test_ideal_sgs_penalty_and_sponge_commutators_closed_form),
+    ("curl operands", "g.spec(m.chi * v) - 1j * g.ky * g.spec(m.chi * u)",
+     "g.spec(m.chi * u) - 1j * g.ky * g.spec(m.chi * v)",
+     pins_les.test_ideal_sgs_penalty_and_sponge_commutators_closed_form),
+    ("dropped sponge rate", "G = G + p.sponge_sigma * g.D", "G = G + g.D",
+     pins_les.test_ideal_sgs_penalty_and_sponge_commutators_closed_form),
+    ("commutator order", "(advective_forcing(wbar_d, m_les) - Gbar)", "(Gbar - advective_forcing(wbar_d, m_les))",
+     pins_les.test_ideal_sgs_two_modes_closed_form),
+    ("no projection on D", "Pi = gl.D * (advective_forcing", "Pi = (advective_forcing",
+     pins_les.test_ideal_sgs_is_projected_on_the_les_two_thirds_set),
+    ("model without coefficient", 'g.phys(out["C"] * out["Qh"])', 'g.phys(out["Qh"])',
+     lambda: pins_les.test_model_sgs_enstrophy_identity("leith", 3)),
 ]
 
 
