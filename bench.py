@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,adjoint,cpu,phases")
+    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,sgs,adjoint,cpu,phases")
     ap.add_argument("--tune-cache", default=None,
                     help="strip-width cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -313,6 +313,31 @@ def main():
         result["ab2cn"] = {"value": pts * ka / seca, "ms_per_step": seca / ka * 1e3, "steps": ka,
                            "workload": "as value, AB2CN + AB2 sponge, eta = 2.5 dt"}
         log(f"ab2cn 1024^2 dleith: {seca / ka * 1e3:.3f} ms/step")
+
+    # ---- a-priori SGS analysis: FR 1024^2 -> LES 512^2 (delta = 2), ideal
+    # Pi_FF, the Dynamic Leith model term at the filtered field, their PCC
+    if "sgs" not in skip:
+        frw = configs.config3(precision=32)
+        lesw = configs.config3(precision=32, n=512)
+        F, omf = make_solver(frw, 32, tune=False)
+        L, _ = make_solver(lesw, 32, tune=False)
+        for _ in range(3):
+            F.ideal_sgs(L, omf)
+        torch.cuda.synchronize()
+        ks = max(10, K // 4)
+        t0 = time.perf_counter()
+        for _ in range(ks):
+            pi, model, _ = F.ideal_sgs(L, omf)
+            pcc = L.pcc(pi, model)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        F.close()
+        L.close()
+        result["sgs"] = {"value": pts * ks / secs, "unit": "FR grid-pts/s", "ms_per_analysis": secs / ks * 1e3,
+                         "analyses": ks, "pcc_a_priori": float(pcc[0]),
+                         "workload": "ideal SGS Pi_FF + Dynamic Leith model term + PCC, FR 1024^2 -> "
+                                     "LES 512^2 (delta 2), FP32; LES masks sampled on the LES grid"}
+        log(f"sgs analysis 1024^2 -> 512^2: {secs / ks * 1e3:.3f} ms per analysis")
 
     # ---- adjoint / forward on the differentiable island run
     if "adjoint" not in skip:

@@ -165,6 +165,27 @@ int qg_adjoint_step(qg_handle* h, const void* omega_ckpt, void* lambda,
 int qg_filter_les(qg_handle* fr, qg_handle* les, const void* omega_fr, void* omega_ff,
                   void* hip_stream);
 
+/* The ideal subgrid-scale forcing of the filtered QG equations (Sec. III)
+ * and the closure's model of it (Sec. IV, the a-priori term), for every
+ * member pair of `fr` and `les` (the pairing rules of qg_filter_les):
+ *   G(omega) = D FFT(J) + (1/eta) D curl(chi u) + sigma D FFT(chi_s omega),
+ *   pi_ff    = P_D [ G_les(omega_bar) - H_full(G_fr(omega)) ],
+ * with J the advection by the total velocity, u the total velocity, D the
+ * 2/3 set of each grid, P_D the projection onto the LES one, and
+ * omega_bar = P_D H_full(omega): the forcing that makes an LES tendency on
+ * its 2/3 set equal the filtered FR tendency.  G_fr takes eta, sigma,
+ * chi, chi_s and the inflow of the fr member, G_les those of the les
+ * member (give it H_full of the FR masks for the paper's definition).
+ * pi_model (may be NULL): C D div(base grad omega_bar), the les member's
+ * closure at omega_bar (C from omega_bar for the dynamic closures, zero
+ * without closure).  omega_bar (may be NULL): omega_bar itself.
+ * omega_fr: flat FR fields in fr's layout; outputs: flat fields in les's
+ * layout.  Sizes: 64 <= nx <= 1024 on both grids, ny <= 1024 in 64-bit and
+ * ny <= 2048 in 32-bit runs; else QG_EUNSUPPORTED.  Uses both workspaces
+ * as scratch, like qg_filter_les. */
+int qg_ideal_sgs(qg_handle* fr, qg_handle* les, const void* omega_fr, void* pi_ff,
+                 void* pi_model, void* omega_bar, void* hip_stream);
+
 /* Pattern (Pearson) correlation of two fields per member (Sec. IV):
  * out_dev[i] = <(a - <a>)(b - <b>)> / sqrt(<(a - <a>)^2> <(b - <b>)^2>) over
  * member i's grid, <.> the grid mean, in double precision.  a, b: flat

@@ -147,8 +147,9 @@ static void plan_sizes(Group& g, int adjK) {
   g.nspec = (g.kxn * g.kyn + 255) / 256;
 
   const int cl = g.closure;
-  int F = std::max({rhs_fields(cl), 3, 1});
-  int Pn = std::max({rhs_products(cl), 3, 1});
+  // at least the 5 fields and 4 products of the SGS-analysis pass
+  int F = std::max({rhs_fields(cl), 5});
+  int Pn = std::max({rhs_products(cl), 4});
   if (adjK > 0) {
     F = std::max(F, (smag_family(cl) ? 6 : 4) + 3);
     Pn = std::max(Pn, smag_family(cl) ? 6 : 4);
@@ -869,11 +870,9 @@ static int group_slot(const Handle& h, int i) {
   return -1;
 }
 
-int qg_filter_les(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* omega_ff, void* hip_stream) {
-  if (!Fh || !Lh) return fail(QG_EINVAL, "handle is NULL");
-  if (!omega_fr || !omega_ff) return fail(QG_EINVAL, "omega_fr or omega_ff is NULL");
-  const Handle& F = Fh->h;
-  const Handle& L = Lh->h;
+// Member pairs of an FR and an LES handle: same count, the LES grid the FR
+// grid coarsened by a power of two >= 2, same box and precision.
+static int check_les_pair(const Handle& F, const Handle& L) {
   const int n = (int)F.params.size();
   if ((int)L.params.size() != n) return fail(QG_EINVAL, "the two handles hold different member counts");
   for (int i = 0; i < n; ++i) {
@@ -890,29 +889,56 @@ int qg_filter_les(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* omeg
       return fail(QG_EINVAL, buf);
     }
   }
+  return QG_OK;
+}
+
+// H_full of member i: FR D-compact spectrum at byte offset o_src of its
+// region -> LES spectrum at o_dst, on the LES full set (full = true) or on
+// its 2/3 set.
+static int launch_member_filter(const Handle& F, const Handle& L, int i, long long o_src, long long o_dst,
+                                bool full, hipStream_t st) {
+  const Group& gf = F.groups[F.member_group[i]];
+  const Group& gl = L.groups[L.member_group[i]];
+  const qg_params& a = F.params[i];
+  const int d = a.nx / L.params[i].nx;
+  const double pi = 3.14159265358979323846;
+  FilterArgs A{};
+  A.src = F.table[gf.m0 + group_slot(F, i)].base + o_src;
+  A.dst = L.table[gl.m0 + group_slot(L, i)].base + o_dst;
+  A.kxn_f = gf.kxn; A.kyn_f = gf.kyn; A.myh_f = gf.myh;
+  if (full) {
+    A.kxn_c = gl.kxn_f; A.kyn_c = gl.kyn_f; A.myh_c = gl.myh_f;
+  } else {
+    A.kxn_c = gl.kxn; A.kyn_c = gl.kyn; A.myh_c = gl.myh;
+  }
+  A.two_pi_lx = 2.0 * pi / a.lx;
+  A.two_pi_ly = 2.0 * pi / a.ly;
+  const double dfr = a.lx / a.nx;
+  A.width2 = (d * dfr) * (d * dfr);
+  A.kc2 = (pi / (d * dfr)) * (pi / (d * dfr));
+  A.inv_d2 = 1.0 / ((double)d * d);
+  QG_LAUNCH(launch_filter_les(gf.dbl, A, st));
+  return QG_OK;
+}
+
+int qg_filter_les(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* omega_ff, void* hip_stream) {
+  if (!Fh || !Lh) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega_fr || !omega_ff) return fail(QG_EINVAL, "omega_fr or omega_ff is NULL");
+  const Handle& F = Fh->h;
+  const Handle& L = Lh->h;
+  const int n = (int)F.params.size();
+  int rc0 = check_les_pair(F, L);
+  if (rc0) return rc0;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   for (const auto& g : F.groups) {
     int rc = run_entry(F, g, omega_fr, g.L.wn, st);
     if (rc) return rc;
   }
-  const double pi = 3.14159265358979323846;
   for (int i = 0; i < n; ++i) {
     const Group& gf = F.groups[F.member_group[i]];
     const Group& gl = L.groups[L.member_group[i]];
-    const qg_params& a = F.params[i];
-    const int d = a.nx / L.params[i].nx;
-    FilterArgs A{};
-    A.src = F.table[gf.m0 + group_slot(F, i)].base + gf.L.wn;
-    A.dst = L.table[gl.m0 + group_slot(L, i)].base + gl.L.chih;
-    A.kxn_f = gf.kxn; A.kyn_f = gf.kyn; A.myh_f = gf.myh;
-    A.kxn_c = gl.kxn_f; A.kyn_c = gl.kyn_f; A.myh_c = gl.myh_f;
-    A.two_pi_lx = 2.0 * pi / a.lx;
-    A.two_pi_ly = 2.0 * pi / a.ly;
-    const double dfr = a.lx / a.nx;
-    A.width2 = (d * dfr) * (d * dfr);
-    A.kc2 = (pi / (d * dfr)) * (pi / (d * dfr));
-    A.inv_d2 = 1.0 / ((double)d * d);
-    QG_LAUNCH(launch_filter_les(gf.dbl, A, st));
+    int rc = launch_member_filter(F, L, i, gf.L.wn, gl.L.chih, true, st);
+    if (rc) return rc;
   }
   for (const auto& g : L.groups) {
     Phase P = full_set(base_phase(L, g), g);
@@ -921,6 +947,99 @@ int qg_filter_les(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* omeg
     P.user = omega_ff;
     QG_LAUNCH(launch_colinv(g.dbl, OP_EXIT, 0, P, g.count, st));
     QG_LAUNCH(launch_row(g.dbl, OP_EXIT, 0, P, g.count, st));
+  }
+  return QG_OK;
+}
+
+// The SGS-analysis pass runs at strip width 1.
+static Phase gterms_phase(const Handle& h, const Group& g) {
+  Phase P = base_phase(h, g);
+  P.W = 1;
+  P.logW = 0;
+  P.nparts = g.kxn;
+  return P;
+}
+
+// G(omega) of every member of group g from the D-compact spectrum at o_in
+// to o_out; minus the spectrum at o_sub unless o_sub < 0.
+static int run_gterms(const Handle& h, const Group& g, long long o_in, long long o_out, long long o_sub,
+                      hipStream_t st) {
+  Phase P = gterms_phase(h, g);
+  P.nf = 5;
+  P.o_in = o_in;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_GTERMS, 0, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_GTERMS, 0, P, g.count, st));
+  P.o_out = o_out;
+  P.stage = o_sub >= 0 ? 1 : 0;
+  P.o_in2 = o_sub >= 0 ? o_sub : 0;
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_GTERMS, 0, P, g.count, st));
+  return QG_OK;
+}
+
+// The closure's term C D div(base grad omega) at the D-compact spectrum
+// o_in (C from it for the dynamic closures) -> o_out.
+static int run_model_term(const Handle& h, const Group& g, long long o_in, long long o_out, hipStream_t st) {
+  const int cl = g.closure;
+  Phase P = base_phase(h, g);
+  P.stage = SGS_STAGE;
+  P.nf = rhs_fields(cl);
+  P.o_in = o_in;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+  if (!dynamic_closure(cl)) {
+    P.o_out = o_out;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+  } else {
+    P.o_out = g.L.jsp;
+    P.o_aux = g.L.qsp;
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    P.o_in = o_out;
+    QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
+  }
+  return QG_OK;
+}
+
+int qg_ideal_sgs(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* pi_ff, void* pi_model,
+                 void* omega_bar, void* hip_stream) {
+  if (!Fh || !Lh) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega_fr || !pi_ff) return fail(QG_EINVAL, "omega_fr or pi_ff is NULL");
+  const Handle& F = Fh->h;
+  const Handle& L = Lh->h;
+  int rc0 = check_les_pair(F, L);
+  if (rc0) return rc0;
+  for (const Handle* hp : {&F, &L})
+    for (const auto& g : hp->groups)
+      if (!gterms_ok(g.dbl, gterms_phase(*hp, g)))
+        return fail(QG_EUNSUPPORTED, "the SGS analysis needs 64 <= nx <= 1024, and ny <= 1024 in 64-bit runs "
+                                     "(ny <= 2048 in 32-bit runs)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  try {
+    // FR: omega -> wn, G(omega) -> jsp
+    for (const auto& g : F.groups) {
+      int rc = run_entry(F, g, omega_fr, g.L.wn, st);
+      if (!rc) rc = run_gterms(F, g, g.L.wn, g.L.jsp, -1, st);
+      if (rc) return rc;
+    }
+    // filtered omega and filtered G on the LES 2/3 set -> wn, acc
+    for (int i = 0; i < (int)F.params.size(); ++i) {
+      const Group& gf = F.groups[F.member_group[i]];
+      const Group& gl = L.groups[L.member_group[i]];
+      int rc = launch_member_filter(F, L, i, gf.L.wn, gl.L.wn, false, st);
+      if (!rc) rc = launch_member_filter(F, L, i, gf.L.jsp, gl.L.acc, false, st);
+      if (rc) return rc;
+    }
+    for (const auto& g : L.groups) {
+      int rc = run_gterms(L, g, g.L.wn, g.L.x, g.L.acc, st);
+      if (!rc) rc = run_exit(L, g, g.L.x, pi_ff, st);
+      if (!rc && omega_bar) rc = run_exit(L, g, g.L.wn, omega_bar, st);
+      if (!rc && pi_model) {
+        rc = run_model_term(L, g, g.L.wn, g.L.x, st);
+        if (!rc) rc = run_exit(L, g, g.L.x, pi_model, st);
+      }
+      if (rc) return rc;
+    }
+  } catch (...) {
+    return fail(QG_EINVAL, "internal error in qg_ideal_sgs");
   }
   return QG_OK;
 }

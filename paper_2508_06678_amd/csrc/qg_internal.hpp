@@ -23,13 +23,17 @@ enum Op : int {
   OP_ADJ_EXIT = 9,  // adjoint of the exit transform (physical -> spectral)
   OP_ADJ_ENTRY = 10,// adjoint of the entry transform (spectral -> physical)
   OP_PEN = 11,      // AB2CN: D curl(chi u) of the total velocity
-  OP_SPONGE = 12    // AB2CN: omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
+  OP_SPONGE = 12,   // AB2CN: omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
+  OP_GTERMS = 13    // SGS analysis: D FFT(J) + (1/eta) D curl(chi u) + sigma D FFT(chi_s omega)
 };
 
 // RK stage code of the AB2CN update in the column-forward / combine passes
 constexpr int AB2CN_STAGE = 9;
 // coefficient slot of the AB2CN history flag (0: no history yet)
 constexpr int AB2CN_FLAG_SLOT = 30;
+// stage code of the right-hand-side pass that writes the closure's term
+// C D div(base grad omega) instead of updating the state
+constexpr int SGS_STAGE = 10;
 
 // Per-member constants, resident on the device.
 struct MemberDev {
@@ -126,6 +130,9 @@ hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s);
 hipError_t launch_pcc(bool dbl, const Phase& P, int nmem, const void* a, const void* b, double* out,
                       hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// whether the SGS-analysis pass (field-parallel row and column kernels at
+// strip width 1) fits the group's sizes
+bool gterms_ok(bool dbl, const Phase& P);
 
 // Field counts per phase and closure.
 __host__ __device__ constexpr int rhs_fields(int cl) { return cl == 0 || cl == 2 ? 4 : cl == 1 ? 6 : cl == 4 ? 8 : 12; }
@@ -136,12 +143,14 @@ __host__ __device__ constexpr bool dynamic_closure(int cl) { return cl == 3 || c
 // Fields (thread groups) and products of the field-parallel row pass.
 __host__ __device__ constexpr int rowp_nb(int op, int cl) {
   return op == OP_B ? 3
+       : op == OP_GTERMS ? 5
        : (op == OP_PEN || op == OP_SPONGE) ? 2
        : op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4) + (cl == 0 ? 1 : 3)
        : ((cl == 1 || cl == 3) ? 6 : 4);
 }
 __host__ __device__ constexpr int rowp_np(int op, int cl) {
   return op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4)
+       : op == OP_GTERMS ? 4
        : op == OP_PEN ? 2
        : (op == OP_B || op == OP_SPONGE || cl == 0) ? 1 : 3;
 }

@@ -228,6 +228,11 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     const bool first = rptr<double>(M, P.o_coef)[AB2CN_FLAG_SLOT] == 0.0;
     V x = gld(cptr<T>(M, (f == 0 || first) ? P.o_in : P.o_in2) + idx);
     return zero_mean ? cmake<V>(T(0), T(0)) : x;
+  } else if constexpr (OP == OP_GTERMS) {
+    // fields u', v', omega_x, omega_y, omega
+    V x = gld(cptr<T>(M, P.o_in) + idx);
+    if (f == 4) return zero_mean ? cmake<V>(T(0), T(0)) : x;
+    return rhs_field<T, 0>(M, f, x, w, mx, my, false);
   } else if constexpr (OP == OP_MASKGRAD) {
     V x = gld(cptr<T>(M, P.o_in) + idx);
     return f == 0 ? mul_ia(x, T(w.kx)) : mul_ia(x, T(w.ky));
@@ -793,7 +798,24 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
   constexpr int nbase = smag ? 6 : 4;
   const int nx = P.nx;
   auto F = [&](int f) -> V { return buf[f * bstride + q + (q >> PADS)]; };
-  if constexpr (OP == OP_PEN) {
+  if constexpr (OP == OP_GTERMS) {
+    // 0: J = (U + u') omega_x + (V + v') omega_y, 1: chi (U + u'),
+    // 2: chi (V + v'), 3: chi_s omega
+    const long long a = (long long)ya * nx + q, b = a + nx;
+    if (grp == 0) {
+      const V u = F(0), vv = F(1), wx = F(2), wy = F(3);
+      return vadd<T>(vmul<T>(cmake<V>(U + u.x, U + u.y), wx), vmul<T>(cmake<V>(Vv + vv.x, Vv + vv.y), wy));
+    }
+    if (grp == 3) {
+      const T* chs = rptr<T>(M, P.o_phys) + 5LL * nx * P.ny;
+      const V w = F(4);
+      return cmake<V>(chs[a] * w.x, chs[b] * w.y);
+    }
+    const T* chi = rptr<T>(M, P.o_phys) + 4LL * nx * P.ny;
+    const V vel = F(grp - 1);
+    const T base = grp == 1 ? U : Vv;
+    return cmake<V>(chi[a] * (base + vel.x), chi[b] * (base + vel.y));
+  } else if constexpr (OP == OP_PEN) {
     // chi times the total velocity: product 0 chi (U + u'), 1 chi (V + v')
     const long long a = (long long)ya * nx + q, b = a + nx;
     const T* chi = rptr<T>(M, P.o_phys) + 4LL * nx * P.ny;
@@ -1175,11 +1197,27 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
         Q[i] = cadd(Q[i], mul_ia(tile_at(i), T(w.ky)));
       }
     }
+    const T C = T(M.coef_static);
+    if (P.stage == AB2CN_STAGE || P.stage == SGS_STAGE) {
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+        V cq = cmake<V>(T(0), T(0));
+        if constexpr (CL != 0) cq = cscale(Q[i], C);
+        if (P.stage == AB2CN_STAGE) {
+          ab2cn_update<T>(M, P, (int)sidx(i), mxs_(i), my, cadd(R[i], cq));
+        } else {
+          if (mxs_(i) == 0 && my == 0) cq = cmake<V>(T(0), T(0));
+          gst(cptr<T>(M, P.o_out) + sidx(i), cq);
+        }
+      }
+      return;
+    }
     const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
     const V* wn = cptr<T>(M, P.o_in2);
     V* acc = cptr<T>(M, P.o_aux);
     V* xout = cptr<T>(M, P.o_in);
-    const T C = T(M.coef_static);
     const double dt = M.dt;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
@@ -1392,7 +1430,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   constexpr int np = OP == OP_RHS ? (CL == 0 ? 1 : dyn ? 6 : 3)
-                   : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : OP == OP_PEN ? 2 : 1;
+                   : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : OP == OP_PEN ? 2
+                   : OP == OP_GTERMS ? 4 : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const MemberDev M = member_const(P, blockIdx.z);
@@ -1457,6 +1496,16 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       V v = csub(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(0, w, iy), wv.ky));
       if (mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
       gst(cptr<T>(M, P.o_out) + id, v);
+    } else if constexpr (OP == OP_GTERMS) {
+      // G = F(J) + (1/eta) (i kx F(chi v) - i ky F(chi u)) + sigma F(chi_s omega);
+      // stage != 0: minus the spectrum at o_in2
+      const Wave<T> wv = wave<T>(M, mx, my);
+      const T ie = T(M.pen_a / M.dt), sg = T(M.sponge_a / M.dt);
+      const V pen = csub(mul_ia(at(2, w, iy), wv.kx), mul_ia(at(1, w, iy), wv.ky));
+      V g = cadd(cadd(at(0, w, iy), cscale(pen, ie)), cscale(at(3, w, iy), sg));
+      if (P.stage != 0) g = csub(g, gld(cptr<T>(M, P.o_in2) + id));
+      if (mx == 0 && my == 0) g = cmake<V>(T(0), T(0));
+      gst(cptr<T>(M, P.o_out) + id, g);
     } else if constexpr (OP == OP_ADJ_B) {
       // lambda_s = F(l_w) - (i ky F(l_u) - i kx F(l_v)) / |k|^2 -> LS, LW, LK = dt/6 LS
       const Wave<T> wv = wave<T>(M, mx, my);
@@ -1489,6 +1538,14 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       }
     } else if constexpr (!dyn) {
       const Wave<T> wv = wave<T>(M, mx, my);
+      if (P.stage == SGS_STAGE) {
+        V cq = cmake<V>(T(0), T(0));
+        if constexpr (CL != 0)
+          cq = cscale(cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky)), T(M.coef_static));
+        if (mx == 0 && my == 0) cq = cmake<V>(T(0), T(0));
+        gst(cptr<T>(M, P.o_out) + id, cq);
+        continue;
+      }
       if (P.stage == AB2CN_STAGE) {
         const V j = at(0, w, iy);
         V N = cmake<V>(-j.x, -j.y);
@@ -1584,9 +1641,13 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double* c = rptr<double>(M, P.o_coef);
-    c[P.stage] = C;
-    c[8 + 2 * P.stage] = hm;
-    c[9 + 2 * P.stage] = mm;
+    if (P.stage == SGS_STAGE) {
+      c[0] = C;
+    } else {
+      c[P.stage] = C;
+      c[8 + 2 * P.stage] = hm;
+      c[9 + 2 * P.stage] = mm;
+    }
   }
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.kxn * P.kyn) return;
@@ -1596,6 +1657,13 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   const Wave<T> w = wave<T>(M, mx, my);
   const V* jsp = cptr<T>(M, P.o_out);
   const V* qsp = cptr<T>(M, P.o_aux);
+  if (P.stage == SGS_STAGE) {
+    // the closure's term C Q alone, to o_in
+    V cq = cscale(qsp[q], T(C));
+    if (mx == 0 && my == 0) cq = cmake<V>(T(0), T(0));
+    gst(cptr<T>(M, P.o_in) + q, cq);
+    return;
+  }
   if (P.stage == AB2CN_STAGE) {
     const V j = jsp[q];
     ab2cn_update<T>(M, P, q, mx, my, cadd(cmake<V>(-j.x, -j.y), cscale(qsp[q], T(C))));
@@ -1845,8 +1913,8 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
-  if constexpr (OP == OP_PEN || OP == OP_SPONGE) {
-    // field-parallel kernel only (the sizes it cannot take are refused at init)
+  if constexpr (OP == OP_PEN || OP == OP_SPONGE || OP == OP_GTERMS) {
+    // field-parallel kernel only (the sizes it cannot take are refused before)
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) launch_rowp_t<T, OP, CL>(P, nmem, s);
     return;
   }
@@ -1860,6 +1928,7 @@ static int colfwdp_products(int op, int cl) {
   if (op == OP_RHS) return cl == 0 ? 1 : (cl == 3 || cl == 4) ? 6 : 3;
   if (op == OP_ADJ_B) return 3;
   if (op == OP_PEN) return 2;
+  if (op == OP_GTERMS) return 4;
   if (op == OP_ADJ_RHS) return cl == 1 ? 6 : 4;
   return 1;
 }
@@ -1889,8 +1958,8 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
-  if constexpr (OP == OP_PEN) {
-    // product-parallel kernel only (the sizes it cannot take are refused at init)
+  if constexpr (OP == OP_PEN || OP == OP_GTERMS) {
+    // product-parallel kernel only (the sizes it cannot take are refused before)
     if (colfwdp_ok(sizeof(T) == 8, OP, CL, P)) launch_colfwdp_t<T, OP, CL>(P, nmem, s);
     return;
   }
@@ -1927,6 +1996,7 @@ template <typename T> void colinv_dispatch(int op, int cl, const Phase& P, int n
     case OP_EXIT: case OP_ADJ_ENTRY: launch_colinv_t<T, OP_EXIT, 0>(P, n, s); break;
     case OP_MASKGRAD: launch_colinv_t<T, OP_MASKGRAD, 0>(P, n, s); break;
     case OP_SPONGE: launch_colinv_t<T, OP_SPONGE, 0>(P, n, s); break;
+    case OP_GTERMS: launch_colinv_t<T, OP_GTERMS, 0>(P, n, s); break;
     case OP_ADJ_B: launch_colinv_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colinv_t, T, OP_ADJ_RHS, cl, P, n, s); break;
     default: break;
@@ -1942,6 +2012,7 @@ template <typename T> void row_dispatch(int op, int cl, const Phase& P, int n, h
     case OP_MASKFWD: launch_row_t<T, OP_MASKFWD, 0>(P, n, s); break;
     case OP_PEN: launch_row_t<T, OP_PEN, 0>(P, n, s); break;
     case OP_SPONGE: launch_row_t<T, OP_SPONGE, 0>(P, n, s); break;
+    case OP_GTERMS: launch_row_t<T, OP_GTERMS, 0>(P, n, s); break;
     case OP_MASKGRAD: launch_row_t<T, OP_MASKGRAD, 0>(P, n, s); break;
     case OP_ADJ_B: launch_row_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_row_t, T, OP_ADJ_RHS, cl, P, n, s); break;
@@ -1955,6 +2026,7 @@ template <typename T> void colfwd_dispatch(int op, int cl, const Phase& P, int n
     case OP_ENTRY: case OP_ADJ_EXIT: launch_colfwd_t<T, OP_ENTRY, 0>(P, n, s); break;
     case OP_MASKFWD: launch_colfwd_t<T, OP_MASKFWD, 0>(P, n, s); break;
     case OP_PEN: launch_colfwd_t<T, OP_PEN, 0>(P, n, s); break;
+    case OP_GTERMS: launch_colfwd_t<T, OP_GTERMS, 0>(P, n, s); break;
     case OP_ADJ_B: launch_colfwd_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colfwd_t, T, OP_ADJ_RHS, cl, P, n, s); break;
     default: break;
@@ -1990,6 +2062,9 @@ extern template void row_dispatch<double>(int, int, const Phase&, int, hipStream
 hipError_t launch_colinv(bool dbl, int op, int cl, const Phase& P, int n, hipStream_t s) {
   if (dbl) colinv_dispatch<double>(op, cl, P, n, s); else colinv_dispatch<float>(op, cl, P, n, s);
   return hipGetLastError();
+}
+bool gterms_ok(bool dbl, const Phase& P) {
+  return P.W == 1 && rowp_ok(dbl, OP_GTERMS, 0, P) && colfwdp_ok(dbl, OP_GTERMS, 0, P);
 }
 int row_launch_blocks(bool dbl, int op, int cl, const Phase& P) {
   const bool par = (op == OP_RHS || op == OP_B || op == OP_ADJ_RHS) && rowp_ok(dbl, op, cl, P);

@@ -128,6 +128,21 @@ class Solver:
         _lib.check(self.L.qg_filter_les(self.h, les.h, _ptr(omega_fr), _ptr(out), _stream(self.device)))
         return out
 
+    def ideal_sgs(self, les, omega_fr, model=True, bar=True):
+        """Ideal SGS forcing of every member pair (this solver: the
+        fully-resolved grids, `les`: the coarsened ones) at the FR fields
+        omega_fr.  Returns (pi_ff, pi_model or None, omega_bar or None), flat
+        fields in `les`'s layout."""
+        self._check_flat(omega_fr, "omega_fr")
+        new = lambda: torch.empty(les.total, dtype=les.dtype, device=les.device)
+        pi_ff = new()
+        pi_m = new() if model else None
+        wbar = new() if bar else None
+        _lib.check(self.L.qg_ideal_sgs(self.h, les.h, _ptr(omega_fr), _ptr(pi_ff),
+                                       _ptr(pi_m) if pi_m is not None else None,
+                                       _ptr(wbar) if wbar is not None else None, _stream(self.device)))
+        return pi_ff, pi_m, wbar
+
     def pcc(self, a, b):
         """Pattern correlation of two flat fields, one float64 per member."""
         self._check_flat(a, "a")

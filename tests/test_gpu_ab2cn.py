@@ -98,3 +98,41 @@ def test_mixed_schemes_in_one_handle():
     say("mixed handle: rk4", ea, "ab2cn", eb)
     assert ea < 1e-12 and eb < 1e-12
     S.close()
+
+
+@pytest.mark.parametrize("closure,code", [("smag", 1), ("dsmag", 3)])
+def test_every_column_width(closure, code, tmp_path):
+    """Every strip width the tuner may choose, forced through its cache file:
+    the widths whose product strips overflow the product-parallel column
+    kernel (W ny = 4096 for three products, W ny >= 2048 for six) take the
+    general one, which must carry the AB2CN update too."""
+    import json
+
+    import torch
+    wl = configs.ab2cn_island(32, 512, 256, closure=closure, dt=5e-4)
+    m = wl.members[0]
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    nsteps = 3
+    S0 = solver_for([m], 32)
+    w0 = to_np(S0.pack([m.omega0])).reshape(256, 512)
+    S0.close()
+    wh, hist, refs = qg.enter(w0, M.g), None, []
+    for _ in range(nsteps):
+        wh, hist = ab2cn.step_spectral(wh, hist, M)
+        refs.append(qg.leave(wh, M.g))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/512x256/fp32/closure{code}/members1"
+    for W in (2, 4, 8, 16):
+        path = tmp_path / f"w{W}.json"
+        path.write_text(json.dumps({key + "/fwd": W, key + "/inv": 4}))
+        S = solver_for([m], 32)
+        S.autotune(str(path))
+        assert S.column_widths() == [W]
+        om = S.pack([m.omega0])
+        worst = 0.0
+        for n in range(1, nsteps + 1):
+            S.step(om, 1, use_graph=False)
+            worst = max(worst, rel_l2(to_np(om).reshape(256, 512), refs[n - 1]) / n)
+        say("AB2CN", closure, "W", W, "worst rel L2 per step", worst)
+        assert worst < 1e-5
+        S.close()

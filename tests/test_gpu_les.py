@@ -36,8 +36,8 @@ def test_filter_matches_oracle(precision, nx, ny, delta):
     om = F.pack([m.omega0 for m in fr_members])
     got = L.unpack(F.filter_les(L, om))
     tol = 1e-12 if precision == 64 else 1e-5
-    for g, m in zip(got, fr_members):
-        w = to_np(F.unpack(om)[fr_members.index(m)]).reshape(ny, nx)
+    for i, g in enumerate(got):
+        w = to_np(F.unpack(om)[i]).reshape(ny, nx)
         ref = oles.filter_to(qg.leave(qg.enter(w, qg.Grid(nx, ny, 2 * math.pi, math.pi)),
                                       qg.Grid(nx, ny, 2 * math.pi, math.pi)), 2 * math.pi, math.pi, delta)
         err = rel_l2(to_np(g).reshape(ny // delta, nx // delta), ref)
@@ -90,5 +90,74 @@ def test_a_posteriori_vorticity_correlation():
     ref = oles.pcc(lT, oles.filter_to(fT, 2 * math.pi, math.pi, 2))
     say("a posteriori PCC", got, ref)
     assert abs(got - ref) < 1e-10
+    F.close()
+    L.close()
+
+
+# ---------------------------------------------------------------------------
+# ideal SGS forcing and the closure's model term (a priori)
+# ---------------------------------------------------------------------------
+def les_pairs(nx, ny, delta, closure, seeds=(3, 4)):
+    """FR island members with small-scale-rich fields, and LES members on the
+    coarsened grids whose masks are H_full of the FR masks."""
+    fr = [island(nx, ny, "none", seed=s) for s in seeds]
+    for m in fr:
+        m.omega0 = inputs.spectrum_noise(nx, ny, 2 * math.pi, math.pi, m.meta["seed"], 2.0, 0.1)
+    les = [island(nx // delta, ny // delta, closure, seed=s) for s in seeds]
+    for mf, ml in zip(fr, les):
+        ml.chi = oles.filter_to(mf.chi, 2 * math.pi, math.pi, delta)
+        ml.chi_s = oles.filter_to(mf.chi_s, 2 * math.pi, math.pi, delta)
+    return fr, les
+
+
+@pytest.mark.parametrize("precision,nx,ny,delta,closure", [
+    (64, 256, 128, 2, "smag"), (64, 256, 128, 4, "leith"), (64, 256, 128, 2, "dsmag"),
+    (64, 256, 128, 2, "dleith"), (32, 1024, 512, 2, "dsmag"), (32, 512, 256, 2, "none")])
+def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure):
+    """Pi_FF, the model term at omega_bar and omega_bar itself against the
+    oracle; Pi_FF is a difference of forcings of size ||G||, so its error is
+    measured against that scale."""
+    fr, les = les_pairs(nx, ny, delta, closure)
+    F = solver_for(fr, precision)
+    L = solver_for(les, precision)
+    om = F.pack([m.omega0 for m in fr])
+    pi, model, wbar = F.ideal_sgs(L, om)
+    pcc = L.pcc(pi, model).cpu().numpy() if closure != "none" else None
+    tol = 1e-12 if precision == 64 else 1e-5
+    shp = (ny // delta, nx // delta)
+    for i, (mf, ml) in enumerate(zip(fr, les)):
+        Mf = oracle_model(mf.params, mf.chi, mf.chi_s)
+        Ml = oracle_model(ml.params, ml.chi, ml.chi_s)
+        w = to_np(F.unpack(om)[i]).reshape(ny, nx)
+        ref_pi, ref_wbar = oles.ideal_sgs(w, Mf, Ml)
+        ref_model = oles.model_sgs(ref_wbar, Ml)
+        Gbar = Ml.g.phys(oles.spectral_to_coarse(oles.advective_forcing(qg.enter(w, Mf.g), Mf), Mf.g,
+                                                 shp[1], shp[0], delta))
+        g_pi = to_np(L.unpack(pi)[i]).reshape(shp)
+        e_pi = float(np.linalg.norm(g_pi - ref_pi) / np.linalg.norm(Gbar))
+        e_w = rel_l2(to_np(L.unpack(wbar)[i]).reshape(shp), ref_wbar)
+        say("ideal sgs", precision, nx, ny, delta, closure, i, "pi/|G|", e_pi, "pi rel", rel_l2(g_pi, ref_pi),
+            "wbar", e_w)
+        assert e_pi < tol
+        assert e_w < tol
+        if closure == "none":
+            assert np.max(np.abs(to_np(L.unpack(model)[i]))) == 0.0
+            continue
+        e_m = rel_l2(to_np(L.unpack(model)[i]).reshape(shp), ref_model)
+        ref_pcc = oles.pcc(ref_pi, ref_model)
+        say("   model", e_m, "PCC a priori", pcc[i], ref_pcc)
+        assert e_m < tol
+        assert abs(pcc[i] - ref_pcc) < (1e-10 if precision == 64 else 1e-3)
+    F.close()
+    L.close()
+
+
+def test_ideal_sgs_refuses_unsupported_sizes():
+    fr = [island(2048, 256, "none", seed=1)]
+    les = [island(1024, 128, "smag", seed=1)]
+    F = solver_for(fr, 64)
+    L = solver_for(les, 64)
+    with pytest.raises(RuntimeError, match="SGS analysis"):
+        F.ideal_sgs(L, F.pack([fr[0].omega0]))
     F.close()
     L.close()
