@@ -1049,7 +1049,13 @@ int qg_pcc(qg_handle* H, const void* a, const void* b, double* out_dev, void* hi
   if (!a || !b || !out_dev) return fail(QG_EINVAL, "a, b or out_dev is NULL");
   Handle& h = H->h;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  for (const auto& g : h.groups) QG_LAUNCH(launch_pcc(g.dbl, base_phase(h, g), g.count, a, b, out_dev, st));
+  for (const auto& g : h.groups) {
+    // one block per 8192 points, at most 64, within the dpart area
+    const long long npts = (long long)g.nx * g.ny;
+    const long long cap = (5LL * (g.ny / 2) + 2LL * g.nspec + 8) / 5;
+    const int nblk = (int)std::max(1LL, std::min({(npts + 8191) / 8192, 64LL, cap}));
+    QG_LAUNCH(launch_pcc(g.dbl, base_phase(h, g), g.count, nblk, a, b, out_dev, st));
+  }
   return QG_OK;
 }
 

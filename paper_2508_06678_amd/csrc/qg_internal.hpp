@@ -127,7 +127,8 @@ struct FilterArgs {
   double inv_d2;               // 1 / delta^2
 };
 hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s);
-hipError_t launch_pcc(bool dbl, const Phase& P, int nmem, const void* a, const void* b, double* out,
+// nblk blocks per member; the member's dpart area must hold 5 nblk doubles
+hipError_t launch_pcc(bool dbl, const Phase& P, int nmem, int nblk, const void* a, const void* b, double* out,
                       hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // whether the SGS-analysis pass (field-parallel row and column kernels at

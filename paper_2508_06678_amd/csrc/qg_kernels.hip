@@ -1723,26 +1723,54 @@ __global__ void __launch_bounds__(256) k_filter_les(FilterArgs A) {
 }
 
 // ---------------------------------------------------------------- PCC
-// Pattern correlation of two fields per member (one block per member):
-// means first, then the centred sums, in double precision with a fixed
-// summation order.
+// Pattern correlation of two fields per member, two-pass in double
+// precision with fixed summation orders: (1) per-block sums of a and b,
+// (2) the means from those partials, then per-block centred sums of
+// (a - <a>)(b - <b>), (a - <a>)^2, (b - <b>)^2, (3) one block per member
+// adds them up.  Partials live in the member's dpart area: 2 doubles per
+// block, then 3 per block.
+constexpr int PCC_THREADS = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(1024) k_pcc(Phase P, const void* a, const void* b, double* out) {
-  __shared__ double red[16];
-  const MemberDev M = member_const(P, blockIdx.x);
+__global__ void __launch_bounds__(PCC_THREADS) k_pcc_sums(Phase P, const void* a, const void* b) {
+  __shared__ double red[PCC_THREADS / 64];
+  const MemberDev M = member_const(P, blockIdx.z);
   const long long n = (long long)P.nx * P.ny;
   const T* x = reinterpret_cast<const T*>(reinterpret_cast<const char*>(a) + M.omega_off);
   const T* y = reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + M.omega_off);
   double sx = 0.0, sy = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) { sx += (double)x[i]; sy += (double)y[i]; }
+  for (long long i = (long long)blockIdx.x * PCC_THREADS + threadIdx.x; i < n; i += (long long)gridDim.x * PCC_THREADS) {
+    sx += (double)x[i];
+    sy += (double)y[i];
+  }
   sx = block_sum(sx, red);
   sy = block_sum(sy, red);
+  if (threadIdx.x == 0) {
+    double* part = rptr<double>(M, P.o_dpart) + 2 * blockIdx.x;
+    part[0] = sx;
+    part[1] = sy;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(PCC_THREADS) k_pcc_centred(Phase P, const void* a, const void* b) {
+  __shared__ double red[PCC_THREADS / 64];
   __shared__ double mean[2];
-  if (threadIdx.x == 0) { mean[0] = sx / (double)n; mean[1] = sy / (double)n; }
+  const MemberDev M = member_const(P, blockIdx.z);
+  const long long n = (long long)P.nx * P.ny;
+  double* part = rptr<double>(M, P.o_dpart);
+  if (threadIdx.x == 0) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < (int)gridDim.x; ++k) { sx += part[2 * k]; sy += part[2 * k + 1]; }
+    mean[0] = sx / (double)n;
+    mean[1] = sy / (double)n;
+  }
   __syncthreads();
   const double mx = mean[0], my = mean[1];
+  const T* x = reinterpret_cast<const T*>(reinterpret_cast<const char*>(a) + M.omega_off);
+  const T* y = reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + M.omega_off);
   double sxy = 0.0, sxx = 0.0, syy = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+  for (long long i = (long long)blockIdx.x * PCC_THREADS + threadIdx.x; i < n; i += (long long)gridDim.x * PCC_THREADS) {
     const double dx = (double)x[i] - mx, dy = (double)y[i] - my;
     sxy += dx * dy;
     sxx += dx * dx;
@@ -1751,8 +1779,24 @@ __global__ void __launch_bounds__(1024) k_pcc(Phase P, const void* a, const void
   sxy = block_sum(sxy, red);
   sxx = block_sum(sxx, red);
   syy = block_sum(syy, red);
-  if (threadIdx.x == 0) out[M.user_index] = sxy / sqrt(sxx * syy);
+  if (threadIdx.x == 0) {
+    double* c = part + 2 * gridDim.x + 3 * blockIdx.x;
+    c[0] = sxy;
+    c[1] = sxx;
+    c[2] = syy;
+  }
 }
+
+#if QG_HAS(4)
+__global__ void __launch_bounds__(64) k_pcc_final(Phase P, int nblk, double* out) {
+  const MemberDev M = member_const(P, blockIdx.x);
+  if (threadIdx.x != 0) return;
+  const double* c = rptr<double>(M, P.o_dpart) + 2 * nblk;
+  double sxy = 0.0, sxx = 0.0, syy = 0.0;
+  for (int k = 0; k < nblk; ++k) { sxy += c[3 * k]; sxx += c[3 * k + 1]; syy += c[3 * k + 2]; }
+  out[M.user_index] = sxy / sqrt(sxx * syy);
+}
+#endif
 
 // C of the dynamic closures for diagnostics (slot 0 of the coef area).
 #if QG_HAS(4)
@@ -2119,9 +2163,17 @@ hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s) {
   else hipLaunchKernelGGL(k_filter_les<float>, grid, dim3(256), 0, s, A);
   return hipGetLastError();
 }
-hipError_t launch_pcc(bool dbl, const Phase& P, int n, const void* a, const void* b, double* out, hipStream_t s) {
-  if (dbl) hipLaunchKernelGGL(k_pcc<double>, dim3(n), dim3(1024), 0, s, P, a, b, out);
-  else hipLaunchKernelGGL(k_pcc<float>, dim3(n), dim3(1024), 0, s, P, a, b, out);
+hipError_t launch_pcc(bool dbl, const Phase& P, int n, int nblk, const void* a, const void* b, double* out,
+                      hipStream_t s) {
+  const dim3 grid(nblk, 1, n);
+  if (dbl) {
+    hipLaunchKernelGGL(k_pcc_sums<double>, grid, dim3(PCC_THREADS), 0, s, P, a, b);
+    hipLaunchKernelGGL(k_pcc_centred<double>, grid, dim3(PCC_THREADS), 0, s, P, a, b);
+  } else {
+    hipLaunchKernelGGL(k_pcc_sums<float>, grid, dim3(PCC_THREADS), 0, s, P, a, b);
+    hipLaunchKernelGGL(k_pcc_centred<float>, grid, dim3(PCC_THREADS), 0, s, P, a, b);
+  }
+  hipLaunchKernelGGL(k_pcc_final, dim3(n), dim3(64), 0, s, P, nblk, out);
   return hipGetLastError();
 }
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {

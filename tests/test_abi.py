@@ -97,6 +97,9 @@ def test_null_arguments():
     assert L.qg_step(None, None, 1, 0, None, 1, None) == _lib.QG_EINVAL
     assert L.qg_diag(None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_adjoint_step(None, None, None, 1, None, None) == _lib.QG_EINVAL
+    assert L.qg_filter_les(None, None, None, None, None) == _lib.QG_EINVAL
+    assert L.qg_ideal_sgs(None, None, None, None, None, None, None) == _lib.QG_EINVAL
+    assert L.qg_pcc(None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_run_phase(None, 0, 1, 1, None) == _lib.QG_EINVAL
     L.qg_destroy(None)
 

@@ -110,21 +110,36 @@ def les_pairs(nx, ny, delta, closure, seeds=(3, 4)):
     return fr, les
 
 
-@pytest.mark.parametrize("precision,nx,ny,delta,closure", [
-    (64, 256, 128, 2, "smag"), (64, 256, 128, 4, "leith"), (64, 256, 128, 2, "dsmag"),
-    (64, 256, 128, 2, "dleith"), (32, 1024, 512, 2, "dsmag"), (32, 512, 256, 2, "none")])
-def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure):
+@pytest.mark.parametrize("precision,nx,ny,delta,closure,seeds", [
+    (64, 256, 128, 2, "smag", (3, 4)), (64, 256, 128, 4, "leith", (3, 4)),
+    (64, 256, 128, 2, "dsmag", (5, 3)), (64, 256, 128, 2, "dleith", (5, 3)),
+    (32, 1024, 512, 2, "dsmag", (3, 4)), (32, 512, 256, 2, "none", (3, 4))])
+def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure, seeds):
     """Pi_FF, the model term at omega_bar and omega_bar itself against the
-    oracle; Pi_FF is a difference of forcings of size ||G||, so its error is
-    measured against that scale."""
-    fr, les = les_pairs(nx, ny, delta, closure)
+    oracle.  Pi_FF is a difference of forcings of size ||G|| (G_les and the
+    filtered G_fr), so its error is measured against that scale.  The
+    dynamic C is a ratio of grid sums <HM>/<M^2> whose terms cancel by the
+    factor kappa = sum|HM| / |sum HM|, and H = D FFT(J~) - T J_hat and
+    M = r D div(g) - T Q_hat are themselves differences that cancel by
+    kappa_H = (|H| + |T J|)/|H| and kappa_M = (|M| + |T Q|)/|M|.  In
+    32-bit runs the model term is therefore checked in two factors: its
+    shape Q = model / C against the oracle's to 1e-5 (the GPU's C taken as
+    the least-squares factor between its model term and the oracle's Q),
+    and C against the oracle's within the first-order
+    bound 1e-6 kappa (kappa_H + kappa_M) + 1e-5 (per-entry errors ~1e-6 of
+    the operands, from FFT chains of ~log2 N rounded passes); 64-bit runs
+    check the model term whole to 1e-12.
+    The seeds of the dynamic cases give one member with C > 0 and one where
+    the clip sets C = 0."""
+    fr, les = les_pairs(nx, ny, delta, closure, seeds)
     F = solver_for(fr, precision)
     L = solver_for(les, precision)
     om = F.pack([m.omega0 for m in fr])
     pi, model, wbar = F.ideal_sgs(L, om)
-    pcc = L.pcc(pi, model).cpu().numpy() if closure != "none" else None
+    pcc = L.pcc(pi, model).cpu().numpy()
     tol = 1e-12 if precision == 64 else 1e-5
     shp = (ny // delta, nx // delta)
+    positive_c = 0
     for i, (mf, ml) in enumerate(zip(fr, les)):
         Mf = oracle_model(mf.params, mf.chi, mf.chi_s)
         Ml = oracle_model(ml.params, ml.chi, ml.chi_s)
@@ -134,30 +149,45 @@ def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure):
         Gbar = Ml.g.phys(oles.spectral_to_coarse(oles.advective_forcing(qg.enter(w, Mf.g), Mf), Mf.g,
                                                  shp[1], shp[0], delta))
         g_pi = to_np(L.unpack(pi)[i]).reshape(shp)
+        g_model = to_np(L.unpack(model)[i]).reshape(shp)
         e_pi = float(np.linalg.norm(g_pi - ref_pi) / np.linalg.norm(Gbar))
         e_w = rel_l2(to_np(L.unpack(wbar)[i]).reshape(shp), ref_wbar)
         say("ideal sgs", precision, nx, ny, delta, closure, i, "pi/|G|", e_pi, "pi rel", rel_l2(g_pi, ref_pi),
             "wbar", e_w)
         assert e_pi < tol
         assert e_w < tol
-        if closure == "none":
-            assert np.max(np.abs(to_np(L.unpack(model)[i]))) == 0.0
+        if not np.any(ref_model):   # no closure, or the dynamic clip at C = 0
+            assert not np.any(g_model)
+            assert np.isnan(pcc[i])
             continue
-        e_m = rel_l2(to_np(L.unpack(model)[i]).reshape(shp), ref_model)
+        tol_m = tol
+        if closure in ("dsmag", "dleith"):
+            positive_c += 1
+            out = {}
+            qg.rhs(qg.enter(ref_wbar, Ml.g), Ml, out)
+            g = Ml.g
+            H, M = g.phys(out["Hh"]), g.phys(out["Mh"])
+            kappa = float(np.sum(np.abs(H * M)) / abs(np.sum(H * M)))
+            nrm = np.linalg.norm
+            k_h = float((nrm(out["Hh"]) + nrm(g.T * out["Jh"])) / nrm(out["Hh"]))
+            k_m = float((nrm(out["Mh"]) + nrm(g.T * out["Qh"])) / nrm(out["Mh"]))
+            say("   C", out["C"], "kappa", kappa, "kappa_H", k_h, "kappa_M", k_m)
+            if precision == 32:
+                q_ref = ref_model / out["C"]
+                c_gpu = float(np.sum(g_model * q_ref) / np.sum(q_ref * q_ref))
+                e_c = abs(c_gpu - out["C"]) / out["C"]
+                bar_c = 1e-5 + 1e-6 * kappa * (k_h + k_m)
+                e_q = rel_l2(g_model / c_gpu, q_ref)
+                say("   C gpu", c_gpu, "rel", e_c, "bar", bar_c, "shape Q rel", e_q)
+                assert e_c < bar_c
+                assert e_q < 1e-5
+                tol_m = 1e-5 + bar_c
+        e_m = rel_l2(g_model, ref_model)
         ref_pcc = oles.pcc(ref_pi, ref_model)
-        say("   model", e_m, "PCC a priori", pcc[i], ref_pcc)
-        assert e_m < tol
+        say("   model", e_m, "bar", tol_m, "PCC a priori", pcc[i], ref_pcc)
+        assert e_m < tol_m
         assert abs(pcc[i] - ref_pcc) < (1e-10 if precision == 64 else 1e-3)
-    F.close()
-    L.close()
-
-
-def test_ideal_sgs_refuses_unsupported_sizes():
-    fr = [island(2048, 256, "none", seed=1)]
-    les = [island(1024, 128, "smag", seed=1)]
-    F = solver_for(fr, 64)
-    L = solver_for(les, 64)
-    with pytest.raises(RuntimeError, match="SGS analysis"):
-        F.ideal_sgs(L, F.pack([fr[0].omega0]))
+    if closure in ("dsmag", "dleith"):
+        assert positive_c >= 1
     F.close()
     L.close()
