@@ -1,0 +1,159 @@
+"""The paper's flow past a circular island (Sec. IV-A) as a runnable set-up,
+and the a-priori analysis of its Table I: a fully-resolved (FR) run sampled
+at regular snapshots; at each snapshot the ideal SGS forcing Pi_FF on the
+LES grid, each closure's model term at the filtered field, and their
+pattern correlation (PCC); the PCCs averaged over the snapshots.
+
+    python -m paper_2508_06678_amd.experiments island [--n 1024]
+        [--steps 1000000] [--every 5000] [--precision 64]
+
+Constants the paper states: Lx = Ly = 8 pi; island diameter 2 pi/5 centred
+0.35 Lx from the western edge, mid-channel; a sponge of width 0.05 Lx on all
+four edges; inflow 2; Re = 200; beta = 0; eta = 1.025 dt and
+eta_sponge = eta; dt = 1e-4; FR grid 1024^2; delta = 2; T = 100 (10^6
+steps) with snapshots every 5000 steps; the AB2CN scheme.
+
+Left open by the paper and fixed here: the island edge (tanh over two FR
+cells), the start (rest plus a 1e-3 rms perturbation at 1 <= |k| <= 8 that
+breaks the symmetry), the averaging window (all snapshots, and those with
+t >= 20, after the spin-up the paper describes) and the region of interest
+(the PCC is reported over the whole box and over the box inside the sponge
+layers less one filter width).  The LES masks are H_full of the FR masks.
+
+Every field operation runs in the HIP library (steps, filtering, Pi_FF,
+model terms, whole-box PCC); the region-of-interest PCC is a diagnostic
+formed here from those fields.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import configs, inputs
+from .solver import Solver
+
+CLOSURES = ("smag", "leith", "dsmag", "dleith")
+
+
+def island_fr(n=1024, precision=64, dt=1e-4, seed=0):
+    """The FR member of the island application (Sec. IV-A)."""
+    lx = ly = 8.0 * math.pi
+    eta = 1.025 * dt
+    p = configs.base_params(n, n, lx, ly, beta=0.0, re=200.0, dt=dt, eta=eta, u_in=2.0,
+                            sponge_sigma=1.0 / eta, closure="none", precision=precision)
+    p["scheme"] = "ab2cn"
+    chi = inputs.island_mask(n, n, lx, ly, 0.35 * lx, 0.5 * ly, math.pi / 5.0)
+    chi_s = inputs.sponge_mask(n, n, lx, ly, thickness=0.05 * lx, sides="xy")
+    w0 = inputs.bandpass_noise(n, n, lx, ly, seed, 1.0, 8.0, 1e-3)
+    return configs.Member(p, chi, chi_s, w0, dict(geometry="island", seed=seed, lx=lx))
+
+
+def les_params(fr_params, delta, closure, dt=1e-3):
+    """The LES member on the grid coarsened by delta: same physics, the
+    closure's default coefficient (the PCC does not depend on it)."""
+    p = dict(fr_params)
+    p.update(nx=fr_params["nx"] // delta, ny=fr_params["ny"] // delta, closure=closure,
+             c=configs.STATIC_C[closure], dt=dt, scheme="rk4")
+    return p
+
+
+def filtered_masks(fr, fr_solver, delta):
+    """H_full of the FR masks on the LES grid, through the library's filter
+    (which drops the mean mode of a state; H(0) = 1, so the mean is added
+    back)."""
+    lp = les_params(fr.params, delta, "none")
+    zero = np.zeros((lp["ny"], lp["nx"]))
+    tmp = Solver([lp], [zero], [zero], device=fr_solver.device)
+    out = []
+    for m in (fr.chi, fr.chi_s):
+        flat = fr_solver.pack([m])
+        bar = fr_solver.filter_les(tmp, flat) + float(np.mean(m))
+        out.append(tmp.unpack(bar)[0].clone())
+    tmp.close()
+    return out
+
+
+def region_of_interest(n_les, lx, sponge_width, delta_ff):
+    """Boolean (ny, nx) mask of the LES grid inside the sponge layers less
+    one filter width."""
+    x = np.arange(n_les) * (lx / n_les)
+    inner = (x >= sponge_width + delta_ff) & (x <= lx - sponge_width - delta_ff)
+    return np.logical_and.outer(inner, inner)
+
+
+def masked_pcc(a, b, mask):
+    x = a[mask].double()
+    y = b[mask].double()
+    dx = x - x.mean()
+    dy = y - y.mean()
+    return float((dx * dy).mean() / torch.sqrt((dx * dx).mean() * (dy * dy).mean()))
+
+
+def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.0):
+    """Run the FR member for nsteps, analysing every `every` steps; returns
+    the per-snapshot records and the averages."""
+    p = fr.params
+    F = Solver([p], [fr.chi], [fr.chi_s])
+    om = F.pack([fr.omega0])
+    chi_bar, chs_bar = filtered_masks(fr, F, delta)
+    les = {c: Solver([les_params(p, delta, c)], [chi_bar], [chs_bar]) for c in closures}
+    lx = fr.meta.get("lx", p["lx"])
+    n_les = p["nx"] // delta
+    roi = torch.as_tensor(region_of_interest(n_les, lx, 0.05 * lx, delta * lx / p["nx"]), device=om.device)
+    records = []
+    t0 = time.perf_counter()
+    for k in range(nsteps // every):
+        F.step(om, every)
+        d = F.diag(om)[0][0].cpu().numpy()
+        rec = dict(step=(k + 1) * every, t=(k + 1) * every * p["dt"], energy=float(d[0]),
+                   enstrophy=float(d[1]), cfl=float(d[6]), nonfinite=bool(d[7] != 0))
+        if rec["nonfinite"]:
+            log(json.dumps(rec))
+            raise RuntimeError(f"non-finite FR state at step {rec['step']}")
+        for c, L in les.items():
+            pi, model, _ = F.ideal_sgs(L, om, bar=False)
+            rec[f"pcc_{c}"] = float(L.pcc(pi, model)[0])
+            rec[f"pcc_roi_{c}"] = masked_pcc(pi.view(n_les, n_les), model.view(n_les, n_les), roi)
+            if c in ("dsmag", "dleith"):
+                rec[f"C_{c}"] = float(L.diag(F.filter_les(L, om))[0][0, 2])
+        rec["wall_s"] = round(time.perf_counter() - t0, 2)
+        records.append(rec)
+        log(json.dumps(rec))
+    F.close()
+    for L in les.values():
+        L.close()
+    summary = {}
+    for key in [k for k in records[0] if k.startswith("pcc_")]:
+        vals = np.array([r[key] for r in records], dtype=np.float64)
+        late = np.array([r[key] for r in records if r["t"] >= t_avg], dtype=np.float64)
+        summary[key] = {"mean_all": float(np.nanmean(vals)) if np.isfinite(vals).any() else None,
+                        f"mean_t_ge_{t_avg:g}": (float(np.nanmean(late)) if late.size and np.isfinite(late).any()
+                                                 else None)}
+    return records, summary
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("case", choices=["island"])
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
+    ap.add_argument("--dt", type=float, default=1e-4)
+    ap.add_argument("--steps", type=int, default=1_000_000)
+    ap.add_argument("--every", type=int, default=5000)
+    ap.add_argument("--delta", type=int, default=2)
+    args = ap.parse_args(argv)
+    fr = island_fr(args.n, args.precision, args.dt)
+    records, summary = a_priori(fr, args.steps, args.every, args.delta,
+                                log=lambda s: print(s, flush=True))
+    print(json.dumps({"summary": summary, "case": args.case, "n": args.n, "precision": args.precision,
+                      "dt": args.dt, "steps": args.steps, "every": args.every, "delta": args.delta}),
+          flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

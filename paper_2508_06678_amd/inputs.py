@@ -47,12 +47,17 @@ def cape_mask(nx, ny, lx, ly, coast=0.2, height=0.6, width=0.3, xc=None, eps=Non
     return upper * lower
 
 
-def sponge_mask(nx, ny, lx, ly, thickness=None):
-    """chi_s = max(0, 1 - d/d_s), d = distance to the x ends (x = 0 == lx)."""
+def sponge_mask(nx, ny, lx, ly, thickness=None, sides="x"):
+    """chi_s = max(0, 1 - d/d_s), d = distance to the x ends (x = 0 == lx),
+    or (sides="xy") to the nearest of the four box edges."""
     if thickness is None:
         thickness = lx / 16.0
-    X, _ = grid_xy(nx, ny, lx, ly)
+    X, Y = grid_xy(nx, ny, lx, ly)
     d = np.minimum(X, lx - X)
+    if sides == "xy":
+        d = np.minimum(d, np.minimum(Y, ly - Y))
+    elif sides != "x":
+        raise ValueError("sides must be 'x' or 'xy'")
     return np.maximum(0.0, 1.0 - d / thickness)
 
 

@@ -1,0 +1,50 @@
+"""Host logic of the island set-up (Sec. IV-A) and of the a-priori driver:
+the constants the paper states, the four-sided sponge ramp and the region
+of interest.  CPU only."""
+import math
+
+import numpy as np
+
+from paper_2508_06678_amd import experiments, inputs
+
+
+def test_island_constants_follow_the_paper():
+    fr = experiments.island_fr(256, 64, dt=1e-4)
+    p = fr.params
+    assert p["lx"] == p["ly"] == 8 * math.pi
+    assert p["re"] == 200.0 and p["beta"] == 0.0 and p["u_in"] == 2.0
+    assert p["eta"] == 1.025e-4 and abs(p["sponge_sigma"] * p["eta"] - 1.0) < 1e-15   # eta_sponge = eta
+    assert p["scheme"] == "ab2cn" and p["closure"] == "none"
+    # island of diameter 2 pi/5 centred 0.35 Lx, mid-channel: chi = 1/2 on its edge
+    dx = p["lx"] / 256
+    x = np.arange(256) * dx
+    row = fr.chi[128]
+    inside = x[row > 0.5]
+    assert abs(inside.mean() - 0.35 * p["lx"]) < dx
+    assert abs((inside.max() - inside.min() + dx) - 2 * math.pi / 5) < 2 * dx
+    # sponge: 1 on every edge, 0 beyond 0.05 Lx
+    s = fr.chi_s
+    assert s[0, 128] == 1.0 and s[128, 0] == 1.0 and s[128, 128] == 0.0
+    w = 0.05 * p["lx"]
+    assert np.all(s[128][(x > w) & (x < p["lx"] - w)] == 0.0)
+    les = experiments.les_params(p, 2, "dleith")
+    assert les["nx"] == 128 and les["closure"] == "dleith" and les["eta"] == p["eta"]
+
+
+def test_four_sided_sponge_is_the_distance_ramp():
+    s = inputs.sponge_mask(64, 32, 2.0, 1.0, thickness=0.25, sides="xy")
+    X, Y = inputs.grid_xy(64, 32, 2.0, 1.0)
+    d = np.minimum(np.minimum(X, 2.0 - X), np.minimum(Y, 1.0 - Y))
+    assert np.allclose(s, np.maximum(0.0, 1.0 - d / 0.25), atol=0, rtol=0)
+    sx = inputs.sponge_mask(64, 32, 2.0, 1.0, thickness=0.25)
+    assert np.all(sx[:, 32] == 0.0) and np.all(sx[:, 0] == 1.0)
+
+
+def test_region_of_interest_excludes_sponge_and_filter_width():
+    lx = 8 * math.pi
+    roi = experiments.region_of_interest(128, lx, 0.05 * lx, 2 * lx / 256)
+    x = np.arange(128) * lx / 128
+    edge = 0.05 * lx + 2 * lx / 256
+    assert roi.shape == (128, 128)
+    assert np.array_equal(roi[64], (x >= edge) & (x <= lx - edge))
+    assert np.array_equal(roi[:, 64], roi[64])

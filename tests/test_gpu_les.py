@@ -191,3 +191,39 @@ def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure, seeds):
         assert positive_c >= 1
     F.close()
     L.close()
+
+
+def test_a_priori_driver_matches_oracle():
+    """The island set-up at 128^2 (dt 1e-3): 20 AB2CN steps, snapshots every
+    10; the driver's PCCs (whole box and region of interest) at the last
+    snapshot against the oracle's pipeline -- AB2CN run, H_full of the
+    masks, Pi_FF, model terms, PCC."""
+    import torch
+
+    from oracle import ab2cn
+    from paper_2508_06678_amd import experiments
+    fr = experiments.island_fr(128, 64, dt=1e-3)
+    recs, summary = experiments.a_priori(fr, 20, 10, 2, closures=("smag", "dleith"), log=lambda s: None)
+    assert [r["step"] for r in recs] == [10, 20]
+    lx = fr.params["lx"]
+    Mf = oracle_model(fr.params, fr.chi, fr.chi_s)
+    wT = ab2cn.run(fr.omega0, Mf, 20)[0]
+    chi_bar = oles.filter_to(fr.chi, lx, lx, 2)
+    chs_bar = oles.filter_to(fr.chi_s, lx, lx, 2)
+    roi = experiments.region_of_interest(64, lx, 0.05 * lx, 2 * lx / 128)
+    for c in ("smag", "dleith"):
+        Ml = oracle_model(experiments.les_params(fr.params, 2, c), chi_bar, chs_bar)
+        ref_pi, ref_wbar = oles.ideal_sgs(wT, Mf, Ml)
+        ref_model = oles.model_sgs(ref_wbar, Ml)
+        if not np.any(ref_model):      # the dynamic clip at C = 0
+            say("driver", c, "C = 0")
+            assert math.isnan(recs[-1][f"pcc_{c}"])
+            continue
+        ref = oles.pcc(ref_pi, ref_model)
+        ref_roi = oles.pcc(ref_pi[roi], ref_model[roi])
+        got, got_roi = recs[-1][f"pcc_{c}"], recs[-1][f"pcc_roi_{c}"]
+        say("driver", c, got, ref, got_roi, ref_roi)
+        assert abs(got - ref) < 1e-9
+        assert abs(got_roi - ref_roi) < 1e-9
+    assert summary["pcc_smag"]["mean_all"] == pytest.approx(np.mean([r["pcc_smag"] for r in recs]))
+    torch.cuda.synchronize()
