@@ -1,28 +1,39 @@
-"""The paper's flow past a circular island (Sec. IV-A) as a runnable set-up,
-and the a-priori analysis of its Table I: a fully-resolved (FR) run sampled
-at regular snapshots; at each snapshot the ideal SGS forcing Pi_FF on the
-LES grid, each closure's model term at the filtered field, and their
-pattern correlation (PCC); the PCCs averaged over the snapshots.
+"""The paper's flows past a circular island (Sec. IV-A) and past an
+idealized cape (Sec. IV-B) as runnable set-ups, and the a-priori analysis of
+its Tables I and III: a fully-resolved (FR) run sampled at regular
+snapshots; at each snapshot the ideal SGS forcing Pi_FF on the LES grid,
+each closure's model term at the filtered field, and their pattern
+correlation (PCC); the PCCs averaged over the snapshots.
 
-    python -m paper_2508_06678_amd.experiments island [--n 1024]
-        [--steps 1000000] [--every 5000] [--precision 64]
+    python -m paper_2508_06678_amd.experiments island|cape [--beta B]
+        [--n 1024] [--steps 1000000] [--every 5000] [--precision 64]
 
-Constants the paper states: Lx = Ly = 8 pi; island diameter 2 pi/5 centred
-0.35 Lx from the western edge, mid-channel; a sponge of width 0.05 Lx on all
-four edges; inflow 2; Re = 200; beta = 0; eta = 1.025 dt and
-eta_sponge = eta; dt = 1e-4; FR grid 1024^2; delta = 2; T = 100 (10^6
-steps) with snapshots every 5000 steps; the AB2CN scheme.
+Constants the paper states: Lx = Ly = 8 pi; inflow 2; Re = 200;
+eta = 1.025 dt and eta_sponge = eta; dt = 1e-4; FR grid 1024^2; delta = 2;
+T = 100 (10^6 steps) with snapshots every 5000 steps; the AB2CN scheme.
+Island: diameter 2 pi/5 centred 0.35 Lx from the western edge,
+mid-channel; beta = 0; a sponge of width 0.05 Lx on all four edges.  Cape:
+land below y = 4 exp(-((x - 0.2 Lx)/1)^2); beta in {0, 0.1, 1}; sponge
+parameters 0.125 Lx and 0.1 Lx.
 
-Left open by the paper and fixed here: the island edge (tanh over two FR
-cells), the start (rest plus a 1e-3 rms perturbation at 1 <= |k| <= 8 that
-breaks the symmetry), the averaging window (all snapshots, and those with
-t >= 20, after the spin-up the paper describes) and the region of interest
-(the PCC is reported over the whole box and over the box inside the sponge
-layers less one filter width).  The LES masks are H_full of the FR masks.
+Left open by the paper and fixed here: the land edges (tanh over two FR
+cells; the cape measured from the southern edge and lifted off the
+periodic seam by two smoothing widths), the cape's sponge (read as
+thickness 0.125 Lx along the x edges and 0.1 Lx along the y edges), the
+start (rest plus a 1e-3 rms perturbation at 1 <= |k| <= 8 that breaks the
+symmetry), the averaging window (all snapshots, and those with t >= 20,
+after the spin-up the paper describes) and the region of interest (the PCC
+is reported over the whole box and over the box inside the sponge layers
+less one filter width).  The LES masks are H_full of the FR masks.
+
+Besides the PCC of the whole Pi_FF, each snapshot reports it over open
+water (the region of interest where the filtered land mask is below 0.05)
+and the PCC of the advection commutator alone (the analysis handles built
+without penalization and sponge), to show which part of Pi_FF sets it.
 
 Every field operation runs in the HIP library (steps, filtering, Pi_FF,
-model terms, whole-box PCC); the region-of-interest PCC is a diagnostic
-formed here from those fields.
+model terms, whole-box PCC); the masked PCCs are diagnostics formed here
+from those fields.
 """
 import argparse
 import json
@@ -49,7 +60,22 @@ def island_fr(n=1024, precision=64, dt=1e-4, seed=0):
     chi = inputs.island_mask(n, n, lx, ly, 0.35 * lx, 0.5 * ly, math.pi / 5.0)
     chi_s = inputs.sponge_mask(n, n, lx, ly, thickness=0.05 * lx, sides="xy")
     w0 = inputs.bandpass_noise(n, n, lx, ly, seed, 1.0, 8.0, 1e-3)
-    return configs.Member(p, chi, chi_s, w0, dict(geometry="island", seed=seed, lx=lx))
+    return configs.Member(p, chi, chi_s, w0, dict(geometry="island", seed=seed, lx=lx,
+                                                  sponge_x=0.05 * lx, sponge_y=0.05 * lx))
+
+
+def cape_fr(n=1024, precision=64, dt=1e-4, beta=0.0, seed=0):
+    """The FR member of the cape application (Sec. IV-B)."""
+    lx = ly = 8.0 * math.pi
+    eta = 1.025 * dt
+    p = configs.base_params(n, n, lx, ly, beta=beta, re=200.0, dt=dt, eta=eta, u_in=2.0,
+                            sponge_sigma=1.0 / eta, closure="none", precision=precision)
+    p["scheme"] = "ab2cn"
+    chi = inputs.gaussian_cape_mask(n, n, lx, ly, 0.2 * lx, 4.0, 1.0)
+    chi_s = inputs.sponge_mask(n, n, lx, ly, thickness=0.125 * lx, sides="xy", thickness_y=0.1 * lx)
+    w0 = inputs.bandpass_noise(n, n, lx, ly, seed, 1.0, 8.0, 1e-3)
+    return configs.Member(p, chi, chi_s, w0, dict(geometry="cape", seed=seed, lx=lx,
+                                                  sponge_x=0.125 * lx, sponge_y=0.1 * lx))
 
 
 def les_params(fr_params, delta, closure, dt=1e-3):
@@ -77,12 +103,14 @@ def filtered_masks(fr, fr_solver, delta):
     return out
 
 
-def region_of_interest(n_les, lx, sponge_width, delta_ff):
-    """Boolean (ny, nx) mask of the LES grid inside the sponge layers less
-    one filter width."""
+def region_of_interest(n_les, lx, sponge_x, delta_ff, sponge_y=None):
+    """Boolean (ny, nx) mask of the (square) LES grid inside the sponge
+    layers less one filter width."""
     x = np.arange(n_les) * (lx / n_les)
-    inner = (x >= sponge_width + delta_ff) & (x <= lx - sponge_width - delta_ff)
-    return np.logical_and.outer(inner, inner)
+    sy = sponge_x if sponge_y is None else sponge_y
+    inner_x = (x >= sponge_x + delta_ff) & (x <= lx - sponge_x - delta_ff)
+    inner_y = (x >= sy + delta_ff) & (x <= lx - sy - delta_ff)
+    return np.logical_and.outer(inner_y, inner_x)
 
 
 def masked_pcc(a, b, mask):
@@ -101,9 +129,15 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
     om = F.pack([fr.omega0])
     chi_bar, chs_bar = filtered_masks(fr, F, delta)
     les = {c: Solver([les_params(p, delta, c)], [chi_bar], [chs_bar]) for c in closures}
+    # the same analysis with the advection commutator alone
+    pj = dict(p, eta=math.inf, sponge_sigma=0.0, scheme="rk4")
+    FJ = Solver([pj], [fr.chi], [fr.chi_s])
+    lesj = {c: Solver([les_params(pj, delta, c)], [chi_bar], [chs_bar]) for c in closures}
     lx = fr.meta.get("lx", p["lx"])
     n_les = p["nx"] // delta
-    roi = torch.as_tensor(region_of_interest(n_les, lx, 0.05 * lx, delta * lx / p["nx"]), device=om.device)
+    roi = torch.as_tensor(region_of_interest(n_les, lx, fr.meta["sponge_x"], delta * lx / p["nx"],
+                                             fr.meta["sponge_y"]), device=om.device)
+    sea = roi & (chi_bar.view(n_les, n_les) < 0.05)
     records = []
     t0 = time.perf_counter()
     for k in range(nsteps // every):
@@ -118,16 +152,25 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
             pi, model, _ = F.ideal_sgs(L, om, bar=False)
             rec[f"pcc_{c}"] = float(L.pcc(pi, model)[0])
             rec[f"pcc_roi_{c}"] = masked_pcc(pi.view(n_les, n_les), model.view(n_les, n_les), roi)
+            rec[f"pcc_sea_{c}"] = masked_pcc(pi.view(n_les, n_les), model.view(n_les, n_les), sea)
+            pij, _, _ = FJ.ideal_sgs(lesj[c], om, model=False, bar=False)
+            rec[f"pcc_J_{c}"] = float(lesj[c].pcc(pij, model)[0])
+            rec[f"pcc_J_sea_{c}"] = masked_pcc(pij.view(n_les, n_les), model.view(n_les, n_les), sea)
+            if c == closures[0]:
+                a = pi.view(n_les, n_les)
+                rec["pi_rms_sea_over_land"] = float(a[sea].double().pow(2).mean().sqrt()
+                                                    / a[~sea].double().pow(2).mean().sqrt())
             if c in ("dsmag", "dleith"):
                 rec[f"C_{c}"] = float(L.diag(F.filter_les(L, om))[0][0, 2])
         rec["wall_s"] = round(time.perf_counter() - t0, 2)
         records.append(rec)
         log(json.dumps(rec))
     F.close()
-    for L in les.values():
+    FJ.close()
+    for L in list(les.values()) + list(lesj.values()):
         L.close()
     summary = {}
-    for key in [k for k in records[0] if k.startswith("pcc_")]:
+    for key in [k for k in records[0] if k.startswith("pcc_") or k.startswith("pi_rms")]:
         vals = np.array([r[key] for r in records], dtype=np.float64)
         late = np.array([r[key] for r in records if r["t"] >= t_avg], dtype=np.float64)
         summary[key] = {"mean_all": float(np.nanmean(vals)) if np.isfinite(vals).any() else None,
@@ -138,7 +181,8 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("case", choices=["island"])
+    ap.add_argument("case", choices=["island", "cape"])
+    ap.add_argument("--beta", type=float, default=0.0, help="cape only")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--precision", type=int, default=64, choices=[32, 64])
     ap.add_argument("--dt", type=float, default=1e-4)
@@ -146,10 +190,14 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=5000)
     ap.add_argument("--delta", type=int, default=2)
     args = ap.parse_args(argv)
-    fr = island_fr(args.n, args.precision, args.dt)
+    if args.case == "island":
+        fr = island_fr(args.n, args.precision, args.dt)
+    else:
+        fr = cape_fr(args.n, args.precision, args.dt, args.beta)
     records, summary = a_priori(fr, args.steps, args.every, args.delta,
                                 log=lambda s: print(s, flush=True))
-    print(json.dumps({"summary": summary, "case": args.case, "n": args.n, "precision": args.precision,
+    print(json.dumps({"summary": summary, "case": args.case, "beta": fr.params["beta"], "n": args.n,
+                      "precision": args.precision,
                       "dt": args.dt, "steps": args.steps, "every": args.every, "delta": args.delta}),
           flush=True)
     return 0

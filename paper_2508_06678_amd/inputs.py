@@ -47,18 +47,32 @@ def cape_mask(nx, ny, lx, ly, coast=0.2, height=0.6, width=0.3, xc=None, eps=Non
     return upper * lower
 
 
-def sponge_mask(nx, ny, lx, ly, thickness=None, sides="x"):
+def sponge_mask(nx, ny, lx, ly, thickness=None, sides="x", thickness_y=None):
     """chi_s = max(0, 1 - d/d_s), d = distance to the x ends (x = 0 == lx),
-    or (sides="xy") to the nearest of the four box edges."""
+    or (sides="xy") to the nearest of the four box edges, with thickness_y
+    (default: thickness) along the y edges."""
     if thickness is None:
         thickness = lx / 16.0
     X, Y = grid_xy(nx, ny, lx, ly)
-    d = np.minimum(X, lx - X)
+    ramp = np.maximum(0.0, 1.0 - np.minimum(X, lx - X) / thickness)
     if sides == "xy":
-        d = np.minimum(d, np.minimum(Y, ly - Y))
+        ty = thickness if thickness_y is None else thickness_y
+        ramp = np.maximum(ramp, 1.0 - np.minimum(Y, ly - Y) / ty)
     elif sides != "x":
         raise ValueError("sides must be 'x' or 'xy'")
-    return np.maximum(0.0, 1.0 - d / thickness)
+    return ramp
+
+
+def gaussian_cape_mask(nx, ny, lx, ly, xc, height, length, eps=None):
+    """Land below y = height exp(-((x - xc)/length)^2), measured from the
+    southern edge: chi = (1 - tanh((y - h(x))/eps))/2 (1 + tanh((y - 2 eps)/eps))/2
+    for y in [0, ly), the second factor lifting the land off the periodic
+    seam at y = 0 (eps: two grid cells by default)."""
+    if eps is None:
+        eps = 2.0 * lx / nx
+    X, Y = grid_xy(nx, ny, lx, ly)
+    h = height * np.exp(-((X - xc) / length) ** 2)
+    return 0.25 * (1.0 - np.tanh((Y - h) / eps)) * (1.0 + np.tanh((Y - 2.0 * eps) / eps))
 
 
 def _wavenumbers(nx, ny, lx, ly):

@@ -43,8 +43,33 @@ def test_four_sided_sponge_is_the_distance_ramp():
 def test_region_of_interest_excludes_sponge_and_filter_width():
     lx = 8 * math.pi
     roi = experiments.region_of_interest(128, lx, 0.05 * lx, 2 * lx / 256)
+    roi2 = experiments.region_of_interest(128, lx, 0.125 * lx, 2 * lx / 256, 0.1 * lx)
+    x2 = np.arange(128) * lx / 128
+    assert np.array_equal(roi2[64], (x2 >= 0.125 * lx + lx / 128) & (x2 <= lx - 0.125 * lx - lx / 128))
+    assert np.array_equal(roi2[:, 64], (x2 >= 0.1 * lx + lx / 128) & (x2 <= lx - 0.1 * lx - lx / 128))
     x = np.arange(128) * lx / 128
     edge = 0.05 * lx + 2 * lx / 256
     assert roi.shape == (128, 128)
     assert np.array_equal(roi[64], (x >= edge) & (x <= lx - edge))
     assert np.array_equal(roi[:, 64], roi[64])
+
+
+def test_cape_set_up():
+    fr = experiments.cape_fr(256, 64, dt=1e-4, beta=0.1)
+    p = fr.params
+    assert p["beta"] == 0.1 and p["scheme"] == "ab2cn" and p["u_in"] == 2.0
+    lx = p["lx"]
+    dx = lx / 256
+    x = np.arange(256) * dx
+    ic = int(round(0.2 * lx / dx))
+    col = fr.chi[:, ic]
+    y = np.arange(256) * dx
+    land = y[col > 0.5]
+    assert abs(land.max() - 4.0) < 2 * dx          # the cape's tip: height 4 at x = 0.2 Lx
+    assert land.min() < 3 * 2 * dx                 # land starts at the southern edge
+    far = fr.chi[:, int(round(0.7 * lx / dx))]
+    assert far.max() < 0.5                         # no land far from the cape
+    # sponge: 0.125 Lx along the x edges, 0.1 Lx along the y edges
+    s = fr.chi_s
+    assert s[128, int(0.12 * lx / dx)] > 0.0 and s[128, int(0.13 * lx / dx) + 1] == 0.0
+    assert s[int(0.09 * lx / dx), 128] > 0.0 and s[int(0.11 * lx / dx) + 1, 128] == 0.0

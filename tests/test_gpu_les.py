@@ -225,5 +225,12 @@ def test_a_priori_driver_matches_oracle():
         say("driver", c, got, ref, got_roi, ref_roi)
         assert abs(got - ref) < 1e-9
         assert abs(got_roi - ref_roi) < 1e-9
+        # the advection commutator alone: the same pipeline without penalization and sponge
+        pj = dict(fr.params, eta=math.inf, sponge_sigma=0.0)
+        MfJ = oracle_model(pj, fr.chi, fr.chi_s)
+        MlJ = oracle_model(experiments.les_params(pj, 2, c), chi_bar, chs_bar)
+        ref_j = oles.pcc(oles.ideal_sgs(wT, MfJ, MlJ)[0], ref_model)
+        say("driver J only", c, recs[-1][f"pcc_J_{c}"], ref_j)
+        assert abs(recs[-1][f"pcc_J_{c}"] - ref_j) < 1e-9
     assert summary["pcc_smag"]["mean_all"] == pytest.approx(np.mean([r["pcc_smag"] for r in recs]))
     torch.cuda.synchronize()
