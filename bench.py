@@ -128,16 +128,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic.json")
 
 
+KERNEL_SOURCES = ("qg_fft.hpp", "qg_internal.hpp", "qg_kernels.hip")
+
+
 def kernel_sources_digest():
-    """SHA-256 over the HIP sources, to tell whether counters taken earlier
-    still describe the kernels that run now."""
+    """SHA-256 over the kernel sources (device code and the launch
+    arguments it reads; the host runtime is not part of it), to tell whether
+    counters taken earlier still describe the kernels that run now."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2508_06678_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

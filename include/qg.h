@@ -186,6 +186,14 @@ int qg_filter_les(qg_handle* fr, qg_handle* les, const void* omega_fr, void* ome
 int qg_ideal_sgs(qg_handle* fr, qg_handle* les, const void* omega_fr, void* pi_ff,
                  void* pi_model, void* omega_bar, void* hip_stream);
 
+/* The closure's term Pi = C D div(base grad omega) of every member at the
+ * physical fields omega (projected onto the 2/3 set on entry; C from omega
+ * for the dynamic closures, zero without closure): the a-posteriori model
+ * term Pi_LES of Sec. IV when omega is an LES state.  omega, out: flat
+ * device fields in the handle's layout.  Uses the workspace as scratch,
+ * like qg_filter_les. */
+int qg_closure_term(qg_handle* h, const void* omega, void* out, void* hip_stream);
+
 /* Pattern (Pearson) correlation of two fields per member (Sec. IV):
  * out_dev[i] = <(a - <a>)(b - <b>)> / sqrt(<(a - <a>)^2> <(b - <b>)^2>) over
  * member i's grid, <.> the grid mean, in double precision.  a, b: flat

@@ -1044,6 +1044,24 @@ int qg_ideal_sgs(qg_handle* Fh, qg_handle* Lh, const void* omega_fr, void* pi_ff
   return QG_OK;
 }
 
+int qg_closure_term(qg_handle* H, const void* omega, void* out, void* hip_stream) {
+  if (!H) return fail(QG_EINVAL, "handle is NULL");
+  if (!omega || !out) return fail(QG_EINVAL, "omega or out is NULL");
+  const Handle& h = H->h;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  try {
+    for (const auto& g : h.groups) {
+      int rc = run_entry(h, g, omega, g.L.wn, st);
+      if (!rc) rc = run_model_term(h, g, g.L.wn, g.L.x, st);
+      if (!rc) rc = run_exit(h, g, g.L.x, out, st);
+      if (rc) return rc;
+    }
+  } catch (...) {
+    return fail(QG_EINVAL, "internal error in qg_closure_term");
+  }
+  return QG_OK;
+}
+
 int qg_pcc(qg_handle* H, const void* a, const void* b, double* out_dev, void* hip_stream) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   if (!a || !b || !out_dev) return fail(QG_EINVAL, "a, b or out_dev is NULL");

@@ -26,6 +26,14 @@ after the spin-up the paper describes) and the region of interest (the PCC
 is reported over the whole box and over the box inside the sponge layers
 less one filter width).  The LES masks are H_full of the FR masks.
 
+The a-posteriori mode (--mode posteriori) steps one LES per closure (and
+one without closure) from the filtered FR start with dt_LES = 1e-3 (eta =
+1.025 dt_LES, as the paper uses for every run; c the default static
+coefficients, the paper's tuned values not being stated) and reports
+PCC(omega_LES, omega_FF), PCC(Pi_LES, Pi_FF) per snapshot and the phase
+shift phi = argmin ||omega_LES(t - phi) - omega_FF(t)|| over snapshot lags
+(Sec. IV-A, Table II).
+
 Besides the PCC of the whole Pi_FF, each snapshot reports it over open
 water (the region of interest where the filtered land mask is below 0.05)
 and the PCC of the advection commutator alone (the analysis handles built
@@ -179,6 +187,97 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
     return records, summary
 
 
+def les_run_params(fr_params, delta, closure, les_dt):
+    """An LES member that is stepped: time step les_dt, with the FR run's
+    ratio eta/dt (the paper uses eta = 1.025 dt for every simulation) and
+    eta_sponge = eta, the FR run's scheme."""
+    p = les_params(fr_params, delta, closure, dt=les_dt)
+    eta = fr_params["eta"] * les_dt / fr_params["dt"]
+    p.update(eta=eta, sponge_sigma=1.0 / eta, scheme=fr_params.get("scheme", "rk4"))
+    return p
+
+
+def phase_shift(les_series, ff_series, times, t_min, max_lag):
+    """phi = argmin over snapshot lags of the mean over t >= t_min of
+    ||omega_LES(t - phi) - omega_FF(t)||_2^2 (the paper's phase shift), in
+    time units; les_series, ff_series: (snapshots, points) tensors."""
+    dts = float(times[1] - times[0])
+    best, best_lag = None, 0
+    n = len(times)
+    for lag in range(-max_lag, max_lag + 1):
+        ts = [i for i in range(n) if times[i] >= t_min and 0 <= i - lag < n]
+        if not ts:
+            continue
+        idx = torch.as_tensor(ts, device=ff_series.device)
+        d = les_series[idx - lag] - ff_series[idx]
+        e = float((d.double() ** 2).sum(dim=1).mean())
+        if best is None or e < best:
+            best, best_lag = e, lag
+    return best_lag * dts
+
+
+def a_posteriori(fr, nsteps, every, delta=2, closures=("none",) + CLOSURES, les_dt=1e-3, log=print,
+                 t_avg=20.0, max_lag=20):
+    """The FR run and one LES run per closure (grid coarsened by delta, time
+    step les_dt) from the filtered FR start; at every snapshot
+    PCC(omega_LES, omega_FF) and PCC(Pi_LES, Pi_FF) (Pi_LES the closure's
+    term at omega_LES; Pi_FF the full ideal forcing and the advection
+    commutator alone); at the end the phase shift of each LES against the
+    filtered field."""
+    p = fr.params
+    ratio = int(round(les_dt / p["dt"]))
+    if ratio < 1 or every % ratio:
+        raise ValueError("every must be a multiple of les_dt / dt")
+    F = Solver([p], [fr.chi], [fr.chi_s])
+    om = F.pack([fr.omega0])
+    chi_bar, chs_bar = filtered_masks(fr, F, delta)
+    # analysis handles on the LES grid (Pi_FF with the FR run's physics)
+    La = Solver([les_params(p, delta, "none")], [chi_bar], [chs_bar])
+    pj = dict(p, eta=math.inf, sponge_sigma=0.0, scheme="rk4")
+    FJ = Solver([pj], [fr.chi], [fr.chi_s])
+    LJ = Solver([les_params(pj, delta, "none")], [chi_bar], [chs_bar])
+    les = {c: Solver([les_run_params(p, delta, c, les_dt)], [chi_bar], [chs_bar]) for c in closures}
+    ff0 = F.filter_les(La, om)
+    w = {c: ff0.clone() for c in closures}
+    ff_hist, w_hist, times, records = [], {c: [] for c in closures}, [], []
+    t0 = time.perf_counter()
+    for k in range(nsteps // every):
+        F.step(om, every)
+        for c, L in les.items():
+            L.step(w[c], every // ratio)
+        t = (k + 1) * every * p["dt"]
+        ff = F.filter_les(La, om)
+        pi_ff, _, _ = F.ideal_sgs(La, om, model=False, bar=False)
+        pi_j, _, _ = FJ.ideal_sgs(LJ, om, model=False, bar=False)
+        rec = dict(step=(k + 1) * every, t=t)
+        for c, L in les.items():
+            d = L.diag(w[c])[0][0].cpu().numpy()
+            if d[7] != 0:
+                log(json.dumps(rec))
+                raise RuntimeError(f"non-finite LES state ({c}) at t = {t}")
+            rec[f"pcc_w_{c}"] = float(L.pcc(w[c], ff)[0])
+            if c != "none":
+                pi_les = L.closure_term(w[c])
+                rec[f"pcc_sgs_{c}"] = float(L.pcc(pi_les, pi_ff)[0])
+                rec[f"pcc_sgs_J_{c}"] = float(L.pcc(pi_les, pi_j)[0])
+            w_hist[c].append(w[c].clone())
+        ff_hist.append(ff)
+        times.append(t)
+        rec["wall_s"] = round(time.perf_counter() - t0, 2)
+        records.append(rec)
+        log(json.dumps(rec))
+    ffs = torch.stack(ff_hist)
+    summary = {}
+    for key in [k for k in records[0] if k.startswith("pcc_")]:
+        late = np.array([r[key] for r in records if r["t"] >= t_avg], dtype=np.float64)
+        summary[key] = float(np.nanmean(late)) if late.size and np.isfinite(late).any() else None
+    for c in closures:
+        summary[f"phase_{c}"] = phase_shift(torch.stack(w_hist[c]), ffs, times, t_avg, max_lag)
+    for S in [F, La, FJ, LJ] + list(les.values()):
+        S.close()
+    return records, summary
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("case", choices=["island", "cape"])
@@ -189,14 +288,20 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1_000_000)
     ap.add_argument("--every", type=int, default=5000)
     ap.add_argument("--delta", type=int, default=2)
+    ap.add_argument("--mode", choices=["priori", "posteriori"], default="priori")
+    ap.add_argument("--les-dt", type=float, default=1e-3)
     args = ap.parse_args(argv)
     if args.case == "island":
         fr = island_fr(args.n, args.precision, args.dt)
     else:
         fr = cape_fr(args.n, args.precision, args.dt, args.beta)
-    records, summary = a_priori(fr, args.steps, args.every, args.delta,
-                                log=lambda s: print(s, flush=True))
-    print(json.dumps({"summary": summary, "case": args.case, "beta": fr.params["beta"], "n": args.n,
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if args.mode == "priori":
+        records, summary = a_priori(fr, args.steps, args.every, args.delta, log=log)
+    else:
+        records, summary = a_posteriori(fr, args.steps, args.every, args.delta, les_dt=args.les_dt, log=log)
+    print(json.dumps({"summary": summary, "mode": args.mode, "case": args.case, "beta": fr.params["beta"],
+                      "n": args.n,
                       "precision": args.precision,
                       "dt": args.dt, "steps": args.steps, "every": args.every, "delta": args.delta}),
           flush=True)

@@ -143,6 +143,14 @@ class Solver:
                                        _ptr(wbar) if wbar is not None else None, _stream(self.device)))
         return pi_ff, pi_m, wbar
 
+    def closure_term(self, omega):
+        """The closure's term C D div(base grad omega) of every member at the
+        flat fields omega (a new flat tensor)."""
+        self._check_flat(omega, "omega")
+        out = torch.empty(self.total, dtype=self.dtype, device=self.device)
+        _lib.check(self.L.qg_closure_term(self.h, _ptr(omega), _ptr(out), _stream(self.device)))
+        return out
+
     def pcc(self, a, b):
         """Pattern correlation of two flat fields, one float64 per member."""
         self._check_flat(a, "a")

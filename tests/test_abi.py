@@ -100,6 +100,7 @@ def test_null_arguments():
     assert L.qg_filter_les(None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_ideal_sgs(None, None, None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_pcc(None, None, None, None, None) == _lib.QG_EINVAL
+    assert L.qg_closure_term(None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_run_phase(None, 0, 1, 1, None) == _lib.QG_EINVAL
     L.qg_destroy(None)
 

@@ -73,3 +73,26 @@ def test_cape_set_up():
     s = fr.chi_s
     assert s[128, int(0.12 * lx / dx)] > 0.0 and s[128, int(0.13 * lx / dx) + 1] == 0.0
     assert s[int(0.09 * lx / dx), 128] > 0.0 and s[int(0.11 * lx / dx) + 1, 128] == 0.0
+
+
+def test_phase_shift_recovers_a_known_lag():
+    """omega_LES(t) = omega_FF(t + 3 dt_s): the argmin of
+    ||omega_LES(t - phi) - omega_FF(t)|| is phi = 3 dt_s."""
+    import torch
+    rng = np.random.default_rng(0)
+    n, pts, dts = 60, 50, 0.5
+    base = torch.as_tensor(np.cumsum(rng.standard_normal((n + 10, pts)), axis=0))
+    ff = base[:n]
+    les = base[3:n + 3]
+    times = [dts * (i + 1) for i in range(n)]
+    assert experiments.phase_shift(les, ff, times, 5.0, 8) == 3 * dts
+    assert experiments.phase_shift(ff, ff, times, 5.0, 8) == 0.0
+    assert experiments.phase_shift(ff, les, times, 5.0, 8) == -3 * dts
+
+
+def test_les_run_params_keep_the_eta_rule():
+    fr = experiments.island_fr(256, 64, dt=1e-4)
+    p = experiments.les_run_params(fr.params, 2, "smag", 1e-3)
+    assert p["nx"] == 128 and p["dt"] == 1e-3 and p["scheme"] == "ab2cn"
+    assert abs(p["eta"] - 1.025e-3) < 1e-18 and abs(p["sponge_sigma"] * p["eta"] - 1.0) < 1e-15
+    assert p["closure"] == "smag" and p["c"] == 0.17

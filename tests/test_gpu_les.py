@@ -234,3 +234,56 @@ def test_a_priori_driver_matches_oracle():
         assert abs(recs[-1][f"pcc_J_{c}"] - ref_j) < 1e-9
     assert summary["pcc_smag"]["mean_all"] == pytest.approx(np.mean([r["pcc_smag"] for r in recs]))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("closure", ["smag", "leith", "dsmag"])
+def test_closure_term_matches_oracle(closure):
+    """qg_closure_term at a field against the oracle's model term, and equal
+    to the model term qg_ideal_sgs forms at omega_bar."""
+    fr, les = les_pairs(256, 128, 2, closure, (5,))
+    F = solver_for(fr, 64)
+    L = solver_for(les, 64)
+    om = F.pack([fr[0].omega0])
+    pi, model, wbar = F.ideal_sgs(L, om)
+    got = L.closure_term(wbar)
+    Ml = oracle_model(les[0].params, les[0].chi, les[0].chi_s)
+    ref = oles.model_sgs(to_np(wbar).reshape(64, 128), Ml)
+    e = rel_l2(to_np(got).reshape(64, 128), ref)
+    e2 = rel_l2(to_np(got), to_np(model))
+    say("closure term", closure, e, e2)
+    assert np.any(ref)
+    assert e < 1e-12 and e2 < 1e-12
+    F.close()
+    L.close()
+
+
+def test_a_posteriori_driver_matches_oracle():
+    """The island set-up at 128^2: FR dt 1e-3, LES 64^2 with dt 2e-3, a
+    snapshot every 10 FR steps; PCC(omega_LES, omega_FF) and PCC(Pi_LES,
+    Pi_FF) at the first snapshot against the oracle (AB2CN runs of both,
+    H_full, model term, ideal forcing)."""
+    from oracle import ab2cn
+    from paper_2508_06678_amd import experiments
+    fr = experiments.island_fr(128, 64, dt=1e-3)
+    recs, summary = experiments.a_posteriori(fr, 20, 10, 2, closures=("none", "smag"), les_dt=2e-3,
+                                             log=lambda s: None, t_avg=0.0, max_lag=1)
+    lx = fr.params["lx"]
+    Mf = oracle_model(fr.params, fr.chi, fr.chi_s)
+    chi_bar = oles.filter_to(fr.chi, lx, lx, 2)
+    chs_bar = oles.filter_to(fr.chi_s, lx, lx, 2)
+    w0 = qg.leave(qg.enter(fr.omega0, Mf.g), Mf.g)
+    wT = ab2cn.run(w0, Mf, 10)[0]
+    ff = oles.filter_to(wT, lx, lx, 2)
+    Ma = oracle_model(experiments.les_params(fr.params, 2, "none"), chi_bar, chs_bar)
+    pi_ff = oles.ideal_sgs(wT, Mf, Ma)[0]
+    for c in ("none", "smag"):
+        Ml = oracle_model(experiments.les_run_params(fr.params, 2, c, 2e-3), chi_bar, chs_bar)
+        wl = ab2cn.run(oles.filter_to(w0, lx, lx, 2), Ml, 5)[0]
+        ref = oles.pcc(wl, ff)
+        say("a posteriori driver", c, recs[0][f"pcc_w_{c}"], ref)
+        assert abs(recs[0][f"pcc_w_{c}"] - ref) < 1e-9
+        if c != "none":
+            ref_sgs = oles.pcc(oles.model_sgs(wl, Ml), pi_ff)
+            say("   sgs", recs[0][f"pcc_sgs_{c}"], ref_sgs)
+            assert abs(recs[0][f"pcc_sgs_{c}"] - ref_sgs) < 1e-9
+    assert set(summary) >= {"phase_none", "phase_smag", "pcc_w_smag", "pcc_sgs_smag"}
