@@ -187,13 +187,13 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
     return records, summary
 
 
-def les_run_params(fr_params, delta, closure, les_dt):
+def les_run_params(fr_params, delta, closure, les_dt, scheme=None):
     """An LES member that is stepped: time step les_dt, with the FR run's
     ratio eta/dt (the paper uses eta = 1.025 dt for every simulation) and
-    eta_sponge = eta, the FR run's scheme."""
+    eta_sponge = eta; the FR run's scheme unless `scheme` is given."""
     p = les_params(fr_params, delta, closure, dt=les_dt)
     eta = fr_params["eta"] * les_dt / fr_params["dt"]
-    p.update(eta=eta, sponge_sigma=1.0 / eta, scheme=fr_params.get("scheme", "rk4"))
+    p.update(eta=eta, sponge_sigma=1.0 / eta, scheme=scheme or fr_params.get("scheme", "rk4"))
     return p
 
 
@@ -217,13 +217,15 @@ def phase_shift(les_series, ff_series, times, t_min, max_lag):
 
 
 def a_posteriori(fr, nsteps, every, delta=2, closures=("none",) + CLOSURES, les_dt=1e-3, log=print,
-                 t_avg=20.0, max_lag=20):
+                 t_avg=20.0, max_lag=20, les_scheme=None):
     """The FR run and one LES run per closure (grid coarsened by delta, time
     step les_dt) from the filtered FR start; at every snapshot
     PCC(omega_LES, omega_FF) and PCC(Pi_LES, Pi_FF) (Pi_LES the closure's
     term at omega_LES; Pi_FF the full ideal forcing and the advection
     commutator alone); at the end the phase shift of each LES against the
-    filtered field."""
+    filtered field.  An LES that turns non-finite stops there: its PCCs are
+    NaN from then on, its phase shift None, and the summary gives the time
+    (``diverged_<closure>``)."""
     p = fr.params
     ratio = int(round(les_dt / p["dt"]))
     if ratio < 1 or every % ratio:
@@ -236,25 +238,32 @@ def a_posteriori(fr, nsteps, every, delta=2, closures=("none",) + CLOSURES, les_
     pj = dict(p, eta=math.inf, sponge_sigma=0.0, scheme="rk4")
     FJ = Solver([pj], [fr.chi], [fr.chi_s])
     LJ = Solver([les_params(pj, delta, "none")], [chi_bar], [chs_bar])
-    les = {c: Solver([les_run_params(p, delta, c, les_dt)], [chi_bar], [chs_bar]) for c in closures}
+    les = {c: Solver([les_run_params(p, delta, c, les_dt, les_scheme)], [chi_bar], [chs_bar]) for c in closures}
     ff0 = F.filter_les(La, om)
     w = {c: ff0.clone() for c in closures}
     ff_hist, w_hist, times, records = [], {c: [] for c in closures}, [], []
+    diverged = {}
     t0 = time.perf_counter()
     for k in range(nsteps // every):
         F.step(om, every)
-        for c, L in les.items():
-            L.step(w[c], every // ratio)
         t = (k + 1) * every * p["dt"]
+        for c, L in les.items():
+            if c not in diverged:
+                L.step(w[c], every // ratio)
         ff = F.filter_les(La, om)
         pi_ff, _, _ = F.ideal_sgs(La, om, model=False, bar=False)
         pi_j, _, _ = FJ.ideal_sgs(LJ, om, model=False, bar=False)
         rec = dict(step=(k + 1) * every, t=t)
         for c, L in les.items():
-            d = L.diag(w[c])[0][0].cpu().numpy()
-            if d[7] != 0:
-                log(json.dumps(rec))
-                raise RuntimeError(f"non-finite LES state ({c}) at t = {t}")
+            if c not in diverged and L.diag(w[c])[0][0, 7].item() != 0:
+                diverged[c] = t          # an LES that blew up: no further steps, NaN from here on
+                w[c].fill_(float("nan"))
+            if c in diverged:
+                rec[f"pcc_w_{c}"] = float("nan")
+                if c != "none":
+                    rec[f"pcc_sgs_{c}"] = rec[f"pcc_sgs_J_{c}"] = float("nan")
+                w_hist[c].append(w[c].clone())
+                continue
             rec[f"pcc_w_{c}"] = float(L.pcc(w[c], ff)[0])
             if c != "none":
                 pi_les = L.closure_term(w[c])
@@ -272,7 +281,10 @@ def a_posteriori(fr, nsteps, every, delta=2, closures=("none",) + CLOSURES, les_
         late = np.array([r[key] for r in records if r["t"] >= t_avg], dtype=np.float64)
         summary[key] = float(np.nanmean(late)) if late.size and np.isfinite(late).any() else None
     for c in closures:
-        summary[f"phase_{c}"] = phase_shift(torch.stack(w_hist[c]), ffs, times, t_avg, max_lag)
+        summary[f"phase_{c}"] = (None if c in diverged
+                                 else phase_shift(torch.stack(w_hist[c]), ffs, times, t_avg, max_lag))
+        if c in diverged:
+            summary[f"diverged_{c}"] = diverged[c]
     for S in [F, La, FJ, LJ] + list(les.values()):
         S.close()
     return records, summary
@@ -290,6 +302,8 @@ def main(argv=None):
     ap.add_argument("--delta", type=int, default=2)
     ap.add_argument("--mode", choices=["priori", "posteriori"], default="priori")
     ap.add_argument("--les-dt", type=float, default=1e-3)
+    ap.add_argument("--les-scheme", choices=["ab2cn", "rk4"], default=None,
+                    help="time scheme of the LES runs (default: the FR run's)")
     args = ap.parse_args(argv)
     if args.case == "island":
         fr = island_fr(args.n, args.precision, args.dt)
@@ -299,8 +313,10 @@ def main(argv=None):
     if args.mode == "priori":
         records, summary = a_priori(fr, args.steps, args.every, args.delta, log=log)
     else:
-        records, summary = a_posteriori(fr, args.steps, args.every, args.delta, les_dt=args.les_dt, log=log)
-    print(json.dumps({"summary": summary, "mode": args.mode, "case": args.case, "beta": fr.params["beta"],
+        records, summary = a_posteriori(fr, args.steps, args.every, args.delta, les_dt=args.les_dt, log=log,
+                                        les_scheme=args.les_scheme)
+    print(json.dumps({"summary": summary, "mode": args.mode, "les_scheme": args.les_scheme,
+                      "case": args.case, "beta": fr.params["beta"],
                       "n": args.n,
                       "precision": args.precision,
                       "dt": args.dt, "steps": args.steps, "every": args.every, "delta": args.delta}),
