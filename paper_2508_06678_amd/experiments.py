@@ -187,11 +187,22 @@ def a_priori(fr, nsteps, every, delta=2, closures=CLOSURES, log=print, t_avg=20.
     return records, summary
 
 
+def parse_closure(spec):
+    """'smag' -> ('smag', default c); 'smag:0.15' -> ('smag', 0.15)."""
+    name, _, c = spec.partition(":")
+    if name not in configs.STATIC_C:
+        raise ValueError(f"unknown closure {name!r}")
+    return name, (float(c) if c else configs.STATIC_C[name])
+
+
 def les_run_params(fr_params, delta, closure, les_dt, scheme=None):
     """An LES member that is stepped: time step les_dt, with the FR run's
     ratio eta/dt (the paper uses eta = 1.025 dt for every simulation) and
-    eta_sponge = eta; the FR run's scheme unless `scheme` is given."""
+    eta_sponge = eta; the FR run's scheme unless `scheme` is given.
+    closure: a name, or 'name:c' for a coefficient other than the default."""
+    closure, c = parse_closure(closure)
     p = les_params(fr_params, delta, closure, dt=les_dt)
+    p["c"] = c
     eta = fr_params["eta"] * les_dt / fr_params["dt"]
     p.update(eta=eta, sponge_sigma=1.0 / eta, scheme=scheme or fr_params.get("scheme", "rk4"))
     return p
@@ -260,12 +271,12 @@ def a_posteriori(fr, nsteps, every, delta=2, closures=("none",) + CLOSURES, les_
                 w[c].fill_(float("nan"))
             if c in diverged:
                 rec[f"pcc_w_{c}"] = float("nan")
-                if c != "none":
+                if not c.startswith("none"):
                     rec[f"pcc_sgs_{c}"] = rec[f"pcc_sgs_J_{c}"] = float("nan")
                 w_hist[c].append(w[c].clone())
                 continue
             rec[f"pcc_w_{c}"] = float(L.pcc(w[c], ff)[0])
-            if c != "none":
+            if not c.startswith("none"):
                 pi_les = L.closure_term(w[c])
                 rec[f"pcc_sgs_{c}"] = float(L.pcc(pi_les, pi_ff)[0])
                 rec[f"pcc_sgs_J_{c}"] = float(L.pcc(pi_les, pi_j)[0])
@@ -304,6 +315,9 @@ def main(argv=None):
     ap.add_argument("--les-dt", type=float, default=1e-3)
     ap.add_argument("--les-scheme", choices=["ab2cn", "rk4"], default=None,
                     help="time scheme of the LES runs (default: the FR run's)")
+    ap.add_argument("--closures", default=None,
+                    help="comma list of LES closures for --mode posteriori, each 'name' or 'name:c' "
+                         "(default: none and the four closures at their default c)")
     args = ap.parse_args(argv)
     if args.case == "island":
         fr = island_fr(args.n, args.precision, args.dt)
@@ -313,8 +327,9 @@ def main(argv=None):
     if args.mode == "priori":
         records, summary = a_priori(fr, args.steps, args.every, args.delta, log=log)
     else:
+        kw = {} if not args.closures else {"closures": tuple(args.closures.split(","))}
         records, summary = a_posteriori(fr, args.steps, args.every, args.delta, les_dt=args.les_dt, log=log,
-                                        les_scheme=args.les_scheme)
+                                        les_scheme=args.les_scheme, **kw)
     print(json.dumps({"summary": summary, "mode": args.mode, "les_scheme": args.les_scheme,
                       "case": args.case, "beta": fr.params["beta"],
                       "n": args.n,

@@ -96,3 +96,13 @@ def test_les_run_params_keep_the_eta_rule():
     assert p["nx"] == 128 and p["dt"] == 1e-3 and p["scheme"] == "ab2cn"
     assert abs(p["eta"] - 1.025e-3) < 1e-18 and abs(p["sponge_sigma"] * p["eta"] - 1.0) < 1e-15
     assert p["closure"] == "smag" and p["c"] == 0.17
+
+
+def test_closure_specs():
+    assert experiments.parse_closure("smag") == ("smag", 0.17)
+    assert experiments.parse_closure("leith:0.15") == ("leith", 0.15)
+    fr = experiments.island_fr(256, 64)
+    assert experiments.les_run_params(fr.params, 2, "smag:0.3", 1e-3)["c"] == 0.3
+    import pytest
+    with pytest.raises(ValueError):
+        experiments.parse_closure("smagorinsky")
