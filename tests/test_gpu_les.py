@@ -287,3 +287,34 @@ def test_a_posteriori_driver_matches_oracle():
             say("   sgs", recs[0][f"pcc_sgs_{c}"], ref_sgs)
             assert abs(recs[0][f"pcc_sgs_{c}"] - ref_sgs) < 1e-9
     assert set(summary) >= {"phase_none", "phase_smag", "pcc_w_smag", "pcc_sgs_smag"}
+
+
+@pytest.mark.parametrize("closure,code", [("smag", 1), ("leith", 2)])
+def test_closure_term_every_column_width(closure, code, tmp_path):
+    """Every strip width the tuner may choose, forced through its cache, for
+    the closure term of a 512x256 32-bit member: at W ny = 4096 the three
+    products overflow the product-parallel column kernel and the general
+    one writes the term."""
+    import json
+
+    import torch
+    m = island(512, 256, closure, seed=5)
+    m.omega0 = inputs.spectrum_noise(512, 256, 2 * math.pi, math.pi, 5, 2.0, 0.1)
+    Ml = oracle_model(m.params, m.chi, m.chi_s)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/512x256/fp32/closure{code}/members1"
+    ref = None
+    for W in (2, 4, 8, 16):
+        path = tmp_path / f"w{W}.json"
+        path.write_text(json.dumps({key + "/fwd": W, key + "/inv": 4}))
+        S = solver_for([m], 32)
+        S.autotune(str(path))
+        assert S.column_widths() == [W]
+        om = S.pack([m.omega0])
+        if ref is None:
+            ref = oles.model_sgs(to_np(om).reshape(256, 512), Ml)
+        got = to_np(S.closure_term(om)).reshape(256, 512)
+        e = rel_l2(got, ref)
+        say("closure term", closure, "W", W, e)
+        assert e < 1e-5
+        S.close()
