@@ -318,3 +318,33 @@ def test_closure_term_every_column_width(closure, code, tmp_path):
         say("closure term", closure, "W", W, e)
         assert e < 1e-5
         S.close()
+
+
+def test_ideal_sgs_ragged_members():
+    """Three member pairs of two sizes (two groups on each side, members
+    interleaved): every pair's Pi_FF and model term against the oracle."""
+    sizes = [(256, 128, "smag", 3), (512, 256, "leith", 4), (256, 128, "dsmag", 5)]
+    fr, les = [], []
+    for nx, ny, cl, seed in sizes:
+        f, l = les_pairs(nx, ny, 2, cl, (seed,))
+        fr += f
+        les += l
+    F = solver_for(fr, 64)
+    L = solver_for(les, 64)
+    om = F.pack([m.omega0 for m in fr])
+    pi, model, wbar = F.ideal_sgs(L, om)
+    for i, (mf, ml) in enumerate(zip(fr, les)):
+        ny, nx = mf.params["ny"], mf.params["nx"]
+        shp = (ny // 2, nx // 2)
+        Mf = oracle_model(mf.params, mf.chi, mf.chi_s)
+        Ml = oracle_model(ml.params, ml.chi, ml.chi_s)
+        w = to_np(F.unpack(om)[i]).reshape(ny, nx)
+        ref_pi, ref_wbar = oles.ideal_sgs(w, Mf, Ml)
+        ref_model = oles.model_sgs(ref_wbar, Ml)
+        g_pi = to_np(L.unpack(pi)[i]).reshape(shp)
+        e_pi = rel_l2(g_pi, ref_pi)
+        e_m = rel_l2(to_np(L.unpack(model)[i]).reshape(shp), ref_model) if np.any(ref_model) else 0.0
+        say("ragged ideal sgs", i, nx, ny, ml.params["closure"], e_pi, e_m)
+        assert e_pi < 1e-10 and e_m < 1e-12
+    F.close()
+    L.close()
