@@ -53,6 +53,9 @@
 
 namespace qg {
 
+// LDS column stride of the compile-time column-inverse path (elements)
+__host__ __device__ constexpr int colinv_stride(int ny) { return ny + (ny >> QG_COL_PADS) + 16; }
+
 // ---------------------------------------------------------------- helpers
 // Workspace pointers come from the member table, so the compiler cannot see
 // that they address global memory and would emit flat loads/stores (which
@@ -279,7 +282,11 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   const T scale = T(M.inv_n);
   if constexpr (LOGN != 0) {
     constexpr int PD = QG_COL_PADS;
-    constexpr int NY = 1 << LOGN, NT = NY / 8, STR = NY + (NY >> PD);
+    // column stride: the padded length plus 16 elements, so that columns
+    // w and w+1 start 32 banks apart and the strip's row-order read-out
+    // below touches each bank twice (the minimum for 8-byte elements)
+    // rather than four times
+    constexpr int NY = 1 << LOGN, NT = NY / 8, STR = colinv_stride(NY);
     const int w = threadIdx.x >> (LOGN - 3);
     const int j = threadIdx.x & (NT - 1);
     const int mx = kx0 + w;
@@ -1921,7 +1928,7 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   const dim3 block(P.Wi * P.ny / COL_EPT);
   if constexpr (OP == OP_RHS || OP == OP_B) {
     // compile-time column lengths for the common sizes
-    const size_t lds = (size_t)P.Wi * (P.ny + (P.ny >> QG_COL_PADS)) * sizeof(cpx<T>);
+    const size_t lds = (size_t)P.Wi * colinv_stride(P.ny) * sizeof(cpx<T>);
     switch (P.logny) {
       case 8: hipLaunchKernelGGL((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
       case 9: hipLaunchKernelGGL((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
