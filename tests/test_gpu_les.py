@@ -348,3 +348,36 @@ def test_ideal_sgs_ragged_members():
         assert e_pi < 1e-10 and e_m < 1e-12
     F.close()
     L.close()
+
+
+def test_ideal_sgs_full_size_cape_fp64():
+    """The cape application's sizes (FR 1024^2 -> LES 512^2, 64-bit), a
+    random-phase field: Pi_FF to 1e-12 of ||G||, the Dynamic Leith and
+    Smagorinsky model terms and omega_bar to 1e-12, against the oracle."""
+    from paper_2508_06678_amd import experiments
+    from paper_2508_06678_amd.solver import Solver
+    fr = experiments.cape_fr(1024, 64, beta=1.0)
+    lx = fr.params["lx"]
+    fr.omega0 = inputs.spectrum_noise(1024, 1024, lx, lx, 7, 2.0, 0.5)
+    chi_bar = oles.filter_to(fr.chi, lx, lx, 2)
+    chs_bar = oles.filter_to(fr.chi_s, lx, lx, 2)
+    F = solver_for([fr], 64)
+    om = F.pack([fr.omega0])
+    Mf = oracle_model(fr.params, fr.chi, fr.chi_s)
+    w = to_np(om).reshape(1024, 1024)
+    for closure in ("dleith", "smag"):
+        lp = experiments.les_params(fr.params, 2, closure)
+        L = Solver([lp], [chi_bar], [chs_bar])
+        pi, model, wbar = F.ideal_sgs(L, om)
+        Ml = oracle_model(lp, chi_bar, chs_bar)
+        ref_pi, ref_wbar = oles.ideal_sgs(w, Mf, Ml)
+        ref_model = oles.model_sgs(ref_wbar, Ml)
+        Gbar = Ml.g.phys(oles.spectral_to_coarse(oles.advective_forcing(qg.enter(w, Mf.g), Mf), Mf.g,
+                                                 512, 512, 2))
+        e_pi = float(np.linalg.norm(to_np(pi).reshape(512, 512) - ref_pi) / np.linalg.norm(Gbar))
+        e_w = rel_l2(to_np(wbar).reshape(512, 512), ref_wbar)
+        e_m = rel_l2(to_np(model).reshape(512, 512), ref_model) if np.any(ref_model) else 0.0
+        say("full-size ideal sgs", closure, e_pi, e_w, e_m, "C>0" if np.any(ref_model) else "C=0")
+        assert e_pi < 1e-12 and e_w < 1e-12 and e_m < 1e-12
+        L.close()
+    F.close()
