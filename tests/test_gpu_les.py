@@ -381,3 +381,24 @@ def test_ideal_sgs_full_size_cape_fp64():
         assert e_pi < 1e-12 and e_w < 1e-12 and e_m < 1e-12
         L.close()
     F.close()
+
+
+def test_les_pairing_errors():
+    """qg_filter_les and qg_ideal_sgs refuse pairs that are not an FR grid
+    and its coarsening: same size, other precision, other member count."""
+    from paper_2508_06678_amd import _lib
+    fr = [island(256, 128, "none", seed=1)]
+    F = solver_for(fr, 64)
+    om = F.pack([fr[0].omega0])
+    cases = [("same grid", [island(256, 128, "smag", seed=1)], 64),
+             ("other precision", [island(128, 64, "smag", seed=1)], 32),
+             ("member count", [island(128, 64, "smag", seed=1), island(128, 64, "smag", seed=2)], 64)]
+    for name, les, prec in cases:
+        L = solver_for(les, prec)
+        for call in (lambda: F.filter_les(L, om), lambda: F.ideal_sgs(L, om)):
+            with pytest.raises(_lib.QGError) as e:
+                call()
+            say("pairing", name, e.value)
+            assert e.value.code == _lib.QG_EINVAL
+        L.close()
+    F.close()
