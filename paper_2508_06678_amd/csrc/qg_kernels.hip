@@ -1644,6 +1644,32 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   using V = cpx<T>;
   __shared__ double red[2 * (COMBINE_THREADS / 64)];
   const MemberDev M = member_const(P, blockIdx.z);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = q < P.kxn * P.kyn;
+  const bool rk = P.stage >= 1 && P.stage <= 4;
+  const V* jsp = cptr<T>(M, P.o_out);
+  const V* qsp = cptr<T>(M, P.o_aux);
+  V* acc = cptr<T>(M, P.o_mp);   // accumulator offset passed in o_mp for this kernel
+  int mx = 0, my = 0;
+  // RK stages: the operands and the part of the right-hand side that does
+  // not depend on C are loaded and formed before the partial sums are
+  // reduced, so that the two memory latencies overlap
+  V r0 = cmake<V>(T(0), T(0)), qv = r0, w0 = r0, a = r0;
+  if (in) {
+    mx = q / P.kyn;
+    my = my_of_iy(q - mx * P.kyn, P.myh, P.kyn);
+    if (rk) {
+      const Wave<T> w = wave<T>(M, mx, my);
+      const V x = gld(cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in) + q);
+      const V j = gld(jsp + q);
+      qv = gld(qsp + q);
+      w0 = gld(cptr<T>(M, P.o_in2) + q);
+      if (P.stage > 1) a = gld(acc + q);
+      r0 = cmake<V>(-j.x, -j.y);
+      r0 = csub(r0, cscale(x, T(w.k2 * M.inv_re + M.mu)));
+      r0 = csub(r0, mul_ia(poisson<T>(M, x, w, mx, my), T(M.beta * w.kx)));
+    }
+  }
   double C, hm, mm;
   dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1656,14 +1682,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
       c[9 + 2 * P.stage] = mm;
     }
   }
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.kxn * P.kyn) return;
-  const int mx = q / P.kyn;
-  const int iy = q - mx * P.kyn;
-  const int my = my_of_iy(iy, P.myh, P.kyn);
-  const Wave<T> w = wave<T>(M, mx, my);
-  const V* jsp = cptr<T>(M, P.o_out);
-  const V* qsp = cptr<T>(M, P.o_aux);
+  if (!in) return;
   if (P.stage == SGS_STAGE) {
     // the closure's term C Q alone, to o_in
     V cq = cscale(qsp[q], T(C));
@@ -1676,30 +1695,21 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
     ab2cn_update<T>(M, P, q, mx, my, cadd(cmake<V>(-j.x, -j.y), cscale(qsp[q], T(C))));
     return;
   }
-  const V* xin = cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in);
-  const V* wn = cptr<T>(M, P.o_in2);
-  V* acc = cptr<T>(M, P.o_mp);   // accumulator offset passed in o_mp for this kernel
-  V* xout = cptr<T>(M, P.o_in);
-  const V x = xin[q];
-  const V j = jsp[q];
-  V r = cmake<V>(-j.x, -j.y);
-  r = csub(r, cscale(x, T(w.k2 * M.inv_re + M.mu)));
-  r = csub(r, mul_ia(poisson<T>(M, x, w, mx, my), T(M.beta * w.kx)));
-  r = cadd(r, cscale(qsp[q], T(C)));
+  V r = cadd(r0, cscale(qv, T(C)));
   if (mx == 0 && my == 0) r = cmake<V>(T(0), T(0));
   const double dt = M.dt;
-  const V w0 = wn[q];
+  V* xout = cptr<T>(M, P.o_in);
   if (P.stage == 1) {
-    acc[q] = cadd(w0, cscale(r, T(dt / 6.0)));
-    xout[q] = cadd(w0, cscale(r, T(dt / 2.0)));
+    gst(acc + q, cadd(w0, cscale(r, T(dt / 6.0))));
+    gst(xout + q, cadd(w0, cscale(r, T(dt / 2.0))));
   } else if (P.stage == 2) {
-    acc[q] = cadd(acc[q], cscale(r, T(dt / 3.0)));
-    xout[q] = cadd(w0, cscale(r, T(dt / 2.0)));
+    gst(acc + q, cadd(a, cscale(r, T(dt / 3.0))));
+    gst(xout + q, cadd(w0, cscale(r, T(dt / 2.0))));
   } else if (P.stage == 3) {
-    acc[q] = cadd(acc[q], cscale(r, T(dt / 3.0)));
-    xout[q] = cadd(w0, cscale(r, T(dt)));
+    gst(acc + q, cadd(a, cscale(r, T(dt / 3.0))));
+    gst(xout + q, cadd(w0, cscale(r, T(dt))));
   } else {
-    xout[q] = cadd(acc[q], cscale(r, T(dt / 6.0)));
+    gst(xout + q, cadd(a, cscale(r, T(dt / 6.0))));
   }
 }
 
