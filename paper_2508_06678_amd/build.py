@@ -1,8 +1,10 @@
 """Build the HIP library libqg.so for gfx950 in-tree (hipcc, no JIT cache).
 
 Sources are compiled in parallel (the kernel file once per slice of its
-launchers, QG_PART = 0..4), then linked into paper_2508_06678_amd/libqg.so.  All device code is built with packed-FP32
-instruction generation disabled.
+launchers, QG_PART = 0..4), then linked into paper_2508_06678_amd/libqg.so.
+All device code is built with packed-FP32 instruction generation disabled.
+Then the C example program qg_example (plain C99 against include/qg.h,
+linked to libqg.so and the HIP runtime) is built beside it.
 """
 import os
 import subprocess
@@ -52,7 +54,28 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_example(verbose)
     return LIB
+
+
+EXAMPLE = os.path.join(PKG, "qg_example")
+
+
+def build_example(verbose=False):
+    """The C program, compiled by the host C compiler: nothing in it is
+    device code."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cc = os.environ.get("CC", "gcc")
+    tmp = EXAMPLE + ".tmp"
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(rocm, "include"), os.path.join(CSRC, "qg_example.c"), "-o", tmp,
+           "-L", PKG, "-lqg", "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":
