@@ -1,4 +1,4 @@
-"""Oracle: exact discrete adjoint of one QG time step (static closures).
+"""Oracle: exact discrete adjoint of one QG time step.
 
 TEST INFRASTRUCTURE ONLY (see the package header).  FP64 throughout.
 
@@ -13,12 +13,23 @@ mean mode are self-adjoint.  A pointwise product adjoins to multiplication by
 its partner; the square root in |S| and |grad omega| adjoins through its
 derivative, taken as 0 where the base vanishes.
 
-The forward map differentiated is exactly ``oracle.qg.step_spectral`` with
-closure in {none, smag, leith, const}: the RK4 A sub-step over the
-right-hand side of Eq. 1 with the eddy-viscosity term of Eq. 8 (Eqs. 9, 12)
-followed by the B sub-step (Eqs. 2-4, exact penalization then sponge).
-The masks, the inflow and the parameters are fixed; the closure coefficient
-c is the one scalar parameter differentiated (C = (c Delta)^2 or (c Delta)^3).
+The forward map differentiated is exactly ``oracle.qg.step_spectral``: the
+RK4 A sub-step over the right-hand side of Eq. 1 with the eddy-viscosity
+term of Eq. 8 (Eqs. 9, 12) followed by the B sub-step (Eqs. 2-4, exact
+penalization then sponge).  The masks, the inflow and the parameters are
+fixed; for the static closures the coefficient c is the one scalar
+parameter differentiated (C = (c Delta)^2 or (c Delta)^3).
+
+For the dynamic closures (Eqs. 10-11, 13) the coefficient is itself a
+function of the stage input x: C = max(<HM>, 0)/<M^2> (grid means) with
+H = D FFT(J(T x)) - T D FFT(J(x)) and M = r D div(g(T x)) - T Q(x).  Its
+derivative adds s grad C to the stage's adjoint, s = <lam, Q>_w, where by
+the chain rule (C > 0)
+    grad C = [J_H^T M + J_M^T (H - 2 C M)] / (N <M^2>),
+J_H^T a = T A_J(T x)^T a - A_J(x)^T T a and J_M^T b = r T A_Q(T x)^T b -
+A_Q(x)^T T b, with A_J, A_Q the linearizations of y -> D FFT(J(y)) and
+y -> D div(base(y) grad y).  Where the clip sets C = 0 the derivative is
+zero (the kink at <HM> = 0 is not differentiated).
 """
 import numpy as np
 
@@ -42,11 +53,69 @@ def dC_dc(m):
     return 0.0
 
 
+def transport_adjoint(y, cJ, cQ, kind, m):
+    """dL/dy (in D) of L = <cJ, D FFT(J(y))>_w + <cQ, D div(base(y) grad y)^>_w,
+    J(y) = u omega_x + v omega_y with the total velocity of y; kind is the
+    base's family ("smag", "leith", "const") or None for no second term."""
+    g = m.g
+    psih = -y * g.inv_k2
+    u, v = qg.velocity(psih, m)
+    wx = g.phys(1j * g.kx * y)
+    wy = g.phys(1j * g.ky * y)
+    lam_J = g.phys(g.D * cJ)
+    lam_u, lam_v = lam_J * wx, lam_J * wy
+    lam_wx, lam_wy = lam_J * u, lam_J * v
+    lam_psi = np.zeros_like(y)
+    if kind is not None:
+        base = qg.closure_base(kind, psih, wx, wy, m)
+        gx = g.phys(-1j * g.kx * g.D * cQ)
+        gy = g.phys(-1j * g.ky * g.D * cQ)
+        lam_wx = lam_wx + gx * base
+        lam_wy = lam_wy + gy * base
+        lam_b = gx * wx + gy * wy
+        safe = np.where(base > 0, base, 1.0)
+        if kind == "smag":
+            pd = g.phys((g.ky ** 2 - g.kx ** 2) * psih)
+            pxy = g.phys(-g.kx * g.ky * psih)
+            lam_pd = np.where(base > 0, pd / safe, 0.0) * lam_b
+            lam_pxy = np.where(base > 0, 4.0 * pxy / safe, 0.0) * lam_b
+            lam_psi = lam_psi + (g.ky ** 2 - g.kx ** 2) * g.spec(lam_pd) - g.kx * g.ky * g.spec(lam_pxy)
+        elif kind == "leith":
+            lam_wx = lam_wx + np.where(base > 0, wx / safe, 0.0) * lam_b
+            lam_wy = lam_wy + np.where(base > 0, wy / safe, 0.0) * lam_b
+    lam_psi = lam_psi + 1j * g.ky * g.spec(lam_u) - 1j * g.kx * g.spec(lam_v)
+    lam_y = -1j * g.kx * g.spec(lam_wx) - 1j * g.ky * g.spec(lam_wy) - g.inv_k2 * lam_psi
+    return g.D * lam_y
+
+
+def dynamic_rhs_adjoint(x, lam, m):
+    """Dynamic closures: (dL/dx, 0) for stage input x and lam = dL/dR."""
+    g, p = m.g, m.p
+    kind = "smag" if p.closure == "dsmag" else "leith"
+    lam = _zero_mean(lam)
+    fw = {}
+    qg.rhs(x, m, fw)
+    C = fw["C"]
+    lam_x = -(g.k2 * m.inv_re + p.mu) * lam - g.inv_k2 * (1j * p.beta * g.kx) * lam
+    lam_x = g.D * lam_x + transport_adjoint(x, -lam, C * lam, kind, m)
+    if fw["HM"] > 0.0 and fw["MM"] > 0.0:
+        s = g.N * g.mean_product(lam, fw["Qh"])                # <lam, Q>_w = dL/dC
+        f = s / (g.N * fw["MM"])
+        a = f * fw["Mh"]
+        b = f * (fw["Hh"] - 2.0 * C * fw["Mh"])
+        r = float(p.test_ratio) ** (2 if p.closure == "dsmag" else 3)
+        lam_x = lam_x + g.T * transport_adjoint(g.T * x, a, r * b, kind, m) \
+            - transport_adjoint(x, g.T * a, g.T * b, kind, m)
+    return g.D * lam_x, 0.0
+
+
 def rhs_adjoint(x, lam, m):
     """Given stage input x (in D) and lam = dL/dR, return (dL/dx, <lam, dR/dc>_w)."""
     g, p = m.g, m.p
+    if p.closure in ("dsmag", "dleith"):
+        return dynamic_rhs_adjoint(x, lam, m)
     if p.closure not in ("none", "smag", "leith", "const"):
-        raise NotImplementedError("the oracle adjoint covers static closures only")
+        raise NotImplementedError(p.closure)
     fw = {}
     qg.rhs(x, m, fw)
     lam = _zero_mean(lam)

@@ -100,3 +100,60 @@ def test_rollout_gradient_central_fd(closure):
     mm = make(closure=closure, c=c - h)
     fdc = (adj.loss(qg.run(w0, mp, n), tgt) - adj.loss(qg.run(w0, mm, n), tgt)) / (2 * h)
     assert gc == pytest.approx(fdc, rel=1e-6)
+
+
+# ---------------------------------------------------------------- dynamic closures
+@pytest.mark.parametrize("closure", ["dsmag", "dleith"])
+def test_dynamic_rhs_adjoint_central_fd(closure):
+    """C = max(<HM>,0)/<M^2> depends on the stage input: the adjoint's s grad C
+    term (2% and 13% of this directional derivative) must be exact.  State
+    with C > 0, away from the clip."""
+    m = make(closure=closure, c=0.0)
+    x = rstate(m, 4)
+    out = {}
+    qg.rhs(x, m, out)
+    assert out["C"] > 0.0
+    d = rstate(m, 104)
+    lam = rstate(m, 204)
+    h = 1e-6
+    fd = (ip(m, qg.rhs(x + h * d, m), lam) - ip(m, qg.rhs(x - h * d, m), lam)) / (2 * h)
+    la, dc = adj.rhs_adjoint(x, lam, m)
+    assert dc == 0.0
+    assert ip(m, d, la) == pytest.approx(fd, rel=1e-8)
+
+
+@pytest.mark.parametrize("closure", ["dsmag", "dleith"])
+def test_dynamic_rhs_adjoint_clipped(closure):
+    """Where <HM> < 0 the clip sets C = 0 in a neighbourhood: the adjoint is
+    the closure-free one, and central differences agree."""
+    m = make(closure=closure, c=0.0)
+    x = rstate(m, 6)
+    out = {}
+    qg.rhs(x, m, out)
+    assert out["HM"] < 0.0 and out["C"] == 0.0
+    lam = rstate(m, 206)
+    la, _ = adj.rhs_adjoint(x, lam, m)
+    m0 = make(closure="none", c=0.0)
+    la0, _ = adj.rhs_adjoint(x, lam, m0)
+    assert np.max(np.abs(la - la0)) <= 1e-13 * np.max(np.abs(la0))
+    d = rstate(m, 106)
+    h = 1e-6
+    fd = (ip(m, qg.rhs(x + h * d, m), lam) - ip(m, qg.rhs(x - h * d, m), lam)) / (2 * h)
+    assert ip(m, d, la) == pytest.approx(fd, rel=1e-8)
+
+
+@pytest.mark.parametrize("closure", ["dsmag", "dleith"])
+def test_dynamic_rollout_gradient_central_fd(closure):
+    m = make(closure=closure, c=0.0)
+    g = m.g
+    w0 = g.phys(rstate(m, 4))
+    tgt = g.phys(rstate(m, 8, 0.5))
+    n = 3
+    wT = qg.run(w0, m, n)
+    gw, gc = adj.run_adjoint(w0, adj.loss_grad(wT, tgt), m, n)
+    assert gc == 0.0
+    h = 1e-4
+    for d in inputs.random_directions(w0.shape, 3, 5):
+        lp = adj.loss(qg.run(w0 + h * d, m, n), tgt)
+        lm = adj.loss(qg.run(w0 - h * d, m, n), tgt)
+        assert np.sum(gw * d) == pytest.approx((lp - lm) / (2 * h), rel=1e-7)

@@ -134,3 +134,25 @@ def test_les_mutation_is_caught(monkeypatch, name, old, new, pin):
     mod = mutated("les", old, new)
     monkeypatch.setattr(pins_les, "les", mod)
     must_fail(pin)
+
+
+import tests.test_oracle_adjoint as pins_adj  # noqa: E402
+
+ADJ_MUTATIONS = [
+    ("test level without T", "g.T * transport_adjoint(g.T * x, a, r * b, kind, m)",
+     "g.T * transport_adjoint(x, a, r * b, kind, m)",
+     lambda: pins_adj.test_dynamic_rhs_adjoint_central_fd("dleith")),
+    ("M factor in grad C", "(fw[\"Hh\"] - 2.0 * C * fw[\"Mh\"])", "(fw[\"Hh\"] - C * fw[\"Mh\"])",
+     lambda: pins_adj.test_dynamic_rhs_adjoint_central_fd("dsmag")),
+    ("test ratio power in grad C", "** (2 if p.closure == \"dsmag\" else 3)", "** (3 if p.closure == \"dsmag\" else 2)",
+     lambda: pins_adj.test_dynamic_rhs_adjoint_central_fd("dleith")),
+    ("flux cotangent sign", "gx = g.phys(-1j * g.kx * g.D * cQ)", "gx = g.phys(1j * g.kx * g.D * cQ)",
+     lambda: pins_adj.test_dynamic_rhs_adjoint_central_fd("dsmag")),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", ADJ_MUTATIONS, ids=[m[0] for m in ADJ_MUTATIONS])
+def test_adjoint_mutation_is_caught(monkeypatch, name, old, new, pin):
+    mod = mutated("adjoint", old, new)
+    monkeypatch.setattr(pins_adj, "adj", mod)
+    must_fail(pin)
