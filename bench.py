@@ -346,9 +346,12 @@ def main():
     if "adjoint" not in skip:
         w5 = configs.config5(precision=64)
         seg = w5.meta["ckpt_every"]
+        w5d = configs.config5(precision=64)
+        for m in w5d.members:   # the same run with the dynamic Leith closure
+            m.params["closure"] = "dleith"
         ratios = {}
-        for prec in (64, 32):
-            S, om = make_solver(w5, prec, adj=seg)
+        for prec, wl, tag in ((64, w5, ""), (32, w5, ""), (64, w5d, "_dleith")):
+            S, om = make_solver(wl, prec, adj=seg)
             w0 = om.clone()
             S.step(om, 5, use_graph=True)
             torch.cuda.synchronize()
@@ -365,8 +368,8 @@ def main():
             torch.cuda.synchronize()
             ta = time.perf_counter() - a0
             S.close()
-            ratios[f"fp{prec}"] = ta / tf
-            log(f"adjoint/forward fp{prec}: {ta / tf:.2f} ({ta * 1e3:.1f} ms / {tf * 1e3:.1f} ms, {seg} steps)")
+            ratios[f"fp{prec}{tag}"] = ta / tf
+            log(f"adjoint/forward fp{prec}{tag}: {ta / tf:.2f} ({ta * 1e3:.1f} ms / {tf * 1e3:.1f} ms, {seg} steps)")
         result["adjoint_forward_ratio"] = ratios
 
     if "cpu" not in skip:

@@ -143,13 +143,16 @@ int qg_init(const qg_params* params, int32_t n_members,
 int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
             void* ckpt_out, int32_t use_graph, void* hip_stream);
 
-/* Discrete adjoint of qg_step over one segment (static closures and
- * QG_SCHEME_RK4 only).
+/* Discrete adjoint of qg_step over one segment (QG_SCHEME_RK4 only).
  * omega_ckpt: omega at the segment start (as saved by qg_step);
  * lambda: on entry dL/d omega at the segment end, on return dL/d omega at
  * the segment start (both physical, same layout as omega);
  * grad_c_dev: n_members doubles on the device; dL/dc of each member is
- * ADDED to it.  nsteps <= adj_segment_k given to qg_init. */
+ * ADDED to it (0 for the dynamic closures, which have no c).
+ * nsteps <= adj_segment_k given to qg_init.
+ * For the dynamic closures the coefficient C = max(<HM>, 0)/<M^2> of every
+ * stage is differentiated with respect to the stage input (through H and
+ * M, Eqs. 10-11, 13); where the clip sets C = 0 its derivative is 0. */
 int qg_adjoint_step(qg_handle* h, const void* omega_ckpt, void* lambda,
                     int64_t nsteps, double* grad_c_dev, void* hip_stream);
 

@@ -176,7 +176,7 @@ static void plan_sizes(Group& g, int adjK) {
   L.mf = take(mf);
   L.mp = take(mp);
   L.phys = take(6LL * g.nx * g.ny * rs);
-  L.part = take((long long)std::max(g.kxn, g.kxn_f) * 2 * 8);   // one slot per strip at W = 1
+  L.part = take((long long)std::max(g.kxn, g.kxn_f) * 3 * 8);   // three slots per strip at W = 1
   L.coef = take(32 * 8);
   // row-block partial sums (at most ny/2 blocks, 5 values each), then the
   // spectral partial sums of the diagnostics
@@ -188,6 +188,15 @@ static void plan_sizes(Group& g, int adjK) {
     L.adj_store = take((long long)align256(spec) * (4LL * adjK + 1));  // LS, then 4 stage inputs per step
   } else {
     L.adj_lam = L.adj_lacc = L.adj_lk = L.adj_store = -1;
+  }
+  if (adjK > 0 && dynamic_closure(cl)) {
+    L.adj_h = take(spec);
+    L.adj_m = take(spec);
+    L.adj_a = take(spec);
+    L.adj_b = take(spec);
+    L.adj_e = take(spec);
+  } else {
+    L.adj_h = L.adj_m = L.adj_a = L.adj_b = L.adj_e = -1;
   }
   L.total = o;
   g.region_bytes = o;
@@ -604,6 +613,8 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
   }
   const int cl = g.closure;
   const int nb = smag_family(cl) ? 6 : 4;
+  const bool dyn = dynamic_closure(cl);
+  const int clb = cl == 3 ? 1 : cl == 4 ? 2 : cl;   // the adjoint kernels of the closure's base family
   for (long long n = nsteps - 1; n >= 0; --n) {
     Phase B = base_phase(h, g);
     B.o_in = g.L.adj_lam;
@@ -620,13 +631,49 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
       A.o_in = slot(n, s - 1);
       A.o_in2 = g.L.adj_lk;
       A.nf = nb + (cl == 0 ? 1 : 3);
-      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
-      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
-      if (cl != 0)
+      if (dyn) {
+        // the stage's coefficient as a function of its input: the forward
+        // pass again (H, M and the partial sums of <lambda, Q>), the
+        // cotangents of H and M, then the transport adjoint at the stage
+        // input and at its test-filtered copy, summed into adj_e
+        Phase Fp = base_phase(h, g);
+        Fp.nf = rhs_fields(cl);
+        Fp.o_in = slot(n, s - 1);
+        QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, Fp, g.count, st));
+        QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, Fp, g.count, st));
+        Fp.o_out = g.L.jsp;
+        Fp.o_aux = g.L.qsp;
+        Fp.o_in2 = g.L.adj_lk;
+        Fp.adj_dyn = 1;
+        Fp.o_h = g.L.adj_h;
+        Fp.o_m = g.L.adj_m;
+        QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, Fp, g.count, st));
+        Phase Kp = base_phase(h, g);
+        Kp.o_h = g.L.adj_h;
+        Kp.o_m = g.L.adj_m;
+        Kp.o_a = g.L.adj_a;
+        Kp.o_b = g.L.adj_b;
+        QG_LAUNCH(launch_adj_dyn_prep(g.dbl, Kp, g.count, st));
+        for (int mode = 1; mode <= 2; ++mode) {
+          Phase G = A;
+          G.adj_mode = mode;
+          G.o_a = g.L.adj_a;
+          G.o_b = g.L.adj_b;
+          G.o_e = g.L.adj_e;
+          QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+          QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+          QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+        }
+        A.adj_dyn = 1;
+        A.o_e = g.L.adj_e;
+      }
+      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
+      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
+      if (cl != 0 && !dyn)
         QG_LAUNCH(launch_adj_grad_c(A, g.count, row_launch_blocks(g.dbl, OP_ADJ_RHS, cl, A), nullptr, 0, st));
       A.o_out = LS;
       A.o_aux = g.L.adj_lacc;
-      QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, cl, A, g.count, st));
+      QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
     }
     QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, g.L.adj_lam, g.L.adj_lacc, st));
   }
@@ -1118,8 +1165,6 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
   if (h.adjK <= 0) return fail(QG_ESTATE, "handle was built without adjoint storage (adj_segment_k = 0)");
   if (nsteps < 1 || nsteps > h.adjK) return fail(QG_EINVAL, "nsteps must be in [1, adj_segment_k]");
   for (const auto& g : h.groups) {
-    if (dynamic_closure(g.closure))
-      return fail(QG_EUNSUPPORTED, "the adjoint covers the static closures only");
     if (g.scheme != QG_SCHEME_RK4)
       return fail(QG_EUNSUPPORTED, "the adjoint covers the RK4 scheme only");
   }

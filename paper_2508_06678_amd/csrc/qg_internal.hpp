@@ -34,6 +34,9 @@ constexpr int AB2CN_FLAG_SLOT = 30;
 // stage code of the right-hand-side pass that writes the closure's term
 // C D div(base grad omega) instead of updating the state
 constexpr int SGS_STAGE = 10;
+// coefficient slot holding C of the stage whose adjoint is being formed
+// (dynamic closures)
+constexpr int ADJ_C_SLOT = 31;
 
 // Per-member constants, resident on the device.
 struct MemberDev {
@@ -62,6 +65,7 @@ struct RegionLayout {
   long long wn, acc, x, jsp, qsp, chih, mf, mp, phys, part, coef, dpart;
   long long ab_pen, ab_hist, ab_wss;               // AB2CN: D curl(chi u), explicit terms, omega**
   long long adj_lam, adj_lacc, adj_lk, adj_store;  // adjoint buffers
+  long long adj_h, adj_m, adj_a, adj_b, adj_e;      // dynamic-closure adjoint: H, M, their cotangents, extra term
   long long total;
 };
 
@@ -86,6 +90,16 @@ struct Phase {
   void* user;             // user physical output (exit, diag nu_e)
   const void* user_in;    // user physical input (entry)
   long long user_stride;  // elements between saves (unused: 0)
+  // dynamic-closure adjoint (all 0 elsewhere).  adj_dyn: in the forward
+  // column pass of a dynamic closure, store H (o_h) and M (o_m) and the
+  // partial sums of <lambda, Q> with lambda at o_in2; in the adjoint
+  // right-hand-side pass, take C from ADJ_C_SLOT and add the term at o_e.
+  // adj_mode 1 / 2: the adjoint right-hand-side pass with the transport
+  // cotangents formed from o_a, o_b (at the stage input / at its
+  // test-filtered copy), its result written (1) or added after the test
+  // filter (2) to o_e.
+  int adj_dyn, adj_mode;
+  long long o_h, o_m, o_a, o_b, o_e;
 };
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048
@@ -113,6 +127,9 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, hipStream_t s);
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int nmem, hipStream_t s);
+// dynamic-closure adjoint: C, s = <lambda, Q> and <M^2> from the partial
+// sums, then the cotangents a = (s/<M^2>) M, b = (s/<M^2>)(H - 2 C M)
+hipError_t launch_adj_dyn_prep(bool dbl, const Phase& P, int nmem, hipStream_t s);
 
 // One member pair of the LES filter: FR D-compact spectrum -> coarse
 // full-set compact spectrum.

@@ -203,6 +203,16 @@ __device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x,
   return cmake<V>(psi.x * a, psi.y * a);
 }
 
+// Flux coefficient of the adjoint right-hand-side pass: 1 for the transport
+// cotangent passes, the stage's C for a dynamic closure, else the static
+// coefficient.
+template <typename T>
+__device__ __forceinline__ T adj_coef(const MemberDev& M, const Phase& P) {
+  if (P.adj_mode != 0) return T(1);
+  if (P.adj_dyn) return T(rptr<double>(M, P.o_coef)[ADJ_C_SLOT]);
+  return T(M.coef_static);
+}
+
 // mylim: test_mylim(mx) of the dynamic closures (-2: evaluate in_test)
 template <typename T, int OP, int CL>
 __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy,
@@ -244,15 +254,35 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     return zero_mean ? cmake<V>(T(0), T(0)) : l;
   } else {  // OP_ADJ_RHS: forward fields of the stage input, then -l, -i kx l, -i ky l
     constexpr int nb = (CL == 1) ? 6 : 4;
+    const bool t = P.adj_mode != 0 && in_test(M, P.nx, P.ny, mx, my);
     if (f < nb) {
       V x = gld(cptr<T>(M, P.o_in) + idx);
+      if (P.adj_mode == 2 && !t) x = cmake<V>(T(0), T(0));   // the test-filtered stage input
       return rhs_field<T, CL>(M, f, x, w, mx, my, false);
     }
-    V l = gld(cptr<T>(M, P.o_in2) + idx);
     if (zero_mean) return cmake<V>(T(0), T(0));
     const int a = f - nb;
-    if (a == 0) return cmake<V>(-l.x, -l.y);
-    return mul_ia(l, a == 1 ? T(-w.kx) : T(-w.ky));
+    if (P.adj_mode == 0) {
+      V l = gld(cptr<T>(M, P.o_in2) + idx);
+      if (a == 0) return cmake<V>(-l.x, -l.y);
+      return mul_ia(l, a == 1 ? T(-w.kx) : T(-w.ky));
+    }
+    // transport cotangents: the Jacobian's cJ and the flux's cQ, given as
+    // cJ, -i kx cQ, -i ky cQ (flux coefficient 1)
+    //   mode 1 (stage input x):        cJ = -T a,  cQ = -T b
+    //   mode 2 (test-filtered T x):    cJ = a,     cQ = r b
+    V cj, cq;
+    if (P.adj_mode == 1) {
+      if (!t) return cmake<V>(T(0), T(0));
+      const V av = gld(cptr<T>(M, P.o_a) + idx), bv = gld(cptr<T>(M, P.o_b) + idx);
+      cj = cmake<V>(-av.x, -av.y);
+      cq = cmake<V>(-bv.x, -bv.y);
+    } else {
+      cj = gld(cptr<T>(M, P.o_a) + idx);
+      cq = cscale(gld(cptr<T>(M, P.o_b) + idx), T(M.r_test));
+    }
+    if (a == 0) return cj;
+    return mul_ia(cq, a == 1 ? T(-w.kx) : T(-w.ky));
   }
 }
 
@@ -707,7 +737,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     constexpr bool smag = (CL == 1);
     constexpr int nb = smag ? 6 : 4;
     const T U = T(M.u_in), Vv = T(M.v_in);
-    const T coef = T(M.coef_static);
+    const T coef = adj_coef<T>(M, P);
     V wx[ROW_EPT], wy[ROW_EPT], lJ[ROW_EPT], t0[ROW_EPT], t1[ROW_EPT];
     row_c2r<T>(C, mf + 2 * fstride, wx);
     row_c2r<T>(C, mf + 3 * fstride, wy);
@@ -959,7 +989,8 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   constexpr int PADS = LOGN ? QG_ROW_PADS : 3;  // one pad slot per 2^PADS
   const MemberDev M = member_const(P, mem);
   // member constants read once, not per point
-  const T U = T(M.u_in), Vv = T(M.v_in), coef = T(M.coef_static);
+  const T U = T(M.u_in), Vv = T(M.v_in);
+  const T coef = OP == OP_ADJ_RHS ? adj_coef<T>(M, P) : T(M.coef_static);
   const int nx = P.nx;
   const int bstride = nx + (nx >> PADS);
   const int lg = P.lognx - 3;
@@ -1272,12 +1303,18 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       A[i] = mul_ia(tile_at(i), w.kx);
     }
     colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
+    double sl = 0.0;   // adjoint: partial sum of <lambda, Q>
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
       const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       A[i] = cadd(A[i], mul_ia(tile_at(i), w.ky));
       qsp[sidx(i)] = A[i];
+      if (P.adj_dyn) {
+        const V l = cptr<T>(M, P.o_in2)[sidx(i)];
+        const double wt = mxs_(i) == 0 ? 1.0 : 2.0;
+        sl += wt * ((double)l.x * (double)A[i].x + (double)l.y * (double)A[i].y);
+      }
     }
     colfwd_load_fft<T, EPT>(P, M, tile, twl, 4, kx0);
 #pragma unroll
@@ -1308,6 +1345,10 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       jsp[sidx(i)] = j;
       const V h = in_test(M, P.nx, P.ny, mxs_(i), my) ? csub(A[i], j) : A[i];
       const V g = B[i];
+      if (P.adj_dyn) {
+        cptr<T>(M, P.o_h)[sidx(i)] = h;
+        cptr<T>(M, P.o_m)[sidx(i)] = g;
+      }
       const double wt = mxs_(i) == 0 ? 1.0 : 2.0;
       hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
       mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
@@ -1318,6 +1359,10 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
+    }
+    if (P.adj_dyn) {
+      const double ssl = block_sum(sl, red);
+      if (threadIdx.x == 0) rptr<double>(M, P.o_part)[2 * P.nparts + strip] = ssl;
     }
   } else if constexpr (OP == OP_ADJ_B) {
     // lambda_s = FFT(lambda_w) - (1/|k|^2)(i ky FFT(lambda_u) - i kx FFT(lambda_v));
@@ -1401,6 +1446,22 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
         Lpsi[i] = cadd(Lpsi[i], cscale(tile_at(i), T(-w.kx * w.ky)));
       }
     }
+    if (P.adj_mode != 0) {
+      // transport cotangent pass: its term alone, written (mode 1) or added
+      // to the test-filtered modes (mode 2)
+      V* E = cptr<T>(M, P.o_e);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (!owned(i)) continue;
+        const int my = my_of_iy(iys_(i), P.myh, P.kyn);
+        const Wave<T> w = wave<T>(M, mxs_(i), my);
+        const long long id = sidx(i);
+        const V e = csub(Lx[i], cscale(Lpsi[i], T(w.inv_k2)));
+        if (P.adj_mode == 1) E[id] = e;
+        else if (in_test(M, P.nx, P.ny, mxs_(i), my)) E[id] = cadd(E[id], e);
+      }
+      return;
+    }
     const V* lin = cptr<T>(M, P.o_in2);     // l = LK (stage input adjoint)
     const V* ls = cptr<T>(M, P.o_out);      // LS
     V* lw = cptr<T>(M, P.o_aux);            // LW
@@ -1419,6 +1480,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       V lp = cadd(Lpsi[i], mul_ia(l, T(M.beta * w.kx)));
       V lx = csub(Lx[i], cscale(l, T(w.k2 * M.inv_re + M.mu)));
       lx = csub(lx, cscale(lp, T(w.inv_k2)));
+      if (P.adj_dyn) lx = cadd(lx, cptr<T>(M, P.o_e)[id]);   // the dynamic coefficient's term
       lw[id] = cadd(lw[id], lx);
       if (P.stage > 1) lk[id] = cadd(cscale(ls[id], T(cs)), cscale(lx, T(ds)));
     }
@@ -1483,7 +1545,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     return one ? tile[p * n + padp<CPD>(y)] : tile[p * n + y * P.W + w];
   };
   const int nm = P.W * P.kyn;
-  double hm = 0.0, mm = 0.0;
+  double hm = 0.0, mm = 0.0, sl = 0.0;
   // test filter of the dynamic closures: one column per block when W = 1
   const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   for (int q = threadIdx.x; q < nm; q += blockDim.x) {
@@ -1529,12 +1591,22 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
         lpsi = cadd(lpsi, cscale(at(5, w, iy), -wv.kx * wv.ky));
       }
       const V Lx = cadd(mul_ia(at(2, w, iy), -wv.kx), mul_ia(at(3, w, iy), -wv.ky));
+      if (P.adj_mode != 0) {
+        // transport cotangent pass: its term alone, written (mode 1) or
+        // added to the test-filtered modes (mode 2)
+        const V e = csub(Lx, cscale(lpsi, wv.inv_k2));
+        V* E = cptr<T>(M, P.o_e) + id;
+        if (P.adj_mode == 1) gst(E, e);
+        else if (in_test(M, P.nx, P.ny, mx, my)) gst(E, cadd(gld(E), e));
+        continue;
+      }
       V* lk = cptr<T>(M, P.o_in2);
       V l = gld(lk + id);
       if (mx == 0 && my == 0) l = cmake<V>(T(0), T(0));
       const V lp = cadd(lpsi, mul_ia(l, T(M.beta * wv.kx)));
       V lx = csub(Lx, cscale(l, T(wv.k2 * M.inv_re + M.mu)));
       lx = csub(lx, cscale(lp, wv.inv_k2));
+      if (P.adj_dyn) lx = cadd(lx, gld(cptr<T>(M, P.o_e) + id));   // the dynamic coefficient's term
       V* lw = cptr<T>(M, P.o_aux);
       gst(lw + id, cadd(gld(lw + id), lx));
       if (P.stage > 1) {
@@ -1603,6 +1675,13 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       const double wt = mx == 0 ? 1.0 : 2.0;
       hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
       mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
+      if (P.adj_dyn) {
+        // adjoint: H and M kept, partial sum of <lambda, Q>
+        gst(cptr<T>(M, P.o_h) + id, h);
+        gst(cptr<T>(M, P.o_m) + id, g);
+        const V l = gld(cptr<T>(M, P.o_in2) + id);
+        sl += wt * ((double)l.x * (double)Q.x + (double)l.y * (double)Q.y);
+      }
     }
   }
   if constexpr (OP == OP_RHS && dyn) {
@@ -1612,6 +1691,10 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
+    }
+    if (P.adj_dyn) {
+      const double ssl = block_sum(sl, red);
+      if (threadIdx.x == 0) rptr<double>(M, P.o_part)[2 * P.nparts + strip] = ssl;
     }
   }
 }
@@ -1711,6 +1794,39 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   } else {
     gst(xout + q, cadd(a, cscale(r, T(dt / 6.0))));
   }
+}
+
+// ---------------------------------------------------------------- dynamic-closure adjoint
+// Per stage of the reverse sweep, after the forward column pass has kept H,
+// M and the partial sums of <HM>, <M^2> and s = <lambda, Q>: C exactly as
+// the forward step formed it, then the cotangents of H and M,
+//   a = (s/<M^2>) M,  b = (s/<M^2>)(H - 2 C M)   (zero where the clip holds),
+// and C to ADJ_C_SLOT for the flux term of the stage's adjoint.
+template <typename T>
+__global__ void __launch_bounds__(COMBINE_THREADS) k_adj_dyn_prep(Phase P) {
+  using V = cpx<T>;
+  __shared__ double red[2 * (COMBINE_THREADS / 64)];
+  const MemberDev M = member_const(P, blockIdx.z);
+  double C, hm, mm;
+  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
+  // s from its partials, in a fixed order as well
+  const double* ps = rptr<double>(M, P.o_part) + 2 * P.nparts;
+  double sv = 0.0;
+  for (int i = threadIdx.x; i < P.nparts; i += blockDim.x) sv += ps[i];
+  for (int o = 32; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+  __syncthreads();   // every thread has read red in dyn_coefficient
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sv;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) s += red[w];
+  if (blockIdx.x == 0 && threadIdx.x == 0) rptr<double>(M, P.o_coef)[ADJ_C_SLOT] = C;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.kxn * P.kyn) return;
+  const double f = (hm > 0.0 && mm > 0.0) ? s / mm : 0.0;
+  const V h = gld(cptr<T>(M, P.o_h) + q), g = gld(cptr<T>(M, P.o_m) + q);
+  const double gx = g.x, gy = g.y;
+  gst(cptr<T>(M, P.o_a) + q, cmake<V>(T(f * gx), T(f * gy)));
+  gst(cptr<T>(M, P.o_b) + q, cmake<V>(T(f * ((double)h.x - 2.0 * C * gx)), T(f * ((double)h.y - 2.0 * C * gy))));
 }
 
 // ---------------------------------------------------------------- LES filter
@@ -2191,6 +2307,12 @@ hipError_t launch_pcc(bool dbl, const Phase& P, int n, int nblk, const void* a, 
     hipLaunchKernelGGL(k_pcc_centred<float>, grid, dim3(PCC_THREADS), 0, s, P, a, b);
   }
   hipLaunchKernelGGL(k_pcc_final, dim3(n), dim3(64), 0, s, P, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_adj_dyn_prep(bool dbl, const Phase& P, int n, hipStream_t s) {
+  dim3 grid((P.kxn * P.kyn + COMBINE_THREADS - 1) / COMBINE_THREADS, 1, n);
+  if (dbl) hipLaunchKernelGGL(k_adj_dyn_prep<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  else hipLaunchKernelGGL(k_adj_dyn_prep<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {
