@@ -634,8 +634,8 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
       if (dyn) {
         // the stage's coefficient as a function of its input: the forward
         // pass again (H, M and the partial sums of <lambda, Q>), the
-        // cotangents of H and M, then the transport adjoint at the stage
-        // input and at its test-filtered copy, summed into adj_e
+        // cotangents of H and M, the transport adjoint at the test-filtered
+        // stage input into adj_e; the stage's own pass below takes the rest
         Phase Fp = base_phase(h, g);
         Fp.nf = rhs_fields(cl);
         Fp.o_in = slot(n, s - 1);
@@ -654,17 +654,17 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
         Kp.o_a = g.L.adj_a;
         Kp.o_b = g.L.adj_b;
         QG_LAUNCH(launch_adj_dyn_prep(g.dbl, Kp, g.count, st));
-        for (int mode = 1; mode <= 2; ++mode) {
-          Phase G = A;
-          G.adj_mode = mode;
-          G.o_a = g.L.adj_a;
-          G.o_b = g.L.adj_b;
-          G.o_e = g.L.adj_e;
-          QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
-          QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
-          QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
-        }
+        Phase G = A;
+        G.adj_mode = 1;
+        G.o_a = g.L.adj_a;
+        G.o_b = g.L.adj_b;
+        G.o_e = g.L.adj_e;
+        QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+        QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+        QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
         A.adj_dyn = 1;
+        A.o_a = g.L.adj_a;
+        A.o_b = g.L.adj_b;
         A.o_e = g.L.adj_e;
       }
       QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));

@@ -93,11 +93,10 @@ struct Phase {
   // dynamic-closure adjoint (all 0 elsewhere).  adj_dyn: in the forward
   // column pass of a dynamic closure, store H (o_h) and M (o_m) and the
   // partial sums of <lambda, Q> with lambda at o_in2; in the adjoint
-  // right-hand-side pass, take C from ADJ_C_SLOT and add the term at o_e.
-  // adj_mode 1 / 2: the adjoint right-hand-side pass with the transport
-  // cotangents formed from o_a, o_b (at the stage input / at its
-  // test-filtered copy), its result written (1) or added after the test
-  // filter (2) to o_e.
+  // right-hand-side pass, fold C (ADJ_C_SLOT) and the cotangents -T a,
+  // -T b of H and M (o_a, o_b) into the pass's input and add the term at
+  // o_e.  adj_mode 1: the transport pass at the test-filtered stage input
+  // with the cotangents a, r b, its result test-filtered to o_e.
   int adj_dyn, adj_mode;
   long long o_h, o_m, o_a, o_b, o_e;
 };

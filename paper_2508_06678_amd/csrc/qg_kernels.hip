@@ -203,13 +203,11 @@ __device__ __forceinline__ cpx<T> rhs_field(const MemberDev& M, int f, cpx<T> x,
   return cmake<V>(psi.x * a, psi.y * a);
 }
 
-// Flux coefficient of the adjoint right-hand-side pass: 1 for the transport
-// cotangent passes, the stage's C for a dynamic closure, else the static
-// coefficient.
+// Flux coefficient of the adjoint right-hand-side pass: 1 for the dynamic
+// closures (their flux cotangent carries C), else the static coefficient.
 template <typename T>
 __device__ __forceinline__ T adj_coef(const MemberDev& M, const Phase& P) {
-  if (P.adj_mode != 0) return T(1);
-  if (P.adj_dyn) return T(rptr<double>(M, P.o_coef)[ADJ_C_SLOT]);
+  if (P.adj_mode != 0 || P.adj_dyn) return T(1);
   return T(M.coef_static);
 }
 
@@ -254,32 +252,35 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     return zero_mean ? cmake<V>(T(0), T(0)) : l;
   } else {  // OP_ADJ_RHS: forward fields of the stage input, then -l, -i kx l, -i ky l
     constexpr int nb = (CL == 1) ? 6 : 4;
-    const bool t = P.adj_mode != 0 && in_test(M, P.nx, P.ny, mx, my);
+    const bool t = (P.adj_mode != 0 || P.adj_dyn) && in_test(M, P.nx, P.ny, mx, my);
     if (f < nb) {
       V x = gld(cptr<T>(M, P.o_in) + idx);
-      if (P.adj_mode == 2 && !t) x = cmake<V>(T(0), T(0));   // the test-filtered stage input
+      if (P.adj_mode == 1 && !t) x = cmake<V>(T(0), T(0));   // the test-filtered stage input
       return rhs_field<T, CL>(M, f, x, w, mx, my, false);
     }
     if (zero_mean) return cmake<V>(T(0), T(0));
     const int a = f - nb;
-    if (P.adj_mode == 0) {
-      V l = gld(cptr<T>(M, P.o_in2) + idx);
-      if (a == 0) return cmake<V>(-l.x, -l.y);
-      return mul_ia(l, a == 1 ? T(-w.kx) : T(-w.ky));
-    }
-    // transport cotangents: the Jacobian's cJ and the flux's cQ, given as
-    // cJ, -i kx cQ, -i ky cQ (flux coefficient 1)
-    //   mode 1 (stage input x):        cJ = -T a,  cQ = -T b
-    //   mode 2 (test-filtered T x):    cJ = a,     cQ = r b
+    // the Jacobian's cotangent cJ and the flux's cQ, given as cJ, -i kx cQ,
+    // -i ky cQ (the row pass's flux coefficient is 1 where cQ carries it):
+    //   static closures:            cJ = -l,          cQ = l (coefficient c)
+    //   dynamic, at the stage input: cJ = -l - T a,   cQ = C l - T b
+    //   dynamic, at T x (mode 1):    cJ = a,          cQ = r b
+    // with l the stage's cotangent and a, b those of H and M
     V cj, cq;
     if (P.adj_mode == 1) {
-      if (!t) return cmake<V>(T(0), T(0));
-      const V av = gld(cptr<T>(M, P.o_a) + idx), bv = gld(cptr<T>(M, P.o_b) + idx);
-      cj = cmake<V>(-av.x, -av.y);
-      cq = cmake<V>(-bv.x, -bv.y);
-    } else {
       cj = gld(cptr<T>(M, P.o_a) + idx);
       cq = cscale(gld(cptr<T>(M, P.o_b) + idx), T(M.r_test));
+    } else {
+      const V l = gld(cptr<T>(M, P.o_in2) + idx);
+      cj = cmake<V>(-l.x, -l.y);
+      cq = l;
+      if (P.adj_dyn) {
+        cq = cscale(l, T(rptr<double>(M, P.o_coef)[ADJ_C_SLOT]));
+        if (t) {
+          cj = csub(cj, gld(cptr<T>(M, P.o_a) + idx));
+          cq = csub(cq, gld(cptr<T>(M, P.o_b) + idx));
+        }
+      }
     }
     if (a == 0) return cj;
     return mul_ia(cq, a == 1 ? T(-w.kx) : T(-w.ky));
@@ -1447,18 +1448,16 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       }
     }
     if (P.adj_mode != 0) {
-      // transport cotangent pass: its term alone, written (mode 1) or added
-      // to the test-filtered modes (mode 2)
+      // transport pass at the test-filtered stage input: its term,
+      // test-filtered, to o_e
       V* E = cptr<T>(M, P.o_e);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (!owned(i)) continue;
         const int my = my_of_iy(iys_(i), P.myh, P.kyn);
         const Wave<T> w = wave<T>(M, mxs_(i), my);
-        const long long id = sidx(i);
         const V e = csub(Lx[i], cscale(Lpsi[i], T(w.inv_k2)));
-        if (P.adj_mode == 1) E[id] = e;
-        else if (in_test(M, P.nx, P.ny, mxs_(i), my)) E[id] = cadd(E[id], e);
+        E[sidx(i)] = in_test(M, P.nx, P.ny, mxs_(i), my) ? e : cmake<V>(T(0), T(0));
       }
       return;
     }
@@ -1592,12 +1591,10 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       }
       const V Lx = cadd(mul_ia(at(2, w, iy), -wv.kx), mul_ia(at(3, w, iy), -wv.ky));
       if (P.adj_mode != 0) {
-        // transport cotangent pass: its term alone, written (mode 1) or
-        // added to the test-filtered modes (mode 2)
+        // transport pass at the test-filtered stage input: its term,
+        // test-filtered, to o_e
         const V e = csub(Lx, cscale(lpsi, wv.inv_k2));
-        V* E = cptr<T>(M, P.o_e) + id;
-        if (P.adj_mode == 1) gst(E, e);
-        else if (in_test(M, P.nx, P.ny, mx, my)) gst(E, cadd(gld(E), e));
+        gst(cptr<T>(M, P.o_e) + id, in_test(M, P.nx, P.ny, mx, my) ? e : cmake<V>(T(0), T(0)));
         continue;
       }
       V* lk = cptr<T>(M, P.o_in2);
