@@ -135,3 +135,35 @@ def test_dynamic_adjoint_central_fd_on_gpu():
         say("  fd", fd, "adjoint", ad)
         assert ad == pytest.approx(fd, rel=1e-6)
     S.close()
+
+
+def test_dynamic_rollout_through_autograd():
+    """torch.autograd over a dynamic-Leith rollout with two checkpointed
+    segments: d loss/d omega0 against central differences; the coefficient
+    has no c, so d loss/dc is 0."""
+    import torch
+
+    from paper_2508_06678_amd.autograd import QGRollout
+    nx, ny = 64, 32
+    m = island(nx, ny, "dleith", seed=8)
+    seg, nsteps = 2, 4
+    S = solver_for([m], 64, adj_segment_k=seg)
+    w0 = S.pack([m.omega0]).requires_grad_(True)
+    c = torch.tensor([0.0], dtype=torch.float64, requires_grad=True)
+    tgt = S.pack([inputs.bandpass_noise(nx, ny, 2 * math.pi, math.pi, 11, 2, 8, 0.3)])
+
+    def loss_of(w):
+        return torch.mean((QGRollout.apply(w, c, S, nsteps, seg) - tgt) ** 2)
+
+    L = loss_of(w0)
+    L.backward()
+    assert c.grad.item() == 0.0
+    h = 1e-4
+    for d in inputs.random_directions((ny, nx), 2, 7):
+        dd = S.pack([d])
+        with torch.no_grad():
+            fd = (loss_of(w0 + h * dd).item() - loss_of(w0 - h * dd).item()) / (2 * h)
+        ad = torch.sum(w0.grad * dd).item()
+        say("  autograd fd", fd, "adjoint", ad)
+        assert ad == pytest.approx(fd, rel=1e-6)
+    S.close()
