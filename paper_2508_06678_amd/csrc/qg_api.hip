@@ -176,7 +176,7 @@ static void plan_sizes(Group& g, int adjK) {
   L.mf = take(mf);
   L.mp = take(mp);
   L.phys = take(6LL * g.nx * g.ny * rs);
-  L.part = take((long long)std::max(g.kxn, g.kxn_f) * 3 * 8);   // three slots per strip at W = 1
+  L.part = take((long long)std::max(g.kxn, g.kxn_f) * 2 * 8);   // one slot per strip at W = 1
   L.coef = take(32 * 8);
   // row-block partial sums (at most ny/2 blocks, 5 values each), then the
   // spectral partial sums of the diagnostics
@@ -190,13 +190,13 @@ static void plan_sizes(Group& g, int adjK) {
     L.adj_lam = L.adj_lacc = L.adj_lk = L.adj_store = -1;
   }
   if (adjK > 0 && dynamic_closure(cl)) {
-    L.adj_h = take(spec);
-    L.adj_m = take(spec);
+    L.adj_hmq = take((long long)align256(spec) * 3 * 4 * adjK);   // H, M, Q of every stage of a segment
+    L.adj_cs = take(3LL * 4 * adjK * 8);                          // C, <HM>, <M^2> of every stage
     L.adj_a = take(spec);
     L.adj_b = take(spec);
     L.adj_e = take(spec);
   } else {
-    L.adj_h = L.adj_m = L.adj_a = L.adj_b = L.adj_e = -1;
+    L.adj_hmq = L.adj_cs = L.adj_a = L.adj_b = L.adj_e = -1;
   }
   L.total = o;
   g.region_bytes = o;
@@ -389,8 +389,14 @@ static int run_exit(const Handle& h, const Group& g, long long o_in, void* dst, 
   return QG_OK;
 }
 
+// Where the adjoint's segment recompute keeps a dynamic stage's H, M, Q
+// and (C, <HM>, <M^2>) (byte offsets in the member region).
+struct StageStore {
+  long long h, m, q, cs;
+};
+
 // One RK4 stage (s = 1..4): colinv -> row -> colfwd (-> combine for dynamic).
-static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st) {
+static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, const StageStore* keep = nullptr) {
   Phase P = base_phase(h, g);
   const int cl = g.closure;
   P.stage = s;
@@ -405,15 +411,24 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st) {
     QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
   } else {
     P.o_out = g.L.jsp;
-    P.o_aux = g.L.qsp;
+    P.o_aux = keep ? keep->q : g.L.qsp;
+    if (keep) {
+      P.adj_dyn = 1;
+      P.o_h = keep->h;
+      P.o_m = keep->m;
+    }
     QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
     Phase Q = base_phase(h, g);
     Q.stage = s;
     Q.o_in = g.L.x;
     Q.o_in2 = g.L.wn;
     Q.o_out = g.L.jsp;
-    Q.o_aux = g.L.qsp;
+    Q.o_aux = P.o_aux;
     Q.o_mp = g.L.acc;
+    if (keep) {
+      Q.adj_dyn = 1;
+      Q.o_cs = keep->cs;
+    }
     QG_LAUNCH(launch_combine(g.dbl, OP_RHS, Q, g.count, st));
   }
   return QG_OK;
@@ -600,11 +615,19 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
   const long long slot_bytes = (long long)align256((size_t)spec);
   const long long LS = g.L.adj_store;
   auto slot = [&](long long n, int s) { return g.L.adj_store + (1 + 4 * n + s) * slot_bytes; };
+  const bool dyn = dynamic_closure(g.closure);
+  // dynamic closures: H, M, Q and (C, <HM>, <M^2>) of step n, stage s (1..4)
+  auto keep = [&](long long n, int s) {
+    const long long k = 4 * n + (s - 1);
+    return StageStore{g.L.adj_hmq + (3 * k) * slot_bytes, g.L.adj_hmq + (3 * k + 1) * slot_bytes,
+                      g.L.adj_hmq + (3 * k + 2) * slot_bytes, g.L.adj_cs + 3 * k * 8};
+  };
   Phase C = base_phase(h, g);
   for (long long n = 0; n < nsteps; ++n) {
     QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, 0), g.L.wn, st));
     for (int s = 1; s <= 4; ++s) {
-      int rc = run_stage(h, g, s, st);
+      const StageStore ks = dyn ? keep(n, s) : StageStore{};
+      int rc = run_stage(h, g, s, st, dyn ? &ks : nullptr);
       if (rc) return rc;
       if (s < 4) QG_LAUNCH(launch_spec_copy(g.dbl, C, g.count, slot(n, s), g.L.x, st));
     }
@@ -613,7 +636,6 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
   }
   const int cl = g.closure;
   const int nb = smag_family(cl) ? 6 : 4;
-  const bool dyn = dynamic_closure(cl);
   const int clb = cl == 3 ? 1 : cl == 4 ? 2 : cl;   // the adjoint kernels of the closure's base family
   for (long long n = nsteps - 1; n >= 0; --n) {
     Phase B = base_phase(h, g);
@@ -632,25 +654,17 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
       A.o_in2 = g.L.adj_lk;
       A.nf = nb + (cl == 0 ? 1 : 3);
       if (dyn) {
-        // the stage's coefficient as a function of its input: the forward
-        // pass again (H, M and the partial sums of <lambda, Q>), the
-        // cotangents of H and M, the transport adjoint at the test-filtered
-        // stage input into adj_e; the stage's own pass below takes the rest
-        Phase Fp = base_phase(h, g);
-        Fp.nf = rhs_fields(cl);
-        Fp.o_in = slot(n, s - 1);
-        QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, Fp, g.count, st));
-        QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, Fp, g.count, st));
-        Fp.o_out = g.L.jsp;
-        Fp.o_aux = g.L.qsp;
-        Fp.o_in2 = g.L.adj_lk;
-        Fp.adj_dyn = 1;
-        Fp.o_h = g.L.adj_h;
-        Fp.o_m = g.L.adj_m;
-        QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, Fp, g.count, st));
+        // the stage's coefficient as a function of its input: s = <lambda,
+        // Q> and the cotangents of the kept H and M, the transport adjoint at
+        // the test-filtered stage input into adj_e; the stage's own pass
+        // below takes the rest
+        const StageStore ks = keep(n, s);
         Phase Kp = base_phase(h, g);
-        Kp.o_h = g.L.adj_h;
-        Kp.o_m = g.L.adj_m;
+        Kp.o_in2 = g.L.adj_lk;
+        Kp.o_aux = ks.q;
+        Kp.o_h = ks.h;
+        Kp.o_m = ks.m;
+        Kp.o_cs = ks.cs;
         Kp.o_a = g.L.adj_a;
         Kp.o_b = g.L.adj_b;
         QG_LAUNCH(launch_adj_dyn_prep(g.dbl, Kp, g.count, st));

@@ -65,7 +65,8 @@ struct RegionLayout {
   long long wn, acc, x, jsp, qsp, chih, mf, mp, phys, part, coef, dpart;
   long long ab_pen, ab_hist, ab_wss;               // AB2CN: D curl(chi u), explicit terms, omega**
   long long adj_lam, adj_lacc, adj_lk, adj_store;  // adjoint buffers
-  long long adj_h, adj_m, adj_a, adj_b, adj_e;      // dynamic-closure adjoint: H, M, their cotangents, extra term
+  long long adj_hmq, adj_cs;                        // dynamic-closure adjoint: H, M, Q and (C, <HM>, <M^2>) per stage
+  long long adj_a, adj_b, adj_e;                    // ... the cotangents of H and M, the coefficient's term
   long long total;
 };
 
@@ -90,15 +91,15 @@ struct Phase {
   void* user;             // user physical output (exit, diag nu_e)
   const void* user_in;    // user physical input (entry)
   long long user_stride;  // elements between saves (unused: 0)
-  // dynamic-closure adjoint (all 0 elsewhere).  adj_dyn: in the forward
-  // column pass of a dynamic closure, store H (o_h) and M (o_m) and the
-  // partial sums of <lambda, Q> with lambda at o_in2; in the adjoint
-  // right-hand-side pass, fold C (ADJ_C_SLOT) and the cotangents -T a,
-  // -T b of H and M (o_a, o_b) into the pass's input and add the term at
-  // o_e.  adj_mode 1: the transport pass at the test-filtered stage input
-  // with the cotangents a, r b, its result test-filtered to o_e.
+  // dynamic-closure adjoint (all 0 elsewhere).  adj_dyn: the forward
+  // column pass of a dynamic closure keeps H (o_h) and M (o_m) and the
+  // combine keeps (C, <HM>, <M^2>) at o_cs; in the adjoint right-hand-side
+  // pass, C (ADJ_C_SLOT) and the cotangents -T a, -T b of H and M (o_a,
+  // o_b) are folded into the pass's input and the term at o_e is added.
+  // adj_mode 1: the transport pass at the test-filtered stage input with
+  // the cotangents a, r b, its result test-filtered to o_e.
   int adj_dyn, adj_mode;
-  long long o_h, o_m, o_a, o_b, o_e;
+  long long o_h, o_m, o_a, o_b, o_e, o_cs;
 };
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048
@@ -126,8 +127,9 @@ hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, hipStream_t s);
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int nmem, hipStream_t s);
-// dynamic-closure adjoint: C, s = <lambda, Q> and <M^2> from the partial
-// sums, then the cotangents a = (s/<M^2>) M, b = (s/<M^2>)(H - 2 C M)
+// dynamic-closure adjoint: s = <lambda, Q> (lambda at o_in2, Q at o_aux),
+// then with the kept C, <HM>, <M^2> (o_cs) the cotangents
+// a = (s/<M^2>) M, b = (s/<M^2>)(H - 2 C M) of H and M (o_h, o_m)
 hipError_t launch_adj_dyn_prep(bool dbl, const Phase& P, int nmem, hipStream_t s);
 
 // One member pair of the LES filter: FR D-compact spectrum -> coarse

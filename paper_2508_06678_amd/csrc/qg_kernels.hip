@@ -1304,18 +1304,12 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       A[i] = mul_ia(tile_at(i), w.kx);
     }
     colfwd_load_fft<T, EPT>(P, M, tile, twl, 2, kx0);
-    double sl = 0.0;   // adjoint: partial sum of <lambda, Q>
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
       const Wave<T> w = wave<T>(M, mxs_(i), my_of_iy(iys_(i), P.myh, P.kyn));
       A[i] = cadd(A[i], mul_ia(tile_at(i), w.ky));
       qsp[sidx(i)] = A[i];
-      if (P.adj_dyn) {
-        const V l = cptr<T>(M, P.o_in2)[sidx(i)];
-        const double wt = mxs_(i) == 0 ? 1.0 : 2.0;
-        sl += wt * ((double)l.x * (double)A[i].x + (double)l.y * (double)A[i].y);
-      }
     }
     colfwd_load_fft<T, EPT>(P, M, tile, twl, 4, kx0);
 #pragma unroll
@@ -1360,10 +1354,6 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
-    }
-    if (P.adj_dyn) {
-      const double ssl = block_sum(sl, red);
-      if (threadIdx.x == 0) rptr<double>(M, P.o_part)[2 * P.nparts + strip] = ssl;
     }
   } else if constexpr (OP == OP_ADJ_B) {
     // lambda_s = FFT(lambda_w) - (1/|k|^2)(i ky FFT(lambda_u) - i kx FFT(lambda_v));
@@ -1544,7 +1534,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     return one ? tile[p * n + padp<CPD>(y)] : tile[p * n + y * P.W + w];
   };
   const int nm = P.W * P.kyn;
-  double hm = 0.0, mm = 0.0, sl = 0.0;
+  double hm = 0.0, mm = 0.0;
   // test filter of the dynamic closures: one column per block when W = 1
   const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   for (int q = threadIdx.x; q < nm; q += blockDim.x) {
@@ -1672,12 +1662,9 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       const double wt = mx == 0 ? 1.0 : 2.0;
       hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
       mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
-      if (P.adj_dyn) {
-        // adjoint: H and M kept, partial sum of <lambda, Q>
+      if (P.adj_dyn) {   // kept for the adjoint
         gst(cptr<T>(M, P.o_h) + id, h);
         gst(cptr<T>(M, P.o_m) + id, g);
-        const V l = gld(cptr<T>(M, P.o_in2) + id);
-        sl += wt * ((double)l.x * (double)Q.x + (double)l.y * (double)Q.y);
       }
     }
   }
@@ -1688,10 +1675,6 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
       part[1] = smm;
-    }
-    if (P.adj_dyn) {
-      const double ssl = block_sum(sl, red);
-      if (threadIdx.x == 0) rptr<double>(M, P.o_part)[2 * P.nparts + strip] = ssl;
     }
   }
 }
@@ -1761,6 +1744,12 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
       c[8 + 2 * P.stage] = hm;
       c[9 + 2 * P.stage] = mm;
     }
+    if (P.adj_dyn) {   // kept for the adjoint
+      double* k = rptr<double>(M, P.o_cs);
+      k[0] = C;
+      k[1] = hm;
+      k[2] = mm;
+    }
   }
   if (!in) return;
   if (P.stage == SGS_STAGE) {
@@ -1794,28 +1783,45 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
 }
 
 // ---------------------------------------------------------------- dynamic-closure adjoint
-// Per stage of the reverse sweep, after the forward column pass has kept H,
-// M and the partial sums of <HM>, <M^2> and s = <lambda, Q>: C exactly as
-// the forward step formed it, then the cotangents of H and M,
+// Per stage of the reverse sweep.  k_adj_dot: block partial sums of
+// s = <lambda, Q> (Parseval weights 1 at m_x = 0 else 2) with lambda at
+// o_in2 and the stage's Q at o_aux, to the member's dpart area.
+template <typename T>
+__global__ void __launch_bounds__(COMBINE_THREADS) k_adj_dot(Phase P) {
+  using V = cpx<T>;
+  __shared__ double red[COMBINE_THREADS / 64];
+  const MemberDev M = member_const(P, blockIdx.z);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (q < P.kxn * P.kyn) {
+    const V l = gld(cptr<T>(M, P.o_in2) + q), Q = gld(cptr<T>(M, P.o_aux) + q);
+    v = (q < P.kyn ? 1.0 : 2.0) * ((double)l.x * (double)Q.x + (double)l.y * (double)Q.y);
+  }
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[blockIdx.x] = v;
+}
+
+// k_adj_dyn_prep: the stage's C, <HM>, <M^2> as the forward step kept them
+// (o_cs), s from the k_adj_dot partials in a fixed order, then the
+// cotangents of H and M (kept at o_h, o_m)
 //   a = (s/<M^2>) M,  b = (s/<M^2>)(H - 2 C M)   (zero where the clip holds),
-// and C to ADJ_C_SLOT for the flux term of the stage's adjoint.
+// and C to ADJ_C_SLOT for the stage's own adjoint pass.
 template <typename T>
 __global__ void __launch_bounds__(COMBINE_THREADS) k_adj_dyn_prep(Phase P) {
   using V = cpx<T>;
-  __shared__ double red[2 * (COMBINE_THREADS / 64)];
+  __shared__ double red[COMBINE_THREADS / 64];
   const MemberDev M = member_const(P, blockIdx.z);
-  double C, hm, mm;
-  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
-  // s from its partials, in a fixed order as well
-  const double* ps = rptr<double>(M, P.o_part) + 2 * P.nparts;
+  const double* ps = rptr<double>(M, P.o_dpart);
+  const int nparts = (P.kxn * P.kyn + COMBINE_THREADS - 1) / COMBINE_THREADS;
   double sv = 0.0;
-  for (int i = threadIdx.x; i < P.nparts; i += blockDim.x) sv += ps[i];
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) sv += ps[i];
   for (int o = 32; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-  __syncthreads();   // every thread has read red in dyn_coefficient
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sv;
   __syncthreads();
   double s = 0.0;
   for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) s += red[w];
+  const double* k = rptr<double>(M, P.o_cs);
+  const double C = k[0], hm = k[1], mm = k[2];
   if (blockIdx.x == 0 && threadIdx.x == 0) rptr<double>(M, P.o_coef)[ADJ_C_SLOT] = C;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.kxn * P.kyn) return;
@@ -2308,8 +2314,13 @@ hipError_t launch_pcc(bool dbl, const Phase& P, int n, int nblk, const void* a, 
 }
 hipError_t launch_adj_dyn_prep(bool dbl, const Phase& P, int n, hipStream_t s) {
   dim3 grid((P.kxn * P.kyn + COMBINE_THREADS - 1) / COMBINE_THREADS, 1, n);
-  if (dbl) hipLaunchKernelGGL(k_adj_dyn_prep<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
-  else hipLaunchKernelGGL(k_adj_dyn_prep<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  if (dbl) {
+    hipLaunchKernelGGL(k_adj_dot<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
+    hipLaunchKernelGGL(k_adj_dyn_prep<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  } else {
+    hipLaunchKernelGGL(k_adj_dot<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
+    hipLaunchKernelGGL(k_adj_dyn_prep<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  }
   return hipGetLastError();
 }
 hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {
