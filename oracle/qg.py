@@ -36,7 +36,8 @@ selectable where it matters):
     integer inequality (requires dx = dy);
   * Delta = lx / nx; averages <.> are plain means over the whole grid;
   * clipping: coefficient level C = max(<HM>, 0)/<M^2> (clip_mode 0); the
-    pointwise H+ reading is clip_mode 1;
+    pointwise reading (clip_mode 1) clips H at every grid point,
+    C = <max(H, 0) M>/<M^2>, with no further clip of the ratio;
   * the dynamic coefficient is recomputed at every RK stage.
 """
 from dataclasses import dataclass, field

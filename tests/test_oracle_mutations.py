@@ -54,6 +54,8 @@ QG_MUTATIONS = [
      lambda: pins_phys.test_dynamic_coefficient_inside_test_filter("dleith", 3)),
     ("viscosity sign", "- (g.k2 * m.inv_re + p.mu) * wh", "+ (g.k2 * m.inv_re + p.mu) * wh",
      lambda: pins_phys.test_single_shell_rk4_exact("none", 0.0)),
+    ("pointwise clip of the product", "np.mean(np.maximum(H, 0.0) * M)", "np.mean(np.maximum(H * M, 0.0))",
+     lambda: pins_phys.test_pointwise_clip_reading("dleith")),
 ]
 
 
