@@ -94,8 +94,13 @@ enum {
  *  test_ratio   Delta~/Delta of the test filter, integer in {2, 3, 4};
  *               the test filter keeps |k| <= k_max / test_ratio with k_max
  *               the largest retained wavenumber (Sec. III-A, dynamic models)
- *  clip_mode    0: C = max(<HM>, 0)/<M^2>.  1 (pointwise H+) is not
- *               implemented on the GPU and returns QG_EUNSUPPORTED.
+ *  clip_mode    dynamic closures only (Sec. III-A, the clip of H).
+ *               0: C = max(<HM>, 0)/<M^2>, the clip applied to the
+ *               average.  1: C = <max(H, 0) M>/<M^2>, H clipped at every
+ *               grid point (C may then be negative: the ratio is not
+ *               clipped again); needs nx >= 64 (and nx <= 2048 in 64-bit
+ *               runs) and has no adjoint (qg_adjoint_step returns
+ *               QG_EUNSUPPORTED for a handle that holds it).
  *  fp64_lowk    in 32-bit runs, modes with |k| <= fp64_lowk invert the
  *               Poisson equation in double precision
  *  scheme       QG_SCHEME_*.  QG_SCHEME_AB2CN needs nx >= 64 (and

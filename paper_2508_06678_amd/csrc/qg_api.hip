@@ -50,8 +50,9 @@ static int validate(const qg_params& p, int idx) {
   if (!(p.dt > 0) || !std::isfinite(p.dt)) return bad(QG_EINVAL, "dt must be positive and finite");
   if (p.closure < 0 || p.closure > 4) return bad(QG_EINVAL, "unknown closure");
   if (p.precision != 32 && p.precision != 64) return bad(QG_EINVAL, "precision must be 32 or 64");
-  if (p.clip_mode == 1) return bad(QG_EUNSUPPORTED, "pointwise clipping (clip_mode 1) is not implemented");
-  if (p.clip_mode != 0) return bad(QG_EINVAL, "clip_mode must be 0 or 1");
+  if (p.clip_mode != 0 && p.clip_mode != 1) return bad(QG_EINVAL, "clip_mode must be 0 or 1");
+  if (p.clip_mode == 1 && (p.nx < 64 || (p.precision == 64 && p.nx > 2048)))
+    return bad(QG_EUNSUPPORTED, "pointwise clipping (clip_mode 1) needs nx >= 64 (and nx <= 2048 in 64-bit runs)");
   if (p.closure >= 3) {
     const double r = p.test_ratio;
     if (!(r == 2.0 || r == 3.0 || r == 4.0)) return bad(QG_EUNSUPPORTED, "test_ratio must be 2, 3 or 4");
@@ -76,6 +77,7 @@ static int validate(const qg_params& p, int idx) {
 struct Group {
   int nx, ny, lognx, logny, closure;
   int scheme;                    // QG_SCHEME_*
+  int clip;                      // clip_mode of the dynamic closures
   bool dbl;
   int kxn, myh, kyn, W, logW, kxp, RP, logRP;
   int kxn_f, myh_f, kyn_f, kxp_f;
@@ -189,6 +191,12 @@ static void plan_sizes(Group& g, int adjK) {
   } else {
     L.adj_lam = L.adj_lacc = L.adj_lk = L.adj_store = -1;
   }
+  if (g.clip == 1) {
+    L.clip_h = take(spec);
+    L.clip_m = take(spec);
+  } else {
+    L.clip_h = L.clip_m = -1;
+  }
   if (adjK > 0 && dynamic_closure(cl)) {
     L.adj_hmq = take((long long)align256(spec) * 3 * 4 * adjK);   // H, M, Q of every stage of a segment
     L.adj_cs = take(3LL * 4 * adjK * 8);                          // C, <HM>, <M^2> of every stage
@@ -222,7 +230,7 @@ struct Handle {
 
 static bool same_group(const qg_params& a, const qg_params& b) {
   return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.closure == b.closure &&
-         a.scheme == b.scheme;
+         a.scheme == b.scheme && a.clip_mode == b.clip_mode;
 }
 
 // Everything qg_workspace_bytes and qg_init share: grouping, layout.
@@ -254,6 +262,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
       g.ny = params[i].ny;
       g.closure = params[i].closure;
       g.scheme = params[i].scheme;
+      g.clip = dynamic_closure(params[i].closure) ? params[i].clip_mode : 0;
       g.dbl = params[i].precision == 64;
       plan_sizes(g, adjK);
       h.groups.push_back(g);
@@ -389,6 +398,32 @@ static int run_exit(const Handle& h, const Group& g, long long o_in, void* dst, 
   return QG_OK;
 }
 
+// Pointwise clip (clip_mode 1): the dynamic column pass keeps the stage's
+// H and M spectra (clip_keep on its phase), this pass takes them to the grid
+// and sums max(H, 0) M and M^2 per row pair into dpart, and the coefficient
+// is formed from those sums (clip_sums on the combine's phase).
+static void clip_keep(const Group& g, Phase& P) {
+  if (g.clip != 1) return;
+  P.adj_dyn = 1;
+  P.o_h = g.L.clip_h;
+  P.o_m = g.L.clip_m;
+}
+static int run_clip_pass(const Handle& h, const Group& g, hipStream_t st) {
+  if (g.clip != 1) return QG_OK;
+  Phase P = base_phase(h, g);
+  P.nf = 2;
+  P.o_h = g.L.clip_h;
+  P.o_m = g.L.clip_m;
+  QG_LAUNCH(launch_colinv(g.dbl, OP_CLIPF, 0, P, g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_CLIPF, 0, P, g.count, st));
+  return QG_OK;
+}
+static void clip_sums(const Group& g, Phase& Q) {
+  if (g.clip != 1) return;
+  Q.o_part = g.L.dpart;
+  Q.nparts = g.ny / 2;
+}
+
 // Where the adjoint's segment recompute keeps a dynamic stage's H, M, Q
 // and (C, <HM>, <M^2>) (byte offsets in the member region).
 struct StageStore {
@@ -417,7 +452,10 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, con
       P.o_h = keep->h;
       P.o_m = keep->m;
     }
+    clip_keep(g, P);
     QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    int rc = run_clip_pass(h, g, st);
+    if (rc) return rc;
     Phase Q = base_phase(h, g);
     Q.stage = s;
     Q.o_in = g.L.x;
@@ -429,6 +467,7 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, con
       Q.adj_dyn = 1;
       Q.o_cs = keep->cs;
     }
+    clip_sums(g, Q);
     QG_LAUNCH(launch_combine(g.dbl, OP_RHS, Q, g.count, st));
   }
   return QG_OK;
@@ -475,9 +514,14 @@ static int run_ab2cn_step(const Handle& h, const Group& g, hipStream_t st) {
   } else {
     P.o_out = g.L.jsp;
     P.o_aux = g.L.qsp;
+    clip_keep(g, P);
     QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    int rc = run_clip_pass(h, g, st);
+    if (rc) return rc;
     P.o_in = g.L.x;
     P.o_in2 = g.L.wn;
+    P.adj_dyn = 0;
+    clip_sums(g, P);
     QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
   }
   // sponge: omega*, omega** -> omega^{t+1} on D -> wn
@@ -584,6 +628,7 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   const double delta = p.lx / p.nx;
   m.inv_delta = 1.0 / delta;
   m.closure = p.closure;
+  m.clip_mode = p.clip_mode;
   if (p.closure == 1) { m.coef_static = (p.c * delta) * (p.c * delta); m.dcoef_dc = 2.0 * p.c * delta * delta; }
   else if (p.closure == 2) { m.coef_static = std::pow(p.c * delta, 3); m.dcoef_dc = 3.0 * p.c * p.c * delta * delta * delta; }
   const int tr = (int)std::lround(p.test_ratio > 0 ? p.test_ratio : 2.0);
@@ -1053,8 +1098,13 @@ static int run_model_term(const Handle& h, const Group& g, long long o_in, long 
   } else {
     P.o_out = g.L.jsp;
     P.o_aux = g.L.qsp;
+    clip_keep(g, P);
     QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    int rc = run_clip_pass(h, g, st);
+    if (rc) return rc;
     P.o_in = o_out;
+    P.adj_dyn = 0;
+    clip_sums(g, P);
     QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
   }
   return QG_OK;
@@ -1155,7 +1205,11 @@ int qg_diag(qg_handle* H, const void* omega, double* out_dev, void* nu_e_out, vo
       QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
       P.o_out = g.L.jsp;
       P.o_aux = g.L.qsp;
+      clip_keep(g, P);
       QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+      rc = run_clip_pass(h, g, st);
+      if (rc) return rc;
+      clip_sums(g, P);
       QG_LAUNCH(launch_dyn_coef(P, g.count, 0, st));
     }
     Phase D = base_phase(h, g);
@@ -1181,6 +1235,8 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
   for (const auto& g : h.groups) {
     if (g.scheme != QG_SCHEME_RK4)
       return fail(QG_EUNSUPPORTED, "the adjoint covers the RK4 scheme only");
+    if (g.clip == 1)
+      return fail(QG_EUNSUPPORTED, "the adjoint covers the coefficient-level clip (clip_mode 0) only");
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // outside the graph: the caller's fields in, the dL/dc slots cleared

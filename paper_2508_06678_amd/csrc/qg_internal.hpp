@@ -24,7 +24,8 @@ enum Op : int {
   OP_ADJ_ENTRY = 10,// adjoint of the entry transform (spectral -> physical)
   OP_PEN = 11,      // AB2CN: D curl(chi u) of the total velocity
   OP_SPONGE = 12,   // AB2CN: omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
-  OP_GTERMS = 13    // SGS analysis: D FFT(J) + (1/eta) D curl(chi u) + sigma D FFT(chi_s omega)
+  OP_GTERMS = 13,   // SGS analysis: D FFT(J) + (1/eta) D curl(chi u) + sigma D FFT(chi_s omega)
+  OP_CLIPF = 14     // pointwise clip of the dynamic coefficient: sums of max(H, 0) M and M^2 on the grid
 };
 
 // RK stage code of the AB2CN update in the column-forward / combine passes
@@ -57,6 +58,7 @@ struct MemberDev {
   int test_r2;           // test_ratio^2
   int test_kx;           // columns m_x < test_kx hold the test-filtered modes
   int closure;
+  int clip_mode;         // 0: C = max(<HM>, 0)/<M^2>; 1: C = <max(H, 0) M>/<M^2>
 };
 
 // Byte offsets of the buffers inside every member region of a group
@@ -65,6 +67,7 @@ struct RegionLayout {
   long long wn, acc, x, jsp, qsp, chih, mf, mp, phys, part, coef, dpart;
   long long ab_pen, ab_hist, ab_wss;               // AB2CN: D curl(chi u), explicit terms, omega**
   long long adj_lam, adj_lacc, adj_lk, adj_store;  // adjoint buffers
+  long long clip_h, clip_m;                         // pointwise clip: the H and M spectra of the stage
   long long adj_hmq, adj_cs;                        // dynamic-closure adjoint: H, M, Q and (C, <HM>, <M^2>) per stage
   long long adj_a, adj_b, adj_e;                    // ... the cotangents of H and M, the coefficient's term
   long long total;
@@ -163,6 +166,7 @@ __host__ __device__ constexpr bool dynamic_closure(int cl) { return cl == 3 || c
 __host__ __device__ constexpr int rowp_nb(int op, int cl) {
   return op == OP_B ? 3
        : op == OP_GTERMS ? 5
+       : op == OP_CLIPF ? 2
        : (op == OP_PEN || op == OP_SPONGE) ? 2
        : op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4) + (cl == 0 ? 1 : 3)
        : ((cl == 1 || cl == 3) ? 6 : 4);
@@ -170,6 +174,7 @@ __host__ __device__ constexpr int rowp_nb(int op, int cl) {
 __host__ __device__ constexpr int rowp_np(int op, int cl) {
   return op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4)
        : op == OP_GTERMS ? 4
+       : op == OP_CLIPF ? 0
        : op == OP_PEN ? 2
        : (op == OP_B || op == OP_SPONGE || cl == 0) ? 1 : 3;
 }

@@ -239,6 +239,9 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     const bool first = rptr<double>(M, P.o_coef)[AB2CN_FLAG_SLOT] == 0.0;
     V x = gld(cptr<T>(M, (f == 0 || first) ? P.o_in : P.o_in2) + idx);
     return zero_mean ? cmake<V>(T(0), T(0)) : x;
+  } else if constexpr (OP == OP_CLIPF) {
+    // the stage's H (field 0) and M (field 1), mean modes included
+    return gld(cptr<T>(M, f == 0 ? P.o_h : P.o_m) + idx);
   } else if constexpr (OP == OP_GTERMS) {
     // fields u', v', omega_x, omega_y, omega
     V x = gld(cptr<T>(M, P.o_in) + idx);
@@ -1016,6 +1019,27 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
     }
   }
+  if constexpr (OP == OP_CLIPF) {
+    // sums of max(H, 0) M and M^2 over the two rows (group 0's points)
+    double hp = 0.0, mm = 0.0;
+    if (grp == 0) {
+#pragma unroll
+      for (int t = 0; t < EPT; ++t) {
+        const int q = j + t * ng;
+        const V h = buf[q + (q >> PADS)], m = buf[bstride + q + (q >> PADS)];
+        hp += fmax((double)h.x, 0.0) * (double)m.x + fmax((double)h.y, 0.0) * (double)m.y;
+        mm += (double)m.x * (double)m.x + (double)m.y * (double)m.y;
+      }
+    }
+    hp = block_sum(hp, red);
+    mm = block_sum(mm, red);
+    if (threadIdx.x == 0) {
+      double* d = rptr<double>(M, P.o_dpart) + 2 * item_slot;
+      d[0] = hp;
+      d[1] = mm;
+    }
+    return;
+  }
   // ---- product grp at this thread's points q = j + t ng
   V v[EPT];
   double dc = 0.0;
@@ -1687,7 +1711,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 // 64-lane wave sums and then the wave sums are added in a fixed order, so
 // every block of a launch forms the same C.  red: 2 doubles per wave.
 __device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, double* red, double& C,
-                                                double& hm_out, double& mm_out) {
+                                                double& hm_out, double& mm_out, int clip_mode = 0) {
   double hm = 0.0, mm = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) { hm += part[2 * i]; mm += part[2 * i + 1]; }
   for (int o = 32; o > 0; o >>= 1) { hm += __shfl_xor(hm, o, 64); mm += __shfl_xor(mm, o, 64); }
@@ -1699,7 +1723,8 @@ __device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, 
   for (int w = 0; w < nw; ++w) { hm += red[2 * w]; mm += red[2 * w + 1]; }
   hm_out = hm;
   mm_out = mm;
-  C = mm > 0.0 ? fmax(hm, 0.0) / mm : 0.0;
+  // clip_mode 1: the numerator is already clipped at every grid point
+  C = mm > 0.0 ? (clip_mode == 1 ? hm : fmax(hm, 0.0)) / mm : 0.0;
 }
 
 template <typename T>
@@ -1734,7 +1759,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
     }
   }
   double C, hm, mm;
-  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
+  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double* c = rptr<double>(M, P.o_coef);
     if (P.stage == SGS_STAGE) {
@@ -1940,7 +1965,7 @@ __global__ void k_dyn_coef(Phase P, int slot) {
   __shared__ double red[2];   // one 64-thread wave
   const MemberDev M = member_const(P, blockIdx.z);
   double C, hm, mm;
-  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm);
+  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
   if (threadIdx.x == 0) rptr<double>(M, P.o_coef)[slot] = C;
 }
 #endif
@@ -2093,7 +2118,7 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
 
 template <typename T, int OP, int CL>
 static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
-  if constexpr (OP == OP_PEN || OP == OP_SPONGE || OP == OP_GTERMS) {
+  if constexpr (OP == OP_PEN || OP == OP_SPONGE || OP == OP_GTERMS || OP == OP_CLIPF) {
     // field-parallel kernel only (the sizes it cannot take are refused before)
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) launch_rowp_t<T, OP, CL>(P, nmem, s);
     return;
@@ -2177,6 +2202,7 @@ template <typename T> void colinv_dispatch(int op, int cl, const Phase& P, int n
     case OP_MASKGRAD: launch_colinv_t<T, OP_MASKGRAD, 0>(P, n, s); break;
     case OP_SPONGE: launch_colinv_t<T, OP_SPONGE, 0>(P, n, s); break;
     case OP_GTERMS: launch_colinv_t<T, OP_GTERMS, 0>(P, n, s); break;
+    case OP_CLIPF: launch_colinv_t<T, OP_CLIPF, 0>(P, n, s); break;
     case OP_ADJ_B: launch_colinv_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_colinv_t, T, OP_ADJ_RHS, cl, P, n, s); break;
     default: break;
@@ -2193,6 +2219,7 @@ template <typename T> void row_dispatch(int op, int cl, const Phase& P, int n, h
     case OP_PEN: launch_row_t<T, OP_PEN, 0>(P, n, s); break;
     case OP_SPONGE: launch_row_t<T, OP_SPONGE, 0>(P, n, s); break;
     case OP_GTERMS: launch_row_t<T, OP_GTERMS, 0>(P, n, s); break;
+    case OP_CLIPF: launch_row_t<T, OP_CLIPF, 0>(P, n, s); break;
     case OP_MASKGRAD: launch_row_t<T, OP_MASKGRAD, 0>(P, n, s); break;
     case OP_ADJ_B: launch_row_t<T, OP_ADJ_B, 0>(P, n, s); break;
     case OP_ADJ_RHS: QG_CL_SWITCH_STATIC(launch_row_t, T, OP_ADJ_RHS, cl, P, n, s); break;

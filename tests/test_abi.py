@@ -59,6 +59,10 @@ def test_workspace_bytes_valid_and_monotone():
     assert rc == 0 and b3 > b1
     rc, b4 = ws([good(precision=32)])
     assert rc == 0 and b4 < b1
+    # the pointwise clip keeps the H and M spectra of a stage
+    rc, b5 = ws([good(closure="dsmag")])
+    rc6, b6 = ws([good(closure="dsmag", clip_mode=1)])
+    assert rc == 0 and rc6 == 0 and b6 > b5
 
 
 @pytest.mark.parametrize("bad,code", [
@@ -69,7 +73,8 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(dt=-1.0), _lib.QG_EINVAL),
     (dict(closure=7), _lib.QG_EINVAL),
     (dict(precision=16), _lib.QG_EINVAL),
-    (dict(clip_mode=1), _lib.QG_EUNSUPPORTED),
+    (dict(clip_mode=1, closure="dsmag", nx=32, ny=32, lx=2 * math.pi, ly=2 * math.pi), _lib.QG_EUNSUPPORTED),
+    (dict(clip_mode=1, closure="dleith", nx=4096, ny=2048), _lib.QG_EUNSUPPORTED),
     (dict(clip_mode=2), _lib.QG_EINVAL),
     (dict(closure="dsmag", test_ratio=2.5), _lib.QG_EUNSUPPORTED),
     (dict(eta=0.0), _lib.QG_EINVAL),
