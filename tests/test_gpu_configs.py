@@ -55,6 +55,34 @@ def test_config1_every_step_fp64():
     S.close()
 
 
+@pytest.mark.parametrize("case", ["C1", "island256_dsmag"])
+def test_fp32_after_100_steps(case):
+    """The FP32 path after 100 steps against the FP64 oracle's 100 steps from
+    the same start (graph replay, tuned widths): the per-step tolerance
+    accumulated over the run, 100 x 1e-5, bounds it (the 100 steps span
+    t = 0.2 and 0.05, far shorter than the flows' divergence times).  C1 at
+    its own size; the dynamic Smagorinsky island of C2 at 256x128."""
+    if case == "C1":
+        m = configs.config1().members[0]
+    else:
+        m = configs.config2(precision=64, nx=256, ny=128).members[0]
+    nx, ny = m.params["nx"], m.params["ny"]
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    S = solver_for([m], 32)
+    S.autotune()
+    om = S.pack([m.omega0])
+    w0 = to_np(om).reshape(ny, nx)
+    S.step(om, 100)
+    ref = w0
+    for k in range(10):
+        ref = qg.run(ref, M, 10)
+        say(case, "oracle step", 10 * (k + 1))
+    err = rel_l2(to_np(om).reshape(ny, nx), ref)
+    say(case, "FP32 after 100 steps, rel L2 against the FP64 oracle", err)
+    assert err < 100 * TOL[32]
+    S.close()
+
+
 @pytest.mark.parametrize("precision", [64, 32])
 def test_config2_island_dynamic_smagorinsky(precision):
     """512x256 dynamic Smagorinsky: steps at the start and after 150 GPU steps."""
