@@ -139,22 +139,29 @@ template <typename T> __device__ __forceinline__ Wave<T> wave(const MemberDev& M
   return w;
 }
 
-// test filter T: test_ratio^2 (ny^2 mx^2 + nx^2 my^2) <= min(Mx ny, My nx)^2
+// test filter T: test_ratio^2 (ny^2 mx^2 + nx^2 my^2) <= min(Mx ny, My nx)^2.
+// The integer test is evaluated in double precision: with nx, ny <= 4096,
+// |m| <= 2048 and test_ratio <= 4 every product is an integer of at most 2^51,
+// so each operation is exact (and full rate, where 64-bit integer
+// multiplies are not).
 __device__ __forceinline__ bool in_test(const MemberDev& M, int nx, int ny, int mx, int my) {
-  long long a = (long long)ny * ny * mx * mx + (long long)nx * nx * my * my;
-  return (long long)M.test_r2 * a <= M.test_lim;
+  const double fx = (double)ny * (double)mx, fy = (double)nx * (double)my;
+  return (double)M.test_r2 * (fx * fx + fy * fy) <= (double)M.test_lim;
 }
 
 // The same set, column by column: the largest |m_y| that passes in column
-// m_x (-1 if none), so that in_test(mx, my) == (|my| <= test_mylim(mx)).
+// m_x (-1 if none), so that in_test(mx, my) == (|my| <= test_mylim(mx));
+// exact double arithmetic as in in_test.
 __device__ __forceinline__ int test_mylim(const MemberDev& M, int nx, int ny, int mx) {
-  const long long a = (long long)M.test_r2 * ny * ny * mx * mx;
-  if (a > M.test_lim) return -1;
-  const long long den = (long long)M.test_r2 * nx * nx;
-  const long long rem = M.test_lim - a;
-  long long s = (long long)sqrt((double)rem / (double)den);
-  while (s > 0 && s * s * den > rem) --s;
-  while ((s + 1) * (s + 1) * den <= rem) ++s;
+  const double fx = (double)ny * (double)mx;
+  const double a = (double)M.test_r2 * (fx * fx);
+  const double lim = (double)M.test_lim;
+  if (a > lim) return -1;
+  const double den = (double)M.test_r2 * ((double)nx * (double)nx);
+  const double rem = lim - a;
+  double s = floor(sqrt(rem / den));
+  while (s > 0.0 && s * s * den > rem) s -= 1.0;
+  while ((s + 1.0) * (s + 1.0) * den <= rem) s += 1.0;
   return (int)s;
 }
 
@@ -325,7 +332,9 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     const int j = threadIdx.x & (NT - 1);
     const int mx = kx0 + w;
     V* buf = tile + w * STR;
-    const int mylim = dynamic_closure(CL) && mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
+    // the test set's extent in this column, for the test-filtered fields
+    // only (the grid-level fields ignore it)
+    const int mylim = dynamic_closure(CL) && f >= rhs_fields(CL) / 2 && mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
