@@ -620,6 +620,9 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   m.two_pi_lx = 2.0 * pi / p.lx;
   m.two_pi_ly = 2.0 * pi / p.ly;
   m.dt = p.dt;
+  m.dt2 = p.dt / 2.0;
+  m.dt3 = p.dt / 3.0;
+  m.dt6 = p.dt / 6.0;
   m.beta = p.beta;
   m.inv_re = (p.re > 0 && std::isfinite(p.re)) ? 1.0 / p.re : 0.0;
   m.mu = p.mu;

@@ -46,6 +46,7 @@ struct MemberDev {
   int user_index;        // position of the member in the caller's order
   double two_pi_lx, two_pi_ly;
   double dt, beta, inv_re, mu, u_in, v_in;
+  double dt2, dt3, dt6;   // dt/2, dt/3, dt/6 of the RK4 weights, formed on the host
   double coef_static;    // (c Delta)^2 or (c Delta)^3; 0 without closure
   double dcoef_dc;       // d coef / d c
   double r_test;         // (Delta~/Delta)^p for the dynamic closures

@@ -120,6 +120,17 @@ __device__ __forceinline__ int xcd_order(int b, int n) {
 // signed m_y of compact index iy
 __device__ __forceinline__ int my_of_iy(int iy, int myh, int kyn) { return iy <= myh ? iy : iy - kyn; }
 
+// q / kyn for 0 <= q < kxn kyn (below 2^23 at every admitted size): the
+// hardware reciprocal puts the quotient within 1e-3 of the truth, one exact
+// 24-bit correction step makes it the integer quotient.  (A 32-bit integer
+// division costs tens of instructions, several of them quarter rate.)
+__device__ __forceinline__ int div_kyn(int q, int kyn) {
+  int m = (int)((float)q * __builtin_amdgcn_rcpf((float)kyn));
+  if (__umul24((unsigned)(m + 1), (unsigned)kyn) <= (unsigned)q) ++m;
+  else if (__umul24((unsigned)m, (unsigned)kyn) > (unsigned)q) --m;
+  return m;
+}
+
 __device__ __forceinline__ float qrcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double qrcp(double x) { return 1.0 / x; }
 
@@ -1219,9 +1230,9 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) {
     const int q = threadIdx.x + i * blockDim.x;
-    const int w = q / P.kyn;
+    const int w = div_kyn(q, P.kyn);
     const int mx = (q < nmodes) ? kx0 + w : P.kxn;
-    own[i] = ((mx < P.kxn ? mx : P.kxn) << 16) | (q - w * P.kyn);
+    own[i] = ((mx < P.kxn ? mx : P.kxn) << 16) | (q - (int)__umul24((unsigned)w, (unsigned)P.kyn));
   }
 #define mxs_(i) (own[i] >> 16)
 #define iys_(i) (own[i] & 0xffff)
@@ -1307,16 +1318,16 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       if (mxs_(i) == 0 && my == 0) r = cmake<V>(T(0), T(0));
       const V w0 = wn[id];
       if (P.stage == 1) {
-        acc[id] = cadd(w0, cscale(r, T(dt / 6.0)));
-        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+        acc[id] = cadd(w0, cscale(r, T(M.dt6)));
+        xout[id] = cadd(w0, cscale(r, T(M.dt2)));
       } else if (P.stage == 2) {
-        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
-        xout[id] = cadd(w0, cscale(r, T(dt / 2.0)));
+        acc[id] = cadd(acc[id], cscale(r, T(M.dt3)));
+        xout[id] = cadd(w0, cscale(r, T(M.dt2)));
       } else if (P.stage == 3) {
-        acc[id] = cadd(acc[id], cscale(r, T(dt / 3.0)));
+        acc[id] = cadd(acc[id], cscale(r, T(M.dt3)));
         xout[id] = cadd(w0, cscale(r, T(dt)));
       } else {
-        xout[id] = cadd(acc[id], cscale(r, T(dt / 6.0)));
+        xout[id] = cadd(acc[id], cscale(r, T(M.dt6)));
       }
     }
   } else if constexpr (OP == OP_RHS) {
@@ -1407,7 +1418,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
     V* ls = cptr<T>(M, P.o_out);
     V* lw = cptr<T>(M, P.o_aux);
     V* lk = cptr<T>(M, P.o_in);
-    const T c6 = T(M.dt / 6.0);
+    const T c6 = T(M.dt6);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
@@ -1489,8 +1500,8 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
     V* lw = cptr<T>(M, P.o_aux);            // LW
     V* lk = cptr<T>(M, P.o_in2);
     const double dt = M.dt;
-    const double cs = P.stage == 4 ? dt / 3.0 : P.stage == 3 ? dt / 3.0 : dt / 6.0;
-    const double ds = P.stage == 4 ? dt : dt / 2.0;
+    const double cs = P.stage == 4 ? M.dt3 : P.stage == 3 ? M.dt3 : M.dt6;
+    const double ds = P.stage == 4 ? dt : M.dt2;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (!owned(i)) continue;
@@ -1571,8 +1582,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   // test filter of the dynamic closures: one column per block when W = 1
   const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   for (int q = threadIdx.x; q < nm; q += blockDim.x) {
-    const int w = one ? 0 : q / P.kyn;
-    const int iy = q - w * P.kyn;
+    const int w = one ? 0 : div_kyn(q, P.kyn);
+    const int iy = q - (int)__umul24((unsigned)w, (unsigned)P.kyn);
     const int mx = kx0 + w;
     if (mx >= P.kxn) continue;
     const int my = my_of_iy(iy, P.myh, P.kyn);
@@ -1604,7 +1615,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       const V l = csub(at(0, w, iy), cscale(lpsi, wv.inv_k2));
       gst(cptr<T>(M, P.o_out) + id, l);
       gst(cptr<T>(M, P.o_aux) + id, l);
-      gst(cptr<T>(M, P.o_in) + id, cscale(l, T(M.dt / 6.0)));
+      gst(cptr<T>(M, P.o_in) + id, cscale(l, T(M.dt6)));
     } else if constexpr (OP == OP_ADJ_RHS) {
       const Wave<T> wv = wave<T>(M, mx, my);
       V lpsi = csub(mul_ia(at(0, w, iy), wv.ky), mul_ia(at(1, w, iy), wv.kx));
@@ -1631,8 +1642,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       gst(lw + id, cadd(gld(lw + id), lx));
       if (P.stage > 1) {
         const double dt = M.dt;
-        const double cs = P.stage == 4 ? dt / 3.0 : P.stage == 3 ? dt / 3.0 : dt / 6.0;
-        const double ds = P.stage == 4 ? dt : dt / 2.0;
+        const double cs = P.stage == 4 ? M.dt3 : P.stage == 3 ? M.dt3 : M.dt6;
+        const double ds = P.stage == 4 ? dt : M.dt2;
         gst(lk + id, cadd(cscale(gld(cptr<T>(M, P.o_out) + id), T(cs)), cscale(lx, T(ds))));
       }
     } else if constexpr (!dyn) {
@@ -1671,16 +1682,16 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       V* xout = cptr<T>(M, P.o_in);
       const double dt = M.dt;
       if (P.stage == 1) {
-        gst(acc + id, cadd(w0, cscale(r, T(dt / 6.0))));
-        gst(xout + id, cadd(w0, cscale(r, T(dt / 2.0))));
+        gst(acc + id, cadd(w0, cscale(r, T(M.dt6))));
+        gst(xout + id, cadd(w0, cscale(r, T(M.dt2))));
       } else if (P.stage == 2) {
-        gst(acc + id, cadd(gld(acc + id), cscale(r, T(dt / 3.0))));
-        gst(xout + id, cadd(w0, cscale(r, T(dt / 2.0))));
+        gst(acc + id, cadd(gld(acc + id), cscale(r, T(M.dt3))));
+        gst(xout + id, cadd(w0, cscale(r, T(M.dt2))));
       } else if (P.stage == 3) {
-        gst(acc + id, cadd(gld(acc + id), cscale(r, T(dt / 3.0))));
+        gst(acc + id, cadd(gld(acc + id), cscale(r, T(M.dt3))));
         gst(xout + id, cadd(w0, cscale(r, T(dt))));
       } else {
-        gst(xout + id, cadd(gld(acc + id), cscale(r, T(dt / 6.0))));
+        gst(xout + id, cadd(gld(acc + id), cscale(r, T(M.dt6))));
       }
     } else {
       const Wave<T> wv = wave<T>(M, mx, my);
@@ -1753,8 +1764,8 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   // reduced, so that the two memory latencies overlap
   V r0 = cmake<V>(T(0), T(0)), qv = r0, w0 = r0, a = r0;
   if (in) {
-    mx = q / P.kyn;
-    my = my_of_iy(q - mx * P.kyn, P.myh, P.kyn);
+    mx = div_kyn(q, P.kyn);
+    my = my_of_iy(q - (int)__umul24((unsigned)mx, (unsigned)P.kyn), P.myh, P.kyn);
     if (rk) {
       const Wave<T> w = wave<T>(M, mx, my);
       const V x = gld(cptr<T>(M, P.stage == 1 ? P.o_in2 : P.o_in) + q);
@@ -1803,16 +1814,16 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   const double dt = M.dt;
   V* xout = cptr<T>(M, P.o_in);
   if (P.stage == 1) {
-    gst(acc + q, cadd(w0, cscale(r, T(dt / 6.0))));
-    gst(xout + q, cadd(w0, cscale(r, T(dt / 2.0))));
+    gst(acc + q, cadd(w0, cscale(r, T(M.dt6))));
+    gst(xout + q, cadd(w0, cscale(r, T(M.dt2))));
   } else if (P.stage == 2) {
-    gst(acc + q, cadd(a, cscale(r, T(dt / 3.0))));
-    gst(xout + q, cadd(w0, cscale(r, T(dt / 2.0))));
+    gst(acc + q, cadd(a, cscale(r, T(M.dt3))));
+    gst(xout + q, cadd(w0, cscale(r, T(M.dt2))));
   } else if (P.stage == 3) {
-    gst(acc + q, cadd(a, cscale(r, T(dt / 3.0))));
+    gst(acc + q, cadd(a, cscale(r, T(M.dt3))));
     gst(xout + q, cadd(w0, cscale(r, T(dt))));
   } else {
-    gst(xout + q, cadd(a, cscale(r, T(dt / 6.0))));
+    gst(xout + q, cadd(a, cscale(r, T(M.dt6))));
   }
 }
 
@@ -1989,8 +2000,8 @@ __global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0.0, z = 0.0;
   if (q < P.kxn * P.kyn) {
-    const int mx = q / P.kyn;
-    const int iy = q - mx * P.kyn;
+    const int mx = div_kyn(q, P.kyn);
+    const int iy = q - (int)__umul24((unsigned)mx, (unsigned)P.kyn);
     const int my = my_of_iy(iy, P.myh, P.kyn);
     const Wave<T> w = wave<T>(M, mx, my);
     const V x = cptr<T>(M, P.o_in)[q];
