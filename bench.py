@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,sgs,adjoint,cpu,phases")
+    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,clip,sgs,adjoint,cpu,phases")
     ap.add_argument("--tune-cache", default=None,
                     help="strip-width cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -316,6 +316,20 @@ def main():
         result["ab2cn"] = {"value": pts * ka / seca, "ms_per_step": seca / ka * 1e3, "steps": ka,
                            "workload": "as value, AB2CN + AB2 sponge, eta = 2.5 dt"}
         log(f"ab2cn 1024^2 dleith: {seca / ka * 1e3:.3f} ms/step")
+
+    # ---- the pointwise clip of the dynamic coefficient (clip_mode 1) on the
+    # same workload: one two-field inverse pass more per stage
+    if "clip" not in skip:
+        wc = configs.config3(precision=32)
+        for m in wc.members:
+            m.params["clip_mode"] = 1
+        S, om = make_solver(wc, 32)
+        kc = max(10, K // 2)
+        secc, _ = time_steps(S, om, kc, W, torch)
+        S.close()
+        result["clip_pointwise"] = {"value": pts * kc / secc, "ms_per_step": secc / kc * 1e3, "steps": kc,
+                                    "workload": "as value, C = <max(H,0) M>/<M^2> (clip_mode 1)"}
+        log(f"pointwise clip 1024^2 dleith: {secc / kc * 1e3:.3f} ms/step")
 
     # ---- a-priori SGS analysis: FR 1024^2 -> LES 512^2 (delta = 2), ideal
     # Pi_FF, the Dynamic Leith model term at the filtered field, their PCC
