@@ -2100,7 +2100,7 @@ template <typename T, int OP, int CL>
 static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(coli_grid(P), P.nf, nmem);
   const dim3 block(P.Wi * P.ny / COL_EPT);
-  if constexpr (OP == OP_RHS || OP == OP_B) {
+  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_CLIPF) {
     // compile-time column lengths for the common sizes
     const size_t lds = (size_t)P.Wi * colinv_stride(P.ny) * sizeof(cpx<T>);
     switch (P.logny) {
