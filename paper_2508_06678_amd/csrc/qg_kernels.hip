@@ -2100,8 +2100,9 @@ template <typename T, int OP, int CL>
 static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(coli_grid(P), P.nf, nmem);
   const dim3 block(P.Wi * P.ny / COL_EPT);
-  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_CLIPF) {
-    // compile-time column lengths for the common sizes
+  {
+    // compile-time column lengths for the common sizes (every op: the
+    // kernel's compile-time path is generic in the field formation)
     const size_t lds = (size_t)P.Wi * colinv_stride(P.ny) * sizeof(cpx<T>);
     switch (P.logny) {
       case 8: hipLaunchKernelGGL((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
@@ -2168,8 +2169,9 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(col_grid(P), 1, nmem);
   const size_t n = col_tile(P);
   const dim3 block(np * ((size_t)P.W * P.ny) / COL_EPT);
-  if constexpr (OP == OP_RHS || OP == OP_B) {
-    // compile-time column lengths for the common sizes (one column per block)
+  {
+    // compile-time column lengths for the common sizes (one column per
+    // block; every op, as for the column-inverse pass)
     const size_t lds = np * n * sizeof(cpx<T>);
     if (P.W == 1) switch (P.logny) {
       case 8: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P); return;
