@@ -6,6 +6,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2508_06678_amd import _lib
@@ -119,3 +120,17 @@ def test_init_rejects_small_or_missing_workspace():
     assert L.qg_init(arr, 1, dummy, dummy, None, 1 << 20, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
     assert L.qg_init(arr, 1, dummy, dummy, ctypes.c_void_p(4096), 16, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
     assert L.qg_init(arr, 1, dummy, dummy, ctypes.c_void_p(4097), 1 << 40, 0, None, ctypes.byref(h)) == _lib.QG_EWORKSPACE
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the product path raises: there is no
+    CPU fallback to take its place."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libqg.so"))
+    with pytest.raises(ImportError, match="missing"):
+        _lib.lib()
+    from paper_2508_06678_amd.solver import Solver
+    m = good()
+    chi = np.zeros((m["ny"], m["nx"]))
+    with pytest.raises(ImportError, match="missing"):
+        Solver([m], [chi], [chi], device="cpu")
