@@ -136,3 +136,28 @@ def test_every_column_width(closure, code, tmp_path):
         say("AB2CN", closure, "W", W, "worst rel L2 per step", worst)
         assert worst < 1e-5
         S.close()
+
+
+@pytest.mark.parametrize("closure,code", [("smag", 1), ("dleith", 4)])
+def test_compile_time_column_lengths(closure, code, tmp_path):
+    """Columns of 512 points at one column per strip (forced through the
+    tuning cache): AB2CN's penalization, right-hand-side and sponge passes
+    then run the compile-time-length column engines.  Three steps in
+    lockstep with the oracle, FP64."""
+    import json
+
+    import torch
+    m = configs.island_member(128, 512, precision=64, beta=1.0, re=1e3, dt=5e-4, eta=1.25e-3, xc=1.5,
+                              radius=0.5, closure=closure, seed=2, rms=0.2, lx=2 * np.pi, ly=8 * np.pi)
+    m.params["scheme"] = "ab2cn"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/128x512/fp64/closure{code}/members1"
+    path = tmp_path / "w1.json"
+    path.write_text(json.dumps({key + "/fwd": 1, key + "/inv": 1}))
+    S = solver_for([m], 64)
+    S.autotune(str(path))
+    assert S.column_widths() == [1] and S.inverse_widths() == [1]
+    worst = lockstep(S, m, 64, (512, 128), 3, use_graph=False)
+    say("AB2CN", closure, "compile-time columns, worst rel L2 per step", worst)
+    assert worst < 1e-12
+    S.close()

@@ -191,3 +191,37 @@ def test_dynamic_adjoint_fp32_vs_fp64(closure, seed):
     err = rel_l2(out[32], out[64])
     say("dynamic adjoint fp32 vs fp64", closure, err)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("closure,code", [("smag", 1), ("dleith", 4)])
+@pytest.mark.parametrize("nx,ny", [(128, 512), (64, 1024)])
+def test_adjoint_at_compile_time_column_lengths(closure, code, nx, ny, tmp_path):
+    """Columns of 512 and 1024 points at one column per strip (forced
+    through the tuning cache): the adjoint's column passes then run their
+    compile-time-length engines.  Two steps against the oracle's adjoint."""
+    import json
+    import torch
+    say("adjoint, compile-time columns", closure, nx, ny)
+    m = island(nx, ny, closure, seed=5)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/{nx}x{ny}/fp64/closure{code}/members1"
+    cache = tmp_path / "w1.json"
+    cache.write_text(json.dumps({key + "/fwd": 1, key + "/inv": 1}))
+    nsteps = 2
+    S = solver_for([m], 64, adj_segment_k=nsteps)
+    S.autotune(str(cache))
+    assert S.column_widths() == [1] and S.inverse_widths() == [1]
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    w0 = to_np(om).reshape(ny, nx)
+    lamT = np.random.default_rng(9).standard_normal((ny, nx))
+    lam = S.pack([lamT])
+    g = torch.zeros(1, dtype=torch.float64, device=om.device)
+    S.adjoint_step(om, lam, nsteps, g)
+    ref_l, ref_c = oadj.run_adjoint(w0, lamT, M, nsteps)
+    err = rel_l2(to_np(lam).reshape(ny, nx), ref_l)
+    say("  lambda rel", err, "dc", g.item(), ref_c)
+    assert err < 1e-11
+    if closure == "smag":
+        assert abs(g.item() - ref_c) <= 1e-10 * abs(ref_c)
+    S.close()
