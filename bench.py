@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ab2cn,clip,sgs,adjoint,cpu,phases")
+    ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ensemble,ab2cn,clip,sgs,adjoint,cpu,phases")
     ap.add_argument("--tune-cache", default=None,
                     help="strip-width cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -301,6 +301,25 @@ def main():
                              "step_roofline_frac": len(bw.members) * step_bytes / (secb / kb) / 1e9
                              / HBM_PEAK_GBS}
         log(f"batched 8x1024^2: {secb / kb * 1e3:.3f} ms/step, {ptsb * kb / secb:.4g} pt-steps/s")
+
+    # ---- the ragged FP32 ensemble of the batched workload: 64 members of
+    # three sizes (32 x 256x128, 24 x 512x256, 8 x 1024x512), closures drawn
+    # over all four, one graph
+    if "ensemble" not in skip:
+        we = configs.config4(precision=32)
+        S, om = make_solver(we, 32)
+        ke = max(10, K // 4)
+        sece, _ = time_steps(S, om, ke, W // 2 + 1, torch)
+        S.close()
+        ebytes = sum(algorithmic_bytes(m.params["nx"], m.params["ny"], 4, m.params["closure"])[1]
+                     for m in we.members)
+        result["ensemble_ragged"] = {
+            "value": we.points * ke / sece, "ms_per_step": sece / ke * 1e3, "steps": ke,
+            "members": len(we.members),
+            "step_roofline_frac": ebytes / (sece / ke) / 1e9 / HBM_PEAK_GBS,
+            "workload": "64 members: 32 x 256x128, 24 x 512x256, 8 x 1024x512, island or cape, "
+                        "closures drawn over the four, FP32"}
+        log(f"ragged ensemble (64 members): {sece / ke * 1e3:.3f} ms/step, {we.points * ke / sece:.4g} pt-steps/s")
 
     # ---- the paper's own scheme (AB2CN + AB2 sponge) on the same workload,
     # with eta = 2.5 dt (explicit penalization needs eta > dt)

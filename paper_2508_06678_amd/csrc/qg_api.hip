@@ -225,6 +225,11 @@ struct Handle {
   std::map<int, hipGraphExec_t> adj_graphs;  // adjoint segment length -> executable graph
   hipStream_t graph_stream = nullptr;      // capture/replay stream (the caller's may be the null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // one capture stream and join event per size group beyond the first: the
+  // groups' step chains become parallel branches of the graph
+  std::vector<hipStream_t> branch_streams;
+  std::vector<hipEvent_t> branch_events;
+  hipEvent_t ev_fork = nullptr;
   std::vector<MemberDev> table;            // host copy of the device member table
 };
 
@@ -556,12 +561,52 @@ static int run_steps_eager(const Handle& h, int n, hipStream_t st) {
   return QG_OK;
 }
 
+// The capture of nsteps steps of every group.  The groups share nothing
+// that a step writes (each has its own members' regions and tables), so
+// each group's chain of launches is captured on a stream of its own, forked
+// from st and joined back: the graph holds one branch per group, which the
+// runtime may run concurrently (small groups then fill the chip together).
+static int make_branches(Handle& h) {
+  const size_t ng = h.groups.size();
+  while (h.branch_streams.size() + 1 < ng) {
+    hipStream_t s;
+    hipEvent_t e;
+    QG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    h.branch_streams.push_back(s);
+    QG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h.branch_events.push_back(e);
+  }
+  if (ng > 1 && !h.ev_fork) QG_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
+  return QG_OK;
+}
+
+static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
+  const size_t ng = h.groups.size();
+  if (ng == 1) return run_steps_eager(h, nsteps, st);
+  QG_HIP(hipEventRecord(h.ev_fork, st));
+  for (size_t i = 1; i < ng; ++i) QG_HIP(hipStreamWaitEvent(h.branch_streams[i - 1], h.ev_fork, 0));
+  for (size_t i = 0; i < ng; ++i) {
+    hipStream_t bs = i == 0 ? st : h.branch_streams[i - 1];
+    for (int k = 0; k < nsteps; ++k) {
+      int rc = run_step(h, h.groups[i], bs);
+      if (rc) return rc;
+    }
+  }
+  for (size_t i = 1; i < ng; ++i) {
+    QG_HIP(hipEventRecord(h.branch_events[i - 1], h.branch_streams[i - 1]));
+    QG_HIP(hipStreamWaitEvent(st, h.branch_events[i - 1], 0));
+  }
+  return QG_OK;
+}
+
 static int get_graph(Handle& h, int nsteps, hipStream_t st, hipGraphExec_t* out) {
   auto it = h.graphs.find(nsteps);
   if (it != h.graphs.end()) { *out = it->second; return QG_OK; }
   hipGraph_t graph;
+  int rc = make_branches(h);
+  if (rc) return rc;
   QG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  int rc = run_steps_eager(h, nsteps, st);
+  rc = capture_steps(h, nsteps, st);
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc) { if (e == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
   if (e != hipSuccess) return fail(QG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -909,6 +954,12 @@ void qg_destroy(qg_handle* H) {
   }
   if (H->h.ev_in) (void)hipEventDestroy(H->h.ev_in);
   if (H->h.ev_out) (void)hipEventDestroy(H->h.ev_out);
+  for (auto s : H->h.branch_streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (auto e : H->h.branch_events) (void)hipEventDestroy(e);
+  if (H->h.ev_fork) (void)hipEventDestroy(H->h.ev_fork);
   delete H;
 }
 
