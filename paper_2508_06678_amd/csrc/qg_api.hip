@@ -580,23 +580,34 @@ static int make_branches(Handle& h) {
   return QG_OK;
 }
 
-static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
+// Inside a capture on st: work(g, stream) for every group, group 0 on st and
+// each further group on its branch stream (make_branches first).
+template <typename F>
+static int capture_branches(Handle& h, hipStream_t st, F work) {
   const size_t ng = h.groups.size();
-  if (ng == 1) return run_steps_eager(h, nsteps, st);
-  QG_HIP(hipEventRecord(h.ev_fork, st));
-  for (size_t i = 1; i < ng; ++i) QG_HIP(hipStreamWaitEvent(h.branch_streams[i - 1], h.ev_fork, 0));
+  if (ng > 1) {
+    QG_HIP(hipEventRecord(h.ev_fork, st));
+    for (size_t i = 1; i < ng; ++i) QG_HIP(hipStreamWaitEvent(h.branch_streams[i - 1], h.ev_fork, 0));
+  }
   for (size_t i = 0; i < ng; ++i) {
-    hipStream_t bs = i == 0 ? st : h.branch_streams[i - 1];
-    for (int k = 0; k < nsteps; ++k) {
-      int rc = run_step(h, h.groups[i], bs);
-      if (rc) return rc;
-    }
+    int rc = work(h.groups[i], i == 0 ? st : h.branch_streams[i - 1]);
+    if (rc) return rc;
   }
   for (size_t i = 1; i < ng; ++i) {
     QG_HIP(hipEventRecord(h.branch_events[i - 1], h.branch_streams[i - 1]));
     QG_HIP(hipStreamWaitEvent(st, h.branch_events[i - 1], 0));
   }
   return QG_OK;
+}
+
+static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
+  return capture_branches(h, st, [&](const Group& g, hipStream_t bs) {
+    for (int k = 0; k < nsteps; ++k) {
+      int rc = run_step(h, g, bs);
+      if (rc) return rc;
+    }
+    return (int)QG_OK;
+  });
 }
 
 static int get_graph(Handle& h, int nsteps, hipStream_t st, hipGraphExec_t* out) {
@@ -1314,12 +1325,11 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
     ex = it->second;
   } else {
     hipGraph_t graph;
+    int rc = make_branches(h);
+    if (rc) return rc;
     QG_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-    int rc = QG_OK;
-    for (const auto& g : h.groups) {
-      rc = adjoint_sweep(h, g, nsteps, gs);
-      if (rc) break;
-    }
+    // the groups' sweeps are independent: one graph branch each
+    rc = capture_branches(h, gs, [&](const Group& g, hipStream_t bs) { return adjoint_sweep(h, g, nsteps, bs); });
     hipError_t e = hipStreamEndCapture(gs, &graph);
     if (rc) { if (e == hipSuccess) (void)hipGraphDestroy(graph); return rc; }
     if (e != hipSuccess) return fail(QG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));

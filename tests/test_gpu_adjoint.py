@@ -225,3 +225,33 @@ def test_adjoint_at_compile_time_column_lengths(closure, code, nx, ny, tmp_path)
     if closure == "smag":
         assert abs(g.item() - ref_c) <= 1e-10 * abs(ref_c)
     S.close()
+
+
+def test_adjoint_of_several_size_groups():
+    """One handle with members of two sizes and three closures (three size
+    groups, one graph branch each): every member's lambda and dL/dc against
+    the oracle's adjoint of that member alone."""
+    import torch
+    ms = [island(128, 64, "smag", seed=4), island(64, 32, "leith", seed=5), island(128, 64, "smag", seed=6),
+          island(64, 32, "dleith", seed=8)]
+    nsteps = 2
+    S = solver_for(ms, 64, adj_segment_k=nsteps)
+    om = S.pack([m.omega0 for m in ms])
+    w0 = [to_np(x) for x in S.unpack(om)]
+    rng = np.random.default_rng(3)
+    lamT = [rng.standard_normal((m.params["ny"], m.params["nx"])) for m in ms]
+    lam = S.pack(lamT)
+    g = torch.zeros(len(ms), dtype=torch.float64, device=om.device)
+    S.adjoint_step(om, lam, nsteps, g)
+    got = [to_np(x) for x in S.unpack(lam)]
+    for i, m in enumerate(ms):
+        M = oracle_model(m.params, m.chi, m.chi_s)
+        ref_l, ref_c = oadj.run_adjoint(w0[i], lamT[i], M, nsteps)
+        err = rel_l2(got[i], ref_l)
+        say("  member", i, m.params["nx"], m.params["closure"], "lambda rel", err, "dc", g[i].item(), ref_c)
+        assert err < 1e-11
+        if m.params["closure"] in ("smag", "leith"):
+            assert abs(g[i].item() - ref_c) <= 1e-10 * abs(ref_c)
+        else:
+            assert g[i].item() == 0.0
+    S.close()
