@@ -144,7 +144,10 @@ int qg_init(const qg_params* params, int32_t n_members,
  * omega is written to ckpt_out (n_saves x all members, flat) after every
  * save_every steps, and the run continues from that written field, so a run
  * restarted from a checkpoint repeats the original bit for bit.
- * use_graph != 0 replays a captured hipGraph of the step sequence. */
+ * use_graph != 0 replays a captured hipGraph of the step sequence (captured
+ * on library-owned streams, one branch per size group so that the groups
+ * run concurrently; ordered after, and before, the caller's stream work by
+ * events). */
 int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
             void* ckpt_out, int32_t use_graph, void* hip_stream);
 
