@@ -1,4 +1,4 @@
-"""Host logic of the island set-up (Sec. IV-A) and of the a-priori driver:
+"""Host logic of the island set-up (Sec. IV-A) and of the a-priori analysis:
 the constants the paper states, the four-sided sponge ramp and the region
 of interest.  CPU only."""
 import math

@@ -193,9 +193,9 @@ def test_ideal_sgs_matches_oracle(precision, nx, ny, delta, closure, seeds):
     L.close()
 
 
-def test_a_priori_driver_matches_oracle():
+def test_a_priori_analysis_matches_oracle():
     """The island set-up at 128^2 (dt 1e-3): 20 AB2CN steps, snapshots every
-    10; the driver's PCCs (whole box and region of interest) at the last
+    10; the analysis routine's PCCs (whole box and region of interest) at the last
     snapshot against the oracle's pipeline -- AB2CN run, H_full of the
     masks, Pi_FF, model terms, PCC."""
     import torch
@@ -216,13 +216,13 @@ def test_a_priori_driver_matches_oracle():
         ref_pi, ref_wbar = oles.ideal_sgs(wT, Mf, Ml)
         ref_model = oles.model_sgs(ref_wbar, Ml)
         if not np.any(ref_model):      # the dynamic clip at C = 0
-            say("driver", c, "C = 0")
+            say("a priori", c, "C = 0")
             assert math.isnan(recs[-1][f"pcc_{c}"])
             continue
         ref = oles.pcc(ref_pi, ref_model)
         ref_roi = oles.pcc(ref_pi[roi], ref_model[roi])
         got, got_roi = recs[-1][f"pcc_{c}"], recs[-1][f"pcc_roi_{c}"]
-        say("driver", c, got, ref, got_roi, ref_roi)
+        say("a priori", c, got, ref, got_roi, ref_roi)
         assert abs(got - ref) < 1e-9
         assert abs(got_roi - ref_roi) < 1e-9
         # the advection commutator alone: the same pipeline without penalization and sponge
@@ -230,7 +230,7 @@ def test_a_priori_driver_matches_oracle():
         MfJ = oracle_model(pj, fr.chi, fr.chi_s)
         MlJ = oracle_model(experiments.les_params(pj, 2, c), chi_bar, chs_bar)
         ref_j = oles.pcc(oles.ideal_sgs(wT, MfJ, MlJ)[0], ref_model)
-        say("driver J only", c, recs[-1][f"pcc_J_{c}"], ref_j)
+        say("a priori, J only", c, recs[-1][f"pcc_J_{c}"], ref_j)
         assert abs(recs[-1][f"pcc_J_{c}"] - ref_j) < 1e-9
     assert summary["pcc_smag"]["mean_all"] == pytest.approx(np.mean([r["pcc_smag"] for r in recs]))
     torch.cuda.synchronize()
@@ -257,7 +257,7 @@ def test_closure_term_matches_oracle(closure):
     L.close()
 
 
-def test_a_posteriori_driver_matches_oracle():
+def test_a_posteriori_analysis_matches_oracle():
     """The island set-up at 128^2: FR dt 1e-3, LES 64^2 with dt 2e-3, a
     snapshot every 10 FR steps; PCC(omega_LES, omega_FF) and PCC(Pi_LES,
     Pi_FF) at the first snapshot against the oracle (AB2CN runs of both,
@@ -280,7 +280,7 @@ def test_a_posteriori_driver_matches_oracle():
         Ml = oracle_model(experiments.les_run_params(fr.params, 2, c, 2e-3), chi_bar, chs_bar)
         wl = ab2cn.run(oles.filter_to(w0, lx, lx, 2), Ml, 5)[0]
         ref = oles.pcc(wl, ff)
-        say("a posteriori driver", c, recs[0][f"pcc_w_{c}"], ref)
+        say("a posteriori", c, recs[0][f"pcc_w_{c}"], ref)
         assert abs(recs[0][f"pcc_w_{c}"] - ref) < 1e-9
         if c != "none":
             ref_sgs = oles.pcc(oles.model_sgs(wl, Ml), pi_ff)
