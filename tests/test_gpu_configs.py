@@ -117,13 +117,17 @@ def test_config3_cape_dynamic_leith_fp32():
 
 
 def test_config4_ensemble_one_launch_fp32():
-    """64 members of three sizes and four closures in one graph launch; the
-    oracle checks a sample of members (every fourth) one by one."""
+    """64 members of three sizes and four closures in one graph launch (one
+    branch per size group), run for the workload's 500 steps; every member
+    finite, and the oracle checks the last step of a sample of members
+    (every fourth) one by one."""
     wl = configs.config4(precision=32)
     S = solver_for(wl.members, 32)
     S.autotune()
     om = S.pack([m.omega0 for m in wl.members])
-    S.step(om, 20)
+    S.step(om, wl.nsteps - 1)
+    out, _ = S.diag(om)
+    assert not out.cpu().numpy()[:, 7].any()
     w_n = [to_np(x) for x in S.unpack(om)]
     S.step(om, 1)
     got = [to_np(x) for x in S.unpack(om)]
