@@ -85,14 +85,16 @@ def test_fp32_after_100_steps(case):
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_config2_island_dynamic_smagorinsky(precision):
-    """512x256 dynamic Smagorinsky: steps at the start and after 150 GPU steps."""
-    m = configs.config2(precision=precision).members[0]
+    """512x256 dynamic Smagorinsky: steps at the start and at the end of the
+    workload's 2000 steps."""
+    wl = configs.config2(precision=precision)
+    m = wl.members[0]
     S = solver_for([m], precision)
     S.autotune()
     M = oracle_model(m.params, m.chi, m.chi_s)
     om = S.pack([m.omega0])
     worst = per_step_check(S, M, om, (256, 512), precision, 2)
-    S.step(om, 150)
+    S.step(om, wl.nsteps - 4)
     worst = max(worst, per_step_check(S, M, om, (256, 512), precision, 2))
     say("C2", precision, "worst per-step rel L2", worst)
     assert worst < TOL[precision]
@@ -102,14 +104,16 @@ def test_config2_island_dynamic_smagorinsky(precision):
 
 
 def test_config3_cape_dynamic_leith_fp32():
-    """1024^2 dynamic Leith FP32: one step from the start and one after 100."""
-    m = configs.config3(precision=32).members[0]
+    """1024^2 dynamic Leith FP32: one step from the start and the last of the
+    workload's 1000 steps."""
+    wl = configs.config3(precision=32)
+    m = wl.members[0]
     S = solver_for([m], 32)
     S.autotune()
     M = oracle_model(m.params, m.chi, m.chi_s)
     om = S.pack([m.omega0])
     worst = per_step_check(S, M, om, (1024, 1024), 32, 1)
-    S.step(om, 100)
+    S.step(om, wl.nsteps - 2)
     worst = max(worst, per_step_check(S, M, om, (1024, 1024), 32, 1))
     say("C3 worst per-step rel L2", worst)
     assert worst < TOL[32]
