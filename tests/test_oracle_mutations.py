@@ -19,7 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def mutated(modname, old, new):
     path = os.path.join(ROOT, "oracle", modname + ".py")
-    src = open(path).read()
+    with open(path) as f:
+        src = f.read()
     assert src.count(old) >= 1, f"mutation anchor not found: {old!r}"
     src = src.replace(old, new, 1)
     mod = types.ModuleType(f"oracle.{modname}")
