@@ -951,6 +951,35 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
   }
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return cleanup(fail(QG_EHIP, std::string("init: ") + hipGetErrorString(e)));
+  // AB2CN's penalty D curl(chi u) is formed as D curl((chi - c) u) + c omega
+  // with c the mask's mean (an identity for any constant c, since the curl
+  // of the total velocity is omega): the transform then carries no large
+  // near-constant product whose rounding the curl would multiply by |k|.
+  // c from the zero mode of the mask's spectrum (the sum of its values).
+  bool ab2cn = false;
+  for (const auto& g : h.groups) ab2cn = ab2cn || g.scheme == QG_SCHEME_AB2CN;
+  if (ab2cn) {
+    for (const auto& g : h.groups) {
+      if (g.scheme != QG_SCHEME_AB2CN) continue;
+      for (int k = 0; k < g.count; ++k) {
+        const char* z0 = g.region0 + (long long)k * g.region_bytes + g.L.chih;
+        double re = 0.0;
+        if (g.dbl) {
+          e = hipMemcpy(&re, z0, sizeof(double), hipMemcpyDeviceToHost);
+        } else {
+          float rf = 0.f;
+          e = hipMemcpy(&rf, z0, sizeof(float), hipMemcpyDeviceToHost);
+          re = rf;
+        }
+        if (e != hipSuccess) return cleanup(fail(QG_EHIP, std::string("init: ") + hipGetErrorString(e)));
+        table[g.m0 + k].pen_c = re / ((double)g.nx * g.ny);
+      }
+    }
+    if (hipMemcpyAsync(h.mem_dev, table.data(), n * sizeof(MemberDev), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return cleanup(fail(QG_EHIP, "member table upload failed"));
+    h.table = table;
+  }
   *out = H;
   return QG_OK;
 }

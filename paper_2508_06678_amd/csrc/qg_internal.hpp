@@ -52,6 +52,7 @@ struct MemberDev {
   double r_test;         // (Delta~/Delta)^p for the dynamic closures
   double lowk2;          // |k|^2 bound of the double-precision Poisson inversion
   double pen_a;          // dt / eta (0 without obstacle)
+  double pen_c;          // AB2CN: the constant split off chi in the penalty's curl (the mask's mean)
   double sponge_a;       // dt * sigma
   double inv_n;          // 1 / (nx ny)
   double inv_delta;      // 1 / Delta = nx / lx

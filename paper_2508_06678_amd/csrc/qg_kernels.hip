@@ -877,12 +877,14 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     const T base = grp == 1 ? U : Vv;
     return cmake<V>(chi[a] * (base + vel.x), chi[b] * (base + vel.y));
   } else if constexpr (OP == OP_PEN) {
-    // chi times the total velocity: product 0 chi (U + u'), 1 chi (V + v')
+    // (chi - c) times the total velocity: product 0 (chi - c)(U + u'),
+    // 1 (chi - c)(V + v'); c is added back as c omega after the curl
     const long long a = (long long)ya * nx + q, b = a + nx;
     const T* chi = rptr<T>(M, P.o_phys) + 4LL * nx * P.ny;
+    const T c = T(M.pen_c);
     const V vel = F(grp);
     const T base = grp == 0 ? U : Vv;
-    return cmake<V>(chi[a] * (base + vel.x), chi[b] * (base + vel.y));
+    return cmake<V>((chi[a] - c) * (base + vel.x), (chi[b] - c) * (base + vel.y));
   } else if constexpr (OP == OP_SPONGE) {
     // omega^{t+1} = omega* - dt sigma chi_s (3/2 omega* - 1/2 omega**)
     const long long a = (long long)ya * nx + q, b = a + nx;
@@ -1593,9 +1595,11 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       if (OP != OP_MASKFWD && mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
       gst(cptr<T>(M, P.o_out) + id, v);
     } else if constexpr (OP == OP_PEN) {
-      // D curl(chi u) = i kx F(chi v) - i ky F(chi u)
+      // D curl(chi u) = i kx F((chi - c) v) - i ky F((chi - c) u) + c omega,
+      // omega the state the velocity came from (o_in)
       const Wave<T> wv = wave<T>(M, mx, my);
       V v = csub(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(0, w, iy), wv.ky));
+      v = cadd(v, cscale(gld(cptr<T>(M, P.o_in) + id), T(M.pen_c)));
       if (mx == 0 && my == 0) v = cmake<V>(T(0), T(0));
       gst(cptr<T>(M, P.o_out) + id, v);
     } else if constexpr (OP == OP_GTERMS) {
