@@ -83,7 +83,7 @@ def algorithmic_bytes(nx, ny, word, closure="dleith", test_ratio=2):
         "colfwd_rhs": P * nM + (2 * nD if dyn else 4 * nD),
         "combine_dyn": 7 * nD if dyn else 0,
         "colinv_b": nD + 3 * nM,
-        "row_b": 3 * nM + 4 * nx * ny * word + nM,
+        "row_b": 3 * nM + 3 * nx * ny * word + nM,
         "colfwd_b": nM + nD,
     }
     step = sum(per[k] * n for k, n in zip(PHASE_NAMES, PHASE_LAUNCHES))

@@ -16,7 +16,7 @@ enum Op : int {
   OP_ENTRY = 2,     // physical omega -> projected spectral state
   OP_EXIT = 3,      // spectral state -> physical omega
   OP_MASKFWD = 4,   // chi -> half spectrum (full set minus Nyquist lines)
-  OP_MASKGRAD = 5,  // spectral gradient of chi -> E, E_x, E_y, S tables
+  OP_MASKGRAD = 5,  // spectral gradient of chi -> S E, S E_x, S E_y tables
   OP_DIAG = 6,      // diagnostics at the state
   OP_ADJ_RHS = 7,   // adjoint of the right-hand side (static closures)
   OP_ADJ_B = 8,     // adjoint of the B sub-step

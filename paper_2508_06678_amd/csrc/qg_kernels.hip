@@ -14,7 +14,9 @@
 //                    column-forward passes read strips) and only the writes
 //                    are scattered (they do not stall the waves and merge in
 //                    L2, see the XCD-aware block order).
-//   physical tables  real [y][x]: E, E_x, E_y, S, chi, chi_sponge.
+//   physical tables  real [y][x]: S E, S E_x, S E_y (the B sub-step
+//                    with the sponge factor folded in), a spare slot, chi,
+//                    chi_sponge.
 //
 // Kernel kinds (Sec. II-C: derivatives in Fourier space, products by
 // collocation, 2/3 de-aliasing of every product):
@@ -670,23 +672,23 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
       }
     }
   } else if constexpr (OP == OP_B) {
-    // omega' = E omega + E_x v - E_y u (total velocity), omega'' = S omega'
+    // omega'' = S (E omega + E_x v - E_y u) (total velocity), with the
+    // tables S E, S E_x, S E_y
     V u[ROW_EPT], v[ROW_EPT], w[ROW_EPT];
     row_c2r<T>(C, mf + 0 * fstride, u);
     row_c2r<T>(C, mf + 1 * fstride, v);
     row_c2r<T>(C, mf + 2 * fstride, w);
-    const T* E = rptr<T>(M, P.o_phys);
-    const T* Ex = E + nxy;
-    const T* Ey = E + 2 * nxy;
-    const T* S = E + 3 * nxy;
+    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SEx = SE + nxy;
+    const T* SEy = SE + 2 * nxy;
     const T U = T(M.u_in), Vv = T(M.v_in);
 #pragma unroll
     for (int i = 0; i < ROW_EPT; ++i) {
       if (!valid(i)) continue;
       const long long a = phys_index(i), b = a + P.nx;
-      T w0 = E[a] * w[i].x + Ex[a] * (Vv + v[i].x) - Ey[a] * (U + u[i].x);
-      T w1 = E[b] * w[i].y + Ex[b] * (Vv + v[i].y) - Ey[b] * (U + u[i].y);
-      w[i] = cmake<V>(S[a] * w0, S[b] * w1);
+      const T w0 = SE[a] * w[i].x + SEx[a] * (Vv + v[i].x) - SEy[a] * (U + u[i].x);
+      const T w1 = SE[b] * w[i].y + SEx[b] * (Vv + v[i].y) - SEy[b] * (U + u[i].y);
+      w[i] = cmake<V>(w0, w1);
     }
     row_r2c<T>(C, w, mp);
   } else if constexpr (OP == OP_ENTRY || OP == OP_MASKFWD) {
@@ -728,30 +730,30 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
         const long long p = p0 + r * P.nx;
         const double gx = r ? (double)cx[i].y : (double)cx[i].x;
         const double gy = r ? (double)cy[i].y : (double)cy[i].x;
+        // the B sub-step's tables S E, S E_x, S E_y (one rounding each)
         const double e = exp(-a * (double)chi[p]);
-        E[p] = T(e);
-        E[p + nxy] = T(-a * gx * e);
-        E[p + 2 * nxy] = T(-a * gy * e);
-        E[p + 3 * nxy] = T(exp(-sa * (double)chs[p]));
+        const double sp = exp(-sa * (double)chs[p]);
+        E[p] = T(sp * e);
+        E[p + nxy] = T(sp * (-a * gx * e));
+        E[p + 2 * nxy] = T(sp * (-a * gy * e));
       }
     }
   } else if constexpr (OP == OP_ADJ_B) {
-    // lambda'' = c2r(lambda); lambda' = S lambda''; products:
-    // 0: E lambda' (omega), 1: -E_y lambda' (u), 2: E_x lambda' (v)
+    // lambda'' = c2r(lambda); products (the transposed tables S E, S E_x,
+    // S E_y): 0: S E lambda'' (omega), 1: -S E_y lambda'' (u), 2: S E_x lambda'' (v)
     V l[ROW_EPT], a0[ROW_EPT], a1[ROW_EPT];
     row_c2r<T>(C, mf, l);
-    const T* E = rptr<T>(M, P.o_phys);
-    const T* Ex = E + nxy;
-    const T* Ey = E + 2 * nxy;
-    const T* S = E + 3 * nxy;
+    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SEx = SE + nxy;
+    const T* SEy = SE + 2 * nxy;
 #pragma unroll
     for (int i = 0; i < ROW_EPT; ++i) {
       if (!valid(i)) { l[i] = a0[i] = a1[i] = cmake<V>(T(0), T(0)); continue; }
       const long long a = phys_index(i), b = a + P.nx;
-      T s0 = S[a] * l[i].x, s1 = S[b] * l[i].y;
-      l[i] = cmake<V>(E[a] * s0, E[b] * s1);
-      a0[i] = cmake<V>(-Ey[a] * s0, -Ey[b] * s1);
-      a1[i] = cmake<V>(Ex[a] * s0, Ex[b] * s1);
+      const T s0 = l[i].x, s1 = l[i].y;
+      l[i] = cmake<V>(SE[a] * s0, SE[b] * s1);
+      a0[i] = cmake<V>(-SEy[a] * s0, -SEy[b] * s1);
+      a1[i] = cmake<V>(SEx[a] * s0, SEx[b] * s1);
     }
     row_r2c<T>(C, l, mp);
     row_r2c<T>(C, a0, mp + pstride);
@@ -895,14 +897,15 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     const T r1 = ws.y - sa * chs[b] * (T(1.5) * ws.y - T(0.5) * wss.y);
     return cmake<V>(r0, r1);
   } else if constexpr (OP == OP_B) {
-    // omega'' = S (E omega + E_x v - E_y u), total velocity
+    // omega'' = S (E omega + E_x v - E_y u), total velocity, from the
+    // tables S E, S E_x, S E_y
     const long long nxy = (long long)nx * P.ny;
-    const T* E = rptr<T>(M, P.o_phys);
+    const T* SE = rptr<T>(M, P.o_phys);
     const V u = F(0), vv = F(1), w = F(2);
     const long long a = (long long)ya * nx + q, b = a + nx;
-    const T w0 = E[a] * w.x + E[nxy + a] * (Vv + vv.x) - E[2 * nxy + a] * (U + u.x);
-    const T w1 = E[b] * w.y + E[nxy + b] * (Vv + vv.y) - E[2 * nxy + b] * (U + u.y);
-    return cmake<V>(E[3 * nxy + a] * w0, E[3 * nxy + b] * w1);
+    const T w0 = SE[a] * w.x + SE[nxy + a] * (Vv + vv.x) - SE[2 * nxy + a] * (U + u.x);
+    const T w1 = SE[b] * w.y + SE[nxy + b] * (Vv + vv.y) - SE[2 * nxy + b] * (U + u.y);
+    return cmake<V>(w0, w1);
   } else if constexpr (OP == OP_RHS) {
     const V wx = F(2), wy = F(3);
     if (grp == 0) {
