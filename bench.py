@@ -9,14 +9,18 @@ adjoint/forward time ratio of the differentiable island run (512x256,
 static Smagorinsky, one 50-step checkpoint segment).
 
 Inputs are synthetic and seeded (masks, sponge ramps, k^-3 random-phase
-initial vorticity) and resident in HBM before timing.  Steps are timed with
-HIP events on the launch stream between synchronisations.  The roofline
-entry is for the kernel with the largest share of the step, timed live
-with HIP events on its stream; its bytes are the algorithmic bytes of one
-launch (what the method must move: mixed-layout fields at the 2/3-pruned
-width and the state on the 2/3 set).  ``cpu_baseline`` is the FP64 NumPy
-oracle (the correctness reference, not a tuned CPU code) on one step of the
-same 1024^2 workload, on the host.
+initial vorticity) and resident in HBM before timing.  Every leg is timed
+with HIP events on the launch stream between synchronisations, as the
+median of five windows of graph replays.  The roofline entry is for the
+kernel with the largest share of the step: its average launch duration
+comes from HIP events bound to each of its dispatches (begin and end of the
+dispatch itself) over a run of eager steps of the same workload, and its
+bytes are the algorithmic bytes of one launch (mixed-layout fields at the
+2/3-pruned width and the state on the 2/3 set).  ``cpu_baseline`` is the
+FP64 NumPy oracle (the correctness reference, not a tuned CPU code) on a few
+steps of the same 1024^2 workload on one host thread; the oracle at the
+other workloads' sizes and the 64-member ensemble over a process pool are
+reported beside it.  The host legs run before the GPU is touched.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -90,37 +94,49 @@ def algorithmic_bytes(nx, ny, word, closure="dleith", test_ratio=2):
     return per, step
 
 
-def time_steps(S, om, steps, warmup, torch):
+WINDOWS = 5
+
+
+def time_steps(S, om, steps, warmup, torch, windows=WINDOWS):
+    """Median over `windows` windows of `steps` graph-replayed steps, HIP
+    events on the launch stream (the torch current stream); returns seconds
+    per window and the wall clock of all windows."""
     S.step(om, warmup, use_graph=True)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    times = []
     t0 = time.perf_counter()
-    e0.record(stream)
-    S.step(om, steps, use_graph=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
-
-
-def time_phases(S, torch, reps=20):
-    """Average duration of each kernel of the step, HIP events on the stream
-    the kernels are launched on (the torch current stream)."""
-    stream = torch.cuda.current_stream()
-    out = {}
-    for ph, name in enumerate(PHASE_NAMES):
-        S.run_phase(ph, stage=2, reps=2)
-        torch.cuda.synchronize()
+    for _ in range(windows):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        S.run_phase(ph, stage=2, reps=reps)
+        S.step(om, steps, use_graph=True)
         e1.record(stream)
         torch.cuda.synchronize()
-        out[name] = e0.elapsed_time(e1) / reps
+        times.append(e0.elapsed_time(e1) / 1e3)
+    wall = time.perf_counter() - t0
+    return float(np.median(times)), wall
+
+
+def time_kernels(S, om, nsteps, kinds=range(len(PHASE_NAMES))):
+    """Average dispatch duration (ms) of each kind of step kernel: HIP events
+    bound to every dispatch of that kind over `nsteps` eager steps
+    (qg_profile_steps), on the launch stream."""
+    out = {}
+    for k in kinds:
+        ms = S.profile_steps(om, nsteps, k)
+        out[PHASE_NAMES[k]] = (float(np.mean(ms)) if ms else 0.0, len(ms))
     return out
+
+
+def survey_bytes_per_point(closure, word):
+    """The scope table's byte model: per grid-point-step 4 [2/3 2 (F + P) + 4/3
+    (RK state) + 16/9 (dynamic split)] + 10 words (B sub-step), F inverse
+    fields and P forward products per right-hand side at full width."""
+    F = {"none": 4, "smag": 6, "leith": 4, "dsmag": 12, "dleith": 8}[closure]
+    P = {"none": 1, "smag": 3, "leith": 3, "dsmag": 6, "dleith": 6}[closure]
+    dyn = 16.0 / 9.0 if closure in ("dsmag", "dleith") else 0.0
+    return (4 * (2.0 / 3.0 * 2 * (F + P) + 4.0 / 3.0 + dyn) + 10) * word
 
 
 TUNE_CACHE = None
@@ -176,22 +192,91 @@ def make_solver(workload, precision, adj=0, tune=True):
     return S, om
 
 
-def cpu_baseline(workload, nsteps):
+def _oracle_model(m):
     from oracle import qg
-    m = workload.members[0]
     p = {k: v for k, v in m.params.items() if k in qg.Params.__dataclass_fields__}
-    M = qg.Model(qg.Params(**p), m.chi, m.chi_s)
-    w = m.omega0
-    qg.step(w, M)  # warm-up (first-touch of the tables)
-    t0 = time.perf_counter()
+    return qg.Model(qg.Params(**p), m.chi, m.chi_s)
+
+
+def oracle_rate(member, nsteps):
+    """Oracle grid-point-steps/s of one member on this thread: median of
+    nsteps single steps after one warm-up step (first touch of the tables)."""
+    from oracle import qg
+    M = _oracle_model(member)
+    w = qg.step(member.omega0, M)
+    times = []
     for _ in range(nsteps):
+        t0 = time.perf_counter()
         w = qg.step(w, M)
-    dt = time.perf_counter() - t0
-    pts = m.params["nx"] * m.params["ny"]
-    return {"value": pts * nsteps / dt, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} step(s) of the {m.params['nx']}x{m.params['ny']} cape workload, "
-                      f"FP64 NumPy oracle with its own radix-2 FFT on 1 host thread "
-                      f"({os.cpu_count()} cores on the host), {dt:.1f} s"}
+        times.append(time.perf_counter() - t0)
+    pts = member.params["nx"] * member.params["ny"]
+    return pts / float(np.median(times)), float(np.sum(times))
+
+
+_POOL_MEMBERS = None
+
+
+def _pool_init():
+    global _POOL_MEMBERS
+    from paper_2508_06678_amd import configs
+    _POOL_MEMBERS = configs.config4(precision=64).members
+
+
+def _pool_member_step(i):
+    from oracle import qg
+    m = _POOL_MEMBERS[i]
+    return qg.step(m.omega0, _oracle_model(m)).shape
+
+
+def cpu_baseline(args):
+    """The oracle on the host: the 1024^2 workload of `value` (one thread,
+    the line's cpu_baseline), the single-member workloads C1 and C2 and the
+    64-member ensemble, one step of every member over a process pool on the
+    host's cores.  Runs before anything touches the GPU (the pool forks)."""
+    import multiprocessing as mp
+    from paper_2508_06678_amd import configs
+    c3 = configs.config3(precision=64).members[0]
+    v3, t3 = oracle_rate(c3, args.cpu_steps)
+    base = {"value": v3, "unit": "grid-pt-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"median of {args.cpu_steps} single steps (after one warm-up step) of the 1024x1024 cape "
+                      f"workload, FP64 NumPy oracle with its own radix-2 FFT on 1 host thread "
+                      f"({os.cpu_count()} cores on the host), {t3:.1f} s"}
+    extra = {}
+    for name, m in (("C1 128x64 island, static Smagorinsky", configs.config1().members[0]),
+                    ("C2 512x256 island, dynamic Smagorinsky", configs.config2(precision=64).members[0])):
+        v, t = oracle_rate(m, 3)
+        extra[name] = {"value": v, "unit": "grid-pt-steps/s", "cores": 1, "seconds": t}
+    n = len(configs.config4(precision=64).members)
+    cores = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_pool_init) as pool:
+        pool.map(_pool_member_step, range(cores))         # workers started, modules imported
+        t0 = time.perf_counter()
+        pool.map(_pool_member_step, range(n))
+        tp = time.perf_counter() - t0
+    pts = configs.config4(precision=64).points
+    extra["C4 64-member ensemble, one step of every member, process pool"] = {
+        "value": pts / tp, "unit": "grid-pt-steps/s", "cores": cores, "seconds": tp}
+    base["other_workloads"] = extra
+    return base
+
+
+def roofline_of(S, om, nx, ny, closure, nsteps, names, members=1):
+    """Dominant kernel by time share over nsteps eager steps, its average
+    dispatch duration from events bound to its dispatches, and its
+    algorithmic bytes per launch (all members of the launch)."""
+    per, _ = algorithmic_bytes(nx, ny, 4, closure)
+    kt = time_kernels(S, om, nsteps)
+    share = {k: kt[k][0] * PHASE_LAUNCHES[i] for i, k in enumerate(PHASE_NAMES)}
+    dom = max(PHASE_NAMES, key=lambda k: share[k])
+    avg_ms, nl = kt[dom]
+    b = per[dom] * members
+    ach = b / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(names[dom]) if members == 1 else None,
+            "kernel": names[dom], "bytes_per_launch": b, "avg_launch_us": avg_ms * 1e3,
+            "launches_timed": nl,
+            "timing": f"HIP events bound to each dispatch (begin, end), {nsteps} eager steps"}, kt, per
 
 
 def main():
@@ -200,9 +285,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--prof-steps", type=int, default=20,
+                    help="eager steps whose kernel dispatches are timed for the roofline entry")
     ap.add_argument("--skip", default="", help="comma list of: fp64,batched,ensemble,ab2cn,clip,sgs,adjoint,cpu,phases")
     ap.add_argument("--tune-cache", default=None,
-                    help="strip-width cache file: read if it holds the workload, else written after tuning")
+                    help="tuning cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -215,6 +302,11 @@ def main():
     skip = set(s for s in args.skip.split(",") if s)
     global TUNE_CACHE
     TUNE_CACHE = args.tune_cache
+    cpu = None
+    if "cpu" not in skip:
+        cpu = cpu_baseline(args)
+        log(f"cpu oracle: {cpu['value']:.4g} pt-steps/s (1 thread, 1024^2); "
+            + "; ".join(f"{k}: {v['value']:.4g} on {v['cores']}" for k, v in cpu["other_workloads"].items()))
     import torch
     from paper_2508_06678_amd import configs
 
@@ -230,22 +322,24 @@ def main():
     wl = configs.config3(precision=32)
     nx, ny = wl.members[0].params["nx"], wl.members[0].params["ny"]
     pts = nx * ny
+    bpp32 = survey_bytes_per_point("dleith", 4)
 
     # ---- FP32, one 1024^2 member (value)
     S, om = make_solver(wl, 32)
     names = kernel_names(nx, ny, S.column_widths()[0])
     sec, wall = time_steps(S, om, K, W, torch)
     value = pts * K / sec
-    log(f"fp32 1024^2 dleith: {sec / K * 1e3:.3f} ms/step, {value:.4g} pt-steps/s (wall {wall:.3f} s)")
+    log(f"fp32 1024^2 dleith: {sec / K * 1e3:.4f} ms/step (median of {WINDOWS} windows of {K}), "
+        f"{value:.4g} pt-steps/s (wall {wall:.3f} s)")
     per, step_bytes = algorithmic_bytes(nx, ny, 4, "dleith")
-    phases = None
+    roof = kt = None
     if "phases" not in skip:
-        phases = time_phases(S, torch)
-        for name in PHASE_NAMES:
-            share = phases[name] * PHASE_LAUNCHES[PHASE_NAMES.index(name)]
-            gbs = per[name] / (phases[name] * 1e-3) / 1e9 if phases[name] > 0 else 0.0
-            log(f"  {name:12s} {phases[name] * 1e3:8.1f} us/launch x{PHASE_LAUNCHES[PHASE_NAMES.index(name)]}"
-                f"  {share * 1e3:8.1f} us/step  {gbs:7.0f} GB/s algorithmic")
+        roof, kt, per = roofline_of(S, om, nx, ny, "dleith", args.prof_steps, names)
+        for i, name in enumerate(PHASE_NAMES):
+            avg, nl = kt[name]
+            gbs = per[name] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+            log(f"  {name:12s} {avg * 1e3:8.2f} us/dispatch x{PHASE_LAUNCHES[i]}  {avg * PHASE_LAUNCHES[i] * 1e3:8.1f}"
+                f" us/step  {gbs:7.0f} GB/s algorithmic  ({nl} dispatches timed)")
     S.close()
     step_gbs = step_bytes / (sec / K) / 1e9
 
@@ -265,17 +359,14 @@ def main():
         "config": {"workload": "coast with Gaussian cape, 1024x1024, 2pi x 2pi, dynamic Leith, "
                                "beta=5, Re=2e4, U=1, eta=1e-4, RK4 dt=2.5e-4, FP32",
                    "grid": [ny, nx], "members": 1, "parallelism": "single GPU"},
+        "timing": f"median of {WINDOWS} windows of K graph-replayed steps, HIP events on the launch stream",
         "step_algorithmic_GBps": step_gbs,
         "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
+        "step_roofline_frac_388B": bpp32 * pts / (sec / K) / 1e9 / HBM_PEAK_GBS,
     }
-    if phases:
-        dom = max(PHASE_NAMES, key=lambda n: phases[n] * PHASE_LAUNCHES[PHASE_NAMES.index(n)])
-        ach = per[dom] / (phases[dom] * 1e-3) / 1e9
-        result["roofline"] = {"bound": "hbm", "kernel": names[dom], "achieved": ach,
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                              "traffic": measured_traffic(names[dom]), "bytes_per_launch": per[dom],
-                              "avg_launch_us": phases[dom] * 1e3}
-        result["kernels_us_per_launch"] = {k: v * 1e3 for k, v in phases.items()}
+    if roof:
+        result["roofline"] = roof
+        result["kernels_us_per_dispatch"] = {k: v[0] * 1e3 for k, v in kt.items()}
 
     # ---- FP64, one member
     if "fp64" not in skip:
@@ -285,8 +376,10 @@ def main():
         S.close()
         _, b64 = algorithmic_bytes(nx, ny, 8, "dleith")
         result["fp64"] = {"value": pts * k64 / sec64, "ms_per_step": sec64 / k64 * 1e3, "steps": k64,
-                          "step_roofline_frac": b64 / (sec64 / k64) / 1e9 / HBM_PEAK_GBS}
-        log(f"fp64 1024^2 dleith: {sec64 / k64 * 1e3:.3f} ms/step")
+                          "step_roofline_frac": b64 / (sec64 / k64) / 1e9 / HBM_PEAK_GBS,
+                          "step_roofline_frac_777B": survey_bytes_per_point("dleith", 8) * pts / (sec64 / k64)
+                          / 1e9 / HBM_PEAK_GBS}
+        log(f"fp64 1024^2 dleith: {sec64 / k64 * 1e3:.4f} ms/step")
 
     # ---- FP32 batched: 8 x 1024^2 in one graph
     if "batched" not in skip:
@@ -294,13 +387,19 @@ def main():
         S, om = make_solver(bw, 32)
         kb = max(10, K // 4)
         secb, _ = time_steps(S, om, kb, W // 2 + 1, torch)
-        S.close()
+        nb = len(bw.members)
         ptsb = bw.points
         result["batched"] = {"value": ptsb * kb / secb, "ms_per_step": secb / kb * 1e3, "steps": kb,
-                             "members": len(bw.members),
-                             "step_roofline_frac": len(bw.members) * step_bytes / (secb / kb) / 1e9
-                             / HBM_PEAK_GBS}
-        log(f"batched 8x1024^2: {secb / kb * 1e3:.3f} ms/step, {ptsb * kb / secb:.4g} pt-steps/s")
+                             "members": nb,
+                             "step_roofline_frac": nb * step_bytes / (secb / kb) / 1e9 / HBM_PEAK_GBS,
+                             "step_roofline_frac_388B": bpp32 * ptsb / (secb / kb) / 1e9 / HBM_PEAK_GBS}
+        if "phases" not in skip:
+            bnames = kernel_names(nx, ny, S.column_widths()[0])
+            broof, bkt, _ = roofline_of(S, om, nx, ny, "dleith", max(5, args.prof_steps // 4), bnames, members=nb)
+            result["batched"]["roofline_dominant"] = broof
+            result["batched"]["kernels_us_per_dispatch"] = {k: v[0] * 1e3 for k, v in bkt.items()}
+        S.close()
+        log(f"batched 8x1024^2: {secb / kb * 1e3:.4f} ms/step, {ptsb * kb / secb:.4g} pt-steps/s")
 
     # ---- the ragged FP32 ensemble of the batched workload: 64 members of
     # three sizes (32 x 256x128, 24 x 512x256, 8 x 1024x512), closures drawn
@@ -319,7 +418,7 @@ def main():
             "step_roofline_frac": ebytes / (sece / ke) / 1e9 / HBM_PEAK_GBS,
             "workload": "64 members: 32 x 256x128, 24 x 512x256, 8 x 1024x512, island or cape, "
                         "closures drawn over the four, FP32"}
-        log(f"ragged ensemble (64 members): {sece / ke * 1e3:.3f} ms/step, {we.points * ke / sece:.4g} pt-steps/s")
+        log(f"ragged ensemble (64 members): {sece / ke * 1e3:.4f} ms/step, {we.points * ke / sece:.4g} pt-steps/s")
 
     # ---- the paper's own scheme (AB2CN + AB2 sponge) on the same workload,
     # with eta = 2.5 dt (explicit penalization needs eta > dt)
@@ -334,7 +433,7 @@ def main():
         S.close()
         result["ab2cn"] = {"value": pts * ka / seca, "ms_per_step": seca / ka * 1e3, "steps": ka,
                            "workload": "as value, AB2CN + AB2 sponge, eta = 2.5 dt"}
-        log(f"ab2cn 1024^2 dleith: {seca / ka * 1e3:.3f} ms/step")
+        log(f"ab2cn 1024^2 dleith: {seca / ka * 1e3:.4f} ms/step")
 
     # ---- the pointwise clip of the dynamic coefficient (clip_mode 1) on the
     # same workload: one two-field inverse pass more per stage
@@ -348,7 +447,7 @@ def main():
         S.close()
         result["clip_pointwise"] = {"value": pts * kc / secc, "ms_per_step": secc / kc * 1e3, "steps": kc,
                                     "workload": "as value, C = <max(H,0) M>/<M^2> (clip_mode 1)"}
-        log(f"pointwise clip 1024^2 dleith: {secc / kc * 1e3:.3f} ms/step")
+        log(f"pointwise clip 1024^2 dleith: {secc / kc * 1e3:.4f} ms/step")
 
     # ---- a-priori SGS analysis: FR 1024^2 -> LES 512^2 (delta = 2), ideal
     # Pi_FF, the Dynamic Leith model term at the filtered field, their PCC
@@ -361,12 +460,19 @@ def main():
             F.ideal_sgs(L, omf)
         torch.cuda.synchronize()
         ks = max(10, K // 4)
-        t0 = time.perf_counter()
-        for _ in range(ks):
-            pi, model, _ = F.ideal_sgs(L, omf)
-            pcc = L.pcc(pi, model)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
+        stream = torch.cuda.current_stream()
+        times = []
+        for _ in range(WINDOWS):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(ks):
+                pi, model, _ = F.ideal_sgs(L, omf)
+                pcc = L.pcc(pi, model)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        secs = float(np.median(times))
         F.close()
         L.close()
         result["sgs"] = {"value": pts * ks / secs, "unit": "FR grid-pts/s", "ms_per_analysis": secs / ks * 1e3,
@@ -375,7 +481,9 @@ def main():
                                      "LES 512^2 (delta 2), FP32; LES masks sampled on the LES grid"}
         log(f"sgs analysis 1024^2 -> 512^2: {secs / ks * 1e3:.3f} ms per analysis")
 
-    # ---- adjoint / forward on the differentiable island run
+    # ---- adjoint / forward on the differentiable island run: one segment of
+    # `seg` steps (recompute + reverse sweep) against `seg` forward steps,
+    # both graph replays, median of five each
     if "adjoint" not in skip:
         w5 = configs.config5(precision=64)
         seg = w5.meta["ckpt_every"]
@@ -383,31 +491,33 @@ def main():
         for m in w5d.members:   # the same run with the dynamic Leith closure
             m.params["closure"] = "dleith"
         ratios = {}
-        for prec, wl, tag in ((64, w5, ""), (32, w5, ""), (64, w5d, "_dleith")):
-            S, om = make_solver(wl, prec, adj=seg)
+        stream = torch.cuda.current_stream()
+        for prec, wl5, tag in ((64, w5, ""), (32, w5, ""), (64, w5d, "_dleith")):
+            S, om = make_solver(wl5, prec, adj=seg)
             w0 = om.clone()
-            S.step(om, 5, use_graph=True)
-            torch.cuda.synchronize()
-            f0 = time.perf_counter()
-            S.step(om, seg, use_graph=True)
-            torch.cuda.synchronize()
-            tf = time.perf_counter() - f0
-            lam = torch.randn_like(om) * 1e-3
+            tf, _ = time_steps(S, om, seg, 5, torch)
+            lam0 = torch.randn_like(om) * 1e-3
             g = torch.zeros(1, dtype=torch.float64, device=om.device)
-            S.adjoint_step(w0, lam.clone(), seg, g)
+            S.adjoint_step(w0, lam0.clone(), seg, g)
             torch.cuda.synchronize()
-            a0 = time.perf_counter()
-            S.adjoint_step(w0, lam, seg, g)
-            torch.cuda.synchronize()
-            ta = time.perf_counter() - a0
+            times = []
+            for _ in range(WINDOWS):
+                lam = lam0.clone()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                S.adjoint_step(w0, lam, seg, g)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1) / 1e3)
+            ta = float(np.median(times))
             S.close()
             ratios[f"fp{prec}{tag}"] = ta / tf
-            log(f"adjoint/forward fp{prec}{tag}: {ta / tf:.2f} ({ta * 1e3:.1f} ms / {tf * 1e3:.1f} ms, {seg} steps)")
+            log(f"adjoint/forward fp{prec}{tag}: {ta / tf:.3f} ({ta * 1e3:.2f} ms / {tf * 1e3:.2f} ms, {seg} steps)")
         result["adjoint_forward_ratio"] = ratios
 
-    if "cpu" not in skip:
-        result["cpu_baseline"] = cpu_baseline(configs.config3(precision=64), args.cpu_steps)
-        log(f"cpu oracle: {result['cpu_baseline']['value']:.4g} pt-steps/s")
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

@@ -25,7 +25,7 @@
  *    linear terms (viscosity, friction, beta), second-order Adams-Bashforth
  *    on the Jacobian, the closure and the penalization curl(chi u / eta),
  *    then the sponge by Adams-Bashforth 2 on omega* and the previous step's
- *    omega**.  Explicit penalization needs eta > dt.  The scheme carries
+ *    omega**.  Explicit penalization needs eta > dt (checked).  The scheme carries
  *    history inside the handle (the previous explicit terms and omega**):
  *    the first step after qg_init is forward Euler on the explicit parts,
  *    and later qg_step calls continue the sequence, so the omega passed in
@@ -85,7 +85,10 @@ enum {
  *  beta, re, mu beta-plane gradient, Reynolds number (re <= 0 or inf means
  *               no molecular viscosity), bottom friction (Eq. 1)
  *  u_in, v_in   uniform inflow added to the zeroth velocity mode
- *  eta          Brinkman porosity (Eq. 2); eta <= 0 or inf disables it
+ *  eta          Brinkman porosity (Eq. 2), must be > 0; inf disables the
+ *               obstacle.  QG_SCHEME_AB2CN members need eta > dt (the
+ *               explicit penalization's stability bound, Sec. II-E);
+ *               qg_init and qg_workspace_bytes return QG_EINVAL otherwise
  *  sponge_sigma 1/eta_sponge (Eq. 3); 0 disables the sponge
  *  dt           time step
  *  c            static c_S or c_L (ignored by the dynamic closures)
@@ -233,15 +236,19 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
  * step).  Synchronises hip_stream. */
 int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
 
-/* Profiling: launch one kernel of the RK4 step `reps` times on hip_stream,
- * on the handle's current workspace contents (call after qg_step; the state
- * it leaves is not meaningful).  QG_SCHEME_AB2CN groups are skipped.  phase: 0 column-inverse of the right-hand
- * side, 1 row pass of the right-hand side, 2 column-forward of the
- * right-hand side, 3 dynamic combine (dynamic closures), 4 column-inverse of
- * the B sub-step, 5 row pass of the B sub-step, 6 column-forward of the B
- * sub-step.  stage: RK stage 1..4 for phases 0-3.  Every size group of the
- * handle is launched; phase 3 is skipped for static closures. */
-int qg_run_phase(qg_handle* h, int32_t phase, int32_t stage, int32_t reps, void* hip_stream);
+/* Profiling: qg_step(h, omega, nsteps) without graphs (the same launches in
+ * the same order on hip_stream, omega updated in place), where every launch
+ * of one kind of step kernel is bound to a pair of HIP events that carry
+ * its dispatch's own begin and end times.  kind: 0 column-inverse pass of
+ * the right-hand side, 1 its row pass, 2 its column-forward pass, 3 the
+ * dynamic combine (dynamic closures only), 4 column-inverse pass of the B
+ * sub-step, 5 its row pass, 6 its column-forward pass; every size group's
+ * launches of that kind are timed.  ms (host, max_launches floats) receives the duration of
+ * each of the first max_launches such launches in milliseconds and
+ * *n_launches their number.  RK4 members only (QG_EUNSUPPORTED otherwise).
+ * Synchronises hip_stream; the library creates and destroys the events. */
+int qg_profile_steps(qg_handle* h, void* omega, int64_t nsteps, int32_t kind, float* ms,
+                     int32_t max_launches, int32_t* n_launches, void* hip_stream);
 
 /* Number of members, total grid points, and the tiling chosen per member:
  * strip width of the column-forward and of the column-inverse passes

@@ -69,6 +69,8 @@ static int validate(const qg_params& p, int idx) {
     if (p.nx < 64) return bad(QG_EUNSUPPORTED, "the AB2CN scheme needs nx >= 64");
     if (p.precision == 64 && (p.nx > 2048 || p.ny > 2048))
       return bad(QG_EUNSUPPORTED, "the AB2CN scheme in 64-bit runs needs nx, ny <= 2048");
+    // explicit penalization is stable only for eta > dt (Sec. II-E)
+    if (!(p.eta > p.dt)) return bad(QG_EINVAL, "the AB2CN scheme needs eta > dt (explicit penalization)");
   }
   return QG_OK;
 }
@@ -429,6 +431,28 @@ static void clip_sums(const Group& g, Phase& Q) {
   Q.nparts = g.ny / 2;
 }
 
+// Profiling runs (qg_profile_steps): every launch of one kind of phase
+// kernel gets a pair of HIP events bound to its dispatch.  Kinds: 0 the
+// right-hand side's column-inverse pass, 1 its row pass, 2 its
+// column-forward pass, 3 the dynamic combine, 4-6 the same three passes of
+// the B sub-step.
+struct ProfState {
+  int kind;
+  std::vector<hipEvent_t> ev;   // begin, end of launch 0, then launch 1, ...
+  int used;
+};
+static thread_local ProfState* g_prof = nullptr;
+
+static Phase timed(Phase P, int kind) {
+  P.ev0 = P.ev1 = nullptr;
+  if (g_prof && g_prof->kind == kind && 2 * (g_prof->used + 1) <= (int)g_prof->ev.size()) {
+    P.ev0 = g_prof->ev[2 * g_prof->used];
+    P.ev1 = g_prof->ev[2 * g_prof->used + 1];
+    ++g_prof->used;
+  }
+  return P;
+}
+
 // Where the adjoint's segment recompute keeps a dynamic stage's H, M, Q
 // and (C, <HM>, <M^2>) (byte offsets in the member region).
 struct StageStore {
@@ -442,13 +466,13 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, con
   P.stage = s;
   P.nf = rhs_fields(cl);
   P.o_in = s == 1 ? g.L.wn : g.L.x;
-  QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
-  QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
+  QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, timed(P, 0), g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, timed(P, 1), g.count, st));
   if (!dynamic_closure(cl)) {
     P.o_in = g.L.x;
     P.o_in2 = g.L.wn;
     P.o_aux = g.L.acc;
-    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, timed(P, 2), g.count, st));
   } else {
     P.o_out = g.L.jsp;
     P.o_aux = keep ? keep->q : g.L.qsp;
@@ -458,7 +482,7 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, con
       P.o_m = keep->m;
     }
     clip_keep(g, P);
-    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
+    QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, timed(P, 2), g.count, st));
     int rc = run_clip_pass(h, g, st);
     if (rc) return rc;
     Phase Q = base_phase(h, g);
@@ -473,7 +497,7 @@ static int run_stage(const Handle& h, const Group& g, int s, hipStream_t st, con
       Q.o_cs = keep->cs;
     }
     clip_sums(g, Q);
-    QG_LAUNCH(launch_combine(g.dbl, OP_RHS, Q, g.count, st));
+    QG_LAUNCH(launch_combine(g.dbl, OP_RHS, timed(Q, 3), g.count, st));
   }
   return QG_OK;
 }
@@ -482,10 +506,10 @@ static int run_b(const Handle& h, const Group& g, hipStream_t st) {
   Phase P = base_phase(h, g);
   P.o_in = g.L.x;
   P.nf = 3;
-  QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, P, g.count, st));
-  QG_LAUNCH(launch_row(g.dbl, OP_B, 0, P, g.count, st));
+  QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, timed(P, 4), g.count, st));
+  QG_LAUNCH(launch_row(g.dbl, OP_B, 0, timed(P, 5), g.count, st));
   P.o_out = g.L.wn;
-  QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, P, g.count, st));
+  QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, timed(P, 6), g.count, st));
   return QG_OK;
 }
 
@@ -1391,6 +1415,9 @@ int qg_set_coef(qg_handle* H, const double* c, void* hip_stream) {
       const int u = g.users[k];
       h.params[u].c = c[u];
       MemberDev m = make_member(h.params[u], h.table[g.m0 + k].base, h.omega_off[u], u);
+      // values qg_init derived on the device are kept: the mask mean split
+      // off in the AB2CN penalty's curl
+      m.pen_c = h.table[g.m0 + k].pen_c;
       h.table[g.m0 + k] = m;
     }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1400,43 +1427,48 @@ int qg_set_coef(qg_handle* H, const double* c, void* hip_stream) {
   return QG_OK;
 }
 
-int qg_run_phase(qg_handle* H, int32_t phase, int32_t stage, int32_t reps, void* hip_stream) {
-  if (!H) return fail(QG_EINVAL, "handle is NULL");
-  if (phase < 0 || phase > 6) return fail(QG_EINVAL, "phase must be in [0, 6]");
-  if (stage < 1 || stage > 4) return fail(QG_EINVAL, "stage must be in [1, 4]");
-  if (reps < 0) return fail(QG_EINVAL, "reps must be >= 0");
+int qg_profile_steps(qg_handle* H, void* omega, int64_t nsteps, int32_t kind, float* ms, int32_t max_launches,
+                     int32_t* n_launches, void* hip_stream) {
+  if (!H || !omega || !ms || !n_launches) return fail(QG_EINVAL, "NULL argument");
+  if (kind < 0 || kind > 6) return fail(QG_EINVAL, "kind must be in [0, 6]");
+  if (nsteps < 0 || max_launches < 0) return fail(QG_EINVAL, "nsteps and max_launches must be >= 0");
   Handle& h = H->h;
+  for (const auto& g : h.groups)
+    if (g.scheme != QG_SCHEME_RK4) return fail(QG_EUNSUPPORTED, "profiling runs take RK4 members only");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  for (int r = 0; r < reps; ++r) {
-    for (const auto& g : h.groups) {
-      if (g.scheme != QG_SCHEME_RK4) continue;   // the phases are those of the RK4 step
-      const int cl = g.closure;
-      Phase P = base_phase(h, g);
-      P.stage = stage;
-      if (phase <= 3) {
-        P.nf = rhs_fields(cl);
-        P.o_in = stage == 1 ? g.L.wn : g.L.x;
-        if (phase == 0) QG_LAUNCH(launch_colinv(g.dbl, OP_RHS, cl, P, g.count, st));
-        if (phase == 1) QG_LAUNCH(launch_row(g.dbl, OP_RHS, cl, P, g.count, st));
-        if (phase == 2) {
-          if (!dynamic_closure(cl)) { P.o_in = g.L.x; P.o_in2 = g.L.wn; P.o_aux = g.L.acc; }
-          else { P.o_out = g.L.jsp; P.o_aux = g.L.qsp; }
-          QG_LAUNCH(launch_colfwd(g.dbl, OP_RHS, cl, P, g.count, st));
-        }
-        if (phase == 3 && dynamic_closure(cl)) {
-          P.o_in = g.L.x; P.o_in2 = g.L.wn; P.o_out = g.L.jsp; P.o_aux = g.L.qsp; P.o_mp = g.L.acc;
-          QG_LAUNCH(launch_combine(g.dbl, OP_RHS, P, g.count, st));
-        }
-      } else {
-        P.o_in = g.L.x;
-        P.nf = 3;
-        if (phase == 4) QG_LAUNCH(launch_colinv(g.dbl, OP_B, 0, P, g.count, st));
-        if (phase == 5) QG_LAUNCH(launch_row(g.dbl, OP_B, 0, P, g.count, st));
-        if (phase == 6) { P.o_out = g.L.x; QG_LAUNCH(launch_colfwd(g.dbl, OP_B, 0, P, g.count, st)); }
-      }
-    }
+  ProfState ps;
+  ps.kind = kind;
+  ps.used = 0;
+  int rc = QG_OK;
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { rc = fail(QG_EHIP, "hipEventCreate failed"); break; }
+    ps.ev.push_back(e);
   }
-  return QG_OK;
+  if (rc == QG_OK) {
+    g_prof = &ps;
+    try {
+      for (const auto& g : h.groups)
+        if (rc == QG_OK) rc = run_entry(h, g, omega, g.L.wn, st);
+      if (rc == QG_OK) rc = run_steps_eager(h, (int)nsteps, st);
+      for (const auto& g : h.groups)
+        if (rc == QG_OK) rc = run_exit(h, g, g.L.wn, omega, st);
+    } catch (...) {
+      rc = fail(QG_EINVAL, "internal error in qg_profile_steps");
+    }
+    g_prof = nullptr;
+  }
+  if (rc == QG_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QG_EHIP, "hipStreamSynchronize failed");
+  if (rc == QG_OK) {
+    for (int i = 0; i < ps.used; ++i)
+      if (hipEventElapsedTime(&ms[i], ps.ev[2 * i], ps.ev[2 * i + 1]) != hipSuccess) {
+        rc = fail(QG_EHIP, "hipEventElapsedTime failed");
+        break;
+      }
+    *n_launches = ps.used;
+  }
+  for (auto e : ps.ev) (void)hipEventDestroy(e);
+  return rc;
 }
 
 int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {

@@ -105,6 +105,10 @@ struct Phase {
   // the cotangents a, r b, its result test-filtered to o_e.
   int adj_dyn, adj_mode;
   long long o_h, o_m, o_a, o_b, o_e, o_cs;
+  // profiling runs only: HIP events bound to this launch's dispatch (begin,
+  // end); null otherwise
+  void* ev0;
+  void* ev1;
 };
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048

@@ -32,6 +32,10 @@
 //             product, extraction of the retained modes, then the spectral
 //             combine of the phase (right-hand side and RK4 update, dynamic
 //             coefficient partial sums, B-step projection, adjoint sums).
+#include <hip/hip_ext.h>
+
+#include <cstdint>
+
 #include "qg_fft.hpp"
 #include "qg_internal.hpp"
 
@@ -1315,10 +1319,10 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       const long long id = sidx(i);
       const V x = xin[id];
       V r = R[i];
-      const T lin = T(w.k2 * M.inv_re + M.mu);
+      const T lin = (w.k2 * T(M.inv_re) + T(M.mu));
       r = csub(r, cscale(x, lin));
       const V psi = poisson<T>(M, x, w, mxs_(i), my);
-      r = csub(r, mul_ia(psi, T(M.beta * w.kx)));
+      r = csub(r, mul_ia(psi, (T(M.beta) * w.kx)));
       if constexpr (CL != 0) r = cadd(r, cscale(Q[i], C));
       if (mxs_(i) == 0 && my == 0) r = cmake<V>(T(0), T(0));
       const V w0 = wn[id];
@@ -1515,8 +1519,8 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       const long long id = sidx(i);
       V l = lin[id];
       if (mxs_(i) == 0 && my == 0) l = cmake<V>(T(0), T(0));
-      V lp = cadd(Lpsi[i], mul_ia(l, T(M.beta * w.kx)));
-      V lx = csub(Lx[i], cscale(l, T(w.k2 * M.inv_re + M.mu)));
+      V lp = cadd(Lpsi[i], mul_ia(l, (T(M.beta) * w.kx)));
+      V lx = csub(Lx[i], cscale(l, (w.k2 * T(M.inv_re) + T(M.mu))));
       lx = csub(lx, cscale(lp, T(w.inv_k2)));
       if (P.adj_dyn) lx = cadd(lx, cptr<T>(M, P.o_e)[id]);   // the dynamic coefficient's term
       lw[id] = cadd(lw[id], lx);
@@ -1641,8 +1645,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       V* lk = cptr<T>(M, P.o_in2);
       V l = gld(lk + id);
       if (mx == 0 && my == 0) l = cmake<V>(T(0), T(0));
-      const V lp = cadd(lpsi, mul_ia(l, T(M.beta * wv.kx)));
-      V lx = csub(Lx, cscale(l, T(wv.k2 * M.inv_re + M.mu)));
+      const V lp = cadd(lpsi, mul_ia(l, (T(M.beta) * wv.kx)));
+      V lx = csub(Lx, cscale(l, (wv.k2 * T(M.inv_re) + T(M.mu))));
       lx = csub(lx, cscale(lp, wv.inv_k2));
       if (P.adj_dyn) lx = cadd(lx, gld(cptr<T>(M, P.o_e) + id));   // the dynamic coefficient's term
       V* lw = cptr<T>(M, P.o_aux);
@@ -1677,8 +1681,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       const V x = gld(xin + id);
       const V j = at(0, w, iy);
       V r = cmake<V>(-j.x, -j.y);
-      r = csub(r, cscale(x, T(wv.k2 * M.inv_re + M.mu)));
-      r = csub(r, mul_ia(poisson<T>(M, x, wv, mx, my), T(M.beta * wv.kx)));
+      r = csub(r, cscale(x, (wv.k2 * T(M.inv_re) + T(M.mu))));
+      r = csub(r, mul_ia(poisson<T>(M, x, wv, mx, my), (T(M.beta) * wv.kx)));
       if constexpr (CL != 0) {
         const V Q = cadd(mul_ia(at(1, w, iy), wv.kx), mul_ia(at(2, w, iy), wv.ky));
         r = cadd(r, cscale(Q, T(M.coef_static)));
@@ -1781,8 +1785,8 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
       w0 = gld(cptr<T>(M, P.o_in2) + q);
       if (P.stage > 1) a = gld(acc + q);
       r0 = cmake<V>(-j.x, -j.y);
-      r0 = csub(r0, cscale(x, T(w.k2 * M.inv_re + M.mu)));
-      r0 = csub(r0, mul_ia(poisson<T>(M, x, w, mx, my), T(M.beta * w.kx)));
+      r0 = csub(r0, cscale(x, (w.k2 * T(M.inv_re) + T(M.mu))));
+      r0 = csub(r0, mul_ia(poisson<T>(M, x, w, mx, my), (T(M.beta) * w.kx)));
     }
   }
   double C, hm, mm;
@@ -2092,6 +2096,18 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 #endif
 
 // ---------------------------------------------------------------- launchers
+// Launch of a phase kernel.  A profiling run sets P.ev0 / P.ev1: the launch
+// then binds the two HIP events to the dispatch itself, so they carry its
+// own begin and end times (no marker of their own in the stream).
+#define QG_KLAUNCH(KERNEL, GRID, BLOCK, LDS, S, P)                                                    \
+  do {                                                                                                \
+    if ((P).ev0)                                                                                      \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, (std::uint32_t)(LDS), S, (hipEvent_t)(P).ev0,        \
+                            (hipEvent_t)(P).ev1, 0u, P);                                              \
+    else                                                                                              \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, P);                                             \
+  } while (0)
+
 // strips of a column pass, padded to a multiple of 8 (XCD-aware order)
 static unsigned col_grid(const Phase& P) { return (unsigned)(((P.kxn + P.W - 1) / P.W + 7) / 8 * 8); }
 static size_t col_tile(const Phase& P) { return (size_t)P.W * P.ny + (P.W == 1 ? P.ny / 8 : 0); }
@@ -2112,13 +2128,13 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
     // kernel's compile-time path is generic in the field formation)
     const size_t lds = (size_t)P.Wi * colinv_stride(P.ny) * sizeof(cpx<T>);
     switch (P.logny) {
-      case 8: hipLaunchKernelGGL((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
-      case 9: hipLaunchKernelGGL((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
-      case 10: hipLaunchKernelGGL((k_colinv<T, OP, CL, 10>), grid, block, lds, s, P); return;
+      case 8: QG_KLAUNCH((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
+      case 9: QG_KLAUNCH((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
+      case 10: QG_KLAUNCH((k_colinv<T, OP, CL, 10>), grid, block, lds, s, P); return;
       default: break;
     }
   }
-  hipLaunchKernelGGL((k_colinv<T, OP, CL, 0>), grid, block, coli_smem(sizeof(T) == 8, P), s, P);
+  QG_KLAUNCH((k_colinv<T, OP, CL, 0>), grid, block, coli_smem(sizeof(T) == 8, P), s, P);
 }
 static int rowp_fields(int op, int cl) { return rowp_nb(op, cl); }
 static size_t rowp_lds(bool dbl, int op, int cl, const Phase& P) {
@@ -2137,10 +2153,10 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   dim3 grid(P.ny / 2, levels, nmem);
   // compile-time transform lengths for the common row lengths
   switch (P.lognx) {
-    case 8: hipLaunchKernelGGL((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P); return;
-    case 9: hipLaunchKernelGGL((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P); return;
-    case 10: hipLaunchKernelGGL((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P); return;
-    default: hipLaunchKernelGGL((k_rowp<T, OP, CL, 0>), grid, block, lds, s, P); return;
+    case 8: QG_KLAUNCH((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P); return;
+    case 9: QG_KLAUNCH((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P); return;
+    case 10: QG_KLAUNCH((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+    default: QG_KLAUNCH((k_rowp<T, OP, CL, 0>), grid, block, lds, s, P); return;
   }
 }
 
@@ -2155,7 +2171,7 @@ static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) { launch_rowp_t<T, OP, CL>(P, nmem, s); return; }
   }
   dim3 grid(P.ny / (2 * P.RP), 1, nmem);
-  hipLaunchKernelGGL((k_row<T, OP, CL>), grid, dim3(row_threads(P)), row_smem(sizeof(T) == 8, P), s, P);
+  QG_KLAUNCH((k_row<T, OP, CL>), grid, dim3(row_threads(P)), row_smem(sizeof(T) == 8, P), s, P);
 }
 static int colfwdp_products(int op, int cl) {
   if (op == OP_RHS) return cl == 0 ? 1 : (cl == 3 || cl == 4) ? 6 : 3;
@@ -2181,13 +2197,13 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
     // block; every op, as for the column-inverse pass)
     const size_t lds = np * n * sizeof(cpx<T>);
     if (P.W == 1) switch (P.logny) {
-      case 8: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P); return;
-      case 9: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 9>), grid, block, lds, s, P); return;
-      case 10: hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+      case 8: QG_KLAUNCH((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P); return;
+      case 9: QG_KLAUNCH((k_colfwdp<T, OP, CL, 9>), grid, block, lds, s, P); return;
+      case 10: QG_KLAUNCH((k_colfwdp<T, OP, CL, 10>), grid, block, lds, s, P); return;
       default: break;
     }
   }
-  hipLaunchKernelGGL((k_colfwdp<T, OP, CL, 0>), grid, block, (np * n + P.ny) * sizeof(cpx<T>), s, P);
+  QG_KLAUNCH((k_colfwdp<T, OP, CL, 0>), grid, block, (np * n + P.ny) * sizeof(cpx<T>), s, P);
 }
 
 template <typename T, int OP, int CL>
@@ -2203,7 +2219,7 @@ static void launch_colfwd_t(const Phase& P, int nmem, hipStream_t s) {
   }
   dim3 grid(col_grid(P), 1, nmem);
   constexpr int EPT = COL_EPT;
-  hipLaunchKernelGGL((k_colfwd<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
+  QG_KLAUNCH((k_colfwd<T, OP, CL, EPT>), grid, dim3(P.W * P.ny / COL_EPT), col_smem(sizeof(T) == 8, P), s, P);
 }
 
 #define QG_CL_SWITCH(FN, T, OP, cl, P, n, s)                 \
@@ -2317,8 +2333,8 @@ hipError_t launch_colfwd(bool dbl, int op, int cl, const Phase& P, int n, hipStr
 }
 hipError_t launch_combine(bool dbl, int, const Phase& P, int n, hipStream_t s) {
   dim3 grid((P.kxn * P.kyn + COMBINE_THREADS - 1) / COMBINE_THREADS, 1, n);
-  if (dbl) hipLaunchKernelGGL(k_combine<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
-  else hipLaunchKernelGGL(k_combine<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  if (dbl) QG_KLAUNCH(k_combine<double>, grid, dim3(COMBINE_THREADS), 0, s, P);
+  else QG_KLAUNCH(k_combine<float>, grid, dim3(COMBINE_THREADS), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_dyn_coef(const Phase& P, int n, int slot, hipStream_t s) {

@@ -173,9 +173,16 @@ class Solver:
         _lib.check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
                                       _stream(self.device)))
 
-    def run_phase(self, phase, stage=2, reps=1):
-        """Launch one kernel of the step reps times (profiling only)."""
-        _lib.check(self.L.qg_run_phase(self.h, int(phase), int(stage), int(reps), _stream(self.device)))
+    def profile_steps(self, omega, nsteps, kind, max_launches=4096):
+        """qg_step without graphs, with the dispatch of every launch of one
+        kind of step kernel timed by HIP events bound to it (profiling);
+        returns the launch durations in milliseconds."""
+        self._check_flat(omega, "omega")
+        ms = (ctypes.c_float * max_launches)()
+        n = ctypes.c_int32(0)
+        _lib.check(self.L.qg_profile_steps(self.h, _ptr(omega), int(nsteps), int(kind), ms, max_launches,
+                                           ctypes.byref(n), _stream(self.device)))
+        return list(ms[:n.value])
 
     def column_widths(self):
         """Strip width of the column-forward pass per member."""

@@ -31,6 +31,22 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def max_rel(a, b):
+    """Largest pointwise difference relative to the largest value of the
+    reference, max |a - b| / max |b|.  A mistake confined to one point, one
+    row or one strip moves the L2 norm by the square root of its share of
+    the grid; here it shows at full size."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def field_err(a, b):
+    """Error of a field against its reference for a gate: the larger of the
+    relative L2 norm and the pointwise (max-norm) relative error."""
+    return max(rel_l2(a, b), max_rel(a, b))
+
+
 def to_np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 

@@ -48,7 +48,7 @@ def ws(params, adj=0):
 
 def test_ab2cn_workspace_holds_its_history():
     rc, b_rk4 = ws([good()])
-    rc2, b_ab = ws([good(scheme="ab2cn")])
+    rc2, b_ab = ws([good(scheme="ab2cn", eta=5e-3)])
     assert rc == 0 and rc2 == 0 and b_ab > b_rk4
 
 
@@ -86,6 +86,9 @@ def test_workspace_bytes_valid_and_monotone():
     (dict(scheme=2), _lib.QG_EINVAL),
     (dict(scheme="ab2cn", nx=32, ny=32, lx=2 * math.pi, ly=2 * math.pi), _lib.QG_EUNSUPPORTED),
     (dict(scheme="ab2cn", nx=4096, ny=2048, lx=2 * math.pi, ly=math.pi), _lib.QG_EUNSUPPORTED),
+    # explicit penalization of the paper's scheme needs eta > dt (Sec. II-E)
+    (dict(scheme="ab2cn", eta=2e-3, dt=2e-3), _lib.QG_EINVAL),
+    (dict(scheme="ab2cn", eta=1e-3, dt=2e-3), _lib.QG_EINVAL),
 ])
 def test_invalid_parameters_are_rejected(bad, code):
     rc, _ = ws([good(**bad)])
@@ -108,7 +111,7 @@ def test_null_arguments():
     assert L.qg_ideal_sgs(None, None, None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_pcc(None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_closure_term(None, None, None, None) == _lib.QG_EINVAL
-    assert L.qg_run_phase(None, 0, 1, 1, None) == _lib.QG_EINVAL
+    assert L.qg_profile_steps(None, None, 1, 0, None, 0, None, None) == _lib.QG_EINVAL
     L.qg_destroy(None)
 
 

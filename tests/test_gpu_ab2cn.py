@@ -12,7 +12,7 @@ import pytest
 
 from oracle import ab2cn, qg
 from paper_2508_06678_amd import configs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -30,7 +30,7 @@ def lockstep(S, m, precision, shape, nsteps, use_graph):
     for n in range(1, nsteps + 1):
         S.step(om, 1, use_graph=use_graph)
         wh, hist = ab2cn.step_spectral(wh, hist, M)
-        err = rel_l2(to_np(om).reshape(shape), qg.leave(wh, M.g))
+        err = field_err(to_np(om).reshape(shape), qg.leave(wh, M.g))
         worst = max(worst, err / n)
     return worst
 
@@ -77,7 +77,7 @@ def test_history_carries_across_calls_and_graphs():
     # a restart without the history would take a forward-Euler step: O(dt^2)
     # away, far above this bound
     for key in (((2, 4), False), ((3, 3), True)):
-        err = rel_l2(outs[key], ref)
+        err = field_err(outs[key], ref)
         say("AB2CN chunks", key, "rel L2 vs one call", err)
         assert err < 1e-13
 
@@ -93,8 +93,8 @@ def test_mixed_schemes_in_one_handle():
     got_a, got_b = (to_np(x).reshape(64, 128) for x in S.unpack(om))
     Ma = oracle_model(a.params, a.chi, a.chi_s)
     Mb = oracle_model(b.params, b.chi, b.chi_s)
-    ea = rel_l2(got_a, qg.run(w_a, Ma, 3))
-    eb = rel_l2(got_b, ab2cn.run(w_b, Mb, 3)[0])
+    ea = field_err(got_a, qg.run(w_a, Ma, 3))
+    eb = field_err(got_b, ab2cn.run(w_b, Mb, 3)[0])
     say("mixed handle: rk4", ea, "ab2cn", eb)
     assert ea < 1e-12 and eb < 1e-12
     S.close()
@@ -132,7 +132,7 @@ def test_every_column_width(closure, code, tmp_path):
         worst = 0.0
         for n in range(1, nsteps + 1):
             S.step(om, 1, use_graph=False)
-            worst = max(worst, rel_l2(to_np(om).reshape(256, 512), refs[n - 1]) / n)
+            worst = max(worst, field_err(to_np(om).reshape(256, 512), refs[n - 1]) / n)
         say("AB2CN", closure, "W", W, "worst rel L2 per step", worst)
         assert worst < 1e-5
         S.close()

@@ -8,7 +8,7 @@ import pytest
 from oracle import adjoint as oadj
 from oracle import qg
 from paper_2508_06678_amd import configs, inputs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -40,7 +40,7 @@ def test_adjoint_matches_oracle(closure, nx, ny):
     g = torch.zeros(1, dtype=torch.float64, device=om.device)
     S.adjoint_step(om, lam, nsteps, g)
     ref_l, ref_c = oadj.run_adjoint(w0, lamT, M, nsteps)
-    err = rel_l2(to_np(lam).reshape(ny, nx), ref_l)
+    err = field_err(to_np(lam).reshape(ny, nx), ref_l)
     say("  lambda rel", err, "dc", g.item(), ref_c)
     assert err < 1e-11
     if closure != "none":
@@ -99,7 +99,7 @@ def test_dynamic_adjoint_matches_oracle(closure, nx, ny, seed):
     g = torch.zeros(1, dtype=torch.float64, device=om.device)
     S.adjoint_step(om, lam, nsteps, g)
     ref_l, ref_c = oadj.run_adjoint(w0, lamT, M, nsteps)
-    err = rel_l2(to_np(lam).reshape(ny, nx), ref_l)
+    err = field_err(to_np(lam).reshape(ny, nx), ref_l)
     say("  lambda rel", err, "dc", g.item(), ref_c)
     assert err < 1e-11
     assert g.item() == 0.0 and ref_c == 0.0
@@ -219,7 +219,7 @@ def test_adjoint_at_compile_time_column_lengths(closure, code, nx, ny, tmp_path)
     g = torch.zeros(1, dtype=torch.float64, device=om.device)
     S.adjoint_step(om, lam, nsteps, g)
     ref_l, ref_c = oadj.run_adjoint(w0, lamT, M, nsteps)
-    err = rel_l2(to_np(lam).reshape(ny, nx), ref_l)
+    err = field_err(to_np(lam).reshape(ny, nx), ref_l)
     say("  lambda rel", err, "dc", g.item(), ref_c)
     assert err < 1e-11
     if closure == "smag":
@@ -247,7 +247,7 @@ def test_adjoint_of_several_size_groups():
     for i, m in enumerate(ms):
         M = oracle_model(m.params, m.chi, m.chi_s)
         ref_l, ref_c = oadj.run_adjoint(w0[i], lamT[i], M, nsteps)
-        err = rel_l2(got[i], ref_l)
+        err = field_err(got[i], ref_l)
         say("  member", i, m.params["nx"], m.params["closure"], "lambda rel", err, "dc", g[i].item(), ref_c)
         assert err < 1e-11
         if m.params["closure"] in ("smag", "leith"):

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import qg
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -39,6 +39,6 @@ def test_c_program_matches_binding_and_oracle(tmp_path):
     assert np.array_equal(got, w20)
     M = oracle_model(PARAMS, chi, chs)
     ref = qg.run(w0, M, 20)
-    err = rel_l2(w20, ref)
+    err = field_err(w20, ref)
     print("C program vs oracle, 20 steps:", err, flush=True)
     assert err < 20 * 1e-12

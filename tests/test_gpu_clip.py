@@ -20,7 +20,7 @@ import pytest
 from oracle import ab2cn, qg
 from oracle import les as oles
 from paper_2508_06678_amd import configs, inputs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -68,7 +68,7 @@ def test_rk4_steps(precision, closure):
     for _ in range(3):
         w_n = to_np(om).reshape(64, 128)
         S.step(om, 1, use_graph=False)
-        err = rel_l2(to_np(om).reshape(64, 128), qg.step(w_n, M1))
+        err = field_err(to_np(om).reshape(64, 128), qg.step(w_n, M1))
         worst = max(worst, err)
     say("  worst rel L2 per step", worst)
     assert worst < TOL[precision]
@@ -88,7 +88,7 @@ def test_diag_coefficient(closure):
     assert ref[2] != 0
     np.testing.assert_allclose(out[2], ref[2], rtol=1e-10)
     np.testing.assert_allclose(out[3:7], ref[3:7], rtol=1e-10, atol=1e-14)
-    assert rel_l2(to_np(nu).reshape(128, 256), nu_ref) < 1e-10
+    assert field_err(to_np(nu).reshape(128, 256), nu_ref) < 1e-10
     S.close()
 
 
@@ -105,7 +105,7 @@ def test_graph_replay_and_mixed_clip_modes():
     got = [to_np(x) for x in S.unpack(om)]
     for m, wi, g in zip(ms, w_in, got):
         M = oracle_model(m.params, m.chi, m.chi_s)
-        err = rel_l2(g, qg.run(wi, M, 2))
+        err = field_err(g, qg.run(wi, M, 2))
         say("  member", m.params["nx"], m.params["closure"], "clip", m.params["clip_mode"], err)
         assert err < 1e-12
     assert rel_l2(got[0], got[1]) > 1e-9     # the two readings differ
@@ -134,7 +134,7 @@ def test_every_strip_width(tmp_path, precision):
         S.step(om, 1, use_graph=False)
         if ref is None:
             ref = qg.step(w_in, M)
-        err = rel_l2(to_np(om).reshape(ny, nx), ref)
+        err = field_err(to_np(om).reshape(ny, nx), ref)
         say("  W", W, "Wi", Wi, err)
         assert err < TOL[precision]
         S.close()
@@ -154,7 +154,7 @@ def test_ab2cn_every_step():
     for n in range(1, 11):
         S.step(om, 1, use_graph=False)
         wh, hist = ab2cn.step_spectral(wh, hist, M)
-        worst = max(worst, rel_l2(to_np(om).reshape(64, 128), qg.leave(wh, M.g)) / n)
+        worst = max(worst, field_err(to_np(om).reshape(64, 128), qg.leave(wh, M.g)) / n)
     say("AB2CN clip 1 worst rel L2 per step", worst)
     assert worst < 1e-12
     S.close()
@@ -178,7 +178,7 @@ def test_closure_term(precision):
     ref = oles.model_sgs(w, M)
     assert np.any(ref)
     if precision == 64:
-        e = rel_l2(got, ref)
+        e = field_err(got, ref)
         say("closure term clip 1", e)
         assert e < 1e-12
     else:

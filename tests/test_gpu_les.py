@@ -11,7 +11,7 @@ import pytest
 from oracle import les as oles
 from oracle import qg
 from paper_2508_06678_amd import configs, inputs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 

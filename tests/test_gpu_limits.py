@@ -23,7 +23,7 @@ import pytest
 
 from oracle import ab2cn, qg
 from paper_2508_06678_amd import configs, inputs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -46,10 +46,16 @@ def member(nx, ny, closure, clip=0, scheme="rk4"):
     return m
 
 
-def one_step(m, precision):
+def one_step(m, precision, new_coef=None):
+    """One step of member m on the GPU against the oracle's; with new_coef the
+    closure coefficient is changed through qg_set_coef after qg_init (and in
+    the oracle's parameters)."""
     nx, ny = m.params["nx"], m.params["ny"]
     say("case", nx, ny, precision, m.params["closure"], "clip", m.params["clip_mode"], m.params["scheme"])
     S = solver_for([m], precision)
+    if new_coef is not None:
+        S.set_coef([new_coef])
+        m.params["c"] = new_coef
     M = oracle_model(m.params, m.chi, m.chi_s)
     om = S.pack([m.omega0])
     w_in = to_np(om).reshape(ny, nx)
@@ -59,7 +65,7 @@ def one_step(m, precision):
         ref = qg.leave(wh, M.g)
     else:
         ref = qg.step(w_in, M)
-    err = rel_l2(to_np(om).reshape(ny, nx), ref)
+    err = field_err(to_np(om).reshape(ny, nx), ref)
     say("  rel L2", err)
     S.close()
     return err
@@ -119,4 +125,15 @@ def test_ab2cn_penalty_conditioning_fully_solid_fp32(solid):
     err = one_step(m, 32)
     say("  kappa", kappa, "u_r kappa", 2.0 ** -24 * kappa)
     assert kappa > 1e3
+    assert err < TOL[32]
+
+
+def test_set_coef_keeps_the_ab2cn_penalty_split():
+    """qg_set_coef rebuilds the member constants; the mask mean that qg_init
+    split off the AB2CN penalty's curl must survive it, or a fully solid FP32
+    box drifts back to the literal form's rounding (u_r kappa ~ 2e-4)."""
+    m = member(4096, 64, "smag", scheme="ab2cn")
+    m.params["eta"] = 2.5 * m.params["dt"]
+    m.chi = np.full_like(m.chi, 1.0)
+    err = one_step(m, 32, new_coef=0.13)
     assert err < TOL[32]

@@ -1,10 +1,13 @@
-"""GPU parity: the HIP path through the C ABI against the oracle, element by
-element on the same seeded inputs.
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs, compared point by point.
 
-Tolerances (per step, relative L2 of the physical vorticity): 1e-12 in
-FP64 and 1e-5 in FP32, as the method's accuracy targets state.  Sizes span
-several column strips and row blocks with ragged tails (kx counts that are
-not multiples of the strip width).
+Tolerances (per step, physical vorticity): 1e-12 in FP64 and 1e-5 in FP32,
+as the method's accuracy targets state, applied both to the relative L2
+norm of the difference and to the largest pointwise difference relative to
+the largest value (``field_err``), so that a mistake confined to one point,
+row or strip cannot hide in the norm.  Sizes span several column strips and
+row blocks with ragged tails (kx counts that are not multiples of the strip
+width).
 """
 import math
 
@@ -13,7 +16,7 @@ import pytest
 
 from oracle import qg
 from paper_2508_06678_amd import configs, inputs
-from tests.bridge import HAVE_GPU, oracle_model, rel_l2, solver_for, to_np
+from tests.bridge import HAVE_GPU, oracle_model, field_err, max_rel, rel_l2, solver_for, to_np
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")]
 
@@ -50,7 +53,7 @@ def test_entry_exit_projection(precision, nx, ny):
     M = oracle_model(m.params, m.chi, m.chi_s)
     ref = qg.leave(qg.enter(w, M.g), M.g)
     got = to_np(om).reshape(ny, nx)
-    err = rel_l2(got, ref)
+    err = field_err(got, ref)
     say("  rel", err)
     assert err < (1e-14 if precision == 64 else 3e-7)
     S.close()
@@ -69,7 +72,7 @@ def test_one_step(precision, closure):
     got = to_np(om).reshape(64, 128)
     w_in = to_np(S.pack([w0])).reshape(64, 128)   # the input as the GPU saw it
     ref = qg.step(w_in, M)
-    err = rel_l2(got, ref)
+    err = field_err(got, ref)
     say("  rel", err)
     assert err < TOL[precision]
     S.close()
@@ -88,7 +91,7 @@ def test_config1_per_step(precision):
         w_n = to_np(om).reshape(64, 128)
         S.step(om, 1, use_graph=False)
         ref = qg.step(w_n, M)
-        err = rel_l2(to_np(om).reshape(64, 128), ref)
+        err = field_err(to_np(om).reshape(64, 128), ref)
         worst = max(worst, err)
     say("  worst", worst)
     assert worst < TOL[precision]
@@ -118,7 +121,7 @@ def test_batched_ragged_members():
     for m, wi, g in zip(ms, w_in, got):
         M = oracle_model(m.params, m.chi, m.chi_s)
         ref = qg.run(wi, M, 2)
-        err = rel_l2(g, ref)
+        err = field_err(g, ref)
         say("  member", m.params["nx"], m.params["ny"], m.params["closure"], err)
         assert err < 1e-12
     S.close()
@@ -139,7 +142,7 @@ def test_diag(closure):
     np.testing.assert_allclose(out[2], ref[2], rtol=1e-10, atol=1e-300)
     np.testing.assert_allclose(out[3:7], ref[3:7], rtol=1e-10, atol=1e-14)
     assert out[7] == 0.0
-    assert rel_l2(to_np(nu).reshape(64, 128), nu_ref) < 1e-10 or np.all(nu_ref == 0)
+    assert field_err(to_np(nu).reshape(64, 128), nu_ref) < 1e-10 or np.all(nu_ref == 0)
     bad = om.clone()
     bad[17] = float("nan")
     out2, _ = S.diag(bad)
@@ -174,7 +177,35 @@ def test_every_strip_width(tmp_path, precision):
         S.step(om, 1, use_graph=False)
         if ref is None:
             ref = qg.step(w_in, M)
-        err = rel_l2(to_np(om).reshape(ny, nx), ref)
+        err = field_err(to_np(om).reshape(ny, nx), ref)
         say("  W", W, "Wi", Wi, err)
         assert err < TOL[precision]
         S.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_oversized_dt_cfl_and_nonfinite_flag(precision):
+    """Failure detection on the device: the island channel with 50 times its
+    time step.  qg_diag's CFL agrees with the oracle's and exceeds 1 at the
+    start; the run then grows without bound and the non-finite flag fires
+    within 20 steps (the oracle's run blows up within 8)."""
+    m = configs.config1().members[0]
+    m.params["dt"] = 50 * m.params["dt"]
+    S = solver_for([m], precision)
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    om = S.pack([m.omega0])
+    out = S.diag(om)[0].cpu().numpy()[0]
+    ref, _ = qg.diag(to_np(om).reshape(64, 128), M)
+    say("oversized dt", precision, "CFL", out[6], "oracle", ref[6])
+    assert out[6] > 1.0 and out[7] == 0.0
+    assert abs(out[6] - ref[6]) <= (1e-12 if precision == 64 else 1e-5) * ref[6]
+    fired = None
+    for n in range(1, 21):
+        S.step(om, 1, use_graph=False)
+        out = S.diag(om)[0].cpu().numpy()[0]
+        say("  step", n, "CFL", out[6], "nonfinite", out[7])
+        if out[7] == 1.0:
+            fired = n
+            break
+    assert fired is not None
+    S.close()

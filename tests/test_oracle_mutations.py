@@ -57,6 +57,13 @@ QG_MUTATIONS = [
      lambda: pins_phys.test_single_shell_rk4_exact("none", 0.0)),
     ("pointwise clip of the product", "np.mean(np.maximum(H, 0.0) * M)", "np.mean(np.maximum(H * M, 0.0))",
      lambda: pins_phys.test_pointwise_clip_reading("dleith")),
+    ("diagnostics nu_e mean of the magnitude", "float(nu.mean())", "float(np.abs(nu - nu.mean()).mean())",
+     lambda: pins_phys.test_diag_eddy_viscosity_field_and_statistics("leith")),
+    ("diagnostics nu_e statistics swapped", "float(nu.min()), float(nu.mean()), float(nu.max())",
+     "float(nu.min()), float(nu.max()), float(nu.mean())",
+     lambda: pins_phys.test_diag_eddy_viscosity_field_and_statistics("dsmag")),
+    ("diagnostics CFL without the time step", "* p.dt / g.delta", "/ g.delta",
+     pins_phys.test_oversized_dt_drives_cfl_past_one_until_nonfinite),
 ]
 
 
