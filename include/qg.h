@@ -228,13 +228,29 @@ int qg_set_coef(qg_handle* h, const double* c_host, void* hip_stream);
 int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
             void* hip_stream);
 
-/* Time candidate FFT tilings for every size group on hip_stream and keep
- * the fastest; results are cached in the JSON file at cache_path (nullable:
- * no file).  The timed steps run on the workspace: the spectral state is
- * not meaningful afterwards (the next qg_step enters omega again) and the
- * history of QG_SCHEME_AB2CN members starts again (forward-Euler first
- * step).  Synchronises hip_stream. */
+/* Choose the launch configuration of every size group by timing: the
+ * tunables are the strip width of the column-forward pass (W) and of the
+ * column-inverse pass (Wi), the radix schedule of the compile-time row and
+ * column transforms (rows and columns of 256, 512 or 1024 points; schedule
+ * 0: radix 8 then 4 or 2, e.g. 1024 = 8 8 8 2; schedule 1: radix 4 first,
+ * e.g. 1024 = 8 4 4 8) and the row pairs per block of the step's row pass
+ * (1 or 2).  All combinations of the admissible values are searched
+ * jointly: each is captured as a graph of four steps of the group and timed
+ * round-robin three times (after two warm-up rounds) on a stream of the
+ * tuner's own, and the fastest is kept.  The choice is cached in the flat
+ * JSON file at cache_path (nullable: no file) under the group's key with
+ * the suffixes /fwd, /inv, /rsched, /csched, /rpb; a tunable found in the
+ * cache is taken as given and only the others are searched.  Every choice
+ * computes the same step (to rounding).  The timed steps run on the
+ * workspace: the spectral state is not meaningful afterwards (the next
+ * qg_step enters omega again) and the history of QG_SCHEME_AB2CN members
+ * starts again (forward-Euler first step).  Synchronises hip_stream. */
 int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
+
+/* The launch configuration of every member's size group: out (host,
+ * n_members x 5 int32) receives W, Wi, row schedule, column schedule and
+ * row pairs per block (see qg_autotune). */
+int qg_tuning(const qg_handle* h, int32_t* out);
 
 /* Profiling: qg_step(h, omega, nsteps) without graphs (the same launches in
  * the same order on hip_stream, omega updated in place), where every launch

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "qg_fft.hpp"
 #include "qg_internal.hpp"
 #include "../../include/qg.h"
 
@@ -93,6 +94,11 @@ struct Group {
   void* twx;
   void* twy;
   long long o_twx, o_twy;        // offsets in the global area
+  void* twx1;                    // the same for pass schedule 1
+  void* twy1;
+  long long o_twx1, o_twy1;
+  int rsch, csch;                // pass schedules of the row / column compile-time engines
+  int rpb;                       // row pairs per block of the step's row pass
 };
 
 // Strip width W of the column passes: W * ny <= one tile, at least 64
@@ -288,6 +294,10 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     const int cs = g.dbl ? 16 : 8;
     g.o_twx = o; o += align256((long long)g.nx * cs);
     g.o_twy = o; o += align256((long long)g.ny * cs);
+    g.o_twx1 = o; o += align256((long long)g.nx * cs);
+    g.o_twy1 = o; o += align256((long long)g.ny * cs);
+    g.rsch = g.csch = 0;
+    g.rpb = 1;
   }
   int m0 = 0;
   for (auto& g : h.groups) {
@@ -338,13 +348,17 @@ static void twiddles(int n, std::vector<long double>& re, std::vector<long doubl
 // keeps exp(-2 pi i t k / (Ns R)) at (Ns - 8) + k (R - 1) + t - 1, taken
 // from the full table (index t k N / (Ns R)).  n - 8 entries; the rest of
 // the n slots is zero.
-static void pass_twiddles(int n, const std::vector<long double>& fre, const std::vector<long double>& fim,
+// Per-pass table of the transforms of length n under pass schedule sch (see
+// qg_fft.hpp): the pass with sub-length ns and radix r keeps
+// exp(-2 pi i t k / (ns r)) at (ns - 8) + k (r - 1) + (t - 1).
+static void pass_twiddles(int n, int sch, const std::vector<long double>& fre, const std::vector<long double>& fim,
                           std::vector<long double>& re, std::vector<long double>& im) {
   re.assign(n, 0.0L);
   im.assign(n, 0.0L);
-  for (int ns = 8; ns < n; ns *= 8) {
-    const int rem = n / ns;
-    const int r = rem >= 8 ? 8 : rem;
+  const int logn = ilog2(n);
+  for (int logns = 3; logns < logn;) {
+    const int ns = 1 << logns;
+    const int r = 1 << pass_log_radix(logn, logns, sch);
     const int stride = n / (ns * r);
     for (int k = 0; k < ns; ++k)
       for (int t = 1; t < r; ++t) {
@@ -352,6 +366,7 @@ static void pass_twiddles(int n, const std::vector<long double>& fre, const std:
         re[o] = fre[(long long)t * k * stride];
         im[o] = fim[(long long)t * k * stride];
       }
+    logns += pass_log_radix(logn, logns, sch);
   }
 }
 
@@ -370,6 +385,8 @@ static Phase base_phase(const Handle& h, const Group& g) {
   P.o_mf = g.L.mf; P.o_mp = g.L.mp; P.o_phys = g.L.phys;
   P.o_part = g.L.part; P.o_coef = g.L.coef; P.o_dpart = g.L.dpart;
   P.twx = g.twx; P.twy = g.twy;
+  P.twx1 = g.twx1; P.twy1 = g.twy1;
+  P.rsch = g.rsch; P.csch = g.csch; P.rpb = g.rpb;
   return P;
 }
 
@@ -932,16 +949,18 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
     g.region0 = h.ws + reinterpret_cast<long long>(g.region0);
     g.twx = h.ws + g.o_twx;
     g.twy = h.ws + g.o_twy;
+    g.twx1 = h.ws + g.o_twx1;
+    g.twy1 = h.ws + g.o_twy1;
     for (int k = 0; k < g.count; ++k) {
       const int u = g.users[k];
       table[g.m0 + k] = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
     }
-    for (int axis = 0; axis < 2; ++axis) {
-      const int len = axis == 0 ? g.nx : g.ny;
+    for (int axis = 0; axis < 4; ++axis) {
+      const int len = (axis & 1) == 0 ? g.nx : g.ny;
       std::vector<long double> fre, fim, re, im;
       twiddles(len, fre, fim);
-      pass_twiddles(len, fre, fim, re, im);
-      void* dst = axis == 0 ? g.twx : g.twy;
+      pass_twiddles(len, axis >> 1, fre, fim, re, im);
+      void* dst = axis == 0 ? g.twx : axis == 1 ? g.twy : axis == 2 ? g.twx1 : g.twy1;
       if (g.dbl) {
         std::vector<double> t(2 * len);
         for (int m = 0; m < len; ++m) { t[2 * m] = (double)re[m]; t[2 * m + 1] = (double)im[m]; }
@@ -1471,64 +1490,130 @@ int qg_profile_steps(qg_handle* H, void* omega, int64_t nsteps, int32_t kind, fl
   return rc;
 }
 
+// One candidate tuning of a size group.
+struct Tuning {
+  int W, Wi, rsch, csch, rpb;
+};
+static void apply_tuning(Group& g, const Tuning& t) {
+  set_width(g, t.W);
+  set_inv_width(g, t.Wi);
+  g.rsch = t.rsch;
+  g.csch = t.csch;
+  g.rpb = t.rpb;
+}
+
 int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   Handle& h = H->h;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   std::map<std::string, int> cache;
   if (cache_path) read_width_cache(cache_path, cache);
-  hipEvent_t e0, e1;
-  QG_HIP(hipEventCreate(&e0));
-  QG_HIP(hipEventCreate(&e1));
+  // candidates run as captured graphs on a stream of the tuner's own,
+  // ordered after the caller's earlier work
+  hipStream_t ts = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ein = nullptr;
+  QG_HIP(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking));
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ein) (void)hipEventDestroy(ein);
+    if (ts) { (void)hipStreamSynchronize(ts); (void)hipStreamDestroy(ts); }
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipEventCreateWithFlags(&ein, hipEventDisableTiming) != hipSuccess || hipEventRecord(ein, st) != hipSuccess ||
+      hipStreamWaitEvent(ts, ein, 0) != hipSuccess) {
+    cleanup();
+    return fail(QG_EHIP, "autotune: stream or event set-up failed");
+  }
+  constexpr int TUNE_STEPS = 4;   // steps per timed graph
   int rc = QG_OK;
   bool changed = false;
-  auto time_group = [&](Group& g, float* ms) -> int {
-    for (int k = 0; k < 2; ++k) { int r = run_step(h, g, st); if (r) return r; }
-    if (hipEventRecord(e0, st) != hipSuccess) return fail(QG_EHIP, "event record");
-    for (int k = 0; k < 4; ++k) { int r = run_step(h, g, st); if (r) return r; }
-    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(QG_EHIP, "event timing");
-    return QG_OK;
-  };
-  auto valid = [&](const Group& g, int W) { return W >= min_width(g) && W <= max_width(g) && is_pow2(W); };
+  auto valid_w = [&](const Group& g, int W) { return W >= min_width(g) && W <= max_width(g) && is_pow2(W); };
   for (auto& g : h.groups) {
+    if (rc) break;
     const std::string key = group_key(g);
-    auto itf = cache.find(key + "/fwd");
-    auto iti = cache.find(key + "/inv");
-    if (itf != cache.end() && iti != cache.end() && valid(g, itf->second) && valid(g, iti->second)) {
-      set_width(g, itf->second);
-      set_inv_width(g, iti->second);
+    // admissible values of every tunable; a value found in the cache fixes it
+    std::vector<int> Ws, Wis, rs, cs, rp;
+    for (int W = min_width(g); W <= max_width(g); W *= 2) { Ws.push_back(W); Wis.push_back(W); }
+    const bool ct_rows = g.nx == 256 || g.nx == 512 || g.nx == 1024;
+    const bool ct_cols = g.ny == 256 || g.ny == 512 || g.ny == 1024;
+    rs = ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
+    cs = ct_cols ? std::vector<int>{0, 1} : std::vector<int>{0};
+    rp = g.ny >= 64 ? std::vector<int>{1, 2} : std::vector<int>{1};
+    auto fix = [&](const char* name, std::vector<int>& vals, bool ok_range) {
+      auto it = cache.find(key + name);
+      if (it == cache.end()) return;
+      if (ok_range) vals.assign(1, it->second);
+    };
+    {
+      auto it = cache.find(key + "/fwd");
+      fix("/fwd", Ws, it != cache.end() && valid_w(g, it->second));
+      it = cache.find(key + "/inv");
+      fix("/inv", Wis, it != cache.end() && valid_w(g, it->second));
+      it = cache.find(key + "/rsched");
+      fix("/rsched", rs, it != cache.end() && (it->second == 0 || (ct_rows && it->second == 1)));
+      it = cache.find(key + "/csched");
+      fix("/csched", cs, it != cache.end() && (it->second == 0 || (ct_cols && it->second == 1)));
+      it = cache.find(key + "/rpb");
+      fix("/rpb", rp, it != cache.end() && (it->second == 1 || (g.ny >= 64 && it->second == 2)));
+    }
+    std::vector<Tuning> cand;
+    for (int W : Ws)
+      for (int Wi : Wis)
+        for (int r : rs)
+          for (int c : cs)
+            for (int q : rp) cand.push_back(Tuning{W, Wi, r, c, q});
+    if (cand.size() == 1) {
+      apply_tuning(g, cand[0]);
       continue;
     }
-    // forward strip width first (inverse width at its default), then the
-    // inverse width.  The device first runs steps for a while (clocks ramp up
-    // from idle), then the candidates are timed round-robin three times and
-    // each keeps its fastest time.
-    {
-      float ms = 0.f;
-      for (int k = 0; k < 8 && rc == QG_OK; ++k) rc = time_group(g, &ms);
+    // every candidate as a graph of TUNE_STEPS steps of this group
+    std::vector<hipGraphExec_t> ex(cand.size(), nullptr);
+    for (size_t i = 0; i < cand.size() && rc == QG_OK; ++i) {
+      apply_tuning(g, cand[i]);
+      hipGraph_t graph;
+      if (hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(QG_EHIP, "autotune: capture failed");
+        break;
+      }
+      int r2 = QG_OK;
+      for (int k = 0; k < TUNE_STEPS && r2 == QG_OK; ++k) r2 = run_step(h, g, ts);
+      hipError_t e = hipStreamEndCapture(ts, &graph);
+      if (r2) { if (e == hipSuccess) (void)hipGraphDestroy(graph); rc = r2; break; }
+      if (e != hipSuccess) { rc = fail(QG_EHIP, std::string("autotune capture: ") + hipGetErrorString(e)); break; }
+      e = hipGraphInstantiate(&ex[i], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) { ex[i] = nullptr; rc = fail(QG_EHIP, "autotune: graph instantiation failed"); }
     }
-    for (int pass = 0; pass < 2 && rc == QG_OK; ++pass) {
-      std::map<int, float> best;
-      for (int round = 0; round < 3 && rc == QG_OK; ++round)
-        for (int W = min_width(g); W <= max_width(g) && rc == QG_OK; W *= 2) {
-          if (pass == 0) set_width(g, W); else set_inv_width(g, W);
-          float ms = 0.f;
-          rc = time_group(g, &ms);
-          if (rc == QG_OK && (!best.count(W) || ms < best[W])) best[W] = ms;
+    // warm-up (clocks ramp up from idle), then three round-robin rounds;
+    // each candidate keeps its fastest time
+    std::vector<float> best(cand.size(), 1e30f);
+    for (int round = -2; round < 3 && rc == QG_OK; ++round)
+      for (size_t i = 0; i < cand.size() && rc == QG_OK; ++i) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, ts) != hipSuccess || hipGraphLaunch(ex[i], ts) != hipSuccess ||
+            hipEventRecord(e1, ts) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(QG_EHIP, "autotune: timing failed");
+          break;
         }
-      int bestW = pass == 0 ? g.W : g.Wi;
-      float bt = 1e30f;
-      for (auto& kv : best)
-        if (kv.second < bt) { bt = kv.second; bestW = kv.first; }
-      if (pass == 0) set_width(g, bestW); else set_inv_width(g, bestW);
-    }
+        if (round >= 0 && ms < best[i]) best[i] = ms;
+      }
+    for (auto x : ex)
+      if (x) (void)hipGraphExecDestroy(x);
+    if (rc) break;
+    size_t bi = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+      if (best[i] < best[bi]) bi = i;
+    apply_tuning(g, cand[bi]);
     cache[key + "/fwd"] = g.W;
     cache[key + "/inv"] = g.Wi;
+    cache[key + "/rsched"] = g.rsch;
+    cache[key + "/csched"] = g.csch;
+    cache[key + "/rpb"] = g.rpb;
     changed = true;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  cleanup();
   if (rc) return rc;
   // the timed steps advanced the AB2CN members' history: start it again
   for (const auto& g : h.groups) {
@@ -1544,6 +1629,21 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
   h.adj_graphs.clear();
   if (changed && cache_path) write_width_cache(cache_path, cache);
   QG_HIP(hipStreamSynchronize(st));
+  return QG_OK;
+}
+
+int qg_tuning(const qg_handle* H, int32_t* out) {
+  if (!H || !out) return fail(QG_EINVAL, "NULL argument");
+  const Handle& h = H->h;
+  for (size_t i = 0; i < h.params.size(); ++i) {
+    const Group& g = h.groups[h.member_group[i]];
+    int32_t* o = out + 5 * i;
+    o[0] = g.W;
+    o[1] = g.Wi;
+    o[2] = g.rsch;
+    o[3] = g.csch;
+    o[4] = g.rpb;
+  }
   return QG_OK;
 }
 

@@ -14,15 +14,14 @@
 // transforms use the conjugate twiddles and are also unnormalised (callers
 // fold 1/(nx ny) into the spectral data).
 //
-// Every engine runs the same pass schedule: radix 8 while at least three
-// factors of two remain, then one radix-4 or radix-2 pass.  Twiddles come
-// from a per-pass table staged in LDS (computed on the host in extended
-// precision and rounded once): the pass with sub-transform length Ns >= 8
-// and radix R keeps exp(-2 pi i t k / (Ns R)) at
+// The passes follow a schedule of radices (pass_log_radix below).  Twiddles
+// come from a per-pass table (computed on the host in extended precision
+// and rounded once), one per schedule: the pass with sub-transform length
+// Ns >= 8 and radix R keeps exp(-2 pi i t k / (Ns R)) at
 //     (Ns - 8) + k (R - 1) + (t - 1),   0 <= k < Ns,  1 <= t < R,
-// so a butterfly reads its R - 1 twiddles from consecutive slots; the table
-// of a length-N transform has N - 8 entries (the first pass, Ns = 1, needs
-// none).
+// so a butterfly reads its R - 1 twiddles from consecutive slots; the pass
+// fills slots [Ns - 8, Ns R - 8), so the table of a length-N transform has
+// N - 8 entries whatever the schedule (the first pass, Ns = 1, needs none).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -46,6 +45,20 @@ template <typename V> __device__ __forceinline__ V cscale(V a, decltype(V{}.x) s
 // multiplication by +i and by -i
 template <typename V> __device__ __forceinline__ V cmul_i(V a) { return cmake<V>(-a.y, a.x); }
 template <typename V> __device__ __forceinline__ V cmul_mi(V a) { return cmake<V>(a.y, -a.x); }
+
+// Pass schedules.  A transform of length 2^logn is a sequence of Stockham
+// passes; the pass with sub-transform length 2^logns has radix
+// 2^pass_log_radix(logn, logns, sch).  The first pass (logns = 0) is radix
+// 8 in every schedule (its inputs come from registers).  Schedule 0: radix 8
+// while three factors of two remain, then one radix-4 or radix-2 pass
+// (1024 = 8 8 8 2); schedule 1: radix 4 while more than three factors
+// remain, then the rest in one pass (1024 = 8 4 4 8, 512 = 8 4 4 4, 256 =
+// 8 4 8).  The run-time engines use schedule 0; the compile-time ones take
+// either (a tuning choice), each with its own twiddle table.
+__host__ __device__ constexpr int pass_log_radix(int logn, int logns, int sch) {
+  return logns == 0 ? 3 : sch == 0 ? (logn - logns >= 3 ? 3 : logn - logns) : (logn - logns > 3 ? 2 : logn - logns);
+}
+constexpr int NSCHED = 2;
 
 // Radix-2/4/8 DFT kernels in registers.  INV selects exp(+2 pi i / R).
 template <typename V, bool INV> __device__ __forceinline__ void dft2(V* v) {
@@ -86,6 +99,41 @@ template <typename V, bool INV> __device__ __forceinline__ void dft8(V* v) {
   dft4<V, INV>(b0, b1, b2, b3);
   v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
   v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+}
+
+// Length-8 DFT whose inputs v_t with bit t of ZM set are known to be zero
+// (band-limited data: the 2/3 rule and the test filter leave whole blocks of
+// a transform's input empty).  The first layer of the split drops the
+// additions with a zero operand; the rest is dft8.
+template <typename V, bool INV, int ZM> __device__ __forceinline__ void dft8z(V* v) {
+  using T = decltype(V{}.x);
+  if constexpr (ZM == 0) {
+    dft8<V, INV>(v);
+  } else {
+    const T h = T(0.70710678118654752440084436210485);
+    V a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool z0 = (ZM >> t) & 1, z1 = (ZM >> (t + 4)) & 1;
+      if (z0 && z1) { a[t] = cmake<V>(T(0), T(0)); b[t] = a[t]; }
+      else if (z1) { a[t] = v[t]; b[t] = v[t]; }
+      else if (z0) { a[t] = v[t + 4]; b[t] = cmake<V>(-v[t + 4].x, -v[t + 4].y); }
+      else { a[t] = cadd(v[t], v[t + 4]); b[t] = csub(v[t], v[t + 4]); }
+    }
+    if (!INV) {
+      b[1] = cmake<V>((b[1].x + b[1].y) * h, (b[1].y - b[1].x) * h);
+      b[2] = cmul_mi(b[2]);
+      b[3] = cmake<V>((b[3].y - b[3].x) * h, -(b[3].x + b[3].y) * h);
+    } else {
+      b[1] = cmake<V>((b[1].x - b[1].y) * h, (b[1].y + b[1].x) * h);
+      b[2] = cmul_i(b[2]);
+      b[3] = cmake<V>(-(b[3].x + b[3].y) * h, (b[3].x - b[3].y) * h);
+    }
+    dft4<V, INV>(a[0], a[1], a[2], a[3]);
+    dft4<V, INV>(b[0], b[1], b[2], b[3]);
+    v[0] = a[0]; v[2] = a[1]; v[4] = a[2]; v[6] = a[3];
+    v[1] = b[0]; v[3] = b[1]; v[5] = b[2]; v[7] = b[3];
+  }
 }
 
 template <typename V, int R, bool INV> __device__ __forceinline__ void dftR(V* v) {
@@ -265,10 +313,11 @@ __device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restri
 template <int P> __device__ __forceinline__ int padp(int i) { return i + (i >> P); }
 
 // First pass (radix 8) from registers: butterfly j writes x'[8 j + t].
-template <typename V, bool INV, int P>
+// ZM: inputs known to be zero (bit t: x[j + t N/8]), see dft8z.
+template <typename V, bool INV, int P, int ZM = 0>
 __device__ __forceinline__ void fft1c_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active) {
   static_assert(P >= 3, "pad period of at least 8");
-  if (active) dftR<V, 8, INV>(v);
+  if (active) dft8z<V, INV, ZM>(v);
   __syncthreads();
   if (active) {
     V* wb = buf + 8 * j + (j >> (P - 3));
@@ -278,17 +327,23 @@ __device__ __forceinline__ void fft1c_pass0(V (&v)[8], V* __restrict__ buf, int 
   __syncthreads();
 }
 
-template <typename V, int LOGN, int LOGNS, bool INV, int P>
+// One pass of the compile-time engine, radix R = 2^pass_log_radix(LOGN,
+// LOGNS, SCH), N/8 threads with 8 elements each (8/R butterflies per
+// thread: j + b N/8).  A pass before the last has Ns dividing N/8, so the
+// butterflies of a thread share their twiddles and their outputs lie N R/8
+// apart; in the last pass (Ns R = N) every butterfly index is below Ns.
+template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH>
 __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
   constexpr int N = 1 << LOGN;
   constexpr int NS = 1 << LOGNS;
-  constexpr int REM = LOGN - LOGNS;
-  constexpr int R = REM >= 3 ? 8 : REM == 2 ? 4 : 2;
-  constexpr int logR = R == 8 ? 3 : R == 4 ? 2 : 1;
+  constexpr int logR = pass_log_radix(LOGN, LOGNS, SCH);
+  constexpr int R = 1 << logR;
+  constexpr bool LAST = LOGNS + logR == LOGN;
   constexpr int NB = 8 / R;          // butterflies per thread
   constexpr int nt = N / 8;          // threads per transform
   constexpr int NR = N / R;
   static_assert(LOGN >= P + 3 && LOGNS >= 3, "compile-time engine: N >= 8 * 2^P, passes after the first");
+  static_assert(LAST || NB == 1 || nt % NS == 0, "a pass before the last has Ns dividing N/8");
   V v[NB][R];
   if (active) {
     const V* rb = buf + padp<P>(j);
@@ -296,8 +351,7 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
       for (int t = 0; t < R; ++t) v[b][t] = rb[b * (nt + (nt >> P)) + t * (NR + (NR >> P))];
-      // butterfly j + b nt; in a radix-4/2 pass (the last) it is below Ns
-      const int k = NB == 1 ? (j & (NS - 1)) : j + b * nt;
+      const int k = (NB > 1 && LAST) ? j + b * nt : (j & (NS - 1));
       const V* w = tw + (NS - 8) + k * (R - 1);
 #pragma unroll
       for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], INV ? cconj(w[t - 1]) : w[t - 1]);
@@ -306,28 +360,32 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
   }
   __syncthreads();
   if (active) {
-    if constexpr (NB == 1) {
-      const int k = j & (NS - 1);
-      V* wb = buf + padp<P>(((j >> LOGNS) << (LOGNS + logR)) + k);
-#pragma unroll
-      for (int t = 0; t < R; ++t) wb[t * NS + ((t * NS) >> P)] = v[0][t];
-    } else {
+    if constexpr (NB > 1 && LAST) {
       V* wb = buf + padp<P>(j);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int t = 0; t < R; ++t) wb[b * (nt + (nt >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
       }
+    } else {
+      constexpr int BO = nt * R;   // output offset of the thread's next butterfly
+      const int k = j & (NS - 1);
+      V* wb = buf + padp<P>(((j >> LOGNS) << (LOGNS + logR)) + k);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) wb[b * (BO + (BO >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
+      }
     }
   }
   __syncthreads();
-  if constexpr (REM > 3) fft1c_pass<V, LOGN, LOGNS + 3, INV, P>(buf, tw, j, active);
+  if constexpr (!LAST) fft1c_pass<V, LOGN, LOGNS + logR, INV, P, SCH>(buf, tw, j, active);
 }
 
-// Passes after the first (fft1c_pass0), compile-time length.
-template <typename V, int LOGN, bool INV, int P>
+// Passes after the first (fft1c_pass0), compile-time length, schedule SCH.
+template <typename V, int LOGN, bool INV, int P, int SCH = 0>
 __device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
-  fft1c_pass<V, LOGN, 3, INV, P>(buf, tw, j, active);
+  fft1c_pass<V, LOGN, 3, INV, P, SCH>(buf, tw, j, active);
 }
 
 // The whole block as one group.

@@ -109,6 +109,13 @@ struct Phase {
   // end); null otherwise
   void* ev0;
   void* ev1;
+  // tuning choices of the compile-time engines of the step's passes: pass
+  // schedule of the row transforms (rsch) and of the column transforms
+  // (csch), with the twiddle tables of schedule 1 (twx1, twy1); row pairs
+  // per block of the row pass (rpb)
+  int rsch, csch, rpb;
+  const void* twx1;
+  const void* twy1;
 };
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048

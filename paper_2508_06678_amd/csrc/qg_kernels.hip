@@ -182,6 +182,14 @@ __device__ __forceinline__ int test_mylim(const MemberDev& M, int nx, int ny, in
   return (int)s;
 }
 
+// Band-limited transform inputs.  A length-N transform of the compile-time
+// engines takes element t of thread j at index j + t N/8.  On the 2/3 set
+// the nonzero indices are |m| <= (N - 1)/3 (m = index, or index - N in the
+// upper half), so the blocks t = 3, 4 are empty; the test filter (test
+// ratio >= 2) keeps |m| <= (N - 1)/6 + 1 <= N/4, so the blocks t = 2..5 are
+// empty.  Bit t of the mask marks an empty block.
+template <bool TEST> __host__ __device__ constexpr int band_zero_mask() { return TEST ? 0x3c : 0x18; }
+
 // psi_hat = -x / |k|^2, in double precision for the lowest modes of 32-bit runs
 template <typename T>
 __device__ __forceinline__ cpx<T> poisson(const MemberDev& M, cpx<T> x, const Wave<T>& w, int mx, int my) {
@@ -321,7 +329,7 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
 // one compile-time-length transform per column (ny/8 threads each, the
 // first pass fed from registers, twiddles from the global table); LOGN = 0
 // the run-time engines.
-template <typename T, int OP, int CL, int LOGN>
+template <typename T, int OP, int CL, int LOGN, int SCH = 0>
 __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -349,29 +357,55 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     const int j = threadIdx.x & (NT - 1);
     const int mx = kx0 + w;
     V* buf = tile + w * STR;
-    // the test set's extent in this column, for the test-filtered fields
-    // only (the grid-level fields ignore it)
-    const int mylim = dynamic_closure(CL) && f >= rhs_fields(CL) / 2 && mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
+    // Rows y = j + t NY/8 of the column (m_y = y, or y - NY in the upper
+    // half).  The 2/3 set keeps |m_y| <= myh = (NY - 1)/3: the blocks t =
+    // 0, 1, 6, 7 hold only such rows, t = 3, 4 none.  The test filter keeps
+    // |m_y| <= test_mylim(m_x) <= (NY - 1)/6 (test ratio >= 2): blocks t =
+    // 2..5 hold none.  Empty blocks are neither formed nor added in the
+    // first radix-8 pass.
+    constexpr int MYH = (NY - 1) / 3;
+    const bool testf = dynamic_closure(CL) && (OP == OP_RHS || OP == OP_DIAG) && f >= rhs_fields(CL) / 2;
     V v[8];
+    if (testf) {
+      // the test set's extent in this column
+      const int mylim = mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int y = j + t * NT;
-      const int my = y < NY / 2 ? y : y - NY;
-      V z = cmake<V>(T(0), T(0));
-      if (mx < P.kxn && my <= P.myh && -my <= P.myh) {
-        const int iy = my >= 0 ? my : my + P.kyn;
-        z = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, mylim), scale);
+      for (int t = 0; t < 8; ++t) {
+        v[t] = cmake<V>(T(0), T(0));
+        if (t >= 2 && t <= 5) continue;
+        const int y = j + t * NT;
+        const int my = t < 4 ? y : y - NY;
+        if (my <= mylim && -my <= mylim) {
+          const int iy = my >= 0 ? my : my + P.kyn;
+          v[t] = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, mylim), scale);
+        }
       }
-      v[t] = z;
+      fft1c_pass0<V, true, PD, band_zero_mask<true>()>(v, buf, j, true);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        v[t] = cmake<V>(T(0), T(0));
+        if (t == 3 || t == 4) continue;
+        const int y = j + t * NT;
+        const int my = t < 4 ? y : y - NY;
+        const bool in = (t <= 1 || t >= 6) || (t == 2 ? my <= MYH : -my <= MYH);
+        if (mx < P.kxn && in) {
+          const int iy = my >= 0 ? my : my + P.kyn;
+          v[t] = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, -1), scale);
+        }
+      }
+      fft1c_pass0<V, true, PD, band_zero_mask<false>()>(v, buf, j, true);
     }
-    fft1c_pass0<V, true, PD>(v, buf, j, true);
-    fft1c_rest<V, LOGN, true, PD>(buf, reinterpret_cast<const V*>(P.twy), j, true);
+    fft1c_rest<V, LOGN, true, PD, SCH>(buf, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), j, true);
+    // rows of the strip: Wi values of row y per thread group of Wi
+    // threads, eight rows NY/8 apart per thread
     V* out = cptr<T>(M, P.o_mf) + (long long)f * NY * P.mfp + kx0;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-      const int c = q & (P.Wi - 1);
-      const int y = q >> P.logWi;
-      gst(out + y * P.mfp + c, tile[c * STR + padp<PD>(y)]);
-    }
+    const int c = threadIdx.x & (P.Wi - 1);
+    const int y0 = threadIdx.x >> P.logWi;
+    const V* src = tile + c * STR + padp<PD>(y0);
+    V* dst = out + y0 * P.mfp + c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) gst(dst + i * (NY / 8) * P.mfp, src[i * (NY / 8 + (NY / 8 >> PD))]);
     return;
   }
   V* twl = tile + P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0);
@@ -1004,6 +1038,55 @@ __device__ __forceinline__ cpx<T> c2r_form(cpx<T> a, cpx<T> b, int k, int nx, in
   return cmake<V>(T(0), T(0));
 }
 
+// The same for the compile-time row engine (row length N = 2^LOGN, element t
+// of thread j at column k = j + t N/8).  Columns m_x < kin hold modes and
+// N - kin < k < N their mirrors; the band between is zero.  At the grid
+// level kin = kxn = (N - 1)/3 + 1, so the blocks t = 3, 4 lie inside the
+// band and t = 0, 1, 6, 7 wholly outside it; at the test level (test ratio
+// >= 2) kin <= (N - 1)/6 + 1 <= N/4, so the blocks t = 2..5 lie inside it.
+// Blocks known to be zero (the bits of band_zero_mask) are neither loaded
+// nor added in the first radix-8 pass of the transform.
+
+template <typename T, int LOGN, bool TL>
+__device__ __forceinline__ void c2r_loadc(RowRaw<T>& r, const cpx<T>* row, int pitch, int j, int kin) {
+  using V = cpx<T>;
+  constexpr int N = 1 << LOGN, NG = N / 8, KIN = (N - 1) / 3 + 1;
+  constexpr int ZM = band_zero_mask<TL>();
+  const V* fw = row + j;          // column j + t NG at fw + t NG
+  const V* bw = row + (N - j);    // its mirror N - j - t NG at bw - t NG (t >= 4)
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    r.a[t] = r.b[t] = cmake<V>(T(0), T(0));
+    if ((ZM >> t) & 1) continue;
+    const bool mirror = t >= 4;
+    bool in;
+    if (mirror) in = (!TL && t >= 6) || (N - t * NG - j) < (TL ? kin : KIN);
+    else in = (!TL && t <= 1) || j + t * NG < (TL ? kin : KIN);
+    if (in) {
+      const V* q = mirror ? bw - t * NG : fw + t * NG;
+      r.a[t] = gld(q);
+      r.b[t] = gld(q + pitch);
+    }
+  }
+}
+
+template <typename T, bool TL>
+__device__ __forceinline__ void c2r_formc(const RowRaw<T>& in, cpx<T> (&v)[8], int j) {
+  using V = cpx<T>;
+  constexpr int ZM = band_zero_mask<TL>();
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if ((ZM >> t) & 1) { v[t] = cmake<V>(T(0), T(0)); continue; }
+    V a = in.a[t], b = in.b[t];
+    if (t < 4) {
+      if (t == 0 && j == 0) { a.y = T(0); b.y = T(0); }   // the m_x = 0 column is real
+      v[t] = cmake<V>(a.x - b.y, a.y + b.x);
+    } else {
+      v[t] = cmake<V>(a.x + b.y, b.x - a.y);
+    }
+  }
+}
+
 // Column limit of the c2r input: the test-filtered level holds no mode at
 // m_x >= test_kx.
 __device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, int lev) {
@@ -1013,7 +1096,7 @@ __device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, int 
 // One item of the row pass: row pair rb of member mem at level lev, from
 // the packed c2r inputs vin (column j + t nx/8 of the thread's group);
 // twl: the x twiddle table (global or staged in LDS).
-template <typename T, int OP, int CL, int LOGN>
+template <typename T, int OP, int CL, int LOGN, int ZM = 0, int SCH = 0>
 __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int lev, const cpx<T> (&vin)[8],
                                           cpx<T>* buf, const cpx<T>* twl, double* red, int item_slot) {
   using V = cpx<T>;
@@ -1024,9 +1107,9 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   // member constants read once, not per point
   const T U = T(M.u_in), Vv = T(M.v_in);
   const T coef = OP == OP_ADJ_RHS ? adj_coef<T>(M, P) : T(M.coef_static);
-  const int nx = P.nx;
+  const int nx = LOGN ? (1 << LOGN) : P.nx;
   const int bstride = nx + (nx >> PADS);
-  const int lg = P.lognx - 3;
+  const int lg = LOGN ? LOGN - 3 : P.lognx - 3;
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
   const int ng = 1 << lg;                      // threads per group
@@ -1041,8 +1124,8 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
 #pragma unroll
     for (int t = 0; t < EPT; ++t) v[t] = vin[t];
     if constexpr (LOGN != 0) {
-      fft1c_pass0<V, true, PADS>(v, mybuf, j, true);
-      fft1c_rest<V, LOGN, true, PADS>(mybuf, twl, j, true);
+      fft1c_pass0<V, true, PADS, ZM>(v, mybuf, j, true);
+      fft1c_rest<V, LOGN, true, PADS, SCH>(mybuf, twl, j, true);
     } else {
       fft1_pass0<V, true>(v, mybuf, j, true);
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
@@ -1085,12 +1168,39 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   // ---- r2c of product grp, keep m_x < kxn
   if constexpr (LOGN != 0) {
     fft1c_pass0<V, false, PADS>(v, mybuf, j, act);
-    fft1c_rest<V, LOGN, false, PADS>(mybuf, twl, j, act);
+    fft1c_rest<V, LOGN, false, PADS, SCH>(mybuf, twl, j, act);
   } else {
     fft1_pass0<V, false>(v, mybuf, j, act);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
   }
-  if (act) {
+  if constexpr (LOGN != 0) {
+    // columns k = j + t N/8 below kxn (t = 0, 1 always, t = 2 for the first
+    // kxn - N/4 threads); the mirror N - k sits at constant offsets below
+    // padp(N - j), except k = 0 whose mirror is itself
+    constexpr int N = 1 << LOGN, NG = N / 8, KXN = (N - 1) / 3 + 1;
+    constexpr int DPAD = NG + (NG >> PADS);
+    if (act) {
+      V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
+      const int o0 = mix_at(C, ya, j);
+      const int iz = padp<PADS>(j);
+      const int izm = padp<PADS>(N - j);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t == 2 && j + 2 * NG >= KXN) break;
+        const V z = mybuf[iz + t * DPAD];
+        const V zm = mybuf[(t == 0 && j == 0) ? 0 : izm - t * DPAD];
+        const int o = o0 + t * NG * P.ny;
+        const V ra = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));     // row ya
+        const V rb2 = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));    // row ya + 1
+        if (C.logW == 0) {
+          gst_pair(dst + o, ra, rb2);
+        } else {
+          gst(dst + o, ra);
+          gst(dst + o + (1 << C.logW), rb2);
+        }
+      }
+    }
+  } else if (act) {
     V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
       const int a = k, b = (nx - k) & (nx - 1);
@@ -1135,7 +1245,7 @@ __device__ __forceinline__ void rowp_load(const Phase& P, int mem, int rb, int l
 
 // Right-hand side, B sub-step and adjoint right-hand side: one block per
 // row pair (grid.x), level (grid.y) and member (grid.z).
-template <typename T, int OP, int CL, int LOGN>
+template <typename T, int OP, int CL, int LOGN, int SCH = 0>
 __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
@@ -1144,18 +1254,48 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   V* buf = reinterpret_cast<V*>(smem_raw);
   // consecutive row pairs on the same XCD: their interleaved output stores
   // meet in one L2
-  int rb = blockIdx.x;
-  if ((gridDim.x & 7) == 0) rb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  int rbb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) rbb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   // the two levels of the dynamic closures (grid and test filter) are
   // independent: one block each
   const int lev = dyn ? (int)blockIdx.y : 0;
-  RowRaw<T> in;
-  rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
-  V vin[8];
-  rowp_form<T>(P, blockIdx.z, lev, in, vin);
   // twiddles straight from the (cached) global table: keeping LDS to the
   // field buffers lets one more block share a compute unit
-  rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, reinterpret_cast<const V*>(P.twx), red, blockIdx.x);
+  const V* twl = reinterpret_cast<const V*>(SCH ? P.twx1 : P.twx);
+  // the step's passes may take several row pairs per block, one after the
+  // other (a tuning choice)
+  const int rpb = (OP == OP_RHS || OP == OP_B) ? P.rpb : 1;
+  for (int r = 0; r < rpb; ++r) {
+  const int rb = rbb * rpb + r;
+  if constexpr (LOGN != 0) {
+    // compile-time row length: loads, packing and the first pass leave out
+    // the blocks of columns the 2/3 set (grid level) or the test filter
+    // (test level) keep empty
+    constexpr int nb = rowp_nb(OP, CL);
+    const MemberDev M = member_const(P, blockIdx.z);
+    const int grp = threadIdx.x >> (LOGN - 3);
+    const int j = threadIdx.x & ((1 << (LOGN - 3)) - 1);
+    const cpx<T>* row = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * ((long long)P.ny * P.mfp) +
+                        (long long)(2 * rb) * P.mfp;
+    RowRaw<T> in;
+    V vin[8];
+    if (dyn && lev == 1) {
+      c2r_loadc<T, LOGN, true>(in, row, P.mfp, j, min(P.kxn, M.test_kx));
+      c2r_formc<T, true>(in, vin, j);
+      rowp_item<T, OP, CL, LOGN, band_zero_mask<true>(), SCH>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
+    } else {
+      c2r_loadc<T, LOGN, false>(in, row, P.mfp, j, P.kxn);
+      c2r_formc<T, false>(in, vin, j);
+      rowp_item<T, OP, CL, LOGN, band_zero_mask<false>(), SCH>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
+    }
+  } else {
+    RowRaw<T> in;
+    rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
+    V vin[8];
+    rowp_form<T>(P, blockIdx.z, lev, in, vin);
+    rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
+  }
+  }
 }
 
 // ---------------------------------------------------------------- AB2CN
@@ -1536,7 +1676,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
 // W ny / 8 threads transform them concurrently, then every thread combines
 // the retained modes straight from LDS.  Used when np W ny / 8 <= 1024 and
 // the strips fit in LDS (in particular W = 1 at ny <= 1024).
-template <typename T, int OP, int CL, int LOGN>
+template <typename T, int OP, int CL, int LOGN, int SCH = 0>
 __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
@@ -1550,11 +1690,11 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   // twiddles then read from the global table)
   const bool one = LOGN != 0 || P.W == 1;
   constexpr int CPD = LOGN ? QG_COL_PADS : 3;   // pad period of the single-column path
-  const int n = P.W * P.ny + (one ? P.ny >> CPD : 0);
+  const int n = LOGN ? (1 << LOGN) + (1 << (LOGN - CPD)) : P.W * P.ny + (one ? P.ny >> CPD : 0);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + np * n;
   if constexpr (LOGN == 0) stage_twiddles<V>(twl, reinterpret_cast<const V*>(P.twy), P.logny);
-  const int lg = P.logW + P.logny - 3;     // log2 of the group size W ny/8
+  const int lg = LOGN ? LOGN - 3 : P.logW + P.logny - 3;     // log2 of the group size W ny/8
   const int grp = threadIdx.x >> lg;
   const int lt = threadIdx.x & ((1 << lg) - 1);
   const int strip = xcd_order(blockIdx.x, gridDim.x);
@@ -1567,7 +1707,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     if constexpr (LOGN != 0) {
       fft1c_pass0<V, false, CPD>(v, tile + grp * n, lt, true);
-      fft1c_rest<V, LOGN, false, CPD>(tile + grp * n, reinterpret_cast<const V*>(P.twy), lt, true);
+      fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), lt,
+                                           true);
     } else {
       __syncthreads();   // twiddles staged
       fft1_pass0<V, false>(v, tile + grp * n, lt, true);
@@ -2127,10 +2268,23 @@ static void launch_colinv_t(const Phase& P, int nmem, hipStream_t s) {
     // compile-time column lengths for the common sizes (every op: the
     // kernel's compile-time path is generic in the field formation)
     const size_t lds = (size_t)P.Wi * colinv_stride(P.ny) * sizeof(cpx<T>);
-    switch (P.logny) {
-      case 8: QG_KLAUNCH((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P); return;
-      case 9: QG_KLAUNCH((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P); return;
-      case 10: QG_KLAUNCH((k_colinv<T, OP, CL, 10>), grid, block, lds, s, P); return;
+    // (their engines assume spectral fields on the 2/3 set)
+    const int logny = P.myh == (P.ny - 1) / 3 && P.kxn == (P.nx - 1) / 3 + 1 ? P.logny : 0;
+    // the step's passes take the tuned pass schedule
+    const bool s1 = (OP == OP_RHS || OP == OP_B) && P.csch == 1;
+    switch (logny) {
+      case 8:
+        if (s1) QG_KLAUNCH((k_colinv<T, OP, CL, 8, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colinv<T, OP, CL, 8>), grid, block, lds, s, P);
+        return;
+      case 9:
+        if (s1) QG_KLAUNCH((k_colinv<T, OP, CL, 9, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colinv<T, OP, CL, 9>), grid, block, lds, s, P);
+        return;
+      case 10:
+        if (s1) QG_KLAUNCH((k_colinv<T, OP, CL, 10, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colinv<T, OP, CL, 10>), grid, block, lds, s, P);
+        return;
       default: break;
     }
   }
@@ -2150,12 +2304,27 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
   const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
   const dim3 block(nb * P.nx / 8);
-  dim3 grid(P.ny / 2, levels, nmem);
-  // compile-time transform lengths for the common row lengths
-  switch (P.lognx) {
-    case 8: QG_KLAUNCH((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P); return;
-    case 9: QG_KLAUNCH((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P); return;
-    case 10: QG_KLAUNCH((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+  // the step's passes take the tuned row pairs per block and pass schedule
+  const bool step = OP == OP_RHS || OP == OP_B;
+  const int rpb = step ? P.rpb : 1;
+  const bool s1 = step && P.rsch == 1;
+  dim3 grid(P.ny / (2 * rpb), levels, nmem);
+  // compile-time transform lengths for the common row lengths (their
+  // engines assume the mixed fields hold the 2/3 set: kxn columns)
+  const int lognx = P.kxn == (P.nx - 1) / 3 + 1 ? P.lognx : 0;
+  switch (lognx) {
+    case 8:
+      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 8, 1>), grid, block, lds, s, P);
+      else QG_KLAUNCH((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P);
+      return;
+    case 9:
+      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 9, 1>), grid, block, lds, s, P);
+      else QG_KLAUNCH((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P);
+      return;
+    case 10:
+      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 10, 1>), grid, block, lds, s, P);
+      else QG_KLAUNCH((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P);
+      return;
     default: QG_KLAUNCH((k_rowp<T, OP, CL, 0>), grid, block, lds, s, P); return;
   }
 }
@@ -2196,10 +2365,20 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
     // compile-time column lengths for the common sizes (one column per
     // block; every op, as for the column-inverse pass)
     const size_t lds = np * n * sizeof(cpx<T>);
+    const bool s1 = (OP == OP_RHS || OP == OP_B) && P.csch == 1;
     if (P.W == 1) switch (P.logny) {
-      case 8: QG_KLAUNCH((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P); return;
-      case 9: QG_KLAUNCH((k_colfwdp<T, OP, CL, 9>), grid, block, lds, s, P); return;
-      case 10: QG_KLAUNCH((k_colfwdp<T, OP, CL, 10>), grid, block, lds, s, P); return;
+      case 8:
+        if (s1) QG_KLAUNCH((k_colfwdp<T, OP, CL, 8, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colfwdp<T, OP, CL, 8>), grid, block, lds, s, P);
+        return;
+      case 9:
+        if (s1) QG_KLAUNCH((k_colfwdp<T, OP, CL, 9, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colfwdp<T, OP, CL, 9>), grid, block, lds, s, P);
+        return;
+      case 10:
+        if (s1) QG_KLAUNCH((k_colfwdp<T, OP, CL, 10, 1>), grid, block, lds, s, P);
+        else QG_KLAUNCH((k_colfwdp<T, OP, CL, 10>), grid, block, lds, s, P);
+        return;
       default: break;
     }
   }

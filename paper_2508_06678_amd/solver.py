@@ -184,6 +184,13 @@ class Solver:
                                            ctypes.byref(n), _stream(self.device)))
         return list(ms[:n.value])
 
+    def tuning(self):
+        """Launch configuration per member: dicts with W, Wi, rsched, csched, rpb."""
+        t = (ctypes.c_int32 * (5 * self.n))()
+        _lib.check(self.L.qg_tuning(self.h, t))
+        keys = ("W", "Wi", "rsched", "csched", "rpb")
+        return [dict(zip(keys, t[5 * i: 5 * i + 5])) for i in range(self.n)]
+
     def column_widths(self):
         """Strip width of the column-forward pass per member."""
         w = (ctypes.c_int32 * self.n)()

@@ -209,3 +209,41 @@ def test_oversized_dt_cfl_and_nonfinite_flag(precision):
             break
     assert fired is not None
     S.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("nx,ny,closure", [(1024, 512, "dleith"), (256, 1024, "dsmag")])
+def test_every_tuning_choice(tmp_path, precision, nx, ny, closure):
+    """Every combination of the tuner's choices for the compile-time engines
+    -- row and column pass schedules (1024 = 8 8 8 2 or 8 4 4 8, 512 = 8 8 8
+    or 8 4 4 4, 256 = 8 8 4 or 8 4 8), one or two row pairs per row block,
+    one or four columns per inverse strip -- forced through the tuning cache,
+    gives the oracle's step to the tolerance."""
+    import json
+    import torch
+    m = member(nx, ny, closure, init="spectrum")
+    M = oracle_model(m.params, m.chi, m.chi_s)
+    code = {"dsmag": 3, "dleith": 4}[closure]
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/{nx}x{ny}/fp{precision}/closure{code}/members1"
+    ref = None
+    wmax = min(4, (2048 if precision == 64 else 4096) // ny)   # widest inverse strip of one tile
+    for rs in (0, 1):
+        for cs in (0, 1):
+            for rpb in (1, 2):
+                for Wi in (1, wmax):
+                    choice = {"/fwd": 1, "/inv": Wi, "/rsched": rs, "/csched": cs, "/rpb": rpb}
+                    cache = tmp_path / f"t{rs}{cs}{rpb}{Wi}.json"
+                    cache.write_text(json.dumps({key + k: v for k, v in choice.items()}))
+                    S = solver_for([m], precision)
+                    S.autotune(str(cache))
+                    assert S.tuning() == [{"W": 1, "Wi": Wi, "rsched": rs, "csched": cs, "rpb": rpb}]
+                    om = S.pack([m.omega0])
+                    w_in = to_np(om).reshape(ny, nx)
+                    S.step(om, 1, use_graph=True)
+                    if ref is None:
+                        ref = qg.step(w_in, M)
+                    err = field_err(to_np(om).reshape(ny, nx), ref)
+                    say("  rsched", rs, "csched", cs, "rpb", rpb, "Wi", Wi, err)
+                    assert err < TOL[precision]
+                    S.close()
