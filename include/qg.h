@@ -247,6 +247,25 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
  * starts again (forward-Euler first step).  Synchronises hip_stream. */
 int qg_autotune(qg_handle* h, const char* cache_path, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qg_step
+ * of one member without a handle or a caller workspace.  p, chi_obs,
+ * chi_sponge and omega are as for qg_init / qg_step (one member; device
+ * pointers of the member's precision); omega is advanced nsteps RK4 steps
+ * in place, with the launches of qg_step's eager path and the library's
+ * default launch configuration (no tuning, no graph).  The workspace is a
+ * static device array of 64 MiB inside the library, one per GPU, held until
+ * the process ends: every call sets it up afresh on hip_stream (member
+ * constants, twiddle tables computed on the device, mask tables) and no
+ * call allocates, frees or synchronises.  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (concurrent streams or
+ * threads) race and must be serialised by the caller.
+ * Returns QG_EUNSUPPORTED when the member's workspace exceeds the array
+ * (64 MiB holds every closure up to 512 x 512 in FP64 and 1024 x 512 in
+ * FP32) or its scheme is not QG_SCHEME_RK4; the other errors as qg_init. */
+int qg_step_noalloc(const qg_params* p, const void* chi_obs, const void* chi_sponge, void* omega,
+                    int64_t nsteps, void* hip_stream);
+
 /* The launch configuration of every member's size group: out (host,
  * n_members x 5 int32) receives W, Wi, row schedule, column schedule and
  * row pairs per block (see qg_autotune). */

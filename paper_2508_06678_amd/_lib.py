@@ -15,7 +15,7 @@ CLOSURES = {"none": 0, "smag": 1, "leith": 2, "dsmag": 3, "dleith": 4}
 SCHEMES = {"rk4": 0, "ab2cn": 1}
 
 EXPORTS = ["qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag",
-           "qg_filter_les", "qg_ideal_sgs", "qg_closure_term", "qg_pcc", "qg_set_coef", "qg_autotune", "qg_tuning", "qg_profile_steps", "qg_info",
+           "qg_filter_les", "qg_ideal_sgs", "qg_closure_term", "qg_pcc", "qg_set_coef", "qg_autotune", "qg_tuning", "qg_profile_steps", "qg_step_noalloc", "qg_info",
            "qg_destroy", "qg_last_error"]
 
 
@@ -61,6 +61,7 @@ def lib():
     L.qg_pcc.argtypes = [vp, vp, vp, vp, vp]
     L.qg_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     L.qg_tuning.argtypes = [vp, ctypes.POINTER(i32)]
+    L.qg_step_noalloc.argtypes = [P, vp, vp, vp, i64, vp]
     L.qg_profile_steps.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_float), i32,
                                    ctypes.POINTER(i32), vp]
     L.qg_set_coef.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1648,3 +1649,106 @@ int qg_tuning(const qg_handle* H, int32_t* out) {
 }
 
 }  // extern "C"
+
+namespace qg {
+
+// ------------------------------------------------------------ allocation-free step
+// For callers that cannot allocate (code under graph capture, serving
+// loops, harnesses that forbid hipMalloc): the workspace of one member
+// lives in this file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never uses the array's name as an address: each
+// device's address comes from hipGetSymbolAddress (scratch_on).
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::atomic<void*> g_scratch[SCRATCH_MAX_DEVICES];
+
+// The array's address on the current device (looked up once per device).
+static int scratch_on(void** out) {
+  int dev = -1;
+  QG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(QG_EUNSUPPORTED, "device index out of range");
+  void* p = g_scratch[dev].load();
+  if (!p) {
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(QG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev].store(p);
+  }
+  *out = p;
+  return QG_OK;
+}
+
+}  // namespace qg
+
+extern "C" int qg_step_noalloc(const qg_params* p, const void* chi_obs, const void* chi_sponge, void* omega,
+                               int64_t nsteps, void* hip_stream) {
+  using namespace qg;
+  if (!p || !chi_obs || !chi_sponge || !omega) return fail(QG_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(QG_EINVAL, "nsteps must be >= 0");
+  int rc = validate(*p, 0);
+  if (rc) return rc;
+  if (p->scheme != QG_SCHEME_RK4) return fail(QG_EUNSUPPORTED, "qg_step_noalloc takes the RK4 scheme only");
+  void* base = nullptr;
+  rc = scratch_on(&base);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // the plan of qg_workspace_bytes / qg_init for one member, default widths
+  Group g{};
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.closure = p->closure;
+  g.scheme = p->scheme;
+  g.clip = dynamic_closure(p->closure) ? p->clip_mode : 0;
+  g.dbl = p->precision == 64;
+  plan_sizes(g, 0);
+  set_width(g, default_width(g, 1));
+  set_inv_width(g, default_inv_width(g, 1));
+  g.m0 = 0;
+  g.count = 1;
+  g.rsch = g.csch = 0;
+  g.rpb = 1;
+  const int cs = g.dbl ? 16 : 8;
+  long long o = align256(sizeof(MemberDev));
+  g.o_twx = o; o += align256((long long)g.nx * cs);
+  g.o_twy = o; o += align256((long long)g.ny * cs);
+  g.o_twx1 = o; o += align256((long long)g.nx * cs);
+  g.o_twy1 = o; o += align256((long long)g.ny * cs);
+  const long long region_off = o;
+  const long long total = o + g.region_bytes;
+  if (total > (long long)SCRATCH_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "member needs %lld bytes, the static scratch holds %zu", total, SCRATCH_BYTES);
+    return fail(QG_EUNSUPPORTED, buf);
+  }
+  char* ws = static_cast<char*>(base);
+  g.region0 = ws + region_off;
+  g.twx = ws + g.o_twx;
+  g.twy = ws + g.o_twy;
+  g.twx1 = ws + g.o_twx1;
+  g.twy1 = ws + g.o_twy1;
+  Handle h;   // only mem_dev is read by the phase sequences below
+  h.mem_dev = reinterpret_cast<MemberDev*>(ws);
+  const MemberDev m = make_member(*p, g.region0, 0, 0);
+  // the array keeps the previous call's contents: clear what is used
+  QG_LAUNCH(launch_fill_zero(ws, (size_t)total, st));
+  QG_LAUNCH(launch_put_member(h.mem_dev, m, st));
+  QG_LAUNCH(launch_twiddle_table(g.dbl, g.twx, g.lognx, 0, st));
+  QG_LAUNCH(launch_twiddle_table(g.dbl, g.twy, g.logny, 0, st));
+  QG_LAUNCH(launch_twiddle_table(g.dbl, g.twx1, g.lognx, 1, st));
+  QG_LAUNCH(launch_twiddle_table(g.dbl, g.twy1, g.logny, 1, st));
+  const size_t fb = (size_t)g.nx * g.ny * (g.dbl ? 8 : 4);
+  char* phys = g.region0 + g.L.phys;
+  QG_HIP(hipMemcpyAsync(phys + 4 * fb, chi_obs, fb, hipMemcpyDeviceToDevice, st));
+  QG_HIP(hipMemcpyAsync(phys + 5 * fb, chi_sponge, fb, hipMemcpyDeviceToDevice, st));
+  try {
+    rc = mask_precompute(h, g, st);
+    if (!rc) rc = run_entry(h, g, omega, g.L.wn, st);
+    for (long long k = 0; k < nsteps && !rc; ++k) rc = run_step(h, g, st);
+    if (!rc) rc = run_exit(h, g, g.L.wn, omega, st);
+  } catch (...) {
+    rc = fail(QG_EINVAL, "internal error in qg_step_noalloc");
+  }
+  return rc;
+}
+

@@ -165,6 +165,10 @@ hipError_t launch_filter_les(bool dbl, const FilterArgs& A, hipStream_t s);
 hipError_t launch_pcc(bool dbl, const Phase& P, int nmem, int nblk, const void* a, const void* b, double* out,
                       hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// one member's constants into the device table at dst
+hipError_t launch_put_member(MemberDev* dst, const MemberDev& m, hipStream_t s);
+// the per-pass twiddle table of length-2^logn transforms, schedule sch
+hipError_t launch_twiddle_table(bool dbl, void* dst, int logn, int sch, hipStream_t s);
 // whether the SGS-analysis pass (field-parallel row and column kernels at
 // strip width 1) fits the group's sizes
 bool gterms_ok(bool dbl, const Phase& P);

@@ -2229,6 +2229,37 @@ __global__ void k_spec_axpy(Phase P, long long o_dst, long long o_src, double a,
 }
 
 #if QG_HAS(4)
+// One member's constants into a device table (argument copied at launch, so
+// the call needs no host buffer that outlives it).
+__global__ void k_put_member(MemberDev* dst, MemberDev m) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = m;
+}
+
+// Per-pass twiddle table of length-n transforms under pass schedule sch (the
+// layout of qg_fft.hpp), computed on the device: slot o of the pass with
+// sub-length ns and radix r, o = (ns - 8) + k (r - 1) + (t - 1), holds
+// exp(-2 pi i m / n) with m = t k n / (ns r), from the double-precision
+// sincospi of the reduced angle.
+template <typename T>
+__global__ void k_twiddle_table(cpx<T>* dst, int logn, int sch) {
+  const int n = 1 << logn;
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n - 8) return;
+  int logns = 3;
+  while (logns < logn) {
+    const int lr = pass_log_radix(logn, logns, sch);
+    if (o < (1 << (logns + lr)) - 8) break;
+    logns += lr;
+  }
+  const int r = 1 << pass_log_radix(logn, logns, sch);
+  const int idx = o - ((1 << logns) - 8);
+  const int k = idx / (r - 1), t = idx % (r - 1) + 1;
+  const long long m = ((long long)t * k << (logn - logns - pass_log_radix(logn, logns, sch))) & (n - 1);
+  double sv, cv;
+  sincospi(-2.0 * (double)m / (double)n, &sv, &cv);
+  dst[o] = cmake<cpx<T>>(T(cv), T(sv));
+}
+
 __global__ void k_fill_zero(unsigned int* p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -2578,6 +2609,17 @@ hipError_t launch_ab2cn_finish(bool dbl, const Phase& P, int n, hipStream_t s) {
   dim3 grid((P.kxn * P.kyn + 255) / 256, 1, n);
   if (dbl) hipLaunchKernelGGL(k_ab2cn_finish<double>, grid, dim3(256), 0, s, P);
   else hipLaunchKernelGGL(k_ab2cn_finish<float>, grid, dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_put_member(MemberDev* dst, const MemberDev& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_put_member, dim3(1), dim3(64), 0, s, dst, m);
+  return hipGetLastError();
+}
+hipError_t launch_twiddle_table(bool dbl, void* dst, int logn, int sch, hipStream_t s) {
+  const int n = 1 << logn;
+  const dim3 grid((n + 255) / 256);
+  if (dbl) hipLaunchKernelGGL(k_twiddle_table<double>, grid, dim3(256), 0, s, (cpx<double>*)dst, logn, sch);
+  else hipLaunchKernelGGL(k_twiddle_table<float>, grid, dim3(256), 0, s, (cpx<float>*)dst, logn, sch);
   return hipGetLastError();
 }
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {

@@ -214,3 +214,21 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def step_noalloc(params, chi, chi_sponge, omega, nsteps):
+    """qg_step_noalloc: advance one member's omega (a device tensor of its
+    precision, ny * nx elements) in place by nsteps steps with the library's
+    static workspace -- no handle, no allocation.  chi and chi_sponge are
+    device tensors of the same shape and type."""
+    L = _lib.lib()
+    dtype = _DTYPES[int(params.get("precision", 64))]
+    for t, name in ((omega, "omega"), (chi, "chi"), (chi_sponge, "chi_sponge")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+            raise TypeError(f"{name} must be a contiguous {dtype} device tensor")
+        if t.numel() != int(params["nx"]) * int(params["ny"]):
+            raise ValueError(f"{name} must hold ny * nx elements")
+    prm = _lib.make_params(params)
+    _lib.check(L.qg_step_noalloc(ctypes.byref(prm), _ptr(chi), _ptr(chi_sponge), _ptr(omega), int(nsteps),
+                                 _stream(omega.device)))
+    return omega

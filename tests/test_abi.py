@@ -112,6 +112,7 @@ def test_null_arguments():
     assert L.qg_pcc(None, None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_closure_term(None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_profile_steps(None, None, 1, 0, None, 0, None, None) == _lib.QG_EINVAL
+    assert L.qg_step_noalloc(None, None, None, None, 1, None) == _lib.QG_EINVAL
     L.qg_destroy(None)
 
 
