@@ -1,5 +1,8 @@
 """Build the HIP library libqg.so for gfx950 in-tree (hipcc, no JIT cache).
 
+The library links the roctx marker library of ROCm (ranges around qg_step,
+qg_adjoint_step and qg_step_noalloc for rocprofv3 --marker-trace).
+
 Sources are compiled in parallel (the kernel file once per slice of its
 launchers, QG_PART = 0..4), then linked into paper_2508_06678_amd/libqg.so.
 All device code is built with packed-FP32 instruction generation disabled.
@@ -49,7 +52,9 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(compile_one, UNITS))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+           "-L", rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -2,6 +2,7 @@
 // workspace layout, the phase sequences of a step / the adjoint / the
 // diagnostics, hipGraph capture and replay, and the C ABI of include/qg.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -19,6 +20,15 @@
 namespace qg {
 
 static thread_local std::string g_err;
+
+// A roctx range over the host span of an entry point (visible in rocprofv3
+// --marker-trace timelines beside the kernels it enqueues).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 static int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -1062,6 +1072,7 @@ int qg_info(const qg_handle* H, int32_t* n_members, int64_t* total_points, int32
 
 int qg_step(qg_handle* H, void* omega, int64_t nsteps, int32_t save_every, void* ckpt_out, int32_t use_graph,
             void* hip_stream) {
+  Range range("qg_step");
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   if (!omega) return fail(QG_EINVAL, "omega is NULL");
   if (nsteps < 0) return fail(QG_EINVAL, "nsteps must be >= 0");
@@ -1365,6 +1376,7 @@ int qg_diag(qg_handle* H, const void* omega, double* out_dev, void* nu_e_out, vo
 
 int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t nsteps, double* grad_c,
                     void* hip_stream) {
+  Range range("qg_adjoint_step");
   if (!H) return fail(QG_EINVAL, "handle is NULL");
   Handle& h = H->h;
   if (!omega_ckpt || !lambda || !grad_c) return fail(QG_EINVAL, "NULL argument");
@@ -1684,6 +1696,7 @@ static int scratch_on(void** out) {
 extern "C" int qg_step_noalloc(const qg_params* p, const void* chi_obs, const void* chi_sponge, void* omega,
                                int64_t nsteps, void* hip_stream) {
   using namespace qg;
+  Range range("qg_step_noalloc");
   if (!p || !chi_obs || !chi_sponge || !omega) return fail(QG_EINVAL, "NULL argument");
   if (nsteps < 0) return fail(QG_EINVAL, "nsteps must be >= 0");
   int rc = validate(*p, 0);
