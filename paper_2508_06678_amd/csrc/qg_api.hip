@@ -172,8 +172,11 @@ static void plan_sizes(Group& g, int adjK) {
   int F = std::max({rhs_fields(cl), 5});
   int Pn = std::max({rhs_products(cl), 4});
   if (adjK > 0) {
-    F = std::max(F, (smag_family(cl) ? 6 : 4) + 3);
-    Pn = std::max(Pn, smag_family(cl) ? 6 : 4);
+    // the adjoint pass's fields and products; the dynamic closures run the
+    // two passes of a stage in one launch (both sets side by side)
+    const int lv = dynamic_closure(cl) ? 2 : 1;
+    F = std::max(F, lv * ((smag_family(cl) ? 6 : 4) + 3));
+    Pn = std::max(Pn, lv * (smag_family(cl) ? 6 : 4));
   }
   const long long spec = (long long)g.kxn * g.kyn * cs;
   const long long mf = std::max((long long)F * g.ny * kxp16, 2LL * g.ny * kxpf16) * cs;
@@ -824,21 +827,37 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
         Kp.o_a = g.L.adj_a;
         Kp.o_b = g.L.adj_b;
         QG_LAUNCH(launch_adj_dyn_prep(g.dbl, Kp, g.count, st));
-        Phase G = A;
-        G.adj_mode = 1;
-        G.o_a = g.L.adj_a;
-        G.o_b = g.L.adj_b;
-        G.o_e = g.L.adj_e;
-        QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
-        QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
-        QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
         A.adj_dyn = 1;
         A.o_a = g.L.adj_a;
         A.o_b = g.L.adj_b;
         A.o_e = g.L.adj_e;
+        // the column-inverse and row passes of both (adj_mode 2): fields
+        // and products of the stage's own pass first, then those of the
+        // transport pass; the latter's column pass forms the term into
+        // adj_e, which the former's column pass below adds
+        Phase T1 = A;
+        T1.adj_mode = 1;
+        T1.adj_dyn = 0;
+        if (row_two_levels_ok(g.dbl, OP_ADJ_RHS, clb, A)) {
+          Phase G = A;
+          G.adj_mode = 2;
+          G.nf = 2 * A.nf;
+          QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+          QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, G, g.count, st));
+          T1.o_mp = g.L.mp + (long long)(smag_family(cl) ? 6 : 4) * g.ny * g.kxp * (g.dbl ? 16 : 8);
+          QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, T1, g.count, st));
+        } else {
+          // the row kernel of these sizes takes one pass at a time
+          QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, T1, g.count, st));
+          QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, T1, g.count, st));
+          QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_RHS, clb, T1, g.count, st));
+          QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
+          QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
+        }
+      } else {
+        QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
+        QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
       }
-      QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
-      QG_LAUNCH(launch_row(g.dbl, OP_ADJ_RHS, clb, A, g.count, st));
       if (cl != 0 && !dyn)
         QG_LAUNCH(launch_adj_grad_c(A, g.count, row_launch_blocks(g.dbl, OP_ADJ_RHS, cl, A), nullptr, 0, st));
       A.o_out = LS;

@@ -138,6 +138,9 @@ hipError_t launch_dyn_coef(const Phase& P, int nmem, int slot, hipStream_t s);
 hipError_t launch_adj_grad_c(const Phase& P, int nmem, int nrowblocks, double* grad_c,
                              int mode, hipStream_t s);
 int row_launch_blocks(bool dbl, int op, int closure, const Phase& P);
+// whether the field-parallel row kernel (the one that takes two levels in
+// one launch) runs op for these sizes
+bool row_two_levels_ok(bool dbl, int op, int closure, const Phase& P);
 hipError_t launch_spec_axpy(bool dbl, const Phase& P, int nmem, long long o_dst,
                             long long o_src, double a, int zero_first, hipStream_t s);
 hipError_t launch_spec_copy(bool dbl, const Phase& P, int nmem, long long o_dst,
@@ -181,7 +184,7 @@ __host__ __device__ constexpr bool dynamic_closure(int cl) { return cl == 3 || c
 
 // Fields (thread groups) and products of the field-parallel row pass.
 __host__ __device__ constexpr int rowp_nb(int op, int cl) {
-  return op == OP_B ? 3
+  return (op == OP_B || op == OP_ADJ_B) ? 3
        : op == OP_GTERMS ? 5
        : op == OP_CLIPF ? 2
        : (op == OP_PEN || op == OP_SPONGE) ? 2
@@ -190,6 +193,7 @@ __host__ __device__ constexpr int rowp_nb(int op, int cl) {
 }
 __host__ __device__ constexpr int rowp_np(int op, int cl) {
   return op == OP_ADJ_RHS ? ((cl == 1 || cl == 3) ? 6 : 4)
+       : op == OP_ADJ_B ? 3
        : op == OP_GTERMS ? 4
        : op == OP_CLIPF ? 0
        : op == OP_PEN ? 2

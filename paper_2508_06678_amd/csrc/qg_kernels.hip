@@ -287,10 +287,20 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     return zero_mean ? cmake<V>(T(0), T(0)) : l;
   } else {  // OP_ADJ_RHS: forward fields of the stage input, then -l, -i kx l, -i ky l
     constexpr int nb = (CL == 1) ? 6 : 4;
-    const bool t = (P.adj_mode != 0 || P.adj_dyn) && in_test(M, P.nx, P.ny, mx, my);
+    // adj_mode 2 (dynamic closures): both passes of a stage in one launch,
+    // the fields of the stage's own pass (mode 0 with the coefficient's
+    // cotangents) first, then those of the transport pass at the
+    // test-filtered input (mode 1)
+    int mode = P.adj_mode, dynp = P.adj_dyn;
+    if (mode == 2) {
+      const int nfl = P.nf / 2;
+      if (f >= nfl) { f -= nfl; mode = 1; dynp = 0; }
+      else { mode = 0; dynp = 1; }
+    }
+    const bool t = (mode != 0 || dynp) && in_test(M, P.nx, P.ny, mx, my);
     if (f < nb) {
       V x = gld(cptr<T>(M, P.o_in) + idx);
-      if (P.adj_mode == 1 && !t) x = cmake<V>(T(0), T(0));   // the test-filtered stage input
+      if (mode == 1 && !t) x = cmake<V>(T(0), T(0));   // the test-filtered stage input
       return rhs_field<T, CL>(M, f, x, w, mx, my, false);
     }
     if (zero_mean) return cmake<V>(T(0), T(0));
@@ -302,14 +312,14 @@ __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& 
     //   dynamic, at T x (mode 1):    cJ = a,          cQ = r b
     // with l the stage's cotangent and a, b those of H and M
     V cj, cq;
-    if (P.adj_mode == 1) {
+    if (mode == 1) {
       cj = gld(cptr<T>(M, P.o_a) + idx);
       cq = cscale(gld(cptr<T>(M, P.o_b) + idx), T(M.r_test));
     } else {
       const V l = gld(cptr<T>(M, P.o_in2) + idx);
       cj = cmake<V>(-l.x, -l.y);
       cq = l;
-      if (P.adj_dyn) {
+      if (dynp) {
         cq = cscale(l, T(rptr<double>(M, P.o_coef)[ADJ_C_SLOT]));
         if (t) {
           cj = csub(cj, gld(cptr<T>(M, P.o_a) + idx));
@@ -944,6 +954,17 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     const T w0 = SE[a] * w.x + SE[nxy + a] * (Vv + vv.x) - SE[2 * nxy + a] * (U + u.x);
     const T w1 = SE[b] * w.y + SE[nxy + b] * (Vv + vv.y) - SE[2 * nxy + b] * (U + u.y);
     return cmake<V>(w0, w1);
+  } else if constexpr (OP == OP_ADJ_B) {
+    // transpose of the B sub-step's pointwise update at the cotangent
+    // lambda'' (every group holds it; group 0's copy is read): 0: S E
+    // lambda'' (omega), 1: -S E_y lambda'' (u), 2: S E_x lambda'' (v)
+    const long long nxy = (long long)nx * P.ny;
+    const T* SE = rptr<T>(M, P.o_phys);
+    const V l = F(0);
+    const long long a = (long long)ya * nx + q, b = a + nx;
+    if (grp == 0) return cmake<V>(SE[a] * l.x, SE[b] * l.y);
+    if (grp == 1) return cmake<V>(-SE[2 * nxy + a] * l.x, -SE[2 * nxy + b] * l.y);
+    return cmake<V>(SE[nxy + a] * l.x, SE[nxy + b] * l.y);
   } else if constexpr (OP == OP_RHS) {
     const V wx = F(2), wy = F(3);
     if (grp == 0) {
@@ -1087,10 +1108,11 @@ __device__ __forceinline__ void c2r_formc(const RowRaw<T>& in, cpx<T> (&v)[8], i
   }
 }
 
-// Column limit of the c2r input: the test-filtered level holds no mode at
-// m_x >= test_kx.
-__device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, int lev) {
-  return lev == 0 ? P.kxn : min(P.kxn, M.test_kx);
+// Column limit of the c2r input: the test-filtered level of a dynamic
+// closure's right-hand side holds no mode at m_x >= test_kx (the second
+// level of an adjoint stage, adj_mode 2, spans the whole 2/3 set).
+__device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, bool test_level) {
+  return test_level ? min(P.kxn, M.test_kx) : P.kxn;
 }
 
 // One item of the row pass: row pair rb of member mem at level lev, from
@@ -1163,7 +1185,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   }
   if constexpr (OP == OP_ADJ_RHS) {
     const double sdc = block_sum(dc, red);
-    if (threadIdx.x == 0) rptr<double>(M, P.o_dpart)[item_slot] = sdc * M.dcoef_dc;
+    if (threadIdx.x == 0 && lev == 0) rptr<double>(M, P.o_dpart)[item_slot] = sdc * M.dcoef_dc;
   }
   // ---- r2c of product grp, keep m_x < kxn
   if constexpr (LOGN != 0) {
@@ -1180,7 +1202,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     constexpr int N = 1 << LOGN, NG = N / 8, KXN = (N - 1) / 3 + 1;
     constexpr int DPAD = NG + (NG >> PADS);
     if (act) {
-      V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
+      V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? lev * np + grp : lev * 3 + grp) * pstride;
       const int o0 = mix_at(C, ya, j);
       const int iz = padp<PADS>(j);
       const int izm = padp<PADS>(N - j);
@@ -1201,7 +1223,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
       }
     }
   } else if (act) {
-    V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? grp : lev * 3 + grp) * pstride;
+    V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? lev * np + grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
       const int a = k, b = (nx - k) & (nx - 1);
       const V z = mybuf[a + (a >> PADS)];
@@ -1221,11 +1243,12 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
 
 // packed c2r inputs of the item from its loads
 template <typename T>
-__device__ __forceinline__ void rowp_form(const Phase& P, int mem, int lev, const RowRaw<T>& in, cpx<T> (&v)[8]) {
+__device__ __forceinline__ void rowp_form(const Phase& P, int mem, bool test_level, const RowRaw<T>& in,
+                                          cpx<T> (&v)[8]) {
   const MemberDev M = member_const(P, mem);
   const int lg = P.lognx - 3;
   const int j = threadIdx.x & ((1 << lg) - 1);
-  const int kin = rowp_kin(P, M, lev);
+  const int kin = rowp_kin(P, M, test_level);
 #pragma unroll
   for (int t = 0; t < 8; ++t) v[t] = c2r_form<T>(in.a[t], in.b[t], j + (t << lg), P.nx, kin);
 }
@@ -1239,8 +1262,9 @@ __device__ __forceinline__ void rowp_load(const Phase& P, int mem, int rb, int l
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
   const long long fstride = (long long)P.ny * P.mfp;   // MF field stride
-  const cpx<T>* src = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * fstride;
-  c2r_load<T>(in, src, P.mfp, 2 * rb, j, 1 << lg, P.nx, rowp_kin(P, M, lev));
+  // the B sub-step's transpose: every group transforms the one cotangent field
+  const cpx<T>* src = cptr<T>(M, P.o_mf) + (long long)(OP == OP_ADJ_B ? 0 : lev * nb + grp) * fstride;
+  c2r_load<T>(in, src, P.mfp, 2 * rb, j, 1 << lg, P.nx, rowp_kin(P, M, OP == OP_RHS && lev == 1));
 }
 
 // Right-hand side, B sub-step and adjoint right-hand side: one block per
@@ -1258,7 +1282,8 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   if ((gridDim.x & 7) == 0) rbb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   // the two levels of the dynamic closures (grid and test filter) are
   // independent: one block each
-  const int lev = dyn ? (int)blockIdx.y : 0;
+  // (and the two passes of a dynamic closure's adjoint stage, adj_mode 2)
+  const int lev = (dyn || OP == OP_ADJ_RHS) ? (int)blockIdx.y : 0;
   // twiddles straight from the (cached) global table: keeping LDS to the
   // field buffers lets one more block share a compute unit
   const V* twl = reinterpret_cast<const V*>(SCH ? P.twx1 : P.twx);
@@ -1275,7 +1300,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
     const MemberDev M = member_const(P, blockIdx.z);
     const int grp = threadIdx.x >> (LOGN - 3);
     const int j = threadIdx.x & ((1 << (LOGN - 3)) - 1);
-    const cpx<T>* row = cptr<T>(M, P.o_mf) + (long long)(lev * nb + grp) * ((long long)P.ny * P.mfp) +
+    const cpx<T>* row = cptr<T>(M, P.o_mf) + (long long)(OP == OP_ADJ_B ? 0 : lev * nb + grp) * ((long long)P.ny * P.mfp) +
                         (long long)(2 * rb) * P.mfp;
     RowRaw<T> in;
     V vin[8];
@@ -1292,7 +1317,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
     RowRaw<T> in;
     rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
     V vin[8];
-    rowp_form<T>(P, blockIdx.z, lev, in, vin);
+    rowp_form<T>(P, blockIdx.z, OP == OP_RHS && lev == 1, in, vin);
     rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
   }
   }
@@ -2332,7 +2357,7 @@ static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
 template <typename T, int OP, int CL>
 static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int nb = rowp_fields(OP, CL);
-  const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) ? 2 : 1;
+  const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) || (OP == OP_ADJ_RHS && P.adj_mode == 2) ? 2 : 1;
   const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
   const dim3 block(nb * P.nx / 8);
   // the step's passes take the tuned row pairs per block and pass schedule
@@ -2367,7 +2392,7 @@ static void launch_row_t(const Phase& P, int nmem, hipStream_t s) {
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) launch_rowp_t<T, OP, CL>(P, nmem, s);
     return;
   }
-  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ADJ_RHS) {
+  if constexpr (OP == OP_RHS || OP == OP_B || OP == OP_ADJ_RHS || OP == OP_ADJ_B) {
     if (rowp_ok(sizeof(T) == 8, OP, CL, P)) { launch_rowp_t<T, OP, CL>(P, nmem, s); return; }
   }
   dim3 grid(P.ny / (2 * P.RP), 1, nmem);
@@ -2528,6 +2553,8 @@ hipError_t launch_colinv(bool dbl, int op, int cl, const Phase& P, int n, hipStr
 bool gterms_ok(bool dbl, const Phase& P) {
   return P.W == 1 && rowp_ok(dbl, OP_GTERMS, 0, P) && colfwdp_ok(dbl, OP_GTERMS, 0, P);
 }
+bool row_two_levels_ok(bool dbl, int op, int cl, const Phase& P) { return rowp_ok(dbl, op, cl, P); }
+
 int row_launch_blocks(bool dbl, int op, int cl, const Phase& P) {
   const bool par = (op == OP_RHS || op == OP_B || op == OP_ADJ_RHS) && rowp_ok(dbl, op, cl, P);
   return par ? P.ny / 2 : P.ny / (2 * P.RP);
