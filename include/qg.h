@@ -233,13 +233,16 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
  * column-inverse pass (Wi), the radix schedule of the compile-time row and
  * column transforms (rows and columns of 256, 512 or 1024 points; schedule
  * 0: radix 8 then 4 or 2, e.g. 1024 = 8 8 8 2; schedule 1: radix 4 first,
- * e.g. 1024 = 8 4 4 8) and the row pairs per block of the step's row pass
- * (1 or 2).  All combinations of the admissible values are searched
+ * e.g. 1024 = 8 4 4 8), the row pairs per block of the step's row pass
+ * (1 or 2) and its synchronisation (block-wide passes of 8 points per
+ * thread, or one wave per transform, 16 points per thread at 1024, with
+ * block barriers only around the pointwise products).  All combinations of
+ * the admissible values are searched
  * jointly: each is captured as a graph of four steps of the group and timed
  * round-robin three times (after two warm-up rounds) on a stream of the
  * tuner's own, and the fastest is kept.  The choice is cached in the flat
  * JSON file at cache_path (nullable: no file) under the group's key with
- * the suffixes /fwd, /inv, /rsched, /csched, /rpb; a tunable found in the
+ * the suffixes /fwd, /inv, /rsched, /csched, /rpb, /rwave; a tunable found in the
  * cache is taken as given and only the others are searched.  Every choice
  * computes the same step (to rounding).  The timed steps run on the
  * workspace: the spectral state is not meaningful afterwards (the next
@@ -267,8 +270,8 @@ int qg_step_noalloc(const qg_params* p, const void* chi_obs, const void* chi_spo
                     int64_t nsteps, void* hip_stream);
 
 /* The launch configuration of every member's size group: out (host,
- * n_members x 5 int32) receives W, Wi, row schedule, column schedule and
- * row pairs per block (see qg_autotune). */
+ * n_members x 6 int32) receives W, Wi, row schedule, column schedule, row
+ * pairs per block and wave-synchronous row transforms (see qg_autotune). */
 int qg_tuning(const qg_handle* h, int32_t* out);
 
 /* Profiling: qg_step(h, omega, nsteps) without graphs (the same launches in

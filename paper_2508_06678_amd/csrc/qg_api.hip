@@ -110,6 +110,7 @@ struct Group {
   long long o_twx1, o_twy1;
   int rsch, csch;                // pass schedules of the row / column compile-time engines
   int rpb;                       // row pairs per block of the step's row pass
+  int rwv;                       // wave-synchronous row transforms
 };
 
 // Strip width W of the column passes: W * ny <= one tile, at least 64
@@ -310,7 +311,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     g.o_twy = o; o += align256((long long)g.ny * cs);
     g.o_twx1 = o; o += align256((long long)g.nx * cs);
     g.o_twy1 = o; o += align256((long long)g.ny * cs);
-    g.rsch = g.csch = 0;
+    g.rsch = g.csch = g.rwv = 0;
     g.rpb = 1;
   }
   int m0 = 0;
@@ -400,7 +401,7 @@ static Phase base_phase(const Handle& h, const Group& g) {
   P.o_part = g.L.part; P.o_coef = g.L.coef; P.o_dpart = g.L.dpart;
   P.twx = g.twx; P.twy = g.twy;
   P.twx1 = g.twx1; P.twy1 = g.twy1;
-  P.rsch = g.rsch; P.csch = g.csch; P.rpb = g.rpb;
+  P.rsch = g.rsch; P.csch = g.csch; P.rpb = g.rpb; P.rwv = g.rwv;
   return P;
 }
 
@@ -1524,7 +1525,7 @@ int qg_profile_steps(qg_handle* H, void* omega, int64_t nsteps, int32_t kind, fl
 
 // One candidate tuning of a size group.
 struct Tuning {
-  int W, Wi, rsch, csch, rpb;
+  int W, Wi, rsch, csch, rpb, rwv;
 };
 static void apply_tuning(Group& g, const Tuning& t) {
   set_width(g, t.W);
@@ -1532,6 +1533,7 @@ static void apply_tuning(Group& g, const Tuning& t) {
   g.rsch = t.rsch;
   g.csch = t.csch;
   g.rpb = t.rpb;
+  g.rwv = t.rwv;
 }
 
 int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
@@ -1565,13 +1567,14 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
     if (rc) break;
     const std::string key = group_key(g);
     // admissible values of every tunable; a value found in the cache fixes it
-    std::vector<int> Ws, Wis, rs, cs, rp;
+    std::vector<int> Ws, Wis, rs, cs, rp, wv;
     for (int W = min_width(g); W <= max_width(g); W *= 2) { Ws.push_back(W); Wis.push_back(W); }
     const bool ct_rows = g.nx == 256 || g.nx == 512 || g.nx == 1024;
     const bool ct_cols = g.ny == 256 || g.ny == 512 || g.ny == 1024;
     rs = ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
     cs = ct_cols ? std::vector<int>{0, 1} : std::vector<int>{0};
     rp = g.ny >= 64 ? std::vector<int>{1, 2} : std::vector<int>{1};
+    wv = ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
     auto fix = [&](const char* name, std::vector<int>& vals, bool ok_range) {
       auto it = cache.find(key + name);
       if (it == cache.end()) return;
@@ -1588,13 +1591,16 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
       fix("/csched", cs, it != cache.end() && (it->second == 0 || (ct_cols && it->second == 1)));
       it = cache.find(key + "/rpb");
       fix("/rpb", rp, it != cache.end() && (it->second == 1 || (g.ny >= 64 && it->second == 2)));
+      it = cache.find(key + "/rwave");
+      fix("/rwave", wv, it != cache.end() && (it->second == 0 || (ct_rows && it->second == 1)));
     }
     std::vector<Tuning> cand;
     for (int W : Ws)
       for (int Wi : Wis)
         for (int r : rs)
           for (int c : cs)
-            for (int q : rp) cand.push_back(Tuning{W, Wi, r, c, q});
+            for (int q : rp)
+              for (int v : wv) cand.push_back(Tuning{W, Wi, r, c, q, v});
     if (cand.size() == 1) {
       apply_tuning(g, cand[0]);
       continue;
@@ -1643,6 +1649,7 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
     cache[key + "/rsched"] = g.rsch;
     cache[key + "/csched"] = g.csch;
     cache[key + "/rpb"] = g.rpb;
+    cache[key + "/rwave"] = g.rwv;
     changed = true;
   }
   cleanup();
@@ -1669,12 +1676,13 @@ int qg_tuning(const qg_handle* H, int32_t* out) {
   const Handle& h = H->h;
   for (size_t i = 0; i < h.params.size(); ++i) {
     const Group& g = h.groups[h.member_group[i]];
-    int32_t* o = out + 5 * i;
+    int32_t* o = out + 6 * i;
     o[0] = g.W;
     o[1] = g.Wi;
     o[2] = g.rsch;
     o[3] = g.csch;
     o[4] = g.rpb;
+    o[5] = g.rwv;
   }
   return QG_OK;
 }
@@ -1738,7 +1746,7 @@ extern "C" int qg_step_noalloc(const qg_params* p, const void* chi_obs, const vo
   set_inv_width(g, default_inv_width(g, 1));
   g.m0 = 0;
   g.count = 1;
-  g.rsch = g.csch = 0;
+  g.rsch = g.csch = g.rwv = 0;
   g.rpb = 1;
   const int cs = g.dbl ? 16 : 8;
   long long o = align256(sizeof(MemberDev));

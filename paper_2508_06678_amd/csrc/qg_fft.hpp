@@ -312,19 +312,46 @@ __device__ __forceinline__ void fft1_rest(V* __restrict__ buf, const V* __restri
 // Ns < 2^P).
 template <int P> __device__ __forceinline__ int padp(int i) { return i + (i >> P); }
 
-// First pass (radix 8) from registers: butterfly j writes x'[8 j + t].
-// ZM: inputs known to be zero (bit t: x[j + t N/8]), see dft8z.
-template <typename V, bool INV, int P, int ZM = 0>
-__device__ __forceinline__ void fft1c_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active) {
+// Synchronisation between the passes of a transform.  Block-wide by
+// default; WAVE: every thread that exchanges data with this one belongs to
+// its wave (a transform of at most 64 threads, aligned to the wave), whose
+// LDS operations are performed in order, so waiting for the wave's own LDS
+// traffic (and keeping the compiler from moving accesses across) suffices.
+template <bool WAVE> __device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  } else {
+    __syncthreads();
+  }
+}
+
+// First pass (radix 8) from registers.  A thread holds EPT = 8 NB0
+// elements: butterflies q = j + b N/EPT (b < NB0), butterfly q taking
+// x[q + t N/8] from v[b + NB0 t] and writing x'[8 q + t].
+// ZM: inputs known to be zero (bit t: x[q + t N/8]), see dft8z.
+template <typename V, bool INV, int P, int ZM = 0, int EPT = 8, bool WAVE = false, int LOGN = 0>
+__device__ __forceinline__ void fft1c_pass0(V (&v)[EPT], V* __restrict__ buf, int j, bool active) {
   static_assert(P >= 3, "pad period of at least 8");
-  if (active) dft8z<V, INV, ZM>(v);
-  __syncthreads();
+  constexpr int NB0 = EPT / 8;
+  static_assert(NB0 == 1 || LOGN > 0, "several butterflies per thread need the length");
+  constexpr int nt = NB0 == 1 ? 0 : (1 << LOGN) / EPT;   // threads per transform
+  V u[NB0][8];
+#pragma unroll
+  for (int b = 0; b < NB0; ++b) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) u[b][t] = v[b + NB0 * t];
+    if (active) dft8z<V, INV, ZM>(u[b]);
+  }
+  fft_sync<WAVE>();
   if (active) {
     V* wb = buf + 8 * j + (j >> (P - 3));
 #pragma unroll
-    for (int t = 0; t < 8; ++t) wb[t] = v[t];
+    for (int b = 0; b < NB0; ++b) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) wb[b * (8 * nt + ((8 * nt) >> P)) + t] = u[b][t];
+    }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 }
 
 // One pass of the compile-time engine, radix R = 2^pass_log_radix(LOGN,
@@ -332,15 +359,15 @@ __device__ __forceinline__ void fft1c_pass0(V (&v)[8], V* __restrict__ buf, int 
 // thread: j + b N/8).  A pass before the last has Ns dividing N/8, so the
 // butterflies of a thread share their twiddles and their outputs lie N R/8
 // apart; in the last pass (Ns R = N) every butterfly index is below Ns.
-template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH>
+template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH, int EPT = 8, bool WAVE = false>
 __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
   constexpr int N = 1 << LOGN;
   constexpr int NS = 1 << LOGNS;
   constexpr int logR = pass_log_radix(LOGN, LOGNS, SCH);
   constexpr int R = 1 << logR;
   constexpr bool LAST = LOGNS + logR == LOGN;
-  constexpr int NB = 8 / R;          // butterflies per thread
-  constexpr int nt = N / 8;          // threads per transform
+  constexpr int NB = EPT / R;        // butterflies per thread
+  constexpr int nt = N / EPT;        // threads per transform
   constexpr int NR = N / R;
   static_assert(LOGN >= P + 3 && LOGNS >= 3, "compile-time engine: N >= 8 * 2^P, passes after the first");
   static_assert(LAST || NB == 1 || nt % NS == 0, "a pass before the last has Ns dividing N/8");
@@ -358,7 +385,7 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
       dftR<V, R, INV>(v[b]);
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
   if (active) {
     if constexpr (NB > 1 && LAST) {
       V* wb = buf + padp<P>(j);
@@ -378,14 +405,15 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
       }
     }
   }
-  __syncthreads();
-  if constexpr (!LAST) fft1c_pass<V, LOGN, LOGNS + logR, INV, P, SCH>(buf, tw, j, active);
+  fft_sync<WAVE>();
+  if constexpr (!LAST) fft1c_pass<V, LOGN, LOGNS + logR, INV, P, SCH, EPT, WAVE>(buf, tw, j, active);
 }
 
-// Passes after the first (fft1c_pass0), compile-time length, schedule SCH.
-template <typename V, int LOGN, bool INV, int P, int SCH = 0>
+// Passes after the first (fft1c_pass0), compile-time length, schedule SCH,
+// EPT elements per thread, wave- or block-wide synchronisation.
+template <typename V, int LOGN, bool INV, int P, int SCH = 0, int EPT = 8, bool WAVE = false>
 __device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
-  fft1c_pass<V, LOGN, 3, INV, P, SCH>(buf, tw, j, active);
+  fft1c_pass<V, LOGN, 3, INV, P, SCH, EPT, WAVE>(buf, tw, j, active);
 }
 
 // The whole block as one group.

@@ -112,8 +112,9 @@ struct Phase {
   // tuning choices of the compile-time engines of the step's passes: pass
   // schedule of the row transforms (rsch) and of the column transforms
   // (csch), with the twiddle tables of schedule 1 (twx1, twy1); row pairs
-  // per block of the row pass (rpb)
-  int rsch, csch, rpb;
+  // per block of the row pass (rpb); wave-synchronous row transforms (rwv:
+  // one wave per transform)
+  int rsch, csch, rpb, rwv;
   const void* twx1;
   const void* twy1;
 };

@@ -1028,8 +1028,8 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
 // c2r input of the packed row pair (rows ya, ya + 1) at column k: the raw
 // loads (spectral m_x = k, or its mirror nx - k), then the packing into one
 // complex row.
-template <typename T> struct RowRaw {
-  cpx<T> a[8], b[8];
+template <typename T, int EPT = 8> struct RowRaw {
+  cpx<T> a[EPT], b[EPT];
 };
 template <typename T>
 __device__ __forceinline__ void c2r_load(RowRaw<T>& r, const cpx<T>* src, int pitch, int ya, int j, int ng, int nx,
@@ -1068,42 +1068,46 @@ __device__ __forceinline__ cpx<T> c2r_form(cpx<T> a, cpx<T> b, int k, int nx, in
 // Blocks known to be zero (the bits of band_zero_mask) are neither loaded
 // nor added in the first radix-8 pass of the transform.
 
-template <typename T, int LOGN, bool TL>
-__device__ __forceinline__ void c2r_loadc(RowRaw<T>& r, const cpx<T>* row, int pitch, int j, int kin) {
+// EPT elements per thread (8, or 16 for one wave per 1024-point row): element
+// e of thread j sits at column k = j + e N/EPT, in block t = e / (EPT/8).
+template <typename T, int LOGN, bool TL, int EPT = 8>
+__device__ __forceinline__ void c2r_loadc(RowRaw<T, EPT>& r, const cpx<T>* row, int pitch, int j, int kin) {
   using V = cpx<T>;
-  constexpr int N = 1 << LOGN, NG = N / 8, KIN = (N - 1) / 3 + 1;
+  constexpr int N = 1 << LOGN, GT = N / EPT, NB0 = EPT / 8, KIN = (N - 1) / 3 + 1;
   constexpr int ZM = band_zero_mask<TL>();
-  const V* fw = row + j;          // column j + t NG at fw + t NG
-  const V* bw = row + (N - j);    // its mirror N - j - t NG at bw - t NG (t >= 4)
+  const V* fw = row + j;          // column j + e GT at fw + e GT
+  const V* bw = row + (N - j);    // its mirror N - j - e GT at bw - e GT (blocks t >= 4)
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    r.a[t] = r.b[t] = cmake<V>(T(0), T(0));
+  for (int e = 0; e < EPT; ++e) {
+    const int t = e / NB0;
+    r.a[e] = r.b[e] = cmake<V>(T(0), T(0));
     if ((ZM >> t) & 1) continue;
     const bool mirror = t >= 4;
     bool in;
-    if (mirror) in = (!TL && t >= 6) || (N - t * NG - j) < (TL ? kin : KIN);
-    else in = (!TL && t <= 1) || j + t * NG < (TL ? kin : KIN);
+    if (mirror) in = (!TL && t >= 6) || (N - e * GT - j) < (TL ? kin : KIN);
+    else in = (!TL && t <= 1) || j + e * GT < (TL ? kin : KIN);
     if (in) {
-      const V* q = mirror ? bw - t * NG : fw + t * NG;
-      r.a[t] = gld(q);
-      r.b[t] = gld(q + pitch);
+      const V* q = mirror ? bw - e * GT : fw + e * GT;
+      r.a[e] = gld(q);
+      r.b[e] = gld(q + pitch);
     }
   }
 }
 
-template <typename T, bool TL>
-__device__ __forceinline__ void c2r_formc(const RowRaw<T>& in, cpx<T> (&v)[8], int j) {
+template <typename T, bool TL, int EPT = 8>
+__device__ __forceinline__ void c2r_formc(const RowRaw<T, EPT>& in, cpx<T> (&v)[EPT], int j) {
   using V = cpx<T>;
-  constexpr int ZM = band_zero_mask<TL>();
+  constexpr int ZM = band_zero_mask<TL>(), NB0 = EPT / 8;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    if ((ZM >> t) & 1) { v[t] = cmake<V>(T(0), T(0)); continue; }
-    V a = in.a[t], b = in.b[t];
+  for (int e = 0; e < EPT; ++e) {
+    const int t = e / NB0;
+    if ((ZM >> t) & 1) { v[e] = cmake<V>(T(0), T(0)); continue; }
+    V a = in.a[e], b = in.b[e];
     if (t < 4) {
-      if (t == 0 && j == 0) { a.y = T(0); b.y = T(0); }   // the m_x = 0 column is real
-      v[t] = cmake<V>(a.x - b.y, a.y + b.x);
+      if (e == 0 && j == 0) { a.y = T(0); b.y = T(0); }   // the m_x = 0 column is real
+      v[e] = cmake<V>(a.x - b.y, a.y + b.x);
     } else {
-      v[t] = cmake<V>(a.x + b.y, b.x - a.y);
+      v[e] = cmake<V>(a.x + b.y, b.x - a.y);
     }
   }
 }
@@ -1118,12 +1122,14 @@ __device__ __forceinline__ int rowp_kin(const Phase& P, const MemberDev& M, bool
 // One item of the row pass: row pair rb of member mem at level lev, from
 // the packed c2r inputs vin (column j + t nx/8 of the thread's group);
 // twl: the x twiddle table (global or staged in LDS).
-template <typename T, int OP, int CL, int LOGN, int ZM = 0, int SCH = 0>
-__device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int lev, const cpx<T> (&vin)[8],
+// EPT points per thread; WV: the transforms synchronise within their wave
+// (one wave per transform), the block only around the products.
+template <typename T, int OP, int CL, int LOGN, int ZM = 0, int SCH = 0, int EPT = 8, bool WV = false>
+__device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int lev, const cpx<T> (&vin)[EPT],
                                           cpx<T>* buf, const cpx<T>* twl, double* red, int item_slot) {
   using V = cpx<T>;
   constexpr int np = rowp_np(OP, CL);
-  constexpr int EPT = 8;                       // points per thread
+  constexpr int LGE = EPT == 16 ? 4 : 3;        // log2 of the points per thread
   constexpr int PADS = LOGN ? QG_ROW_PADS : 3;  // one pad slot per 2^PADS
   const MemberDev M = member_const(P, mem);
   // member constants read once, not per point
@@ -1131,7 +1137,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   const T coef = OP == OP_ADJ_RHS ? adj_coef<T>(M, P) : T(M.coef_static);
   const int nx = LOGN ? (1 << LOGN) : P.nx;
   const int bstride = nx + (nx >> PADS);
-  const int lg = LOGN ? LOGN - 3 : P.lognx - 3;
+  const int lg = LOGN ? LOGN - LGE : P.lognx - 3;
   const int grp = threadIdx.x >> lg;
   const int j = threadIdx.x & ((1 << lg) - 1);
   const int ng = 1 << lg;                      // threads per group
@@ -1146,13 +1152,14 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
 #pragma unroll
     for (int t = 0; t < EPT; ++t) v[t] = vin[t];
     if constexpr (LOGN != 0) {
-      fft1c_pass0<V, true, PADS, ZM>(v, mybuf, j, true);
-      fft1c_rest<V, LOGN, true, PADS, SCH>(mybuf, twl, j, true);
+      fft1c_pass0<V, true, PADS, ZM, EPT, WV, LOGN>(v, mybuf, j, true);
+      fft1c_rest<V, LOGN, true, PADS, SCH, EPT, WV>(mybuf, twl, j, true);
     } else {
       fft1_pass0<V, true>(v, mybuf, j, true);
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
     }
   }
+  if constexpr (WV) __syncthreads();   // every field in physical space before the products read them
   if constexpr (OP == OP_CLIPF) {
     // sums of max(H, 0) M and M^2 over the two rows (group 0's points)
     double hp = 0.0, mm = 0.0;
@@ -1188,30 +1195,31 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     if (threadIdx.x == 0 && lev == 0) rptr<double>(M, P.o_dpart)[item_slot] = sdc * M.dcoef_dc;
   }
   // ---- r2c of product grp, keep m_x < kxn
+  if constexpr (WV) __syncthreads();   // every product formed before the fields' buffers are overwritten
   if constexpr (LOGN != 0) {
-    fft1c_pass0<V, false, PADS>(v, mybuf, j, act);
-    fft1c_rest<V, LOGN, false, PADS, SCH>(mybuf, twl, j, act);
+    fft1c_pass0<V, false, PADS, 0, EPT, WV, LOGN>(v, mybuf, j, act);
+    fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act);
   } else {
     fft1_pass0<V, false>(v, mybuf, j, act);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
   }
   if constexpr (LOGN != 0) {
-    // columns k = j + t N/8 below kxn (t = 0, 1 always, t = 2 for the first
-    // kxn - N/4 threads); the mirror N - k sits at constant offsets below
-    // padp(N - j), except k = 0 whose mirror is itself
-    constexpr int N = 1 << LOGN, NG = N / 8, KXN = (N - 1) / 3 + 1;
-    constexpr int DPAD = NG + (NG >> PADS);
+    // columns k = j + t GT below kxn (GT = N/EPT threads per group); the
+    // mirror N - k sits at constant offsets below padp(N - j), except k = 0
+    // whose mirror is itself
+    constexpr int N = 1 << LOGN, GT = N / EPT, KXN = (N - 1) / 3 + 1;
+    constexpr int DPAD = GT + (GT >> PADS);
     if (act) {
       V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? lev * np + grp : lev * 3 + grp) * pstride;
       const int o0 = mix_at(C, ya, j);
       const int iz = padp<PADS>(j);
       const int izm = padp<PADS>(N - j);
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        if (t == 2 && j + 2 * NG >= KXN) break;
+      for (int t = 0; t < EPT; ++t) {
+        if (t * GT >= KXN || j + t * GT >= KXN) break;
         const V z = mybuf[iz + t * DPAD];
         const V zm = mybuf[(t == 0 && j == 0) ? 0 : izm - t * DPAD];
-        const int o = o0 + t * NG * P.ny;
+        const int o = o0 + t * GT * P.ny;
         const V ra = cmake<V>(T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y));     // row ya
         const V rb2 = cmake<V>(T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x));    // row ya + 1
         if (C.logW == 0) {
@@ -1269,7 +1277,52 @@ __device__ __forceinline__ void rowp_load(const Phase& P, int mem, int rb, int l
 
 // Right-hand side, B sub-step and adjoint right-hand side: one block per
 // row pair (grid.x), level (grid.y) and member (grid.z).
-template <typename T, int OP, int CL, int LOGN, int SCH = 0>
+// One row pair rb at level lev.
+template <typename T, int OP, int CL, int LOGN, int SCH, bool WV>
+__device__ __forceinline__ void rowp_pair(const Phase& P, int rb, int lev, cpx<T>* buf, const cpx<T>* twl,
+                                          double* red) {
+  using V = cpx<T>;
+  constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
+  if constexpr (LOGN != 0) {
+    // compile-time row length: loads, packing and the first pass leave out
+    // the blocks of columns the 2/3 set (grid level) or the test filter
+    // (test level) keep empty.  WV: one wave per transform, 16 points per
+    // thread at 1024 (8 below)
+    constexpr int EPT = (WV && LOGN >= 10) ? 16 : 8;
+    constexpr int LGT = LOGN - (EPT == 16 ? 4 : 3);   // log2 of the threads per transform
+    constexpr int nb = rowp_nb(OP, CL);
+    const MemberDev M = member_const(P, blockIdx.z);
+    const int grp = threadIdx.x >> LGT;
+    const int j = threadIdx.x & ((1 << LGT) - 1);
+    const cpx<T>* row = cptr<T>(M, P.o_mf) +
+                        (long long)(OP == OP_ADJ_B ? 0 : lev * nb + grp) * ((long long)P.ny * P.mfp) +
+                        (long long)(2 * rb) * P.mfp;
+    RowRaw<T, EPT> in;
+    V vin[EPT];
+    if (dyn && lev == 1) {
+      c2r_loadc<T, LOGN, true, EPT>(in, row, P.mfp, j, min(P.kxn, M.test_kx));
+      c2r_formc<T, true, EPT>(in, vin, j);
+      rowp_item<T, OP, CL, LOGN, band_zero_mask<true>(), SCH, EPT, WV>(P, blockIdx.z, rb, lev, vin, buf, twl, red,
+                                                                        rb);
+    } else {
+      c2r_loadc<T, LOGN, false, EPT>(in, row, P.mfp, j, P.kxn);
+      c2r_formc<T, false, EPT>(in, vin, j);
+      rowp_item<T, OP, CL, LOGN, band_zero_mask<false>(), SCH, EPT, WV>(P, blockIdx.z, rb, lev, vin, buf, twl, red,
+                                                                         rb);
+    }
+  } else {
+    RowRaw<T> in;
+    rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
+    V vin[8];
+    rowp_form<T>(P, blockIdx.z, OP == OP_RHS && lev == 1, in, vin);
+    rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
+  }
+}
+
+// Right-hand side, B sub-step and adjoint right-hand side: one block per
+// row pair (grid.x, RPB row pairs one after the other when RPB > 1), level
+// (grid.y) and member (grid.z).
+template <typename T, int OP, int CL, int LOGN, int SCH = 0, bool WV = false, int RPB = 1>
 __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
@@ -1281,45 +1334,18 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   int rbb = blockIdx.x;
   if ((gridDim.x & 7) == 0) rbb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   // the two levels of the dynamic closures (grid and test filter) are
-  // independent: one block each
-  // (and the two passes of a dynamic closure's adjoint stage, adj_mode 2)
+  // independent: one block each (and the two passes of a dynamic closure's
+  // adjoint stage, adj_mode 2)
   const int lev = (dyn || OP == OP_ADJ_RHS) ? (int)blockIdx.y : 0;
   // twiddles straight from the (cached) global table: keeping LDS to the
   // field buffers lets one more block share a compute unit
   const V* twl = reinterpret_cast<const V*>(SCH ? P.twx1 : P.twx);
-  // the step's passes may take several row pairs per block, one after the
-  // other (a tuning choice)
-  const int rpb = (OP == OP_RHS || OP == OP_B) ? P.rpb : 1;
-  for (int r = 0; r < rpb; ++r) {
-  const int rb = rbb * rpb + r;
-  if constexpr (LOGN != 0) {
-    // compile-time row length: loads, packing and the first pass leave out
-    // the blocks of columns the 2/3 set (grid level) or the test filter
-    // (test level) keep empty
-    constexpr int nb = rowp_nb(OP, CL);
-    const MemberDev M = member_const(P, blockIdx.z);
-    const int grp = threadIdx.x >> (LOGN - 3);
-    const int j = threadIdx.x & ((1 << (LOGN - 3)) - 1);
-    const cpx<T>* row = cptr<T>(M, P.o_mf) + (long long)(OP == OP_ADJ_B ? 0 : lev * nb + grp) * ((long long)P.ny * P.mfp) +
-                        (long long)(2 * rb) * P.mfp;
-    RowRaw<T> in;
-    V vin[8];
-    if (dyn && lev == 1) {
-      c2r_loadc<T, LOGN, true>(in, row, P.mfp, j, min(P.kxn, M.test_kx));
-      c2r_formc<T, true>(in, vin, j);
-      rowp_item<T, OP, CL, LOGN, band_zero_mask<true>(), SCH>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
-    } else {
-      c2r_loadc<T, LOGN, false>(in, row, P.mfp, j, P.kxn);
-      c2r_formc<T, false>(in, vin, j);
-      rowp_item<T, OP, CL, LOGN, band_zero_mask<false>(), SCH>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
-    }
+  // (no loop at all for one row pair per block: even a loop of one trip
+  // changes the register allocation of the body)
+  if constexpr (RPB == 1) {
+    rowp_pair<T, OP, CL, LOGN, SCH, WV>(P, rbb, lev, buf, twl, red);
   } else {
-    RowRaw<T> in;
-    rowp_load<T, OP, CL>(P, blockIdx.z, rb, lev, in);
-    V vin[8];
-    rowp_form<T>(P, blockIdx.z, OP == OP_RHS && lev == 1, in, vin);
-    rowp_item<T, OP, CL, LOGN>(P, blockIdx.z, rb, lev, vin, buf, twl, red, rb);
-  }
+    for (int r = 0; r < RPB; ++r) rowp_pair<T, OP, CL, LOGN, SCH, WV>(P, rbb * RPB + r, lev, buf, twl, red);
   }
 }
 
@@ -2354,35 +2380,54 @@ static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   const int nb = rowp_fields(op, cl);
   return P.nx >= 64 && nb * P.nx / 8 <= 1024 && rowp_lds(dbl, op, cl, P) <= 128 * 1024;
 }
+// The compile-time row engines of length 2^LN; the step's passes take the
+// tuned pass schedule (s1) and wave-synchronous transforms (wv).
+template <typename T, int OP, int CL, int LN, int RPB>
+static void launch_rowp_sched(const Phase& P, dim3 grid, dim3 block, size_t lds, hipStream_t s, bool s1, bool wv) {
+  if (wv) {
+    if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, LN, 1, true, RPB>), grid, block, lds, s, P);
+    else QG_KLAUNCH((k_rowp<T, OP, CL, LN, 0, true, RPB>), grid, block, lds, s, P);
+  } else {
+    if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, LN, 1, false, RPB>), grid, block, lds, s, P);
+    else QG_KLAUNCH((k_rowp<T, OP, CL, LN, 0, false, RPB>), grid, block, lds, s, P);
+  }
+}
+template <typename T, int OP, int CL, int LN>
+static void launch_rowp_len(const Phase& P, dim3 grid, dim3 block, size_t lds, hipStream_t s, bool s1, bool wv,
+                            int rpb) {
+  if constexpr (OP == OP_RHS || OP == OP_B) {
+    if (rpb == 2) launch_rowp_sched<T, OP, CL, LN, 2>(P, grid, block, lds, s, s1, wv);
+    else launch_rowp_sched<T, OP, CL, LN, 1>(P, grid, block, lds, s, s1, wv);
+    return;
+  }
+  QG_KLAUNCH((k_rowp<T, OP, CL, LN>), grid, block, lds, s, P);
+}
+
 template <typename T, int OP, int CL>
 static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   const int nb = rowp_fields(OP, CL);
   const int levels = (OP == OP_RHS && (CL == 3 || CL == 4)) || (OP == OP_ADJ_RHS && P.adj_mode == 2) ? 2 : 1;
   const size_t lds = rowp_lds(sizeof(T) == 8, OP, CL, P);
-  const dim3 block(nb * P.nx / 8);
-  // the step's passes take the tuned row pairs per block and pass schedule
+  // the step's passes take the tuned row pairs per block, pass schedule and
+  // synchronisation (one wave per transform: 16 points per thread at 1024)
   const bool step = OP == OP_RHS || OP == OP_B;
-  const int rpb = step ? P.rpb : 1;
+  const int rpb = step && P.rpb == 2 ? 2 : 1;
   const bool s1 = step && P.rsch == 1;
+  const bool wv = step && P.rwv == 1;
+  const dim3 block(nb * (wv && P.nx >= 1024 ? P.nx / 16 : P.nx / 8));
   dim3 grid(P.ny / (2 * rpb), levels, nmem);
   // compile-time transform lengths for the common row lengths (their
   // engines assume the mixed fields hold the 2/3 set: kxn columns)
   const int lognx = P.kxn == (P.nx - 1) / 3 + 1 ? P.lognx : 0;
   switch (lognx) {
-    case 8:
-      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 8, 1>), grid, block, lds, s, P);
-      else QG_KLAUNCH((k_rowp<T, OP, CL, 8>), grid, block, lds, s, P);
-      return;
-    case 9:
-      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 9, 1>), grid, block, lds, s, P);
-      else QG_KLAUNCH((k_rowp<T, OP, CL, 9>), grid, block, lds, s, P);
-      return;
-    case 10:
-      if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, 10, 1>), grid, block, lds, s, P);
-      else QG_KLAUNCH((k_rowp<T, OP, CL, 10>), grid, block, lds, s, P);
-      return;
-    default: QG_KLAUNCH((k_rowp<T, OP, CL, 0>), grid, block, lds, s, P); return;
+    case 8: launch_rowp_len<T, OP, CL, 8>(P, grid, block, lds, s, s1, wv, rpb); return;
+    case 9: launch_rowp_len<T, OP, CL, 9>(P, grid, block, lds, s, s1, wv, rpb); return;
+    case 10: launch_rowp_len<T, OP, CL, 10>(P, grid, block, lds, s, s1, wv, rpb); return;
+    default: break;
   }
+  // the run-time-length engine: one row pair per block
+  grid.x = P.ny / 2;
+  QG_KLAUNCH((k_rowp<T, OP, CL, 0>), grid, dim3(nb * P.nx / 8), lds, s, P);
 }
 
 template <typename T, int OP, int CL>

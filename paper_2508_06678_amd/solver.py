@@ -185,11 +185,11 @@ class Solver:
         return list(ms[:n.value])
 
     def tuning(self):
-        """Launch configuration per member: dicts with W, Wi, rsched, csched, rpb."""
-        t = (ctypes.c_int32 * (5 * self.n))()
+        """Launch configuration per member: dicts with W, Wi, rsched, csched, rpb, rwave."""
+        t = (ctypes.c_int32 * (6 * self.n))()
         _lib.check(self.L.qg_tuning(self.h, t))
-        keys = ("W", "Wi", "rsched", "csched", "rpb")
-        return [dict(zip(keys, t[5 * i: 5 * i + 5])) for i in range(self.n)]
+        keys = ("W", "Wi", "rsched", "csched", "rpb", "rwave")
+        return [dict(zip(keys, t[6 * i: 6 * i + 6])) for i in range(self.n)]
 
     def column_widths(self):
         """Strip width of the column-forward pass per member."""

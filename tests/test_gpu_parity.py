@@ -9,6 +9,7 @@ row or strip cannot hide in the norm.  Sizes span several column strips and
 row blocks with ragged tails (kx counts that are not multiples of the strip
 width).
 """
+import itertools
 import math
 
 import numpy as np
@@ -217,7 +218,8 @@ def test_every_tuning_choice(tmp_path, precision, nx, ny, closure):
     """Every combination of the tuner's choices for the compile-time engines
     -- row and column pass schedules (1024 = 8 8 8 2 or 8 4 4 8, 512 = 8 8 8
     or 8 4 4 4, 256 = 8 8 4 or 8 4 8), one or two row pairs per row block,
-    one or four columns per inverse strip -- forced through the tuning cache,
+    one or four columns per inverse strip, block- or wave-synchronous row
+    transforms -- forced through the tuning cache,
     gives the oracle's step to the tolerance."""
     import json
     import torch
@@ -228,22 +230,19 @@ def test_every_tuning_choice(tmp_path, precision, nx, ny, closure):
     key = f"{arch}/{nx}x{ny}/fp{precision}/closure{code}/members1"
     ref = None
     wmax = min(4, (2048 if precision == 64 else 4096) // ny)   # widest inverse strip of one tile
-    for rs in (0, 1):
-        for cs in (0, 1):
-            for rpb in (1, 2):
-                for Wi in (1, wmax):
-                    choice = {"/fwd": 1, "/inv": Wi, "/rsched": rs, "/csched": cs, "/rpb": rpb}
-                    cache = tmp_path / f"t{rs}{cs}{rpb}{Wi}.json"
-                    cache.write_text(json.dumps({key + k: v for k, v in choice.items()}))
-                    S = solver_for([m], precision)
-                    S.autotune(str(cache))
-                    assert S.tuning() == [{"W": 1, "Wi": Wi, "rsched": rs, "csched": cs, "rpb": rpb}]
-                    om = S.pack([m.omega0])
-                    w_in = to_np(om).reshape(ny, nx)
-                    S.step(om, 1, use_graph=True)
-                    if ref is None:
-                        ref = qg.step(w_in, M)
-                    err = field_err(to_np(om).reshape(ny, nx), ref)
-                    say("  rsched", rs, "csched", cs, "rpb", rpb, "Wi", Wi, err)
-                    assert err < TOL[precision]
-                    S.close()
+    for rs, cs, rpb, Wi, wv in itertools.product((0, 1), (0, 1), (1, 2), (1, wmax), (0, 1)):
+        choice = {"/fwd": 1, "/inv": Wi, "/rsched": rs, "/csched": cs, "/rpb": rpb, "/rwave": wv}
+        cache = tmp_path / f"t{rs}{cs}{rpb}{Wi}{wv}.json"
+        cache.write_text(json.dumps({key + k: v for k, v in choice.items()}))
+        S = solver_for([m], precision)
+        S.autotune(str(cache))
+        assert S.tuning() == [{"W": 1, "Wi": Wi, "rsched": rs, "csched": cs, "rpb": rpb, "rwave": wv}]
+        om = S.pack([m.omega0])
+        w_in = to_np(om).reshape(ny, nx)
+        S.step(om, 1, use_graph=True)
+        if ref is None:
+            ref = qg.step(w_in, M)
+        err = field_err(to_np(om).reshape(ny, nx), ref)
+        say("  rsched", rs, "csched", cs, "rpb", rpb, "Wi", Wi, "rwave", wv, err)
+        assert err < TOL[precision]
+        S.close()
