@@ -38,21 +38,25 @@ PHASE_NAMES = ["colinv_rhs", "row_rhs", "colfwd_rhs", "combine_dyn", "colinv_b",
 PHASE_LAUNCHES = [4, 4, 4, 4, 1, 1, 1]
 
 
-def kernel_names(nx, ny, fwd_width):
-    """Names of the kernels behind each phase (as the profiler lists them):
-    compile-time transform lengths for 256..1024, the single-column forward
-    kernel when the forward strip width is 1."""
+def kernel_names(nx, ny, tuning):
+    """Names of the kernels behind each phase (as the profiler lists them,
+    with every template argument): compile-time transform lengths for
+    256..1024 with the tuned pass schedules, row pairs per block and row
+    synchronisation, the single-column forward kernel when the forward strip
+    width is 1."""
     lx = int(math.log2(nx)) if nx in (256, 512, 1024) else 0
     ly = int(math.log2(ny)) if ny in (256, 512, 1024) else 0
-    lf = ly if fwd_width == 1 else 0
+    lf = ly if tuning["W"] == 1 else 0
+    cs = tuning["csched"]
+    row = f"{tuning['rsched'] if lx else 0}, {'true' if tuning['rwave'] and lx else 'false'}, {tuning['rpb'] if lx else 1}"
     return {
-        "colinv_rhs": f"k_colinv<float, 0, 4, {ly}>",
-        "row_rhs": f"k_rowp<float, 0, 4, {lx}>",
-        "colfwd_rhs": f"k_colfwdp<float, 0, 4, {lf}>",
+        "colinv_rhs": f"k_colinv<float, 0, 4, {ly}, {cs if ly else 0}>",
+        "row_rhs": f"k_rowp<float, 0, 4, {lx}, {row}>",
+        "colfwd_rhs": f"k_colfwdp<float, 0, 4, {lf}, {cs if lf else 0}>",
         "combine_dyn": "k_combine<float>",
-        "colinv_b": f"k_colinv<float, 1, 0, {ly}>",
-        "row_b": f"k_rowp<float, 1, 0, {lx}>",
-        "colfwd_b": f"k_colfwdp<float, 1, 0, {lf}>",
+        "colinv_b": f"k_colinv<float, 1, 0, {ly}, {cs if ly else 0}>",
+        "row_b": f"k_rowp<float, 1, 0, {lx}, {row}>",
+        "colfwd_b": f"k_colfwdp<float, 1, 0, {lf}, {cs if lf else 0}>",
     }
 
 
@@ -291,7 +295,7 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="tuning cache file: read if it holds the workload, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
+                    help="also run a plain 256 MiB elementwise device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -315,9 +319,9 @@ def main():
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)     # a plain streaming kernel: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
-        log("copy calibration: 3 copies of 268435456 bytes")
+        log("copy calibration: 3 elementwise copies (negation) of 268435456 bytes")
         del src, dst
     wl = configs.config3(precision=32)
     nx, ny = wl.members[0].params["nx"], wl.members[0].params["ny"]
@@ -326,7 +330,8 @@ def main():
 
     # ---- FP32, one 1024^2 member (value)
     S, om = make_solver(wl, 32)
-    names = kernel_names(nx, ny, S.column_widths()[0])
+    tuned = S.tuning()[0]
+    names = kernel_names(nx, ny, tuned)
     sec, wall = time_steps(S, om, K, W, torch)
     value = pts * K / sec
     log(f"fp32 1024^2 dleith: {sec / K * 1e3:.4f} ms/step (median of {WINDOWS} windows of {K}), "
@@ -364,6 +369,7 @@ def main():
         "step_roofline_frac": step_gbs / HBM_PEAK_GBS,
         "step_roofline_frac_388B": bpp32 * pts / (sec / K) / 1e9 / HBM_PEAK_GBS,
     }
+    result["tuning"] = tuned
     if roof:
         result["roofline"] = roof
         result["kernels_us_per_dispatch"] = {k: v[0] * 1e3 for k, v in kt.items()}
@@ -394,7 +400,7 @@ def main():
                              "step_roofline_frac": nb * step_bytes / (secb / kb) / 1e9 / HBM_PEAK_GBS,
                              "step_roofline_frac_388B": bpp32 * ptsb / (secb / kb) / 1e9 / HBM_PEAK_GBS}
         if "phases" not in skip:
-            bnames = kernel_names(nx, ny, S.column_widths()[0])
+            bnames = kernel_names(nx, ny, S.tuning()[0])
             broof, bkt, _ = roofline_of(S, om, nx, ny, "dleith", max(5, args.prof_steps // 4), bnames, members=nb)
             result["batched"]["roofline_dominant"] = broof
             result["batched"]["kernels_us_per_dispatch"] = {k: v[0] * 1e3 for k, v in bkt.items()}
