@@ -36,17 +36,19 @@ class QGError(RuntimeError):
         self.code = code
 
 
-_lib = None
+_libs = {}
+POISON_LIB_PATH = os.path.join(_PKG, "libqg_ldspoison.so")
 
 
-def lib():
-    """Load libqg.so once; raise if it has not been built."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_06678_amd.build.build()")
-    L = ctypes.CDLL(LIB_PATH)
+def lib(path=None):
+    """Load libqg.so (or the library at `path`, e.g. the LDS-poison debug
+    build) once; raise if it has not been built."""
+    path = LIB_PATH if path is None else path
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2508_06678_amd.build.build()")
+    L = ctypes.CDLL(path)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     P = ctypes.POINTER(QGParams)
     L.qg_workspace_bytes.argtypes = [P, i32, i32, ctypes.POINTER(sz)]
@@ -74,13 +76,15 @@ def lib():
     for name in EXPORTS:
         if name not in ("qg_destroy", "qg_last_error"):
             getattr(L, name).restype = ctypes.c_int
-    _lib = L
+    _libs[path] = L
     return L
 
 
-def check(rc):
+def check(rc, L=None):
+    """Raise QGError with the library's message (L: the library that
+    returned rc; the default one if None)."""
     if rc != QG_OK:
-        raise QGError(rc, lib().qg_last_error().decode())
+        raise QGError(rc, (L or lib()).qg_last_error().decode())
 
 
 def make_params(d):

@@ -6,6 +6,10 @@ qg_adjoint_step and qg_step_noalloc for rocprofv3 --marker-trace).
 Sources are compiled in parallel (the kernel file once per slice of its
 launchers, QG_PART = 0..4), then linked into paper_2508_06678_amd/libqg.so.
 All device code is built with packed-FP32 instruction generation disabled.
+A debug variant, libqg_ldspoison.so, is linked from the same sources with
+QG_LDS_POISON defined: every kernel sets its LDS to NaN before use and every
+transform pass poisons its buffer before writing, so that a read of LDS
+nothing wrote carries NaN into the result (tests/test_gpu_lds_poison.py).
 Then the C example program qg_example (plain C99 against include/qg.h,
 linked to libqg.so and the HIP runtime) is built beside it.
 """
@@ -20,7 +24,10 @@ CSRC = os.path.join(PKG, "csrc")
 # (source, extra defines, object name)
 UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}"], f"qg_kernels_{i}.o") for i in range(5)] + \
         [("qg_api.hip", [], "qg_api.o")]
+POISON_UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}", "-DQG_LDS_POISON"], f"qg_kernels_poison_{i}.o")
+                for i in range(5)]
 LIB = os.path.join(PKG, "libqg.so")
+LIB_POISON = os.path.join(PKG, "libqg_ldspoison.so")
 ARCH = os.environ.get("QG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -48,17 +55,20 @@ def build(verbose=False):
         subprocess.run(cmd, check=True)
         return obj
 
-    workers = max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    units = UNITS + POISON_UNITS
+    workers = max(1, min(len(units), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(compile_one, UNITS))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(compile_one, units))
+    api = objs[len(UNITS) - 1]
     rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
-           "-L", rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    for lib, lib_objs in ((LIB, objs[:len(UNITS)]), (LIB_POISON, objs[len(UNITS):] + [api])):
+        tmp = lib + ".tmp"
+        cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *lib_objs, "-o", tmp,
+               "-L", rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
     build_example(verbose)
     return LIB
 

@@ -46,6 +46,32 @@ template <typename V> __device__ __forceinline__ V cscale(V a, decltype(V{}.x) s
 template <typename V> __device__ __forceinline__ V cmul_i(V a) { return cmake<V>(-a.y, a.x); }
 template <typename V> __device__ __forceinline__ V cmul_mi(V a) { return cmake<V>(a.y, -a.x); }
 
+// LDS poison (debug builds with QG_LDS_POISON): before a transform pass
+// writes its outputs, the threads of the transform set every element of its
+// LDS buffer to NaN (all bits set, a NaN in both precisions), so that a
+// position the pass fails to write, or a read that runs ahead of the write
+// it depends on, carries NaN into the result.  n: elements of the buffer,
+// tid / nthreads: the thread's index in the transform and their number.
+// Ordinary builds compile this to nothing.
+template <typename V>
+__device__ __forceinline__ void lds_poison(V* buf, int n, int tid, int nthreads, bool active) {
+#ifdef QG_LDS_POISON
+  if (active) {
+    using S = decltype(V{}.x);
+    S nan;
+    __builtin_memset(&nan, 0xff, sizeof(S));
+    for (int i = tid; i < n; i += nthreads) buf[i] = cmake<V>(nan, nan);
+  }
+#else
+  (void)buf; (void)n; (void)tid; (void)nthreads; (void)active;
+#endif
+}
+#ifdef QG_LDS_POISON
+constexpr bool kLdsPoison = true;
+#else
+constexpr bool kLdsPoison = false;
+#endif
+
 // Pass schedules.  A transform of length 2^logn is a sequence of Stockham
 // passes; the pass with sub-transform length 2^logns has radix
 // 2^pass_log_radix(logn, logns, sch).  The first pass (logns = 0) is radix
@@ -190,6 +216,11 @@ __device__ __forceinline__ void stockham_pass(V* __restrict__ buf, const V* __re
     }
   }
   __syncthreads();
+  if constexpr (kLdsPoison) {
+    // the group's vectors span (nb - 1) bs + (N - 1) es + 1 elements
+    lds_poison(buf, (((1 << s.lognb) - 1) * s.bs + ((1 << s.logN) - 1) * s.es) + 1, g.tid, g.nt, g.active);
+    __syncthreads();
+  }
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int q = g.tid + i * g.nt;
@@ -242,9 +273,13 @@ __device__ __forceinline__ void fft_lds(V* __restrict__ buf, const V* __restrict
 __device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
 
 template <typename V, bool INV>
-__device__ __forceinline__ void fft1_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active) {
+__device__ __forceinline__ void fft1_pass0(V (&v)[8], V* __restrict__ buf, int j, bool active, int logN) {
   if (active) dftR<V, 8, INV>(v);
   __syncthreads();
+  if constexpr (kLdsPoison) {
+    lds_poison(buf, 9 << (logN - 3), j, 1 << (logN - 3), active);
+    __syncthreads();
+  }
   if (active) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) buf[9 * j + t] = v[t];
@@ -273,6 +308,10 @@ __device__ __forceinline__ void fft1_pass(V* __restrict__ buf, const V* __restri
     }
   }
   __syncthreads();
+  if constexpr (kLdsPoison) {
+    lds_poison(buf, pad8(1 << logN), j0, nt, active);
+    __syncthreads();
+  }
   if (active) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -343,6 +382,11 @@ __device__ __forceinline__ void fft1c_pass0(V (&v)[EPT], V* __restrict__ buf, in
     if (active) dft8z<V, INV, ZM>(u[b]);
   }
   fft_sync<WAVE>();
+  if constexpr (kLdsPoison) {
+    static_assert(LOGN > 0, "the poisoned extent needs the length");
+    lds_poison(buf, padp<P>(1 << LOGN), j, (1 << LOGN) / EPT, active);
+    fft_sync<WAVE>();
+  }
   if (active) {
     V* wb = buf + 8 * j + (j >> (P - 3));
 #pragma unroll
@@ -386,6 +430,10 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
     }
   }
   fft_sync<WAVE>();
+  if constexpr (kLdsPoison) {
+    lds_poison(buf, padp<P>(N), j, nt, active);
+    fft_sync<WAVE>();
+  }
   if (active) {
     if constexpr (NB > 1 && LAST) {
       V* wb = buf + padp<P>(j);

@@ -117,6 +117,9 @@ struct Phase {
   int rsch, csch, rpb, rwv;
   const void* twx1;
   const void* twy1;
+  // dynamic LDS bytes of the launch (set by the launcher; read by the LDS
+  // poison of debug builds)
+  unsigned lds_bytes;
 };
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048

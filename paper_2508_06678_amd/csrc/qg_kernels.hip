@@ -62,6 +62,20 @@ namespace qg {
 // LDS column stride of the compile-time column-inverse path (elements)
 __host__ __device__ constexpr int colinv_stride(int ny) { return ny + (ny >> QG_COL_PADS) + 16; }
 
+// LDS poison (debug builds with QG_LDS_POISON): a kernel with dynamic LDS
+// first sets all of it to NaN (bytes 0xff), so that a read of an element
+// nothing has written yet carries NaN into the result; the transform passes
+// poison their buffers again before each write phase (lds_poison).
+__device__ __forceinline__ void lds_poison_all(unsigned char* lds, unsigned bytes) {
+#ifdef QG_LDS_POISON
+  unsigned* w = reinterpret_cast<unsigned*>(lds);
+  for (unsigned i = threadIdx.x; i < bytes / 4; i += blockDim.x) w[i] = 0xffffffffu;
+  __syncthreads();
+#else
+  (void)lds; (void)bytes;
+#endif
+}
+
 // ---------------------------------------------------------------- helpers
 // Workspace pointers come from the member table, so the compiler cannot see
 // that they address global memory and would emit flat loads/stores (which
@@ -343,6 +357,7 @@ template <typename T, int OP, int CL, int LOGN, int SCH = 0>
 __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
   V* tile = reinterpret_cast<V*>(smem_raw);
   const MemberDev M = member_const(P, blockIdx.z);
   const int f = blockIdx.y;
@@ -390,7 +405,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
           v[t] = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, mylim), scale);
         }
       }
-      fft1c_pass0<V, true, PD, band_zero_mask<true>()>(v, buf, j, true);
+      fft1c_pass0<V, true, PD, band_zero_mask<true>(), 8, false, LOGN>(v, buf, j, true);
     } else {
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -404,7 +419,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
           v[t] = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, -1), scale);
         }
       }
-      fft1c_pass0<V, true, PD, band_zero_mask<false>()>(v, buf, j, true);
+      fft1c_pass0<V, true, PD, band_zero_mask<false>(), 8, false, LOGN>(v, buf, j, true);
     }
     fft1c_rest<V, LOGN, true, PD, SCH>(buf, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), j, true);
     // rows of the strip: Wi values of row y per thread group of Wi
@@ -437,7 +452,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
       v[t] = z;
     }
     __syncthreads();   // twiddles staged
-    fft1_pass0<V, true>(v, tile, j, true);
+    fft1_pass0<V, true>(v, tile, j, true, P.logny);
     fft1_rest<V, true>(tile, twl, P.logny, j, true);
     V* out = cptr<T>(M, P.o_mf) + (long long)f * ny * P.mfp + kx0;
     for (int y = j; y < ny; y += n8) gst(out + (long long)y * P.mfp, tile[pad8(y)]);
@@ -600,6 +615,7 @@ template <typename T, int OP, int CL>
 __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 : 2)) k_row(Phase P) {
   using V = cpx<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
   const MemberDev M = member_const(P, blockIdx.z);
   RowCtx<T> C;
   C.buf = reinterpret_cast<V*>(smem_raw);
@@ -1155,7 +1171,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
       fft1c_pass0<V, true, PADS, ZM, EPT, WV, LOGN>(v, mybuf, j, true);
       fft1c_rest<V, LOGN, true, PADS, SCH, EPT, WV>(mybuf, twl, j, true);
     } else {
-      fft1_pass0<V, true>(v, mybuf, j, true);
+      fft1_pass0<V, true>(v, mybuf, j, true, P.lognx);
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
     }
   }
@@ -1200,7 +1216,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     fft1c_pass0<V, false, PADS, 0, EPT, WV, LOGN>(v, mybuf, j, act);
     fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act);
   } else {
-    fft1_pass0<V, false>(v, mybuf, j, act);
+    fft1_pass0<V, false>(v, mybuf, j, act, P.lognx);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
   }
   if constexpr (LOGN != 0) {
@@ -1327,6 +1343,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   using V = cpx<T>;
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
   __shared__ double red[16];
   V* buf = reinterpret_cast<V*>(smem_raw);
   // consecutive row pairs on the same XCD: their interleaved output stores
@@ -1416,6 +1433,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
   using V = cpx<T>;
   constexpr int MAXM = EPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + P.W * P.ny;
   __shared__ double red[16];
@@ -1735,6 +1753,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
                    : OP == OP_ADJ_B ? 3 : OP == OP_ADJ_RHS ? (CL == 1 ? 6 : 4) : OP == OP_PEN ? 2
                    : OP == OP_GTERMS ? 4 : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
   __shared__ double red[16];
   const MemberDev M = member_const(P, blockIdx.z);
   // W = 1: padded single-vector path (compile-time length if LOGN != 0,
@@ -1757,12 +1776,12 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     if constexpr (LOGN != 0) {
-      fft1c_pass0<V, false, CPD>(v, tile + grp * n, lt, true);
+      fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, tile + grp * n, lt, true);
       fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), lt,
                                            true);
     } else {
       __syncthreads();   // twiddles staged
-      fft1_pass0<V, false>(v, tile + grp * n, lt, true);
+      fft1_pass0<V, false>(v, tile + grp * n, lt, true, P.logny);
       fft1_rest<V, false>(tile + grp * n, twl, P.logny, lt, true);
     }
   } else {
@@ -2324,11 +2343,13 @@ __global__ void k_fill_zero(unsigned int* p, size_t n) {
 // own begin and end times (no marker of their own in the stream).
 #define QG_KLAUNCH(KERNEL, GRID, BLOCK, LDS, S, P)                                                    \
   do {                                                                                                \
-    if ((P).ev0)                                                                                      \
-      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, (std::uint32_t)(LDS), S, (hipEvent_t)(P).ev0,        \
-                            (hipEvent_t)(P).ev1, 0u, P);                                              \
+    Phase P_ = (P);                                                                                   \
+    P_.lds_bytes = (unsigned)(LDS);                                                                   \
+    if (P_.ev0)                                                                                       \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, (std::uint32_t)(LDS), S, (hipEvent_t)P_.ev0,         \
+                            (hipEvent_t)P_.ev1, 0u, P_);                                              \
     else                                                                                              \
-      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, P);                                             \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, P_);                                            \
   } while (0)
 
 // strips of a column pass, padded to a multiple of 8 (XCD-aware order)

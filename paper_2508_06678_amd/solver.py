@@ -26,10 +26,10 @@ def _stream(device):
 class Solver:
     """A batch of QG members on one GPU (see include/qg.h for the semantics)."""
 
-    def __init__(self, params, chi, chi_sponge, device="cuda:0", adj_segment_k=0):
+    def __init__(self, params, chi, chi_sponge, device="cuda:0", adj_segment_k=0, lib_path=None):
         if isinstance(params, dict):
             params, chi, chi_sponge = [params], [chi], [chi_sponge]
-        self.L = _lib.lib()
+        self.L = _lib.lib(lib_path)
         self.device = torch.device(device)
         self.params = [dict(p) for p in params]
         precs = {int(p.get("precision", 64)) for p in self.params}
@@ -45,7 +45,7 @@ class Solver:
         arr = (_lib.QGParams * self.n)(*[_lib.make_params(p) for p in self.params])
         self._arr = arr
         size = ctypes.c_size_t()
-        _lib.check(self.L.qg_workspace_bytes(arr, self.n, int(adj_segment_k), ctypes.byref(size)))
+        self._check(self.L.qg_workspace_bytes(arr, self.n, int(adj_segment_k), ctypes.byref(size)))
         self.ws_bytes = size.value
         raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
@@ -56,10 +56,13 @@ class Solver:
         cp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in masks])
         sp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in smasks])
         h = ctypes.c_void_p()
-        _lib.check(self.L.qg_init(arr, self.n, cp, sp, _ptr(self.ws), self.ws_bytes,
+        self._check(self.L.qg_init(arr, self.n, cp, sp, _ptr(self.ws), self.ws_bytes,
                                   int(adj_segment_k), _stream(self.device), ctypes.byref(h)))
         self.h = h
         self.adj_segment_k = int(adj_segment_k)
+
+    def _check(self, rc):
+        _lib.check(rc, self.L)
 
     # -------------------------------------------------------------- fields
     def _dev(self, a):
@@ -94,7 +97,7 @@ class Solver:
             if ckpt.numel() < nsave * self.total:
                 raise ValueError("ckpt too small")
             cptr = _ptr(ckpt)
-        _lib.check(self.L.qg_step(self.h, _ptr(omega), int(nsteps), int(save_every), cptr,
+        self._check(self.L.qg_step(self.h, _ptr(omega), int(nsteps), int(save_every), cptr,
                                   1 if use_graph else 0, _stream(self.device)))
         return (omega, ckpt) if save_every else omega
 
@@ -105,7 +108,7 @@ class Solver:
         self._check_flat(lam, "lambda")
         if grad_c.dtype != torch.float64 or grad_c.device != self.device or grad_c.numel() < self.n:
             raise TypeError("grad_c must be a float64 device tensor with one entry per member")
-        _lib.check(self.L.qg_adjoint_step(self.h, _ptr(omega_ckpt), _ptr(lam), int(nsteps),
+        self._check(self.L.qg_adjoint_step(self.h, _ptr(omega_ckpt), _ptr(lam), int(nsteps),
                                           _ptr(grad_c), _stream(self.device)))
         return lam
 
@@ -115,7 +118,7 @@ class Solver:
         self._check_flat(omega, "omega")
         out = torch.zeros(self.n * 8, dtype=torch.float64, device=self.device)
         nu = torch.empty(self.total, dtype=self.dtype, device=self.device) if want_nu else None
-        _lib.check(self.L.qg_diag(self.h, _ptr(omega), _ptr(out),
+        self._check(self.L.qg_diag(self.h, _ptr(omega), _ptr(out),
                                   _ptr(nu) if nu is not None else None, _stream(self.device)))
         return out.view(self.n, 8), nu
 
@@ -125,7 +128,7 @@ class Solver:
         filtered fields in `les`'s layout."""
         self._check_flat(omega_fr, "omega_fr")
         out = torch.empty(les.total, dtype=les.dtype, device=les.device)
-        _lib.check(self.L.qg_filter_les(self.h, les.h, _ptr(omega_fr), _ptr(out), _stream(self.device)))
+        self._check(self.L.qg_filter_les(self.h, les.h, _ptr(omega_fr), _ptr(out), _stream(self.device)))
         return out
 
     def ideal_sgs(self, les, omega_fr, model=True, bar=True):
@@ -138,7 +141,7 @@ class Solver:
         pi_ff = new()
         pi_m = new() if model else None
         wbar = new() if bar else None
-        _lib.check(self.L.qg_ideal_sgs(self.h, les.h, _ptr(omega_fr), _ptr(pi_ff),
+        self._check(self.L.qg_ideal_sgs(self.h, les.h, _ptr(omega_fr), _ptr(pi_ff),
                                        _ptr(pi_m) if pi_m is not None else None,
                                        _ptr(wbar) if wbar is not None else None, _stream(self.device)))
         return pi_ff, pi_m, wbar
@@ -148,7 +151,7 @@ class Solver:
         flat fields omega (a new flat tensor)."""
         self._check_flat(omega, "omega")
         out = torch.empty(self.total, dtype=self.dtype, device=self.device)
-        _lib.check(self.L.qg_closure_term(self.h, _ptr(omega), _ptr(out), _stream(self.device)))
+        self._check(self.L.qg_closure_term(self.h, _ptr(omega), _ptr(out), _stream(self.device)))
         return out
 
     def pcc(self, a, b):
@@ -156,7 +159,7 @@ class Solver:
         self._check_flat(a, "a")
         self._check_flat(b, "b")
         out = torch.zeros(self.n, dtype=torch.float64, device=self.device)
-        _lib.check(self.L.qg_pcc(self.h, _ptr(a), _ptr(b), _ptr(out), _stream(self.device)))
+        self._check(self.L.qg_pcc(self.h, _ptr(a), _ptr(b), _ptr(out), _stream(self.device)))
         return out
 
     def set_coef(self, c):
@@ -165,12 +168,12 @@ class Solver:
         if len(c) != self.n:
             raise ValueError("one coefficient per member")
         arr = (ctypes.c_double * self.n)(*c)
-        _lib.check(self.L.qg_set_coef(self.h, arr, _stream(self.device)))
+        self._check(self.L.qg_set_coef(self.h, arr, _stream(self.device)))
         for p, v in zip(self.params, c):
             p["c"] = v
 
     def autotune(self, cache_path=None):
-        _lib.check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
+        self._check(self.L.qg_autotune(self.h, cache_path.encode() if cache_path else None,
                                       _stream(self.device)))
 
     def profile_steps(self, omega, nsteps, kind, max_launches=4096):
@@ -180,27 +183,27 @@ class Solver:
         self._check_flat(omega, "omega")
         ms = (ctypes.c_float * max_launches)()
         n = ctypes.c_int32(0)
-        _lib.check(self.L.qg_profile_steps(self.h, _ptr(omega), int(nsteps), int(kind), ms, max_launches,
+        self._check(self.L.qg_profile_steps(self.h, _ptr(omega), int(nsteps), int(kind), ms, max_launches,
                                            ctypes.byref(n), _stream(self.device)))
         return list(ms[:n.value])
 
     def tuning(self):
         """Launch configuration per member: dicts with W, Wi, rsched, csched, rpb, rwave."""
         t = (ctypes.c_int32 * (6 * self.n))()
-        _lib.check(self.L.qg_tuning(self.h, t))
+        self._check(self.L.qg_tuning(self.h, t))
         keys = ("W", "Wi", "rsched", "csched", "rpb", "rwave")
         return [dict(zip(keys, t[6 * i: 6 * i + 6])) for i in range(self.n)]
 
     def column_widths(self):
         """Strip width of the column-forward pass per member."""
         w = (ctypes.c_int32 * self.n)()
-        _lib.check(self.L.qg_info(self.h, None, None, w, None))
+        self._check(self.L.qg_info(self.h, None, None, w, None))
         return list(w)
 
     def inverse_widths(self):
         """Strip width of the column-inverse pass per member."""
         w = (ctypes.c_int32 * self.n)()
-        _lib.check(self.L.qg_info(self.h, None, None, None, w))
+        self._check(self.L.qg_info(self.h, None, None, None, w))
         return list(w)
 
     def close(self):

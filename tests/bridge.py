@@ -51,7 +51,7 @@ def to_np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def solver_for(members, precision, adj_segment_k=0):
+def solver_for(members, precision, adj_segment_k=0, lib_path=None):
     from paper_2508_06678_amd.solver import Solver
     params = []
     for m in members:
@@ -61,4 +61,4 @@ def solver_for(members, precision, adj_segment_k=0):
     dt = np.float32 if precision == 32 else np.float64
     chi = [m.chi.astype(dt) for m in members]
     chs = [m.chi_s.astype(dt) for m in members]
-    return Solver(params, chi, chs, adj_segment_k=adj_segment_k)
+    return Solver(params, chi, chs, adj_segment_k=adj_segment_k, lib_path=lib_path)

@@ -21,8 +21,11 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", txt)))
 
 
-def test_every_declared_symbol_is_exported():
-    L = _lib.lib()
+@pytest.mark.parametrize("path", [None, _lib.POISON_LIB_PATH], ids=["libqg", "libqg_ldspoison"])
+def test_every_declared_symbol_is_exported(path):
+    """The library and its LDS-poison debug build load and export every
+    function include/qg.h declares."""
+    L = _lib.lib(path)
     names = declared_functions()
     assert {"qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag"} <= set(names)
     for n in names:
@@ -130,7 +133,7 @@ def test_init_rejects_small_or_missing_workspace():
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """Without the built HIP library the product path raises: there is no
     CPU fallback to take its place."""
-    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "_libs", {})
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libqg.so"))
     with pytest.raises(ImportError, match="missing"):
         _lib.lib()
