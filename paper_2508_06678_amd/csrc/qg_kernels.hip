@@ -2271,18 +2271,24 @@ __global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
 // ---------------------------------------------------------------- adjoint misc
 // dL/dc: the row blocks' partial sums of one adjoint stage, in a fixed
 // order, accumulated into coef slot 24 of the member (mode 0); mode 1 zeroes
-// the slot; mode 2 adds the slot to the caller's grad_c.
+// the slot; mode 2 adds the slot to the caller's grad_c.  One 64-lane wave
+// per member: lane l sums partials l, l + 64, ... (all loads in flight at
+// once), then a fixed butterfly of shuffles adds the lanes.
 #if QG_HAS(4)
-__global__ void k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
+__global__ void __launch_bounds__(64) k_adj_grad_c(Phase P, int nrow, double* grad_c, int mode) {
   const MemberDev& M = P.mem[P.m0 + blockIdx.x];
-  if (threadIdx.x != 0) return;
   double* slot = rptr<double>(M, P.o_coef) + 24;
-  if (mode == 1) { *slot = 0.0; return; }
-  if (mode == 2) { grad_c[M.user_index] += *slot; return; }
+  if (mode != 0) {
+    if (threadIdx.x != 0) return;
+    if (mode == 1) *slot = 0.0;
+    else grad_c[M.user_index] += *slot;
+    return;
+  }
   const double* d = rptr<double>(M, P.o_dpart);
   double s = 0.0;
-  for (int i = 0; i < nrow; ++i) s += d[i];
-  *slot += s;
+  for (int i = threadIdx.x; i < nrow; i += 64) s += d[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) *slot += s;
 }
 #endif
 
