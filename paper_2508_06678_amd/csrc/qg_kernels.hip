@@ -2162,11 +2162,19 @@ __global__ void __launch_bounds__(PCC_THREADS) k_pcc_centred(Phase P, const void
   const MemberDev M = member_const(P, blockIdx.z);
   const long long n = (long long)P.nx * P.ny;
   double* part = rptr<double>(M, P.o_dpart);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    // the first wave: lane k takes block k's sums (at most 64 blocks), then
+    // a fixed shuffle tree, so every block forms the same means
     double sx = 0.0, sy = 0.0;
-    for (int k = 0; k < (int)gridDim.x; ++k) { sx += part[2 * k]; sy += part[2 * k + 1]; }
-    mean[0] = sx / (double)n;
-    mean[1] = sy / (double)n;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += 64) { sx += part[2 * k]; sy += part[2 * k + 1]; }
+    for (int o = 32; o > 0; o >>= 1) {
+      sx += __shfl_xor(sx, o, 64);
+      sy += __shfl_xor(sy, o, 64);
+    }
+    if (threadIdx.x == 0) {
+      mean[0] = sx / (double)n;
+      mean[1] = sy / (double)n;
+    }
   }
   __syncthreads();
   const double mx = mean[0], my = mean[1];
@@ -2193,11 +2201,16 @@ __global__ void __launch_bounds__(PCC_THREADS) k_pcc_centred(Phase P, const void
 #if QG_HAS(4)
 __global__ void __launch_bounds__(64) k_pcc_final(Phase P, int nblk, double* out) {
   const MemberDev M = member_const(P, blockIdx.x);
-  if (threadIdx.x != 0) return;
   const double* c = rptr<double>(M, P.o_dpart) + 2 * nblk;
+  // lane k < nblk (at most 64 blocks) loads block k's sums; fixed shuffle tree
   double sxy = 0.0, sxx = 0.0, syy = 0.0;
-  for (int k = 0; k < nblk; ++k) { sxy += c[3 * k]; sxx += c[3 * k + 1]; syy += c[3 * k + 2]; }
-  out[M.user_index] = sxy / sqrt(sxx * syy);
+  for (int k = threadIdx.x; k < nblk; k += 64) { sxy += c[3 * k]; sxx += c[3 * k + 1]; syy += c[3 * k + 2]; }
+  for (int o = 32; o > 0; o >>= 1) {
+    sxy += __shfl_xor(sxy, o, 64);
+    sxx += __shfl_xor(sxx, o, 64);
+    syy += __shfl_xor(syy, o, 64);
+  }
+  if (threadIdx.x == 0) out[M.user_index] = sxy / sqrt(sxx * syy);
 }
 #endif
 
@@ -2243,18 +2256,29 @@ __global__ void __launch_bounds__(256) k_diag_spectral(Phase P) {
 }
 
 #if QG_HAS(4)
-__global__ void k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
+__global__ void __launch_bounds__(64) k_diag_final(Phase P, int nrow, int nspec, double* out, int) {
   const MemberDev& M = P.mem[P.m0 + blockIdx.x];
-  if (threadIdx.x != 0) return;
   const double* rp = rptr<double>(M, P.o_dpart);
   const double* sp = rptr<double>(M, P.o_aux);
+  // one 64-lane wave per member: lane l takes partials l, l + 64, ... (all
+  // loads in flight at once), then a fixed butterfly of shuffles
   double nus = 0.0, mn = INFINITY, mxv = -INFINITY, cf = 0.0, bad = 0.0;
-  for (int i = 0; i < nrow; ++i) {
+  for (int i = threadIdx.x; i < nrow; i += 64) {
     nus += rp[5 * i]; mn = fmin(mn, rp[5 * i + 1]); mxv = fmax(mxv, rp[5 * i + 2]);
     cf = fmax(cf, rp[5 * i + 3]); bad = fmax(bad, rp[5 * i + 4]);
   }
   double e = 0.0, z = 0.0;
-  for (int i = 0; i < nspec; ++i) { e += sp[2 * i]; z += sp[2 * i + 1]; }
+  for (int i = threadIdx.x; i < nspec; i += 64) { e += sp[2 * i]; z += sp[2 * i + 1]; }
+  for (int o = 32; o > 0; o >>= 1) {
+    nus += __shfl_xor(nus, o, 64);
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mxv = fmax(mxv, __shfl_xor(mxv, o, 64));
+    cf = fmax(cf, __shfl_xor(cf, o, 64));
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+    e += __shfl_xor(e, o, 64);
+    z += __shfl_xor(z, o, 64);
+  }
+  if (threadIdx.x != 0) return;
   const double n2 = M.inv_n * M.inv_n;
   double* o = out + 8 * M.user_index;
   o[0] = 0.5 * e * n2;
