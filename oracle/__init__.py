@@ -30,7 +30,12 @@ and the closures (Sec. III-A, Eqs. 9-13).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against brute-force DFTs, closed forms, conservation laws, exact per-step
-amplification factors or finite differences, except the full nonlinear step
-with a closure, for which no closed form exists ("parity unpinned" beyond the
-invariants listed in the tests).
+amplification factors or finite differences.  The nonlinear step with a
+closure has no closed form as a whole; it is pinned term by term: the
+closure terms by the enstrophy identity and their static coefficient
+formulas, the dynamic coefficient by its invariances and a semi-closed form,
+the time stepping by exact single-shell amplification and exact decays,
+the Jacobian by a two-mode closed form and its conservation laws; and
+``tests/test_oracle_mutations.py`` checks that a planted mistake in any of
+these terms fails one of the pins.
 """
