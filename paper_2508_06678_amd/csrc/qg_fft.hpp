@@ -457,11 +457,100 @@ __device__ __forceinline__ void fft1c_pass(V* __restrict__ buf, const V* __restr
   if constexpr (!LAST) fft1c_pass<V, LOGN, LOGNS + logR, INV, P, SCH, EPT, WAVE>(buf, tw, j, active);
 }
 
+// The twiddles of a thread's butterflies in the pass with sub-length
+// 2^LOGNS (one set when they share them, NB sets in a last pass).
+template <typename V, int LOGN, int LOGNS, int SCH, int EPT>
+struct PassTw {
+  static constexpr int logR = pass_log_radix(LOGN, LOGNS, SCH), R = 1 << logR, NS = 1 << LOGNS;
+  static constexpr bool LAST = LOGNS + logR == LOGN;
+  static constexpr int NB = EPT / R, nt = (1 << LOGN) / EPT;
+  static constexpr int NK = (NB > 1 && LAST) ? NB : 1;
+  V w[NK][R - 1];
+  __device__ __forceinline__ void load(const V* __restrict__ tw, int j) {
+#pragma unroll
+    for (int b = 0; b < NK; ++b) {
+      const int k = NK > 1 ? j + b * nt : (j & (NS - 1));
+#pragma unroll
+      for (int t = 0; t < R - 1; ++t) w[b][t] = tw[(NS - 8) + k * (R - 1) + t];
+    }
+  }
+};
+
+// fft1c_pass with the pass's twiddles given (cur) and the next pass's
+// loaded while this one computes: their latency (an L2 round trip) is
+// no longer exposed after every barrier
+template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH, int EPT, bool WAVE>
+__device__ __forceinline__ void fft1c_pass_pf(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active,
+                                              const PassTw<V, LOGN, LOGNS, SCH, EPT>& cur) {
+  using TW = PassTw<V, LOGN, LOGNS, SCH, EPT>;
+  constexpr int N = 1 << LOGN;
+  constexpr int NS = TW::NS, logR = TW::logR, R = TW::R, NB = TW::NB, nt = TW::nt;
+  constexpr bool LAST = TW::LAST;
+  constexpr int NR = N / R;
+  constexpr int NEXT = LAST ? LOGNS : LOGNS + logR;
+  V v[NB][R];
+  PassTw<V, LOGN, NEXT, SCH, EPT> nxt;
+  if (active) {
+    const V* rb = buf + padp<P>(j);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[b][t] = rb[b * (nt + (nt >> P)) + t * (NR + (NR >> P))];
+    }
+    if constexpr (!LAST) nxt.load(tw, j);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const V* w = cur.w[TW::NK > 1 ? b : 0];
+#pragma unroll
+      for (int t = 1; t < R; ++t) v[b][t] = cmul(v[b][t], INV ? cconj(w[t - 1]) : w[t - 1]);
+      dftR<V, R, INV>(v[b]);
+    }
+  }
+  fft_sync<WAVE>();
+  if constexpr (kLdsPoison) {
+    lds_poison(buf, padp<P>(N), j, nt, active);
+    fft_sync<WAVE>();
+  }
+  if (active) {
+    if constexpr (NB > 1 && LAST) {
+      V* wb = buf + padp<P>(j);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) wb[b * (nt + (nt >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
+      }
+    } else {
+      constexpr int BO = nt * R;
+      const int k = j & (NS - 1);
+      V* wb = buf + padp<P>(((j >> LOGNS) << (LOGNS + logR)) + k);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) wb[b * (BO + (BO >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
+      }
+    }
+  }
+  fft_sync<WAVE>();
+  if constexpr (!LAST) fft1c_pass_pf<V, LOGN, NEXT, INV, P, SCH, EPT, WAVE>(buf, tw, j, active, nxt);
+}
+
+// The twiddles of the first pass after fft1c_pass0 (sub-length 8), for a
+// caller to load before the first pass so that their latency overlaps it.
+template <typename V, int LOGN, int SCH = 0, int EPT = 8>
+__device__ __forceinline__ PassTw<V, LOGN, 3, SCH, EPT> fft1c_first_tw(const V* __restrict__ tw, int j) {
+  PassTw<V, LOGN, 3, SCH, EPT> t;
+  t.load(tw, j);
+  return t;
+}
+
 // Passes after the first (fft1c_pass0), compile-time length, schedule SCH,
-// EPT elements per thread, wave- or block-wide synchronisation.
+// EPT elements per thread, wave- or block-wide synchronisation; the first
+// of them takes the twiddles the caller loaded (fft1c_first_tw), each
+// loads the next one's while it computes.
 template <typename V, int LOGN, bool INV, int P, int SCH = 0, int EPT = 8, bool WAVE = false>
-__device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active) {
-  fft1c_pass<V, LOGN, 3, INV, P, SCH, EPT, WAVE>(buf, tw, j, active);
+__device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active,
+                                           const PassTw<V, LOGN, 3, SCH, EPT>& first) {
+  fft1c_pass_pf<V, LOGN, 3, INV, P, SCH, EPT, WAVE>(buf, tw, j, active, first);
 }
 
 // The whole block as one group.

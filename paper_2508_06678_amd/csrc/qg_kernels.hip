@@ -390,6 +390,9 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     // first radix-8 pass.
     constexpr int MYH = (NY - 1) / 3;
     const bool testf = dynamic_closure(CL) && (OP == OP_RHS || OP == OP_DIAG) && f >= rhs_fields(CL) / 2;
+    // the second pass's twiddles, loaded alongside the column's values
+    const V* twc = reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy);
+    const auto tw1 = fft1c_first_tw<V, LOGN, SCH>(twc, j);
     V v[8];
     if (testf) {
       // the test set's extent in this column
@@ -421,7 +424,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
       }
       fft1c_pass0<V, true, PD, band_zero_mask<false>(), 8, false, LOGN>(v, buf, j, true);
     }
-    fft1c_rest<V, LOGN, true, PD, SCH>(buf, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), j, true);
+    fft1c_rest<V, LOGN, true, PD, SCH>(buf, twc, j, true, tw1);
     // rows of the strip: Wi values of row y per thread group of Wi
     // threads, eight rows NY/8 apart per thread
     V* out = cptr<T>(M, P.o_mf) + (long long)f * NY * P.mfp + kx0;
@@ -1162,6 +1165,10 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   C.ny = P.ny; C.logW = P.logW; C.kxp = P.mfp;
   const long long pstride = (long long)P.ny * P.kxp;   // MP field stride
   V* mybuf = buf + grp * bstride;
+  // the second pass's twiddles (the same slots serve the c2r and the r2c),
+  // loaded before the first pass
+  PassTw<V, LOGN ? LOGN : 10, 3, SCH, EPT> tw1;
+  if constexpr (LOGN != 0) tw1 = fft1c_first_tw<V, LOGN, SCH, EPT>(twl, j);
   // ---- c2r of field lev * nb + grp
   {
     V v[EPT];
@@ -1169,7 +1176,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     for (int t = 0; t < EPT; ++t) v[t] = vin[t];
     if constexpr (LOGN != 0) {
       fft1c_pass0<V, true, PADS, ZM, EPT, WV, LOGN>(v, mybuf, j, true);
-      fft1c_rest<V, LOGN, true, PADS, SCH, EPT, WV>(mybuf, twl, j, true);
+      fft1c_rest<V, LOGN, true, PADS, SCH, EPT, WV>(mybuf, twl, j, true, tw1);
     } else {
       fft1_pass0<V, true>(v, mybuf, j, true, P.lognx);
       fft1_rest<V, true>(mybuf, twl, P.lognx, j, true);
@@ -1214,7 +1221,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   if constexpr (WV) __syncthreads();   // every product formed before the fields' buffers are overwritten
   if constexpr (LOGN != 0) {
     fft1c_pass0<V, false, PADS, 0, EPT, WV, LOGN>(v, mybuf, j, act);
-    fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act);
+    fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act, tw1);
   } else {
     fft1_pass0<V, false>(v, mybuf, j, act, P.lognx);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
@@ -1773,12 +1780,15 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
   if (one) {
     V v[8];
+    // the second pass's twiddles, loaded alongside the column's values
+    const V* twc = reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy);
+    PassTw<V, LOGN ? LOGN : 10, 3, SCH, 8> tw1;
+    if constexpr (LOGN != 0) tw1 = fft1c_first_tw<V, LOGN, SCH>(twc, lt);
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     if constexpr (LOGN != 0) {
       fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, tile + grp * n, lt, true);
-      fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy), lt,
-                                           true);
+      fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, twc, lt, true, tw1);
     } else {
       __syncthreads();   // twiddles staged
       fft1_pass0<V, false>(v, tile + grp * n, lt, true, P.logny);
