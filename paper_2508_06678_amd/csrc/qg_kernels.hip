@@ -598,6 +598,33 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;  // valid in thread 0
 }
 
+// two block-wide fixed-order sums in one pass of barriers (the same order as
+// two block_sum calls; red: 2 doubles per wave)
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wid] = a;
+    red[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) {
+      ta += red[2 * i];
+      tb += red[2 * i + 1];
+    }
+  }
+  a = ta;   // valid in thread 0
+  b = tb;
+}
+
 __device__ __forceinline__ double block_max(double v, double* red) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -1195,8 +1222,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
         mm += (double)m.x * (double)m.x + (double)m.y * (double)m.y;
       }
     }
-    hp = block_sum(hp, red);
-    mm = block_sum(mm, red);
+    block_sum2(hp, mm, red);
     if (threadIdx.x == 0) {
       double* d = rptr<double>(M, P.o_dpart) + 2 * item_slot;
       d[0] = hp;
@@ -1351,7 +1377,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   constexpr bool dyn = OP == OP_RHS && (CL == 3 || CL == 4);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   lds_poison_all(smem_raw, P.lds_bytes);
-  __shared__ double red[16];
+  __shared__ double red[32];   // 2 doubles per wave (block_sum2), up to 16 waves
   V* buf = reinterpret_cast<V*>(smem_raw);
   // consecutive row pairs on the same XCD: their interleaved output stores
   // meet in one L2
@@ -1443,7 +1469,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
   lds_poison_all(smem_raw, P.lds_bytes);
   V* tile = reinterpret_cast<V*>(smem_raw);
   V* twl = tile + P.W * P.ny;
-  __shared__ double red[16];
+  __shared__ double red[32];   // 2 doubles per wave (block_sum2), up to 16 waves
   const MemberDev M = member_const(P, blockIdx.z);
   const int strip = xcd_order(blockIdx.x, gridDim.x);
   if (strip * P.W >= P.kxn) return;
@@ -1617,8 +1643,8 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, (sizeof(T) == 4 ? 4 : 2)) k_c
       hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
       mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
     }
-    double shm = block_sum(hm, red);
-    double smm = block_sum(mm, red);
+    double shm = hm, smm = mm;
+    block_sum2(shm, smm, red);
     if (threadIdx.x == 0) {
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
@@ -1761,7 +1787,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
                    : OP == OP_GTERMS ? 4 : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   lds_poison_all(smem_raw, P.lds_bytes);
-  __shared__ double red[16];
+  __shared__ double red[32];   // 2 doubles per wave (block_sum2), up to 16 waves
   const MemberDev M = member_const(P, blockIdx.z);
   // W = 1: padded single-vector path (compile-time length if LOGN != 0,
   // twiddles then read from the global table)
@@ -1945,8 +1971,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     }
   }
   if constexpr (OP == OP_RHS && dyn) {
-    const double shm = block_sum(hm, red);
-    const double smm = block_sum(mm, red);
+    double shm = hm, smm = mm;
+    block_sum2(shm, smm, red);
     if (threadIdx.x == 0) {
       double* part = rptr<double>(M, P.o_part) + 2 * strip;
       part[0] = shm;
