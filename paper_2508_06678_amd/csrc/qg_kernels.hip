@@ -257,6 +257,15 @@ __device__ __forceinline__ T adj_coef(const MemberDev& M, const Phase& P) {
   return T(M.coef_static);
 }
 
+// A right-hand-side (or diagnostics) field at a test-filtered mode from
+// its already loaded spectral value x (the caller's loads run ahead of the
+// test set's extent).
+template <typename T, int CL>
+__device__ __forceinline__ cpx<T> rhs_test_value(const MemberDev& M, const Phase& P, int f, int mx, int iy, cpx<T> x) {
+  const int my = my_of_iy(iy, P.myh, P.kyn);
+  return rhs_field<T, CL>(M, f, x, wave<T>(M, mx, my), mx, my, true);
+}
+
 // mylim: test_mylim(mx) of the dynamic closures (-2: evaluate in_test)
 template <typename T, int OP, int CL>
 __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy,
@@ -395,7 +404,20 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     const auto tw1 = fft1c_first_tw<V, LOGN, SCH>(twc, j);
     V v[8];
     if (testf) {
-      // the test set's extent in this column
+      // the spectral values of the blocks t = 0, 1, 6, 7 (|m_y| < NY/4 <=
+      // myh: always inside the stored set) are loaded first, so that their
+      // latency overlaps the test set's extent in this column (a double
+      // square root and its exact integer correction)
+      const int mxl = mx < P.kxn ? mx : P.kxn - 1;
+      const V* xin = cptr<T>(M, P.o_in) + (long long)mxl * P.kyn;
+      V xr[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t >= 2 && t <= 5) continue;
+        const int y = j + t * NT;
+        const int my = t < 4 ? y : y - NY;
+        xr[t] = gld(xin + (my >= 0 ? my : my + P.kyn));
+      }
       const int mylim = mx < P.kxn ? test_mylim(M, P.nx, NY, mx) : -1;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -405,7 +427,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
         const int my = t < 4 ? y : y - NY;
         if (my <= mylim && -my <= mylim) {
           const int iy = my >= 0 ? my : my + P.kyn;
-          v[t] = cscale(colinv_value<T, OP, CL>(M, P, f, mx, iy, mylim), scale);
+          v[t] = cscale(rhs_test_value<T, CL>(M, P, f, mx, iy, xr[t]), scale);
         }
       }
       fft1c_pass0<V, true, PD, band_zero_mask<true>(), 8, false, LOGN>(v, buf, j, true);
