@@ -1826,6 +1826,9 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   if (strip * P.W >= P.kxn) return;
   const int kx0 = strip * P.W;
   const V* src = cptr<T>(M, P.o_mp) + (long long)grp * P.ny * P.kxp + (long long)kx0 * P.ny;
+  // test filter of the dynamic closures (one column per block when W = 1),
+  // formed while the column's values arrive rather than after the transform
+  const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   if (one) {
     V v[8];
     // the second pass's twiddles, loaded alongside the column's values
@@ -1857,8 +1860,6 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   };
   const int nm = P.W * P.kyn;
   double hm = 0.0, mm = 0.0;
-  // test filter of the dynamic closures: one column per block when W = 1
-  const int mylim = dyn && one ? test_mylim(M, P.nx, P.ny, kx0) : -2;
   for (int q = threadIdx.x; q < nm; q += blockDim.x) {
     const int w = one ? 0 : div_kyn(q, P.kyn);
     const int iy = q - (int)__umul24((unsigned)w, (unsigned)P.kyn);
