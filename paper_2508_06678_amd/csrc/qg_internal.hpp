@@ -128,7 +128,7 @@ struct Phase {
 constexpr int COL_EPT = 8;
 constexpr int COL_MAX_THREADS = 512;
 __host__ __device__ constexpr int col_tile_elems(bool dbl) { return dbl ? 2048 : 4096; }
-constexpr int COMBINE_THREADS = 256;
+constexpr int COMBINE_THREADS = 512;
 
 // Launchers (defined in qg_kernels.hip).  Each returns hipGetLastError().
 hipError_t launch_colinv(bool dbl, int op, int closure, const Phase& P, int nmem, hipStream_t s);
