@@ -370,13 +370,22 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   V* tile = reinterpret_cast<V*>(smem_raw);
   const MemberDev M = member_const(P, blockIdx.z);
   const int f = blockIdx.y;
-  const int strip = xcd_order(blockIdx.x, gridDim.x);
+  int strip = xcd_order(blockIdx.x, gridDim.x);
+  // test-filtered fields of the dynamic closures vanish beyond column
+  // test_kx; the row pass reads no further, so nothing is written there.
+  // Their strips are spread over the eight XCDs like the full fields'
+  // (consecutive strips on one XCD), not left on the first few.
+  if constexpr (OP == OP_RHS && dynamic_closure(CL)) {
+    if (f >= rhs_fields(CL) / 2) {
+      const int ns = (min(P.kxn, M.test_kx) + P.Wi - 1) / P.Wi;
+      const int s8 = (ns + 7) >> 3;
+      if ((int)(blockIdx.x >> 3) >= s8) return;
+      strip = (blockIdx.x & 7) * s8 + (blockIdx.x >> 3);
+      if (strip >= ns) return;
+    }
+  }
   if (strip * P.Wi >= P.kxn) return;
   const int kx0 = strip * P.Wi;
-  // test-filtered fields of the dynamic closures vanish beyond column
-  // test_kx; the row pass reads no further, so nothing is written there
-  if constexpr (OP == OP_RHS && dynamic_closure(CL))
-    if (f >= rhs_fields(CL) / 2 && kx0 >= M.test_kx) return;
   const int ny = P.ny;
   const int n = P.Wi * ny;
   const T scale = T(M.inv_n);
