@@ -2017,15 +2017,31 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 // Dynamic closures: C = max(<HM>, 0)/<M^2> from the fixed-order sum of the
 // strip partials (every block sums them identically), then the RHS
 // R = -J + C Q - (k^2/Re + mu) x - i beta kx psi and the RK4 update.
-// Every thread of the block loads its share of the partials at once; the
-// 64-lane wave sums and then the wave sums are added in a fixed order, so
-// every block of a launch forms the same C.  red: 2 doubles per wave.
-__device__ __forceinline__ void dyn_coefficient(const double* part, int nparts, double* red, double& C,
-                                                double& hm_out, double& mm_out, int clip_mode = 0) {
+// Every thread of the block (NT threads) loads its share of the partials at
+// once; the 64-lane wave sums and then the wave sums are added in a fixed
+// order, so every block of a launch forms the same C.  red: 2 doubles per
+// wave.  The thread's first pair comes in as `first` (dyn_part_first), so
+// that a caller can issue that load before it waits on loads of its own.
+struct DynPart {
+  double hm, mm;
+};
+__device__ __forceinline__ DynPart dyn_part_first(const double* part, int nparts) {
+  // unconditional (the index clamped; dyn_coefficient adds it only below
+  // nparts), so that no branch puts the load next to its first use
+  const double* pv = part + 2 * min((int)threadIdx.x, nparts - 1);
+  return DynPart{pv[0], pv[1]};
+}
+template <int NT>
+__device__ __forceinline__ void dyn_coefficient(const DynPart& first, const double* part, int nparts, double* red,
+                                                double& C, double& hm_out, double& mm_out, int clip_mode = 0) {
   double hm = 0.0, mm = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) { hm += part[2 * i]; mm += part[2 * i + 1]; }
+  if ((int)threadIdx.x < nparts) {
+    hm += first.hm;
+    mm += first.mm;
+  }
+  for (int i = threadIdx.x + NT; i < nparts; i += NT) { hm += part[2 * i]; mm += part[2 * i + 1]; }
   for (int o = 32; o > 0; o >>= 1) { hm += __shfl_xor(hm, o, 64); mm += __shfl_xor(mm, o, 64); }
-  const int nw = (blockDim.x + 63) >> 6;
+  constexpr int nw = (NT + 63) >> 6;
   if ((threadIdx.x & 63) == 0) { red[2 * (threadIdx.x >> 6)] = hm; red[2 * (threadIdx.x >> 6) + 1] = mm; }
   __syncthreads();
   hm = 0.0;
@@ -2042,7 +2058,9 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   using V = cpx<T>;
   __shared__ double red[2 * (COMBINE_THREADS / 64)];
   const MemberDev M = member_const(P, blockIdx.z);
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  // the partial sums' first load goes out before the per-mode loads
+  const DynPart pf = dyn_part_first(rptr<double>(M, P.o_part), P.nparts);
+  const int q = blockIdx.x * COMBINE_THREADS + threadIdx.x;
   const bool in = q < P.kxn * P.kyn;
   const bool rk = P.stage >= 1 && P.stage <= 4;
   const V* jsp = cptr<T>(M, P.o_out);
@@ -2069,7 +2087,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
     }
   }
   double C, hm, mm;
-  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
+  dyn_coefficient<COMBINE_THREADS>(pf, rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double* c = rptr<double>(M, P.o_coef);
     if (P.stage == SGS_STAGE) {
@@ -2288,7 +2306,8 @@ __global__ void k_dyn_coef(Phase P, int slot) {
   __shared__ double red[2];   // one 64-thread wave
   const MemberDev M = member_const(P, blockIdx.z);
   double C, hm, mm;
-  dyn_coefficient(rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
+  const double* part = rptr<double>(M, P.o_part);
+  dyn_coefficient<64>(dyn_part_first(part, P.nparts), part, P.nparts, red, C, hm, mm, M.clip_mode);
   if (threadIdx.x == 0) rptr<double>(M, P.o_coef)[slot] = C;
 }
 #endif
