@@ -266,6 +266,21 @@ __device__ __forceinline__ cpx<T> rhs_test_value(const MemberDev& M, const Phase
   return rhs_field<T, CL>(M, f, x, wave<T>(M, mx, my), mx, my, true);
 }
 
+// A column-inverse field outside the test set (right-hand side,
+// diagnostics, B sub-step) from its already loaded spectral value x.
+template <typename T, int OP, int CL>
+__device__ __forceinline__ cpx<T> colinv_field(const MemberDev& M, const Phase& P, int f, int mx, int iy, cpx<T> x) {
+  const int my = my_of_iy(iy, P.myh, P.kyn);
+  const Wave<T> w = wave<T>(M, mx, my);
+  if constexpr (OP == OP_B) {
+    if (f == 2) return x;
+    const cpx<T> psi = poisson<T>(M, x, w, mx, my);
+    return f == 0 ? mul_ia(psi, T(-w.ky)) : mul_ia(psi, T(w.kx));
+  } else {
+    return rhs_field<T, CL>(M, f, x, w, mx, my, false);
+  }
+}
+
 // mylim: test_mylim(mx) of the dynamic closures (-2: evaluate in_test)
 template <typename T, int OP, int CL>
 __device__ __forceinline__ cpx<T> colinv_value(const MemberDev& M, const Phase& P, int f, int mx, int iy,
@@ -440,6 +455,32 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
         }
       }
       fft1c_pass0<V, true, PD, band_zero_mask<true>(), 8, false, LOGN>(v, buf, j, true);
+    } else if constexpr (OP == OP_RHS || OP == OP_DIAG || OP == OP_B) {
+      // every load of the column first, then the fields: a field formed
+      // right after its (lane-conditional) load would wait there for all
+      // loads issued before, one round trip per block of rows
+      const V* xin = cptr<T>(M, P.o_in) + (long long)mx * P.kyn;
+      V xr[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        xr[t] = cmake<V>(T(0), T(0));
+        if (t == 3 || t == 4) continue;
+        const int y = j + t * NT;
+        const int my = t < 4 ? y : y - NY;
+        const bool in = (t <= 1 || t >= 6) || (t == 2 ? my <= MYH : -my <= MYH);
+        if (mx < P.kxn && in) xr[t] = gld(xin + (my >= 0 ? my : my + P.kyn));
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        v[t] = cmake<V>(T(0), T(0));
+        if (t == 3 || t == 4) continue;
+        const int y = j + t * NT;
+        const int my = t < 4 ? y : y - NY;
+        const bool in = (t <= 1 || t >= 6) || (t == 2 ? my <= MYH : -my <= MYH);
+        if (mx < P.kxn && in) v[t] = cscale(colinv_field<T, OP, CL>(M, P, f, mx, my >= 0 ? my : my + P.kyn, xr[t]), scale);
+      }
+      fft1c_pass0<V, true, PD, band_zero_mask<false>(), 8, false, LOGN>(v, buf, j, true);
     } else {
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -1169,6 +1210,10 @@ __device__ __forceinline__ void c2r_loadc(RowRaw<T, EPT>& r, const cpx<T>* row, 
       r.b[e] = gld(q + pitch);
     }
   }
+  // keep every load above the first use of any: the loads of the boundary
+  // blocks sit in lane-conditional branches, and a use moved into such a
+  // branch waits there for all loads issued before the later ones go out
+  asm volatile("" ::: "memory");
 }
 
 template <typename T, bool TL, int EPT = 8>
