@@ -288,6 +288,29 @@ int qg_tuning(const qg_handle* h, int32_t* out);
 int qg_profile_steps(qg_handle* h, void* omega, int64_t nsteps, int32_t kind, float* ms,
                      int32_t max_launches, int32_t* n_launches, void* hip_stream);
 
+/* Phase stamps, for the debug build libqg_stamps.so (compiled with
+ * QG_STAMPS; every other build returns QG_EUNSUPPORTED): qg_step(h, omega,
+ * nsteps) without graphs, as qg_profile_steps, during which lane 0 of every
+ * wave of member 0 of the four right-hand-side kernels (kind 0 the row
+ * pass, 1 the column-inverse pass, 2 the column-forward pass and 3 the
+ * combine of the dynamic closures) writes the GPU's 100 MHz real-time
+ * counter at the kernel's phase boundaries into stamps (device memory of
+ * at least 4 x 8192 x 8 uint64, 2 MiB, to be zeroed by the caller): wave w
+ * (the block's linear index times its waves, plus the wave in the block;
+ * the first 8192 waves) of kind k at uint64 (k 8192 + w) 8 + slot.  Slots:
+ * row pass 0 start, 1 loads in, 2 c2r done, 3 products formed, 4 r2c
+ * done, 5 stores complete; column-inverse 0 start, 1 fields formed, 2
+ * transform done, 3 stores complete; column-forward 0 start, 1 loads in, 2
+ * transform done, 3 mode stores complete, 4 partial sums stored; combine 0
+ * start, 1 loads in, 2 coefficient formed, 3 stores complete; slot 7 the
+ * wave's hardware ids (HW_ID low, XCC_ID high 32 bits).  The passes are
+ * stamped on their compile-time-length paths, the column-forward pass on
+ * its one-column path (strip width 1).  A later launch of a kind
+ * overwrites an earlier one's stamps (the last stage's remain).
+ * RK4 members only.  Synchronises hip_stream. */
+int qg_stamp_steps(qg_handle* h, void* omega, int64_t nsteps, void* stamps, size_t stamp_bytes,
+                   void* hip_stream);
+
 /* Number of members, total grid points, and the tiling chosen per member:
  * strip width of the column-forward and of the column-inverse passes
  * (each output array nullable, n_members entries). */

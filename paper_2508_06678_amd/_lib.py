@@ -15,7 +15,7 @@ CLOSURES = {"none": 0, "smag": 1, "leith": 2, "dsmag": 3, "dleith": 4}
 SCHEMES = {"rk4": 0, "ab2cn": 1}
 
 EXPORTS = ["qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag",
-           "qg_filter_les", "qg_ideal_sgs", "qg_closure_term", "qg_pcc", "qg_set_coef", "qg_autotune", "qg_tuning", "qg_profile_steps", "qg_step_noalloc", "qg_info",
+           "qg_filter_les", "qg_ideal_sgs", "qg_closure_term", "qg_pcc", "qg_set_coef", "qg_autotune", "qg_tuning", "qg_profile_steps", "qg_stamp_steps", "qg_step_noalloc", "qg_info",
            "qg_destroy", "qg_last_error"]
 
 
@@ -38,6 +38,7 @@ class QGError(RuntimeError):
 
 _libs = {}
 POISON_LIB_PATH = os.path.join(_PKG, "libqg_ldspoison.so")
+STAMPS_LIB_PATH = os.path.join(_PKG, "libqg_stamps.so")
 
 
 def lib(path=None):
@@ -66,6 +67,7 @@ def lib(path=None):
     L.qg_step_noalloc.argtypes = [P, vp, vp, vp, i64, vp]
     L.qg_profile_steps.argtypes = [vp, vp, i64, i32, ctypes.POINTER(ctypes.c_float), i32,
                                    ctypes.POINTER(i32), vp]
+    L.qg_stamp_steps.argtypes = [vp, vp, i64, vp, sz, vp]
     L.qg_set_coef.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     L.qg_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
                           ctypes.POINTER(i32)]

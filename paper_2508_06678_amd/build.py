@@ -10,6 +10,8 @@ A debug variant, libqg_ldspoison.so, is linked from the same sources with
 QG_LDS_POISON defined: every kernel sets its LDS to NaN before use and every
 transform pass poisons its buffer before writing, so that a read of LDS
 nothing wrote carries NaN into the result (tests/test_gpu_lds_poison.py).
+A second one, libqg_stamps.so (QG_STAMPS, kernels and API), writes per-wave
+phase stamps for qg_stamp_steps (paper_2508_06678_amd/stamps.py).
 Then the C example program qg_example (plain C99 against include/qg.h,
 linked to libqg.so and the HIP runtime) is built beside it.
 """
@@ -26,8 +28,11 @@ UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}"], f"qg_kernels_{i}.o") for i in ra
         [("qg_api.hip", [], "qg_api.o")]
 POISON_UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}", "-DQG_LDS_POISON"], f"qg_kernels_poison_{i}.o")
                 for i in range(5)]
+STAMP_UNITS = [("qg_kernels.hip", [f"-DQG_PART={i}", "-DQG_STAMPS"], f"qg_kernels_stamps_{i}.o")
+               for i in range(5)] + [("qg_api.hip", ["-DQG_STAMPS"], "qg_api_stamps.o")]
 LIB = os.path.join(PKG, "libqg.so")
 LIB_POISON = os.path.join(PKG, "libqg_ldspoison.so")
+LIB_STAMPS = os.path.join(PKG, "libqg_stamps.so")
 ARCH = os.environ.get("QG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -55,13 +60,14 @@ def build(verbose=False):
         subprocess.run(cmd, check=True)
         return obj
 
-    units = UNITS + POISON_UNITS
+    units = UNITS + POISON_UNITS + STAMP_UNITS
     workers = max(1, min(len(units), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(compile_one, units))
-    api = objs[len(UNITS) - 1]
+    n0, n1 = len(UNITS), len(UNITS) + len(POISON_UNITS)
+    api = objs[n0 - 1]
     rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
-    for lib, lib_objs in ((LIB, objs[:len(UNITS)]), (LIB_POISON, objs[len(UNITS):] + [api])):
+    for lib, lib_objs in ((LIB, objs[:n0]), (LIB_POISON, objs[n0:n1] + [api]), (LIB_STAMPS, objs[n1:])):
         tmp = lib + ".tmp"
         cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *lib_objs, "-o", tmp,
                "-L", rocm_lib, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + rocm_lib]

@@ -474,9 +474,12 @@ struct ProfState {
   int used;
 };
 static thread_local ProfState* g_prof = nullptr;
+// Stamp runs (qg_stamp_steps, stamp builds): the caller's stamp buffer
+static thread_local unsigned long long* g_stamps = nullptr;
 
 static Phase timed(Phase P, int kind) {
   P.ev0 = P.ev1 = nullptr;
+  P.stamps = g_stamps;
   if (g_prof && g_prof->kind == kind && 2 * (g_prof->used + 1) <= (int)g_prof->ev.size()) {
     P.ev0 = g_prof->ev[2 * g_prof->used];
     P.ev1 = g_prof->ev[2 * g_prof->used + 1];
@@ -1521,6 +1524,39 @@ int qg_profile_steps(qg_handle* H, void* omega, int64_t nsteps, int32_t kind, fl
   }
   for (auto e : ps.ev) (void)hipEventDestroy(e);
   return rc;
+}
+
+int qg_stamp_steps(qg_handle* H, void* omega, int64_t nsteps, void* stamps, size_t stamp_bytes, void* hip_stream) {
+#ifndef QG_STAMPS
+  (void)H; (void)omega; (void)nsteps; (void)stamps; (void)stamp_bytes; (void)hip_stream;
+  return fail(QG_EUNSUPPORTED, "this library was built without QG_STAMPS: load libqg_stamps.so");
+#else
+  if (!H || !omega || !stamps) return fail(QG_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(QG_EINVAL, "nsteps must be >= 0");
+  if (stamp_bytes < QG_STAMP_BYTES) {
+    char buf[120];
+    snprintf(buf, sizeof buf, "the stamp buffer needs %zu bytes", QG_STAMP_BYTES);
+    return fail(QG_EINVAL, buf);
+  }
+  Handle& h = H->h;
+  for (const auto& g : h.groups)
+    if (g.scheme != QG_SCHEME_RK4) return fail(QG_EUNSUPPORTED, "stamp runs take RK4 members only");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int rc = QG_OK;
+  g_stamps = static_cast<unsigned long long*>(stamps);
+  try {
+    for (const auto& g : h.groups)
+      if (rc == QG_OK) rc = run_entry(h, g, omega, g.L.wn, st);
+    if (rc == QG_OK) rc = run_steps_eager(h, (int)nsteps, st);
+    for (const auto& g : h.groups)
+      if (rc == QG_OK) rc = run_exit(h, g, g.L.wn, omega, st);
+  } catch (...) {
+    rc = fail(QG_EINVAL, "internal error in qg_stamp_steps");
+  }
+  g_stamps = nullptr;
+  if (rc == QG_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QG_EHIP, "hipStreamSynchronize failed");
+  return rc;
+#endif
 }
 
 // One candidate tuning of a size group.

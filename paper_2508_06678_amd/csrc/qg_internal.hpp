@@ -120,7 +120,20 @@ struct Phase {
   // dynamic LDS bytes of the launch (set by the launcher; read by the LDS
   // poison of debug builds)
   unsigned lds_bytes;
+  // stamp builds only (QG_STAMPS; null elsewhere): the per-wave phase
+  // stamps of qg_stamp_steps
+  unsigned long long* stamps;
 };
+
+// Stamp builds: QG_STAMP_KINDS kernels (0 the right-hand side's row pass,
+// 1 its column-inverse pass, 2 its column-forward pass and 3 the combine
+// of the dynamic closures), QG_STAMP_WAVES waves each (member 0), 8 slots
+// per wave: real-time counter values at the kernel's phase boundaries,
+// slot 7 the wave's hardware ids (HW_ID in the low, XCC_ID in the high
+// 32 bits).
+constexpr int QG_STAMP_KINDS = 4;
+constexpr int QG_STAMP_WAVES = 8192;
+constexpr size_t QG_STAMP_BYTES = (size_t)QG_STAMP_KINDS * QG_STAMP_WAVES * 8 * sizeof(unsigned long long);
 
 // Column passes: a strip tile of W * ny elements (4096 float2 or 2048
 // double2, 32 KiB, unless one column is longer) with 8 elements per thread,

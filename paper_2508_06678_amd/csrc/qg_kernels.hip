@@ -76,6 +76,47 @@ __device__ __forceinline__ void lds_poison_all(unsigned char* lds, unsigned byte
 #endif
 }
 
+// Phase stamps (debug builds with QG_STAMPS, for qg_stamp_steps): lane 0 of
+// every wave of member 0 writes the real-time counter (100 MHz) at the
+// phase boundaries of the four right-hand-side kernels, after an empty asm
+// that takes `dep` as an operand, so that the stamp follows the work that
+// produced it.  Slot 0 (the wave's start) also records the wave's hardware
+// ids.  The stamps' own waits perturb the timing slightly.
+#ifdef QG_STAMPS
+__device__ __forceinline__ void stamp_write(unsigned long long* buf, int kind, int slot) {
+  const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+  if (buf && (threadIdx.x & 63) == 0 && blockIdx.z == 0) {
+    const unsigned w = (blockIdx.y * gridDim.x + blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w < (unsigned)QG_STAMP_WAVES) {
+      unsigned long long* s = buf + ((size_t)kind * QG_STAMP_WAVES + w) * 8;
+      s[slot] = t;
+      if (slot == 0)   // hwreg(HW_REG_HW_ID, 0, 32) and hwreg(HW_REG_XCC_ID, 0, 16)
+        s[7] = (unsigned long long)__builtin_amdgcn_s_getreg(63492) |
+               ((unsigned long long)__builtin_amdgcn_s_getreg(30740) << 32);
+    }
+  }
+}
+#define QG_STAMP(kind, slot, dep)                 \
+  do {                                            \
+    asm volatile("" ::"v"(dep) : "memory");       \
+    stamp_write(P.stamps, (kind), (slot));        \
+  } while (0)
+#define QG_STAMP_DRAIN(kind, slot)                    \
+  do {                                                \
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  \
+    stamp_write(P.stamps, (kind), (slot));            \
+  } while (0)
+#define QG_STAMP_LDS(kind, slot)                        \
+  do {                                                  \
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  \
+    stamp_write(P.stamps, (kind), (slot));              \
+  } while (0)
+#else
+#define QG_STAMP(kind, slot, dep) do {} while (0)
+#define QG_STAMP_DRAIN(kind, slot) do {} while (0)
+#define QG_STAMP_LDS(kind, slot) do {} while (0)
+#endif
+
 // ---------------------------------------------------------------- helpers
 // Workspace pointers come from the member table, so the compiler cannot see
 // that they address global memory and would emit flat loads/stores (which
@@ -383,6 +424,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   lds_poison_all(smem_raw, P.lds_bytes);
   V* tile = reinterpret_cast<V*>(smem_raw);
+  if constexpr (OP == OP_RHS) QG_STAMP(1, 0, 0.f);
   const MemberDev M = member_const(P, blockIdx.z);
   const int f = blockIdx.y;
   int strip = xcd_order(blockIdx.x, gridDim.x);
@@ -454,6 +496,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
           v[t] = cscale(rhs_test_value<T, CL>(M, P, f, mx, iy, xr[t]), scale);
         }
       }
+      if constexpr (OP == OP_RHS) QG_STAMP(1, 1, v[0].x);
       fft1c_pass0<V, true, PD, band_zero_mask<true>(), 8, false, LOGN>(v, buf, j, true);
     } else if constexpr (OP == OP_RHS || OP == OP_DIAG || OP == OP_B) {
       // every load of the column first, then the fields: a field formed
@@ -480,6 +523,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
         const bool in = (t <= 1 || t >= 6) || (t == 2 ? my <= MYH : -my <= MYH);
         if (mx < P.kxn && in) v[t] = cscale(colinv_field<T, OP, CL>(M, P, f, mx, my >= 0 ? my : my + P.kyn, xr[t]), scale);
       }
+      if constexpr (OP == OP_RHS) QG_STAMP(1, 1, v[0].x);
       fft1c_pass0<V, true, PD, band_zero_mask<false>(), 8, false, LOGN>(v, buf, j, true);
     } else {
 #pragma unroll
@@ -497,6 +541,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
       fft1c_pass0<V, true, PD, band_zero_mask<false>(), 8, false, LOGN>(v, buf, j, true);
     }
     fft1c_rest<V, LOGN, true, PD, SCH>(buf, twc, j, true, tw1);
+    if constexpr (OP == OP_RHS) QG_STAMP_LDS(1, 2);
     // rows of the strip: Wi values of row y per thread group of Wi
     // threads, eight rows NY/8 apart per thread
     V* out = cptr<T>(M, P.o_mf) + (long long)f * NY * P.mfp + kx0;
@@ -506,6 +551,7 @@ __global__ void __launch_bounds__(COL_MAX_THREADS, 4) k_colinv(Phase P) {
     V* dst = out + y0 * P.mfp + c;
 #pragma unroll
     for (int i = 0; i < 8; ++i) gst(dst + i * (NY / 8) * P.mfp, src[i * (NY / 8 + (NY / 8 >> PD))]);
+    if constexpr (OP == OP_RHS) QG_STAMP_DRAIN(1, 3);
     return;
   }
   V* twl = tile + P.Wi * P.ny + (P.Wi == 1 ? P.ny / 8 : 0);
@@ -1268,6 +1314,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   C.ny = P.ny; C.logW = P.logW; C.kxp = P.mfp;
   const long long pstride = (long long)P.ny * P.kxp;   // MP field stride
   V* mybuf = buf + grp * bstride;
+  if constexpr (OP == OP_RHS) QG_STAMP(0, 1, vin[EPT - 1].x);
   // the second pass's twiddles (the same slots serve the c2r and the r2c),
   // loaded before the first pass
   PassTw<V, LOGN ? LOGN : 10, 3, SCH, EPT> tw1;
@@ -1286,6 +1333,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     }
   }
   if constexpr (WV) __syncthreads();   // every field in physical space before the products read them
+  if constexpr (OP == OP_RHS) QG_STAMP_LDS(0, 2);
   if constexpr (OP == OP_CLIPF) {
     // sums of max(H, 0) M and M^2 over the two rows (group 0's points)
     double hp = 0.0, mm = 0.0;
@@ -1315,6 +1363,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
     for (int t = 0; t < EPT; ++t)
       v[t] = rowp_product<T, OP, CL, PADS>(M, P, buf, bstride, j + t * ng, grp, ya, dc, U, Vv, coef);
   }
+  if constexpr (OP == OP_RHS) QG_STAMP(0, 3, v[0].x);
   if constexpr (OP == OP_ADJ_RHS) {
     const double sdc = block_sum(dc, red);
     if (threadIdx.x == 0 && lev == 0) rptr<double>(M, P.o_dpart)[item_slot] = sdc * M.dcoef_dc;
@@ -1324,6 +1373,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   if constexpr (LOGN != 0) {
     fft1c_pass0<V, false, PADS, 0, EPT, WV, LOGN>(v, mybuf, j, act);
     fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act, tw1);
+    if constexpr (OP == OP_RHS) QG_STAMP_LDS(0, 4);
   } else {
     fft1_pass0<V, false>(v, mybuf, j, act, P.lognx);
     fft1_rest<V, false>(mybuf, twl, P.lognx, j, act);
@@ -1355,6 +1405,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
         }
       }
     }
+    if constexpr (OP == OP_RHS) QG_STAMP_DRAIN(0, 5);
   } else if (act) {
     V* dst = cptr<T>(M, P.o_mp) + (long long)(OP == OP_ADJ_RHS ? lev * np + grp : lev * 3 + grp) * pstride;
     for (int k = j; k < P.kxn; k += ng) {
@@ -1455,6 +1506,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   lds_poison_all(smem_raw, P.lds_bytes);
   __shared__ double red[32];   // 2 doubles per wave (block_sum2), up to 16 waves
   V* buf = reinterpret_cast<V*>(smem_raw);
+  if constexpr (OP == OP_RHS) QG_STAMP(0, 0, 0.f);
   // consecutive row pairs on the same XCD: their interleaved output stores
   // meet in one L2
   int rbb = blockIdx.x;
@@ -1864,6 +1916,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   lds_poison_all(smem_raw, P.lds_bytes);
   __shared__ double red[32];   // 2 doubles per wave (block_sum2), up to 16 waves
+  if constexpr (dyn) QG_STAMP(2, 0, 0.f);
   const MemberDev M = member_const(P, blockIdx.z);
   // W = 1: padded single-vector path (compile-time length if LOGN != 0,
   // twiddles then read from the global table)
@@ -1892,8 +1945,10 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << lg));
     if constexpr (LOGN != 0) {
+      if constexpr (dyn) QG_STAMP(2, 1, v[7].x);
       fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, tile + grp * n, lt, true);
       fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, twc, lt, true, tw1);
+      if constexpr (dyn) QG_STAMP_LDS(2, 2);
     } else {
       __syncthreads();   // twiddles staged
       fft1_pass0<V, false>(v, tile + grp * n, lt, true, P.logny);
@@ -2048,6 +2103,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     }
   }
   if constexpr (OP == OP_RHS && dyn) {
+    QG_STAMP_DRAIN(2, 3);
     double shm = hm, smm = mm;
     block_sum2(shm, smm, red);
     if (threadIdx.x == 0) {
@@ -2055,6 +2111,7 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
       part[0] = shm;
       part[1] = smm;
     }
+    QG_STAMP_DRAIN(2, 4);
   }
 }
 
@@ -2102,6 +2159,7 @@ template <typename T>
 __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   using V = cpx<T>;
   __shared__ double red[2 * (COMBINE_THREADS / 64)];
+  QG_STAMP(3, 0, 0.f);
   const MemberDev M = member_const(P, blockIdx.z);
   // the partial sums' first load goes out before the per-mode loads
   const DynPart pf = dyn_part_first(rptr<double>(M, P.o_part), P.nparts);
@@ -2131,8 +2189,10 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
       r0 = csub(r0, mul_ia(poisson<T>(M, x, w, mx, my), (T(M.beta) * w.kx)));
     }
   }
+  QG_STAMP(3, 1, r0.x);
   double C, hm, mm;
   dyn_coefficient<COMBINE_THREADS>(pf, rptr<double>(M, P.o_part), P.nparts, red, C, hm, mm, M.clip_mode);
+  QG_STAMP(3, 2, C);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double* c = rptr<double>(M, P.o_coef);
     if (P.stage == SGS_STAGE) {
@@ -2178,6 +2238,7 @@ __global__ void __launch_bounds__(COMBINE_THREADS) k_combine(Phase P) {
   } else {
     gst(xout + q, cadd(a, cscale(r, T(M.dt6))));
   }
+  QG_STAMP_DRAIN(3, 3);
 }
 
 // ---------------------------------------------------------------- dynamic-closure adjoint

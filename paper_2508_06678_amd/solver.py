@@ -187,6 +187,16 @@ class Solver:
                                            ctypes.byref(n), _stream(self.device)))
         return list(ms[:n.value])
 
+    def stamp_steps(self, omega, nsteps):
+        """qg_step without graphs, with per-wave phase stamps of the four
+        right-hand-side kernels (the stamp build libqg_stamps.so only);
+        returns them as a (4, 8192, 8) uint64 array on the host."""
+        self._check_flat(omega, "omega")
+        buf = torch.zeros(4 * 8192 * 8, dtype=torch.int64, device=self.device)
+        self._check(self.L.qg_stamp_steps(self.h, _ptr(omega), int(nsteps), _ptr(buf), buf.numel() * 8,
+                                         _stream(self.device)))
+        return buf.cpu().numpy().view(np.uint64).reshape(4, 8192, 8)
+
     def tuning(self):
         """Launch configuration per member: dicts with W, Wi, rsched, csched, rpb, rwave."""
         t = (ctypes.c_int32 * (6 * self.n))()

@@ -21,10 +21,11 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", txt)))
 
 
-@pytest.mark.parametrize("path", [None, _lib.POISON_LIB_PATH], ids=["libqg", "libqg_ldspoison"])
+@pytest.mark.parametrize("path", [None, _lib.POISON_LIB_PATH, _lib.STAMPS_LIB_PATH],
+                         ids=["libqg", "libqg_ldspoison", "libqg_stamps"])
 def test_every_declared_symbol_is_exported(path):
-    """The library and its LDS-poison debug build load and export every
-    function include/qg.h declares."""
+    """The library and its debug builds (LDS poison, phase stamps) load and
+    export every function include/qg.h declares."""
     L = _lib.lib(path)
     names = declared_functions()
     assert {"qg_workspace_bytes", "qg_init", "qg_step", "qg_adjoint_step", "qg_diag"} <= set(names)
@@ -116,6 +117,10 @@ def test_null_arguments():
     assert L.qg_closure_term(None, None, None, None) == _lib.QG_EINVAL
     assert L.qg_profile_steps(None, None, 1, 0, None, 0, None, None) == _lib.QG_EINVAL
     assert L.qg_step_noalloc(None, None, None, None, 1, None) == _lib.QG_EINVAL
+    # the stamp run exists in the stamp build only
+    assert L.qg_stamp_steps(None, None, 1, None, 0, None) == _lib.QG_EUNSUPPORTED
+    S = _lib.lib(_lib.STAMPS_LIB_PATH)
+    assert S.qg_stamp_steps(None, None, 1, None, 0, None) == _lib.QG_EINVAL
     L.qg_destroy(None)
 
 
@@ -142,3 +147,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     chi = np.zeros((m["ny"], m["nx"]))
     with pytest.raises(ImportError, match="missing"):
         Solver([m], [chi], [chi], device="cpu")
+
+
+def test_stamp_report_from_synthetic_stamps():
+    """The stamp report's host logic on hand-made stamps: two waves of the
+    row pass on one SIMD, phases of 1..5 ticks."""
+    from paper_2508_06678_amd import stamps
+    st = np.zeros((4, 8192, 8), dtype=np.uint64)
+    for w, base in ((0, 100), (1, 103)):
+        st[0, w, :6] = base + np.cumsum([0, 1, 2, 3, 4, 5])
+        st[0, w, 7] = (np.uint64(2) << np.uint64(32)) | np.uint64(0x0123)   # XCC 2, CU 1, SIMD 2
+    t, hw = stamps.waves_of(st, 0)
+    assert t.shape == (2, 6)
+    xcc, cu, simd = stamps.placement(hw)
+    assert set(xcc.tolist()) == {2} and len(set(simd.tolist())) == 1
+    text = stamps.report(st, "synthetic")
+    assert "2 waves, span 0.18 us" in text      # (103 + 15) - 100 ticks of 10 ns
+    assert "column-inverse pass: no stamps" in text
