@@ -2115,6 +2115,105 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   }
 }
 
+// The dynamic closures' right-hand-side column pass in two halves, for
+// FP64: six 1024-point FP64 transforms need 110 KB of LDS, so that one
+// block fits a compute unit and a single member's 342 column blocks run
+// in two rounds.  Here three thread groups transform the grid level's
+// products (J, and the two flux components), keep the column's modes of
+// them in registers, then transform the test level's products in the same
+// LDS (their loads in flight during the first half) and form what the
+// one-pass kernel forms: J and Q stored, H, M and the block's partial sums
+// of <HM> and <M^2> (and H, M kept when adj_dyn).  Same arithmetic per
+// mode as k_colfwdp; the partial sums add two modes per thread.
+template <typename T, int CL, int LOGN, int SCH>
+__global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
+  using V = cpx<T>;
+  constexpr int CPD = QG_COL_PADS;
+  constexpr int N = 1 << LOGN, LG = LOGN - 3, NT = 3 << LG;
+  constexpr int n = N + (N >> CPD);
+  constexpr int KYN = 2 * ((N - 1) / 3) + 1;   // the 2/3 set's m_y count
+  constexpr int QM = (KYN + NT - 1) / NT;      // modes per thread
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  lds_poison_all(smem_raw, P.lds_bytes);
+  __shared__ double red[32];
+  QG_STAMP(2, 0, 0.f);
+  const MemberDev M = member_const(P, blockIdx.z);
+  V* tile = reinterpret_cast<V*>(smem_raw);
+  const int grp = threadIdx.x >> LG;
+  const int lt = threadIdx.x & ((1 << LG) - 1);
+  const int kx0 = xcd_order(blockIdx.x, gridDim.x);
+  if (kx0 >= P.kxn) return;
+  const long long pstride = (long long)P.ny * P.kxp;
+  const V* src = cptr<T>(M, P.o_mp) + grp * pstride + (long long)kx0 * P.ny;
+  const int mylim = test_mylim(M, P.nx, P.ny, kx0);
+  const V* twc = reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy);
+  const auto tw1 = fft1c_first_tw<V, LOGN, SCH>(twc, lt);
+  V v[8], w[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << LG));
+#pragma unroll
+  for (int t = 0; t < 8; ++t) w[t] = gld(src + 3 * pstride + lt + (t << LG));
+  QG_STAMP(2, 1, v[7].x);
+  V* buf = tile + grp * n;
+  fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, buf, lt, true);
+  fft1c_rest<V, LOGN, false, CPD, SCH>(buf, twc, lt, true, tw1);
+  // the grid level's products at this thread's modes
+  auto pos = [&](int iy) {
+    const int my = my_of_iy(iy, P.myh, P.kyn);
+    return padp<CPD>(my >= 0 ? my : my + N);
+  };
+  V a0[QM], a1[QM], a2[QM];
+#pragma unroll
+  for (int k = 0; k < QM; ++k) {
+    const int q = threadIdx.x + k * NT;
+    if (q < P.kyn) {
+      const int y = pos(q);
+      a0[k] = tile[y];
+      a1[k] = tile[n + y];
+      a2[k] = tile[2 * n + y];
+    }
+  }
+  __syncthreads();   // every read of the first half before the second half's writes
+  fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(w, buf, lt, true);
+  fft1c_rest<V, LOGN, false, CPD, SCH>(buf, twc, lt, true, tw1);
+  QG_STAMP_LDS(2, 2);
+  double hm = 0.0, mm = 0.0;
+  const int mx = kx0;
+#pragma unroll
+  for (int k = 0; k < QM; ++k) {
+    const int iy = threadIdx.x + k * NT;
+    if (iy >= P.kyn) continue;
+    const int my = my_of_iy(iy, P.myh, P.kyn);
+    const int y = pos(iy);
+    const int id = mx * P.kyn + iy;
+    const Wave<T> wv = wave<T>(M, mx, my);
+    const bool t = my <= mylim && -my <= mylim;
+    const V j = a0[k];
+    const V Q = cadd(mul_ia(a1[k], wv.kx), mul_ia(a2[k], wv.ky));
+    gst(cptr<T>(M, P.o_out) + id, j);
+    gst(cptr<T>(M, P.o_aux) + id, Q);
+    const V b3 = tile[y], b4 = tile[n + y], b5 = tile[2 * n + y];
+    const V h = t ? csub(b3, j) : b3;
+    V g = cscale(cadd(mul_ia(b4, wv.kx), mul_ia(b5, wv.ky)), T(M.r_test));
+    if (t) g = csub(g, Q);
+    const double wt = mx == 0 ? 1.0 : 2.0;
+    hm += wt * ((double)h.x * (double)g.x + (double)h.y * (double)g.y);
+    mm += wt * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
+    if (P.adj_dyn) {   // kept for the adjoint (or the pointwise clip)
+      gst(cptr<T>(M, P.o_h) + id, h);
+      gst(cptr<T>(M, P.o_m) + id, g);
+    }
+  }
+  QG_STAMP_DRAIN(2, 3);
+  block_sum2(hm, mm, red);
+  if (threadIdx.x == 0) {
+    double* part = rptr<double>(M, P.o_part) + 2 * kx0;
+    part[0] = hm;
+    part[1] = mm;
+  }
+  QG_STAMP_DRAIN(2, 4);
+}
+
 // ---------------------------------------------------------------- combine
 // Dynamic closures: C = max(<HM>, 0)/<M^2> from the fixed-order sum of the
 // strip partials (every block sums them identically), then the RHS
@@ -2711,6 +2810,28 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
     // block; every op, as for the column-inverse pass)
     const size_t lds = np * n * sizeof(cpx<T>);
     const bool s1 = (OP == OP_RHS || OP == OP_B) && P.csch == 1;
+    if constexpr (sizeof(T) == 8 && OP == OP_RHS && (CL == 3 || CL == 4)) {
+      // FP64 dynamic closures: the pass in two halves (k_colfwdd), three
+      // transforms' LDS per block
+      if (P.W == 1 && P.logny >= 8 && P.logny <= 10) {
+        const size_t lds2 = 3 * (size_t)(P.ny + (P.ny >> QG_COL_PADS)) * sizeof(cpx<T>);
+        const dim3 block2(3 * P.ny / COL_EPT);
+        switch (P.logny) {
+          case 8:
+            if (s1) QG_KLAUNCH((k_colfwdd<T, CL, 8, 1>), grid, block2, lds2, s, P);
+            else QG_KLAUNCH((k_colfwdd<T, CL, 8, 0>), grid, block2, lds2, s, P);
+            return;
+          case 9:
+            if (s1) QG_KLAUNCH((k_colfwdd<T, CL, 9, 1>), grid, block2, lds2, s, P);
+            else QG_KLAUNCH((k_colfwdd<T, CL, 9, 0>), grid, block2, lds2, s, P);
+            return;
+          default:
+            if (s1) QG_KLAUNCH((k_colfwdd<T, CL, 10, 1>), grid, block2, lds2, s, P);
+            else QG_KLAUNCH((k_colfwdd<T, CL, 10, 0>), grid, block2, lds2, s, P);
+            return;
+        }
+      }
+    }
     if (P.W == 1) switch (P.logny) {
       case 8:
         if (s1) QG_KLAUNCH((k_colfwdp<T, OP, CL, 8, 1>), grid, block, lds, s, P);

@@ -4,9 +4,9 @@ the spread of each phase over the waves, the kernel's span, and how the
 waves were placed on XCDs, compute units and SIMDs (from the hardware ids
 each wave records).
 
-    python -m paper_2508_06678_amd.stamps [--members 1|8] [--steps 3] [--tune-cache PATH]
+    python -m paper_2508_06678_amd.stamps [--members 1|8] [--precision 32|64] [--steps 3] [--tune-cache PATH]
 
-runs the FP32 1024 x 1024 dynamic-Leith cape workload (one member, or the
+runs the 1024 x 1024 dynamic-Leith cape workload (one member, or the
 8-member ensemble, whose member 0 is stamped) and prints a Markdown report.
 Times are the GPU's 100 MHz real-time counter (10 ns ticks); the stamps'
 own waits lengthen the kernels a little.
@@ -98,24 +98,26 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--members", type=int, default=1, choices=(1, 8))
+    ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="the autotuner's cache (tunes and writes it when absent)")
     a = ap.parse_args(argv)
-    wl = configs.config3(precision=32) if a.members == 1 else configs.batched1024(32)
+    wl = configs.config3(precision=a.precision) if a.members == 1 else configs.batched1024(a.precision)
+    dt = np.float32 if a.precision == 32 else np.float64
     params, chi, chs = [], [], []
     for m in wl.members:
         p = dict(m.params)
-        p["precision"] = 32
+        p["precision"] = a.precision
         params.append(p)
-        chi.append(m.chi.astype(np.float32))
-        chs.append(m.chi_s.astype(np.float32))
+        chi.append(m.chi.astype(dt))
+        chs.append(m.chi_s.astype(dt))
     S = Solver(params, chi, chs, lib_path=STAMPS_LIB_PATH)
     try:
         S.autotune(a.tune_cache)
         om = S.pack([m.omega0 for m in wl.members])
         stamps = S.stamp_steps(om, a.steps)
         torch.cuda.synchronize()
-        title = (f"FP32 1024x1024 cape, dynamic Leith, {len(wl.members)} member(s) "
+        title = (f"FP{a.precision} 1024x1024 cape, dynamic Leith, {len(wl.members)} member(s) "
                  f"(member 0 stamped), tuning {json.dumps(S.tuning()[0])}")
         print(report(stamps, title), flush=True)
     finally:
