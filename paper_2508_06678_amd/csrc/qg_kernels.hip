@@ -2115,10 +2115,11 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
   }
 }
 
-// The dynamic closures' right-hand-side column pass in two halves, for
-// FP64: six 1024-point FP64 transforms need 110 KB of LDS, so that one
-// block fits a compute unit and a single member's 342 column blocks run
-// in two rounds.  Here three thread groups transform the grid level's
+// The dynamic closures' right-hand-side column pass in two halves: six
+// 1024-point transforms in one block need 104 KB of LDS in FP64 (one block
+// per compute unit, so that a single member's 342 column blocks run in two
+// rounds) and 52 KB in FP32 (two blocks of 12 waves).  Here three thread
+// groups (6 waves at 1024) transform the grid level's
 // products (J, and the two flux components), keep the column's modes of
 // them in registers, then transform the test level's products in the same
 // LDS (their loads in flight during the first half) and form what the
@@ -2810,8 +2811,8 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
     // block; every op, as for the column-inverse pass)
     const size_t lds = np * n * sizeof(cpx<T>);
     const bool s1 = (OP == OP_RHS || OP == OP_B) && P.csch == 1;
-    if constexpr (sizeof(T) == 8 && OP == OP_RHS && (CL == 3 || CL == 4)) {
-      // FP64 dynamic closures: the pass in two halves (k_colfwdd), three
+    if constexpr (OP == OP_RHS && (CL == 3 || CL == 4)) {
+      // dynamic closures: the pass in two halves (k_colfwdd), three
       // transforms' LDS per block
       if (P.W == 1 && P.logny >= 8 && P.logny <= 10) {
         const size_t lds2 = 3 * (size_t)(P.ny + (P.ny >> QG_COL_PADS)) * sizeof(cpx<T>);
