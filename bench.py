@@ -43,7 +43,8 @@ def kernel_names(nx, ny, tuning):
     with every template argument): compile-time transform lengths for
     256..1024 with the tuned pass schedules, row pairs per block and row
     synchronisation, the single-column forward kernel when the forward strip
-    width is 1."""
+    width is 1 (the two-half one for the dynamic closures' right-hand side
+    at the compile-time lengths)."""
     lx = int(math.log2(nx)) if nx in (256, 512, 1024) else 0
     ly = int(math.log2(ny)) if ny in (256, 512, 1024) else 0
     lf = ly if tuning["W"] == 1 else 0
@@ -52,7 +53,7 @@ def kernel_names(nx, ny, tuning):
     return {
         "colinv_rhs": f"k_colinv<float, 0, 4, {ly}, {cs if ly else 0}>",
         "row_rhs": f"k_rowp<float, 0, 4, {lx}, {row}>",
-        "colfwd_rhs": f"k_colfwdp<float, 0, 4, {lf}, {cs if lf else 0}>",
+        "colfwd_rhs": (f"k_colfwdd<float, 4, {lf}, {cs}>" if lf else "k_colfwdp<float, 0, 4, 0, 0>"),
         "combine_dyn": "k_combine<float>",
         "colinv_b": f"k_colinv<float, 1, 0, {ly}, {cs if ly else 0}>",
         "row_b": f"k_rowp<float, 1, 0, {lx}, {row}>",
