@@ -478,8 +478,12 @@ struct PassTw {
 
 // fft1c_pass with the pass's twiddles given (cur) and the next pass's
 // loaded while this one computes: their latency (an L2 round trip) is
-// no longer exposed after every barrier
-template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH, int EPT, bool WAVE>
+// no longer exposed after every barrier.  TRUNC: the caller reads only the
+// outputs of the 2/3 set, k < (N - 1)/3 + 1 and their mirrors N - k; the
+// last pass then neither writes (nor forms) its output blocks that lie
+// wholly between (at the 1024-point length and a last radix of 8, the
+// blocks k in [384, 640)).
+template <typename V, int LOGN, int LOGNS, bool INV, int P, int SCH, int EPT, bool WAVE, bool TRUNC = false>
 __device__ __forceinline__ void fft1c_pass_pf(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active,
                                               const PassTw<V, LOGN, LOGNS, SCH, EPT>& cur) {
   using TW = PassTw<V, LOGN, LOGNS, SCH, EPT>;
@@ -511,13 +515,17 @@ __device__ __forceinline__ void fft1c_pass_pf(V* __restrict__ buf, const V* __re
     lds_poison(buf, padp<P>(N), j, nt, active);
     fft_sync<WAVE>();
   }
+  // the last pass's output block t holds k in [t NS, (t + 1) NS)
+  constexpr int KX = (N - 1) / 3 + 1;
+  auto skip = [&](int t) constexpr { return TRUNC && LAST && t * NS >= KX && (t + 1) * NS - 1 <= N - KX; };
   if (active) {
     if constexpr (NB > 1 && LAST) {
       V* wb = buf + padp<P>(j);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) wb[b * (nt + (nt >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
+        for (int t = 0; t < R; ++t)
+          if (!skip(t)) wb[b * (nt + (nt >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
       }
     } else {
       constexpr int BO = nt * R;
@@ -526,12 +534,13 @@ __device__ __forceinline__ void fft1c_pass_pf(V* __restrict__ buf, const V* __re
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) wb[b * (BO + (BO >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
+        for (int t = 0; t < R; ++t)
+          if (!skip(t)) wb[b * (BO + (BO >> P)) + t * NS + ((t * NS) >> P)] = v[b][t];
       }
     }
   }
   fft_sync<WAVE>();
-  if constexpr (!LAST) fft1c_pass_pf<V, LOGN, NEXT, INV, P, SCH, EPT, WAVE>(buf, tw, j, active, nxt);
+  if constexpr (!LAST) fft1c_pass_pf<V, LOGN, NEXT, INV, P, SCH, EPT, WAVE, TRUNC>(buf, tw, j, active, nxt);
 }
 
 // The twiddles of the first pass after fft1c_pass0 (sub-length 8), for a
@@ -547,10 +556,10 @@ __device__ __forceinline__ PassTw<V, LOGN, 3, SCH, EPT> fft1c_first_tw(const V* 
 // EPT elements per thread, wave- or block-wide synchronisation; the first
 // of them takes the twiddles the caller loaded (fft1c_first_tw), each
 // loads the next one's while it computes.
-template <typename V, int LOGN, bool INV, int P, int SCH = 0, int EPT = 8, bool WAVE = false>
+template <typename V, int LOGN, bool INV, int P, int SCH = 0, int EPT = 8, bool WAVE = false, bool TRUNC = false>
 __device__ __forceinline__ void fft1c_rest(V* __restrict__ buf, const V* __restrict__ tw, int j, bool active,
                                            const PassTw<V, LOGN, 3, SCH, EPT>& first) {
-  fft1c_pass_pf<V, LOGN, 3, INV, P, SCH, EPT, WAVE>(buf, tw, j, active, first);
+  fft1c_pass_pf<V, LOGN, 3, INV, P, SCH, EPT, WAVE, TRUNC>(buf, tw, j, active, first);
 }
 
 // The whole block as one group.

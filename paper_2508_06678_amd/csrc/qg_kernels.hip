@@ -1372,7 +1372,7 @@ __device__ __forceinline__ void rowp_item(const Phase& P, int mem, int rb, int l
   if constexpr (WV) __syncthreads();   // every product formed before the fields' buffers are overwritten
   if constexpr (LOGN != 0) {
     fft1c_pass0<V, false, PADS, 0, EPT, WV, LOGN>(v, mybuf, j, act);
-    fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV>(mybuf, twl, j, act, tw1);
+    fft1c_rest<V, LOGN, false, PADS, SCH, EPT, WV, true>(mybuf, twl, j, act, tw1);   // columns of the 2/3 set read
     if constexpr (OP == OP_RHS) QG_STAMP_LDS(0, 4);
   } else {
     fft1_pass0<V, false>(v, mybuf, j, act, P.lognx);
@@ -1947,7 +1947,8 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
     if constexpr (LOGN != 0) {
       if constexpr (dyn) QG_STAMP(2, 1, v[7].x);
       fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, tile + grp * n, lt, true);
-      fft1c_rest<V, LOGN, false, CPD, SCH>(tile + grp * n, twc, lt, true, tw1);
+      // the step's passes read rows of the 2/3 set only
+      fft1c_rest<V, LOGN, false, CPD, SCH, 8, false, OP == OP_RHS || OP == OP_B>(tile + grp * n, twc, lt, true, tw1);
       if constexpr (dyn) QG_STAMP_LDS(2, 2);
     } else {
       __syncthreads();   // twiddles staged
@@ -2157,7 +2158,7 @@ __global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
   QG_STAMP(2, 1, v[7].x);
   V* buf = tile + grp * n;
   fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, buf, lt, true);
-  fft1c_rest<V, LOGN, false, CPD, SCH>(buf, twc, lt, true, tw1);
+  fft1c_rest<V, LOGN, false, CPD, SCH, 8, false, true>(buf, twc, lt, true, tw1);
   // the grid level's products at this thread's modes
   auto pos = [&](int iy) {
     const int my = my_of_iy(iy, P.myh, P.kyn);
@@ -2176,7 +2177,7 @@ __global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
   }
   __syncthreads();   // every read of the first half before the second half's writes
   fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(w, buf, lt, true);
-  fft1c_rest<V, LOGN, false, CPD, SCH>(buf, twc, lt, true, tw1);
+  fft1c_rest<V, LOGN, false, CPD, SCH, 8, false, true>(buf, twc, lt, true, tw1);
   QG_STAMP_LDS(2, 2);
   double hm = 0.0, mm = 0.0;
   const int mx = kx0;
