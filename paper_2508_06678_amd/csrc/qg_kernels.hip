@@ -2120,13 +2120,13 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 // 1024-point transforms in one block need 104 KB of LDS in FP64 (one block
 // per compute unit, so that a single member's 342 column blocks run in two
 // rounds) and 52 KB in FP32 (two blocks of 12 waves).  Here three thread
-// groups (6 waves at 1024) transform the grid level's
-// products (J, and the two flux components), keep the column's modes of
-// them in registers, then transform the test level's products in the same
-// LDS (their loads in flight during the first half) and form what the
-// one-pass kernel forms: J and Q stored, H, M and the block's partial sums
-// of <HM> and <M^2> (and H, M kept when adj_dyn).  Same arithmetic per
-// mode as k_colfwdp; the partial sums add two modes per thread.
+// groups (6 waves at 1024) transform the grid level's products (J and the
+// two flux components), keep the column's modes of them in registers, then
+// transform the test level's products in the same LDS (their loads went
+// out before the first half's transform) and form what the one-pass kernel
+// forms: J and Q stored, H, M and the block's partial sums of <HM> and
+// <M^2> (H and M also stored when adj_dyn).  The same arithmetic per mode
+// as k_colfwdp; each thread adds two modes into the partial sums.
 template <typename T, int CL, int LOGN, int SCH>
 __global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
   using V = cpx<T>;
