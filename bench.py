@@ -174,9 +174,14 @@ def measured_traffic(kernel):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("kernel") != kernel or t.get("sources_sha256") != kernel_sources_digest():
+    if t.get("sources_sha256") != kernel_sources_digest():
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+    # the main entry, or the same counters for the kernel's other form
+    # (the tuner's other row synchronisation)
+    e = t if t.get("kernel") == kernel else t.get("alternates", {}).get(kernel)
+    if e is None:
+        return None
+    return 1024.0 * (e["fetch_kib"] * e["fetch_factor"] + e["write_kib"] * e["write_factor"])
 
 
 def make_solver(workload, precision, adj=0, tune=True):
