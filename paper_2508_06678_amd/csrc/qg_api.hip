@@ -773,6 +773,19 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
 // starting from adj_lam and leaving dL/d state at the segment start in
 // adj_lam; dL/dc is accumulated in the workspace.  Workspace-only pointers,
 // so the whole sweep can be captured in a graph.
+// The reverse sweep's passes: at strip width 1 where the compile-time
+// column engines take it.  The tuned width is chosen for the forward step;
+// a reverse pass's row and column launches only have to agree with each
+// other on the mixed layout's strip width (the pitch stays the group's).
+static Phase adj_phase(const Handle& h, const Group& g) {
+  Phase P = base_phase(h, g);
+  if (g.logny >= 8 && g.logny <= 10) {
+    P.W = 1;
+    P.logW = 0;
+  }
+  return P;
+}
+
 static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipStream_t st) {
   const long long spec = (long long)g.kxn * g.kyn * (g.dbl ? 16 : 8);
   const long long slot_bytes = (long long)align256((size_t)spec);
@@ -801,7 +814,7 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
   const int nb = smag_family(cl) ? 6 : 4;
   const int clb = cl == 3 ? 1 : cl == 4 ? 2 : cl;   // the adjoint kernels of the closure's base family
   for (long long n = nsteps - 1; n >= 0; --n) {
-    Phase B = base_phase(h, g);
+    Phase B = adj_phase(h, g);
     B.o_in = g.L.adj_lam;
     B.nf = 1;
     QG_LAUNCH(launch_colinv(g.dbl, OP_ADJ_B, 0, B, g.count, st));
@@ -811,7 +824,7 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
     B.o_in = g.L.adj_lk;
     QG_LAUNCH(launch_colfwd(g.dbl, OP_ADJ_B, 0, B, g.count, st));
     for (int s = 4; s >= 1; --s) {
-      Phase A = base_phase(h, g);
+      Phase A = adj_phase(h, g);
       A.stage = s;
       A.o_in = slot(n, s - 1);
       A.o_in2 = g.L.adj_lk;
@@ -822,7 +835,7 @@ static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipS
         // the test-filtered stage input into adj_e; the stage's own pass
         // below takes the rest
         const StageStore ks = keep(n, s);
-        Phase Kp = base_phase(h, g);
+        Phase Kp = adj_phase(h, g);
         Kp.o_in2 = g.L.adj_lk;
         Kp.o_aux = ks.q;
         Kp.o_h = ks.h;
