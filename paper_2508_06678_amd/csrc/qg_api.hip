@@ -767,12 +767,6 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   return m;
 }
 
-// ------------------------------------------------------------ adjoint sweep
-// Recompute one segment from the state in wn, storing every stage input,
-// then run the adjoint steps in reverse (B-step transpose, stages 4..1),
-// starting from adj_lam and leaving dL/d state at the segment start in
-// adj_lam; dL/dc is accumulated in the workspace.  Workspace-only pointers,
-// so the whole sweep can be captured in a graph.
 // The reverse sweep's passes: at strip width 1 where the compile-time
 // column engines take it.  The tuned width is chosen for the forward step;
 // a reverse pass's row and column launches only have to agree with each
@@ -786,6 +780,12 @@ static Phase adj_phase(const Handle& h, const Group& g) {
   return P;
 }
 
+// ------------------------------------------------------------ adjoint sweep
+// Recompute one segment from the state in wn, storing every stage input,
+// then run the adjoint steps in reverse (B-step transpose, stages 4..1),
+// starting from adj_lam and leaving dL/d state at the segment start in
+// adj_lam; dL/dc is accumulated in the workspace.  Workspace-only pointers,
+// so the whole sweep can be captured in a graph.
 static int adjoint_sweep(const Handle& h, const Group& g, long long nsteps, hipStream_t st) {
   const long long spec = (long long)g.kxn * g.kyn * (g.dbl ? 16 : 8);
   const long long slot_bytes = (long long)align256((size_t)spec);
