@@ -767,6 +767,7 @@ static MemberDev make_member(const qg_params& p, char* base, long long omega_off
   return m;
 }
 
+// ------------------------------------------------------------ adjoint sweep
 // The reverse sweep's passes: at strip width 1 where the compile-time
 // column engines take it.  The tuned width is chosen for the forward step;
 // a reverse pass's row and column launches only have to agree with each
@@ -780,7 +781,6 @@ static Phase adj_phase(const Handle& h, const Group& g) {
   return P;
 }
 
-// ------------------------------------------------------------ adjoint sweep
 // Recompute one segment from the state in wn, storing every stage input,
 // then run the adjoint steps in reverse (B-step transpose, stages 4..1),
 // starting from adj_lam and leaving dL/d state at the segment start in
