@@ -108,6 +108,8 @@ struct Group {
   void* twx1;                    // the same for pass schedule 1
   void* twy1;
   long long o_twx1, o_twy1;
+  void* twx2 = nullptr;          // the row table of pass schedule 2
+  long long o_twx2 = 0;
   int rsch, csch;                // pass schedules of the row / column compile-time engines
   int rpb;                       // row pairs per block of the step's row pass
   int rwv;                       // wave-synchronous row transforms
@@ -311,6 +313,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     g.o_twy = o; o += align256((long long)g.ny * cs);
     g.o_twx1 = o; o += align256((long long)g.nx * cs);
     g.o_twy1 = o; o += align256((long long)g.ny * cs);
+    g.o_twx2 = o; o += align256((long long)g.nx * cs);
     g.rsch = g.csch = g.rwv = 0;
     g.rpb = 1;
   }
@@ -400,7 +403,7 @@ static Phase base_phase(const Handle& h, const Group& g) {
   P.o_mf = g.L.mf; P.o_mp = g.L.mp; P.o_phys = g.L.phys;
   P.o_part = g.L.part; P.o_coef = g.L.coef; P.o_dpart = g.L.dpart;
   P.twx = g.twx; P.twy = g.twy;
-  P.twx1 = g.twx1; P.twy1 = g.twy1;
+  P.twx1 = g.twx1; P.twy1 = g.twy1; P.twx2 = g.twx2;
   P.rsch = g.rsch; P.csch = g.csch; P.rpb = g.rpb; P.rwv = g.rwv;
   return P;
 }
@@ -998,16 +1001,18 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
     g.twy = h.ws + g.o_twy;
     g.twx1 = h.ws + g.o_twx1;
     g.twy1 = h.ws + g.o_twy1;
+    g.twx2 = h.ws + g.o_twx2;
     for (int k = 0; k < g.count; ++k) {
       const int u = g.users[k];
       table[g.m0 + k] = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
     }
-    for (int axis = 0; axis < 4; ++axis) {
+    // x and y tables of schedules 0 and 1, the x table of schedule 2
+    for (int axis = 0; axis < 5; ++axis) {
       const int len = (axis & 1) == 0 ? g.nx : g.ny;
       std::vector<long double> fre, fim, re, im;
       twiddles(len, fre, fim);
       pass_twiddles(len, axis >> 1, fre, fim, re, im);
-      void* dst = axis == 0 ? g.twx : axis == 1 ? g.twy : axis == 2 ? g.twx1 : g.twy1;
+      void* dst = axis == 0 ? g.twx : axis == 1 ? g.twy : axis == 2 ? g.twx1 : axis == 3 ? g.twy1 : g.twx2;
       if (g.dbl) {
         std::vector<double> t(2 * len);
         for (int m = 0; m < len; ++m) { t[2 * m] = (double)re[m]; t[2 * m + 1] = (double)im[m]; }
@@ -1620,7 +1625,8 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
     for (int W = min_width(g); W <= max_width(g); W *= 2) { Ws.push_back(W); Wis.push_back(W); }
     const bool ct_rows = g.nx == 256 || g.nx == 512 || g.nx == 1024;
     const bool ct_cols = g.ny == 256 || g.ny == 512 || g.ny == 1024;
-    rs = ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
+    // schedule 2 (radix 16) for the wave-synchronous 1024-point rows only
+    rs = g.nx == 1024 ? std::vector<int>{0, 1, 2} : ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
     cs = ct_cols ? std::vector<int>{0, 1} : std::vector<int>{0};
     rp = g.ny >= 64 ? std::vector<int>{1, 2} : std::vector<int>{1};
     wv = ct_rows ? std::vector<int>{0, 1} : std::vector<int>{0};
@@ -1635,7 +1641,8 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
       it = cache.find(key + "/inv");
       fix("/inv", Wis, it != cache.end() && valid_w(g, it->second));
       it = cache.find(key + "/rsched");
-      fix("/rsched", rs, it != cache.end() && (it->second == 0 || (ct_rows && it->second == 1)));
+      fix("/rsched", rs, it != cache.end() && (it->second == 0 || (ct_rows && it->second == 1) ||
+                                                (g.nx == 1024 && it->second == 2)));
       it = cache.find(key + "/csched");
       fix("/csched", cs, it != cache.end() && (it->second == 0 || (ct_cols && it->second == 1)));
       it = cache.find(key + "/rpb");
@@ -1649,7 +1656,10 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
         for (int r : rs)
           for (int c : cs)
             for (int q : rp)
-              for (int v : wv) cand.push_back(Tuning{W, Wi, r, c, q, v});
+              for (int v : wv)
+                if (r != 2 || v == 1) cand.push_back(Tuning{W, Wi, r, c, q, v});
+    // schedule 2 and two-wave rows both fixed by the cache: schedule 1
+    if (cand.empty()) cand.push_back(Tuning{Ws[0], Wis[0], 1, cs[0], rp[0], wv[0]});
     if (cand.size() == 1) {
       apply_tuning(g, cand[0]);
       continue;

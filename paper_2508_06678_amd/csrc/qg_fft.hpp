@@ -79,12 +79,18 @@ constexpr bool kLdsPoison = false;
 // while three factors of two remain, then one radix-4 or radix-2 pass
 // (1024 = 8 8 8 2); schedule 1: radix 4 while more than three factors
 // remain, then the rest in one pass (1024 = 8 4 4 8, 512 = 8 4 4 4, 256 =
-// 8 4 8).  The run-time engines use schedule 0; the compile-time ones take
-// either (a tuning choice), each with its own twiddle table.
+// 8 4 8); schedule 2: radix 16 while four factors of two remain, then the
+// rest (1024 = 8 16 8): one LDS exchange fewer, for transforms with 16
+// elements per thread (the wave-synchronous 1024-point rows).  The
+// run-time engines use schedule 0; the compile-time ones take one of them
+// (a tuning choice), each with its own twiddle table.
 __host__ __device__ constexpr int pass_log_radix(int logn, int logns, int sch) {
-  return logns == 0 ? 3 : sch == 0 ? (logn - logns >= 3 ? 3 : logn - logns) : (logn - logns > 3 ? 2 : logn - logns);
+  return logns == 0 ? 3
+       : sch == 0 ? (logn - logns >= 3 ? 3 : logn - logns)
+       : sch == 1 ? (logn - logns > 3 ? 2 : logn - logns)
+                  : (logn - logns >= 4 ? 4 : logn - logns);
 }
-constexpr int NSCHED = 2;
+constexpr int NSCHED = 3;
 
 // Radix-2/4/8 DFT kernels in registers.  INV selects exp(+2 pi i / R).
 template <typename V, bool INV> __device__ __forceinline__ void dft2(V* v) {
@@ -162,8 +168,51 @@ template <typename V, bool INV, int ZM> __device__ __forceinline__ void dft8z(V*
   }
 }
 
+// Length-16 DFT as 4 x 4 (Cooley-Tukey): length-4 DFTs over the stride-4
+// subsequences x[4 n1 + n2], the twiddles w16^(n2 k1), then length-4 DFTs
+// across n2; X[k1 + 4 k2] lands in v[k1 + 4 k2].  w16 = exp(-2 pi i / 16)
+// (its conjugate for INV); with c = cos pi/8, s = sin pi/8:
+// w16^1 = c - i s, w16^2 = (1 - i)/sqrt2, w16^3 = s - i c, w16^4 = -i,
+// w16^6 = -(1 + i)/sqrt2, w16^9 = -c + i s.
+template <typename V, bool INV> __device__ __forceinline__ void dft16(V* v) {
+  using T = decltype(V{}.x);
+  const T c = T(0.92387953251128675613), sn = T(0.38268343236508977173), h = T(0.70710678118654752440);
+  V a[4][4];   // a[n2][k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    a[n2][0] = v[n2];
+    a[n2][1] = v[4 + n2];
+    a[n2][2] = v[8 + n2];
+    a[n2][3] = v[12 + n2];
+    dft4<V, INV>(a[n2][0], a[n2][1], a[n2][2], a[n2][3]);
+  }
+  // multiplication by w = re + i im (forward) or its conjugate (inverse)
+  auto mulw = [](V z, T re, T im) {
+    const T i2 = INV ? -im : im;
+    return cmake<V>(z.x * re - z.y * i2, z.x * i2 + z.y * re);
+  };
+  a[1][1] = mulw(a[1][1], c, -sn);     // w^1
+  a[1][2] = mulw(a[1][2], h, -h);      // w^2
+  a[1][3] = mulw(a[1][3], sn, -c);     // w^3
+  a[2][1] = mulw(a[2][1], h, -h);      // w^2
+  a[2][2] = INV ? cmul_i(a[2][2]) : cmul_mi(a[2][2]);   // w^4 = -i
+  a[2][3] = mulw(a[2][3], -h, -h);     // w^6
+  a[3][1] = mulw(a[3][1], sn, -c);     // w^3
+  a[3][2] = mulw(a[3][2], -h, -h);     // w^6
+  a[3][3] = mulw(a[3][3], -c, sn);     // w^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    dft4<V, INV>(a[0][k1], a[1][k1], a[2][k1], a[3][k1]);
+    v[k1] = a[0][k1];
+    v[k1 + 4] = a[1][k1];
+    v[k1 + 8] = a[2][k1];
+    v[k1 + 12] = a[3][k1];
+  }
+}
+
 template <typename V, int R, bool INV> __device__ __forceinline__ void dftR(V* v) {
-  if constexpr (R == 8) dft8<V, INV>(v);
+  if constexpr (R == 16) dft16<V, INV>(v);
+  else if constexpr (R == 8) dft8<V, INV>(v);
   else if constexpr (R == 4) dft4<V, INV>(v);
   else dft2<V, INV>(v);
 }

@@ -117,6 +117,7 @@ struct Phase {
   int rsch, csch, rpb, rwv;
   const void* twx1;
   const void* twy1;
+  const void* twx2;       // the row table of schedule 2 (radix 16)
   // dynamic LDS bytes of the launch (set by the launcher; read by the LDS
   // poison of debug builds)
   unsigned lds_bytes;

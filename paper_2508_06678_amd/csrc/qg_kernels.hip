@@ -1517,7 +1517,7 @@ __global__ void __launch_bounds__(1024) k_rowp(Phase P) {
   const int lev = (dyn || OP == OP_ADJ_RHS) ? (int)blockIdx.y : 0;
   // twiddles straight from the (cached) global table: keeping LDS to the
   // field buffers lets one more block share a compute unit
-  const V* twl = reinterpret_cast<const V*>(SCH ? P.twx1 : P.twx);
+  const V* twl = reinterpret_cast<const V*>(SCH == 2 ? P.twx2 : SCH ? P.twx1 : P.twx);
   // (no loop at all for one row pair per block: even a loop of one trip
   // changes the register allocation of the body)
   if constexpr (RPB == 1) {
@@ -2726,10 +2726,19 @@ static bool rowp_ok(bool dbl, int op, int cl, const Phase& P) {
   return P.nx >= 64 && nb * P.nx / 8 <= 1024 && rowp_lds(dbl, op, cl, P) <= 128 * 1024;
 }
 // The compile-time row engines of length 2^LN; the step's passes take the
-// tuned pass schedule (s1) and wave-synchronous transforms (wv).
+// tuned pass schedule (s1: schedule 1, or 2 where it applies) and
+// wave-synchronous transforms (wv).  Schedule 2 (radix 16) needs 16
+// elements per thread: the wave-synchronous 1024-point rows; elsewhere
+// schedule 1 stands in for it.
 template <typename T, int OP, int CL, int LN, int RPB>
 static void launch_rowp_sched(const Phase& P, dim3 grid, dim3 block, size_t lds, hipStream_t s, bool s1, bool wv) {
   if (wv) {
+    if constexpr (LN == 10) {
+      if (P.rsch == 2) {
+        QG_KLAUNCH((k_rowp<T, OP, CL, LN, 2, true, RPB>), grid, block, lds, s, P);
+        return;
+      }
+    }
     if (s1) QG_KLAUNCH((k_rowp<T, OP, CL, LN, 1, true, RPB>), grid, block, lds, s, P);
     else QG_KLAUNCH((k_rowp<T, OP, CL, LN, 0, true, RPB>), grid, block, lds, s, P);
   } else {
@@ -2757,7 +2766,7 @@ static void launch_rowp_t(const Phase& P, int nmem, hipStream_t s) {
   // synchronisation (one wave per transform: 16 points per thread at 1024)
   const bool step = OP == OP_RHS || OP == OP_B;
   const int rpb = step && P.rpb == 2 ? 2 : 1;
-  const bool s1 = step && P.rsch == 1;
+  const bool s1 = step && P.rsch >= 1;
   const bool wv = step && P.rwv == 1;
   const dim3 block(nb * (wv && P.nx >= 1024 ? P.nx / 16 : P.nx / 8));
   dim3 grid(P.ny / (2 * rpb), levels, nmem);

@@ -83,10 +83,11 @@ def steps(n):
     {"/fwd": 1, "/inv": 4, "/rsched": 1, "/csched": 1, "/rpb": 1, "/rwave": 0},
     {"/fwd": 1, "/inv": 1, "/rsched": 0, "/csched": 0, "/rpb": 2, "/rwave": 1},
     {"/fwd": 2, "/inv": 2, "/rsched": 0, "/csched": 1, "/rpb": 1, "/rwave": 1},
+    {"/fwd": 1, "/inv": 4, "/rsched": 2, "/csched": 1, "/rpb": 1, "/rwave": 1},
 ])
 def test_compile_time_engines_dynamic_leith(tmp_path, precision, tuning):
     """1024 x 512 dynamic Leith (compile-time rows of 1024 and columns of
-    512, grid and test levels, B sub-step) under three tunings."""
+    512, grid and test levels, B sub-step) under four tunings."""
     say("poison 1024x512 dleith", precision, tuning)
     err, bit = both([island(1024, 512, "dleith")], precision, steps(2), tuning, tmp_path)
     say("  err", err, "bitwise", bit)
