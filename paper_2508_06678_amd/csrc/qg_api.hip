@@ -108,11 +108,12 @@ struct Group {
   void* twx1;                    // the same for pass schedule 1
   void* twy1;
   long long o_twx1, o_twy1;
-  void* twx2 = nullptr;          // the row table of pass schedule 2
-  long long o_twx2 = 0;
+  void* twx2 = nullptr;          // the row and column tables of pass schedule 2
+  void* twy2 = nullptr;
+  long long o_twx2 = 0, o_twy2 = 0;
   int rsch, csch;                // pass schedules of the row / column compile-time engines
   int rpb;                       // row pairs per block of the step's row pass
-  int rwv;                       // wave-synchronous row transforms
+  int rwv;                       // wave-synchronous row transforms (and the FP32 1024-point forward columns of the dynamic closures)
 };
 
 // Strip width W of the column passes: W * ny <= one tile, at least 64
@@ -314,6 +315,7 @@ static int build_layout(const qg_params* params, int n, int adjK, Handle& h) {
     g.o_twx1 = o; o += align256((long long)g.nx * cs);
     g.o_twy1 = o; o += align256((long long)g.ny * cs);
     g.o_twx2 = o; o += align256((long long)g.nx * cs);
+    g.o_twy2 = o; o += align256((long long)g.ny * cs);
     g.rsch = g.csch = g.rwv = 0;
     g.rpb = 1;
   }
@@ -403,8 +405,9 @@ static Phase base_phase(const Handle& h, const Group& g) {
   P.o_mf = g.L.mf; P.o_mp = g.L.mp; P.o_phys = g.L.phys;
   P.o_part = g.L.part; P.o_coef = g.L.coef; P.o_dpart = g.L.dpart;
   P.twx = g.twx; P.twy = g.twy;
-  P.twx1 = g.twx1; P.twy1 = g.twy1; P.twx2 = g.twx2;
+  P.twx1 = g.twx1; P.twy1 = g.twy1; P.twx2 = g.twx2; P.twy2 = g.twy2;
   P.rsch = g.rsch; P.csch = g.csch; P.rpb = g.rpb; P.rwv = g.rwv;
+  P.cwv = g.rwv;   // one choice for the wave-synchronous rows and columns
   return P;
 }
 
@@ -1002,17 +1005,19 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
     g.twx1 = h.ws + g.o_twx1;
     g.twy1 = h.ws + g.o_twy1;
     g.twx2 = h.ws + g.o_twx2;
+    g.twy2 = h.ws + g.o_twy2;
     for (int k = 0; k < g.count; ++k) {
       const int u = g.users[k];
       table[g.m0 + k] = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
     }
-    // x and y tables of schedules 0 and 1, the x table of schedule 2
-    for (int axis = 0; axis < 5; ++axis) {
+    // x and y tables of schedules 0, 1 and 2
+    for (int axis = 0; axis < 6; ++axis) {
       const int len = (axis & 1) == 0 ? g.nx : g.ny;
       std::vector<long double> fre, fim, re, im;
       twiddles(len, fre, fim);
       pass_twiddles(len, axis >> 1, fre, fim, re, im);
-      void* dst = axis == 0 ? g.twx : axis == 1 ? g.twy : axis == 2 ? g.twx1 : axis == 3 ? g.twy1 : g.twx2;
+      void* dst = axis == 0 ? g.twx : axis == 1 ? g.twy : axis == 2 ? g.twx1 : axis == 3 ? g.twy1
+                : axis == 4 ? g.twx2 : g.twy2;
       if (g.dbl) {
         std::vector<double> t(2 * len);
         for (int m = 0; m < len; ++m) { t[2 * m] = (double)re[m]; t[2 * m + 1] = (double)im[m]; }

@@ -113,11 +113,13 @@ struct Phase {
   // schedule of the row transforms (rsch) and of the column transforms
   // (csch), with the twiddle tables of schedule 1 (twx1, twy1); row pairs
   // per block of the row pass (rpb); wave-synchronous row transforms (rwv:
-  // one wave per transform)
-  int rsch, csch, rpb, rwv;
+  // one wave per transform); wave-synchronous radix-16 transforms of the
+  // FP32 1024-point forward columns of the dynamic closures (cwv)
+  int rsch, csch, rpb, rwv, cwv;
   const void* twx1;
   const void* twy1;
-  const void* twx2;       // the row table of schedule 2 (radix 16)
+  const void* twx2;       // the row and column tables of schedule 2 (radix 16)
+  const void* twy2;
   // dynamic LDS bytes of the launch (set by the launcher; read by the LDS
   // poison of debug builds)
   unsigned lds_bytes;

@@ -2127,11 +2127,13 @@ __global__ void __launch_bounds__(1024) k_colfwdp(Phase P) {
 // forms: J and Q stored, H, M and the block's partial sums of <HM> and
 // <M^2> (H and M also stored when adj_dyn).  The same arithmetic per mode
 // as k_colfwdp; each thread adds two modes into the partial sums.
-template <typename T, int CL, int LOGN, int SCH>
-__global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
+template <typename T, int CL, int LOGN, int SCH, bool WV = false>
+__global__ void __launch_bounds__(3 << (LOGN - (WV ? 4 : 3))) k_colfwdd(Phase P) {
   using V = cpx<T>;
+  // WV: one wave per transform, 16 elements per thread, radix-16 schedule
+  constexpr int EPT = WV ? 16 : 8, SC = WV ? 2 : SCH;
   constexpr int CPD = QG_COL_PADS;
-  constexpr int N = 1 << LOGN, LG = LOGN - 3, NT = 3 << LG;
+  constexpr int N = 1 << LOGN, LG = LOGN - (WV ? 4 : 3), NT = 3 << LG;
   constexpr int n = N + (N >> CPD);
   constexpr int KYN = 2 * ((N - 1) / 3) + 1;   // the 2/3 set's m_y count
   constexpr int QM = (KYN + NT - 1) / NT;      // modes per thread
@@ -2148,17 +2150,18 @@ __global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
   const long long pstride = (long long)P.ny * P.kxp;
   const V* src = cptr<T>(M, P.o_mp) + grp * pstride + (long long)kx0 * P.ny;
   const int mylim = test_mylim(M, P.nx, P.ny, kx0);
-  const V* twc = reinterpret_cast<const V*>(SCH ? P.twy1 : P.twy);
-  const auto tw1 = fft1c_first_tw<V, LOGN, SCH>(twc, lt);
-  V v[8], w[8];
+  const V* twc = reinterpret_cast<const V*>(SC == 2 ? P.twy2 : SC ? P.twy1 : P.twy);
+  const auto tw1 = fft1c_first_tw<V, LOGN, SC, EPT>(twc, lt);
+  V v[EPT], w[EPT];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) v[t] = gld(src + lt + (t << LG));
+  for (int t = 0; t < EPT; ++t) v[t] = gld(src + lt + (t << LG));
 #pragma unroll
-  for (int t = 0; t < 8; ++t) w[t] = gld(src + 3 * pstride + lt + (t << LG));
-  QG_STAMP(2, 1, v[7].x);
+  for (int t = 0; t < EPT; ++t) w[t] = gld(src + 3 * pstride + lt + (t << LG));
+  QG_STAMP(2, 1, v[EPT - 1].x);
   V* buf = tile + grp * n;
-  fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(v, buf, lt, true);
-  fft1c_rest<V, LOGN, false, CPD, SCH, 8, false, true>(buf, twc, lt, true, tw1);
+  fft1c_pass0<V, false, CPD, 0, EPT, WV, LOGN>(v, buf, lt, true);
+  fft1c_rest<V, LOGN, false, CPD, SC, EPT, WV, true>(buf, twc, lt, true, tw1);
+  if constexpr (WV) __syncthreads();   // every group's transform before the reads across groups
   // the grid level's products at this thread's modes
   auto pos = [&](int iy) {
     const int my = my_of_iy(iy, P.myh, P.kyn);
@@ -2176,8 +2179,9 @@ __global__ void __launch_bounds__(3 << (LOGN - 3)) k_colfwdd(Phase P) {
     }
   }
   __syncthreads();   // every read of the first half before the second half's writes
-  fft1c_pass0<V, false, CPD, 0, 8, false, LOGN>(w, buf, lt, true);
-  fft1c_rest<V, LOGN, false, CPD, SCH, 8, false, true>(buf, twc, lt, true, tw1);
+  fft1c_pass0<V, false, CPD, 0, EPT, WV, LOGN>(w, buf, lt, true);
+  fft1c_rest<V, LOGN, false, CPD, SC, EPT, WV, true>(buf, twc, lt, true, tw1);
+  if constexpr (WV) __syncthreads();
   QG_STAMP_LDS(2, 2);
   double hm = 0.0, mm = 0.0;
   const int mx = kx0;
@@ -2827,6 +2831,14 @@ static void launch_colfwdp_t(const Phase& P, int nmem, hipStream_t s) {
       if (P.W == 1 && P.logny >= 8 && P.logny <= 10) {
         const size_t lds2 = 3 * (size_t)(P.ny + (P.ny >> QG_COL_PADS)) * sizeof(cpx<T>);
         const dim3 block2(3 * P.ny / COL_EPT);
+        // 1024-point columns with the wave-synchronous choice: one wave
+        // per transform, radix-16 passes (FP32 only: the FP64 form would
+        // hold about 260 registers per lane, one wave per SIMD)
+        if constexpr (sizeof(T) == 4)
+          if (P.logny == 10 && P.cwv) {
+            QG_KLAUNCH((k_colfwdd<T, CL, 10, 0, true>), grid, dim3(3 * P.ny / 16), lds2, s, P);
+            return;
+          }
         switch (P.logny) {
           case 8:
             if (s1) QG_KLAUNCH((k_colfwdd<T, CL, 8, 1>), grid, block2, lds2, s, P);

@@ -95,6 +95,19 @@ def test_compile_time_engines_dynamic_leith(tmp_path, precision, tuning):
 
 
 @pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("rwave", [0, 1])
+def test_columns_of_1024_dynamic_leith(tmp_path, precision, rwave):
+    """512 x 1024 dynamic Leith: the two-half forward column pass over
+    1024-point columns, block-synchronous or (FP32, rwave 1) one wave per
+    transform with radix-16 passes."""
+    tuning = {"/fwd": 1, "/inv": 2, "/rsched": 1, "/csched": 1, "/rpb": 1, "/rwave": rwave}
+    say("poison 512x1024 dleith", precision, tuning)
+    err, bit = both([island(512, 1024, "dleith")], precision, steps(2), tuning, tmp_path)
+    say("  err", err, "bitwise", bit)
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [32, 64])
 @pytest.mark.parametrize("nx,ny,closure", [(256, 256, "dsmag"), (128, 64, "smag"), (4096, 64, "leith"),
                                            (64, 1024, "none"), (32, 32, "dleith")])
 def test_other_engines(precision, nx, ny, closure):
