@@ -631,8 +631,7 @@ static int run_steps_eager(const Handle& h, int n, hipStream_t st) {
 // each group's chain of launches is captured on a stream of its own, forked
 // from st and joined back: the graph holds one branch per group, which the
 // runtime may run concurrently (small groups then fill the chip together).
-static int make_branches(Handle& h) {
-  const size_t ng = h.groups.size();
+static int make_branches(Handle& h, size_t ng) {
   while (h.branch_streams.size() + 1 < ng) {
     hipStream_t s;
     hipEvent_t e;
@@ -665,21 +664,50 @@ static int capture_branches(Handle& h, hipStream_t st, F work) {
   return QG_OK;
 }
 
+// The step's branches: one per group; a handle of one group with
+// SPLIT_MIN members or more runs it as two halves instead (its members
+// share nothing a step writes either), so that the tail of one half's
+// launch overlaps the start of the other's.  (Measured on 1024^2 members:
+// 8 x FP32 0.885 -> 0.851 ms per step, 8 x FP64 1.955 -> 1.875 ms; four
+// or eight parts lose again, and splitting the groups of a ragged ensemble,
+// already a dozen branches, makes its step 25% slower.)
+constexpr int SPLIT_MIN = 4;
+static std::vector<Group> step_units(const Handle& h) {
+  if (h.groups.size() != 1 || h.groups[0].count < SPLIT_MIN) return h.groups;
+  const Group& g = h.groups[0];
+  Group a = g, b = g;
+  a.count = g.count / 2;
+  b.m0 = g.m0 + a.count;
+  b.count = g.count - a.count;
+  return {a, b};
+}
+
 static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
-  return capture_branches(h, st, [&](const Group& g, hipStream_t bs) {
+  const std::vector<Group> units = step_units(h);
+  const size_t nu = units.size();
+  if (nu > 1) {
+    QG_HIP(hipEventRecord(h.ev_fork, st));
+    for (size_t i = 1; i < nu; ++i) QG_HIP(hipStreamWaitEvent(h.branch_streams[i - 1], h.ev_fork, 0));
+  }
+  for (size_t i = 0; i < nu; ++i) {
+    hipStream_t bs = i == 0 ? st : h.branch_streams[i - 1];
     for (int k = 0; k < nsteps; ++k) {
-      int rc = run_step(h, g, bs);
+      int rc = run_step(h, units[i], bs);
       if (rc) return rc;
     }
-    return (int)QG_OK;
-  });
+  }
+  for (size_t i = 1; i < nu; ++i) {
+    QG_HIP(hipEventRecord(h.branch_events[i - 1], h.branch_streams[i - 1]));
+    QG_HIP(hipStreamWaitEvent(st, h.branch_events[i - 1], 0));
+  }
+  return QG_OK;
 }
 
 static int get_graph(Handle& h, int nsteps, hipStream_t st, hipGraphExec_t* out) {
   auto it = h.graphs.find(nsteps);
   if (it != h.graphs.end()) { *out = it->second; return QG_OK; }
   hipGraph_t graph;
-  int rc = make_branches(h);
+  int rc = make_branches(h, step_units(h).size());
   if (rc) return rc;
   QG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   rc = capture_steps(h, nsteps, st);
@@ -1456,7 +1484,7 @@ int qg_adjoint_step(qg_handle* H, const void* omega_ckpt, void* lambda, int64_t 
     ex = it->second;
   } else {
     hipGraph_t graph;
-    int rc = make_branches(h);
+    int rc = make_branches(h, h.groups.size());
     if (rc) return rc;
     QG_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
     // the groups' sweeps are independent: one graph branch each

@@ -110,6 +110,20 @@ def test_graph_equals_eager_bitwise():
     S.close()
 
 
+def test_one_group_in_two_branches():
+    """A handle of one size group of five members: its graph runs the group
+    as two halves (two and three members) on branches of their own, the
+    eager steps as one chain of launches; the two agree bit for bit."""
+    ms = [member(128, 64, "dleith", seed=s, init="spectrum") for s in range(11, 16)]
+    S = solver_for(ms, 32)
+    a = S.pack([m.omega0 for m in ms])
+    b = a.clone()
+    S.step(a, 12, use_graph=False)
+    S.step(b, 12, use_graph=True)
+    assert (a == b).all().item()
+    S.close()
+
+
 def test_batched_ragged_members():
     ms = [member(64, 32, "smag", seed=5), member(128, 64, "dleith", seed=6, init="spectrum"),
           member(64, 32, "leith", seed=7), member(256, 128, "dsmag", seed=8, init="spectrum"),
