@@ -149,8 +149,10 @@ int qg_init(const qg_params* params, int32_t n_members,
  * restarted from a checkpoint repeats the original bit for bit.
  * use_graph != 0 replays a captured hipGraph of the step sequence (captured
  * on library-owned streams, one branch per size group so that the groups
- * run concurrently; ordered after, and before, the caller's stream work by
- * events). */
+ * run concurrently -- a handle of a single size group of four or more
+ * members as two branches of half the members each; ordered after, and
+ * before, the caller's stream work by events).  Graph and eager steps give
+ * the same bits. */
 int qg_step(qg_handle* h, void* omega, int64_t nsteps, int32_t save_every,
             void* ckpt_out, int32_t use_graph, void* hip_stream);
 
@@ -232,12 +234,15 @@ int qg_diag(qg_handle* h, const void* omega, double* out_dev, void* nu_e_out,
  * tunables are the strip width of the column-forward pass (W) and of the
  * column-inverse pass (Wi), the radix schedule of the compile-time row and
  * column transforms (rows and columns of 256, 512 or 1024 points; schedule
- * 0: radix 8 then 4 or 2, e.g. 1024 = 8 8 8 2; schedule 1: radix 4 first,
- * e.g. 1024 = 8 4 4 8), the row pairs per block of the step's row pass
- * (1 or 2) and its synchronisation (block-wide passes of 8 points per
- * thread, or one wave per transform, 16 points per thread at 1024, with
- * block barriers only around the pointwise products).  All combinations of
- * the admissible values are searched
+ * 0: radix 8 then 4 or 2, e.g. 1024 = 8 8 8 2; schedule 1: radix 4s
+ * between radix-8 first and last passes, e.g. 1024 = 8 4 4 8; schedule 2,
+ * 1024-point rows with one wave per transform only: 8 16 8), the row pairs
+ * per block of the step's row pass (1 or 2) and its synchronisation
+ * (block-wide passes of 8 points per thread, or one wave per transform, 16
+ * points per thread at 1024, with block barriers only around the pointwise
+ * products; the same choice gives the FP32 1024-point columns of the
+ * dynamic closures' forward pass one wave per transform under the radix-16
+ * schedule).  All combinations of the admissible values are searched
  * jointly: each is captured as a graph of four steps of the group and timed
  * round-robin three times (after two warm-up rounds) on a stream of the
  * tuner's own, and the fastest is kept.  The choice is cached in the flat
