@@ -135,7 +135,10 @@ int qg_workspace_bytes(const qg_params* params, int32_t n_members,
  * Precomputes the penalization tables E = exp(-dt chi/eta), E_x, E_y (from
  * the spectral gradient of chi) and S = exp(-dt sigma chi_sponge) on the
  * GPU.  Synchronises hip_stream.  Members may differ in every parameter;
- * members of equal (nx, ny, precision, closure) are launched together. */
+ * members of equal (nx, ny, precision, closure) are launched together.
+ * Members of such a group given the same chi_obs and chi_sponge pointers
+ * and equal dt/eta and dt sigma have equal tables: the step reads the
+ * first such member's copy for all of them. */
 int qg_init(const qg_params* params, int32_t n_members,
             const void* const* chi_obs, const void* const* chi_sponge,
             void* workspace, size_t ws_bytes, int32_t adj_segment_k,

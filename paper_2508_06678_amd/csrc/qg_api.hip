@@ -1036,7 +1036,22 @@ int qg_init(const qg_params* params, int32_t n, const void* const* chi_obs, cons
     g.twy2 = h.ws + g.o_twy2;
     for (int k = 0; k < g.count; ++k) {
       const int u = g.users[k];
-      table[g.m0 + k] = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
+      MemberDev& m = table[g.m0 + k];
+      m = make_member(params[u], g.region0 + (long long)k * g.region_bytes, h.omega_off[u], u);
+      m.tab_off = g.L.phys;
+      // a member given the same mask buffers as an earlier member of its
+      // group, with the same dt/eta and dt sigma, has the same tables bit
+      // for bit: its B sub-step reads that member's (one copy read per
+      // step for an ensemble over initial conditions on one geometry)
+      for (int k0 = 0; k0 < k; ++k0) {
+        const int u0 = g.users[k0];
+        const MemberDev& m0 = table[g.m0 + k0];
+        if (chi_obs[u0] == chi_obs[u] && chi_sponge[u0] == chi_sponge[u] && m0.pen_a == m.pen_a &&
+            m0.sponge_a == m.sponge_a) {
+          m.tab_off = (m0.base + g.L.phys) - m.base;
+          break;
+        }
+      }
     }
     // x and y tables of schedules 0, 1 and 2
     for (int axis = 0; axis < 6; ++axis) {
@@ -1521,9 +1536,11 @@ int qg_set_coef(qg_handle* H, const double* c, void* hip_stream) {
       const int u = g.users[k];
       h.params[u].c = c[u];
       MemberDev m = make_member(h.params[u], h.table[g.m0 + k].base, h.omega_off[u], u);
-      // values qg_init derived on the device are kept: the mask mean split
-      // off in the AB2CN penalty's curl
+      // values qg_init derived are kept: the mask mean split off in the
+      // AB2CN penalty's curl, and where the B sub-step's tables are read
+      // (they depend on dt/eta and dt sigma only, which stay)
       m.pen_c = h.table[g.m0 + k].pen_c;
+      m.tab_off = h.table[g.m0 + k].tab_off;
       h.table[g.m0 + k] = m;
     }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1861,7 +1878,8 @@ extern "C" int qg_step_noalloc(const qg_params* p, const void* chi_obs, const vo
   g.twy1 = ws + g.o_twy1;
   Handle h;   // only mem_dev is read by the phase sequences below
   h.mem_dev = reinterpret_cast<MemberDev*>(ws);
-  const MemberDev m = make_member(*p, g.region0, 0, 0);
+  MemberDev m = make_member(*p, g.region0, 0, 0);
+  m.tab_off = g.L.phys;
   // the array keeps the previous call's contents: clear what is used
   QG_LAUNCH(launch_fill_zero(ws, (size_t)total, st));
   QG_LAUNCH(launch_put_member(h.mem_dev, m, st));

@@ -61,6 +61,10 @@ struct MemberDev {
   int test_kx;           // columns m_x < test_kx hold the test-filtered modes
   int closure;
   int clip_mode;         // 0: C = max(<HM>, 0)/<M^2>; 1: C = <max(H, 0) M>/<M^2>
+  // byte offset from base to the tables S E, S E_x, S E_y the B sub-step
+  // reads: the member's own, or those of an earlier member of its group
+  // with the same masks and the same dt/eta and dt sigma (equal bits)
+  long long tab_off;
 };
 
 // Byte offsets of the buffers inside every member region of a group

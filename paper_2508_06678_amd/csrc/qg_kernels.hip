@@ -890,7 +890,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     row_c2r<T>(C, mf + 0 * fstride, u);
     row_c2r<T>(C, mf + 1 * fstride, v);
     row_c2r<T>(C, mf + 2 * fstride, w);
-    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SE = rptr<T>(M, M.tab_off);
     const T* SEx = SE + nxy;
     const T* SEy = SE + 2 * nxy;
     const T U = T(M.u_in), Vv = T(M.v_in);
@@ -955,7 +955,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && OP != OP_ADJ_RHS ? 4 :
     // S E_y): 0: S E lambda'' (omega), 1: -S E_y lambda'' (u), 2: S E_x lambda'' (v)
     V l[ROW_EPT], a0[ROW_EPT], a1[ROW_EPT];
     row_c2r<T>(C, mf, l);
-    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SE = rptr<T>(M, M.tab_off);
     const T* SEx = SE + nxy;
     const T* SEy = SE + 2 * nxy;
 #pragma unroll
@@ -1112,7 +1112,7 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     // omega'' = S (E omega + E_x v - E_y u), total velocity, from the
     // tables S E, S E_x, S E_y
     const long long nxy = (long long)nx * P.ny;
-    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SE = rptr<T>(M, M.tab_off);
     const V u = F(0), vv = F(1), w = F(2);
     const long long a = (long long)ya * nx + q, b = a + nx;
     const T w0 = SE[a] * w.x + SE[nxy + a] * (Vv + vv.x) - SE[2 * nxy + a] * (U + u.x);
@@ -1123,7 +1123,7 @@ __device__ __forceinline__ cpx<T> rowp_product(const MemberDev& M, const Phase& 
     // lambda'' (every group holds it; group 0's copy is read): 0: S E
     // lambda'' (omega), 1: -S E_y lambda'' (u), 2: S E_x lambda'' (v)
     const long long nxy = (long long)nx * P.ny;
-    const T* SE = rptr<T>(M, P.o_phys);
+    const T* SE = rptr<T>(M, M.tab_off);
     const V l = F(0);
     const long long a = (long long)ya * nx + q, b = a + nx;
     if (grp == 0) return cmake<V>(SE[a] * l.x, SE[b] * l.y);

@@ -51,8 +51,10 @@ class Solver:
         off = (-raw.data_ptr()) % 256
         self._ws_raw = raw
         self.ws = raw[off:off + size.value]
-        masks = [self._dev(c) for c in chi]
-        smasks = [self._dev(c) for c in chi_sponge]
+        # members with equal masks get the same device buffers: qg_init
+        # then lets them read one copy of the B sub-step's tables
+        masks = _one_buffer_per_content([self._dev(c) for c in chi])
+        smasks = _one_buffer_per_content([self._dev(c) for c in chi_sponge])
         cp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in masks])
         sp = (ctypes.c_void_p * self.n)(*[m.data_ptr() for m in smasks])
         h = ctypes.c_void_p()
@@ -227,6 +229,16 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _one_buffer_per_content(ts):
+    """The list with every tensor equal to an earlier one replaced by that
+    earlier tensor."""
+    out = []
+    for t in ts:
+        same = next((u for u in out if u.shape == t.shape and u.dtype == t.dtype and torch.equal(u, t)), None)
+        out.append(t if same is None else same)
+    return out
 
 
 def step_noalloc(params, chi, chi_sponge, omega, nsteps):

@@ -124,6 +124,25 @@ def test_one_group_in_two_branches():
     S.close()
 
 
+def test_shared_penalization_tables(monkeypatch):
+    """Members with equal masks (one device buffer each, as the binding
+    passes them) read one member's B sub-step tables; the same members with
+    a buffer of their own each read their own.  Both give the same bits."""
+    from paper_2508_06678_amd import solver as solver_mod
+    ms = [member(128, 64, "dleith", seed=s, init="spectrum") for s in (21, 22, 23)]
+    assert all(np.array_equal(m.chi, ms[0].chi) and np.array_equal(m.chi_s, ms[0].chi_s) for m in ms)
+    out = []
+    for share in (True, False):
+        if not share:
+            monkeypatch.setattr(solver_mod, "_one_buffer_per_content", lambda ts: list(ts))
+        S = solver_for(ms, 32)
+        om = S.pack([m.omega0 for m in ms])
+        S.step(om, 7, use_graph=False)
+        out.append(om.clone())
+        S.close()
+    assert (out[0] == out[1]).all().item()
+
+
 def test_batched_ragged_members():
     ms = [member(64, 32, "smag", seed=5), member(128, 64, "dleith", seed=6, init="spectrum"),
           member(64, 32, "leith", seed=7), member(256, 128, "dsmag", seed=8, init="spectrum"),
