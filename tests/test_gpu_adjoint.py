@@ -270,3 +270,29 @@ def test_adjoint_of_several_size_groups():
         else:
             assert g[i].item() == 0.0
     S.close()
+
+
+def test_adjoint_with_shared_penalization_tables(monkeypatch):
+    """Three members on one geometry (one device buffer per mask, so they
+    read one member's B sub-step tables) and the same members with masks of
+    their own: the adjoint's lambda and dL/dc agree bit for bit."""
+    import torch
+    from paper_2508_06678_amd import solver as solver_mod
+    nx, ny, nsteps = 128, 64, 3
+    ms = [island(nx, ny, "smag", seed=s) for s in (4, 5, 6)]
+    assert all(np.array_equal(m.chi, ms[0].chi) and np.array_equal(m.chi_s, ms[0].chi_s) for m in ms)
+    rng = np.random.default_rng(12)
+    lamT = [rng.standard_normal((ny, nx)) for _ in ms]
+    out = []
+    for share in (True, False):
+        if not share:
+            monkeypatch.setattr(solver_mod, "_one_buffer_per_content", lambda ts: list(ts))
+        S = solver_for(ms, 64, adj_segment_k=nsteps)
+        om = S.pack([m.omega0 for m in ms])
+        lam = S.pack(lamT)
+        g = torch.zeros(len(ms), dtype=torch.float64, device=om.device)
+        S.adjoint_step(om, lam, nsteps, g)
+        out.append((lam.clone(), g.clone()))
+        S.close()
+    assert (out[0][0] == out[1][0]).all().item()
+    assert (out[0][1] == out[1][1]).all().item()
