@@ -404,7 +404,8 @@ def main():
         result["batched"] = {"value": ptsb * kb / secb, "ms_per_step": secb / kb * 1e3, "steps": kb,
                              "members": nb,
                              "step_roofline_frac": nb * step_bytes / (secb / kb) / 1e9 / HBM_PEAK_GBS,
-                             "step_roofline_frac_388B": bpp32 * ptsb / (secb / kb) / 1e9 / HBM_PEAK_GBS}
+                             "step_roofline_frac_388B": bpp32 * ptsb / (secb / kb) / 1e9 / HBM_PEAK_GBS,
+                             "tuning": S.tuning()[0]}
         if "phases" not in skip:
             bnames = kernel_names(nx, ny, S.tuning()[0])
             broof, bkt, _ = roofline_of(S, om, nx, ny, "dleith", max(5, args.prof_steps // 4), bnames, members=nb)

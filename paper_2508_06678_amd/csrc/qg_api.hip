@@ -682,8 +682,9 @@ static std::vector<Group> step_units(const Handle& h) {
   return {a, b};
 }
 
-static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
-  const std::vector<Group> units = step_units(h);
+// nsteps steps of every unit, unit 0 on st and each further unit on a
+// branch stream (make_branches first), forked from st and joined back.
+static int capture_units(Handle& h, const std::vector<Group>& units, int nsteps, hipStream_t st) {
   const size_t nu = units.size();
   if (nu > 1) {
     QG_HIP(hipEventRecord(h.ev_fork, st));
@@ -702,6 +703,8 @@ static int capture_steps(Handle& h, int nsteps, hipStream_t st) {
   }
   return QG_OK;
 }
+
+static int capture_steps(Handle& h, int nsteps, hipStream_t st) { return capture_units(h, step_units(h), nsteps, st); }
 
 static int get_graph(Handle& h, int nsteps, hipStream_t st, hipGraphExec_t* out) {
   auto it = h.graphs.find(nsteps);
@@ -1714,7 +1717,10 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
       apply_tuning(g, cand[0]);
       continue;
     }
-    // every candidate as a graph of TUNE_STEPS steps of this group
+    // every candidate as a graph of TUNE_STEPS steps of this group, in the
+    // branches the step's graph will run it in
+    const bool split = step_units(h).size() > h.groups.size();
+    if (split && (rc = make_branches(h, 2)) != QG_OK) break;
     std::vector<hipGraphExec_t> ex(cand.size(), nullptr);
     for (size_t i = 0; i < cand.size() && rc == QG_OK; ++i) {
       apply_tuning(g, cand[i]);
@@ -1724,7 +1730,9 @@ int qg_autotune(qg_handle* H, const char* cache_path, void* hip_stream) {
         break;
       }
       int r2 = QG_OK;
-      for (int k = 0; k < TUNE_STEPS && r2 == QG_OK; ++k) r2 = run_step(h, g, ts);
+      if (split) r2 = capture_units(h, step_units(h), TUNE_STEPS, ts);
+      else
+        for (int k = 0; k < TUNE_STEPS && r2 == QG_OK; ++k) r2 = run_step(h, g, ts);
       hipError_t e = hipStreamEndCapture(ts, &graph);
       if (r2) { if (e == hipSuccess) (void)hipGraphDestroy(graph); rc = r2; break; }
       if (e != hipSuccess) { rc = fail(QG_EHIP, std::string("autotune capture: ") + hipGetErrorString(e)); break; }
