@@ -152,7 +152,7 @@ int qg_init(const qg_params* params, int32_t n_members,
  * restarted from a checkpoint repeats the original bit for bit.
  * use_graph != 0 replays a captured hipGraph of the step sequence (captured
  * on library-owned streams, one branch per size group so that the groups
- * run concurrently -- a handle of a single size group of four or more
+ * run concurrently -- a handle of a single size group of two or more
  * members as two branches of half the members each; ordered after, and
  * before, the caller's stream work by events).  Graph and eager steps give
  * the same bits. */

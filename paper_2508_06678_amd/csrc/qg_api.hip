@@ -668,10 +668,11 @@ static int capture_branches(Handle& h, hipStream_t st, F work) {
 // SPLIT_MIN members or more runs it as two halves instead (its members
 // share nothing a step writes either), so that the tail of one half's
 // launch overlaps the start of the other's.  (Measured on 1024^2 members:
-// 8 x FP32 0.885 -> 0.851 ms per step, 8 x FP64 1.955 -> 1.875 ms; four
-// or eight parts lose again, and splitting the groups of a ragged ensemble,
-// already a dozen branches, makes its step 25% slower.)
-constexpr int SPLIT_MIN = 4;
+// 8 x FP32 0.885 -> 0.851 ms per step, 8 x FP64 1.955 -> 1.875 ms, 2 x
+// FP32 0.296 -> 0.285 ms, 3 x FP32 0.388 -> 0.385 ms; three, four or eight
+// parts lose again, and splitting the groups of a ragged ensemble, already
+// a dozen branches, makes its step 25% slower.)
+constexpr int SPLIT_MIN = 2;
 static std::vector<Group> step_units(const Handle& h) {
   if (h.groups.size() != 1 || h.groups[0].count < SPLIT_MIN) return h.groups;
   const Group& g = h.groups[0];

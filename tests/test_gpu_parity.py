@@ -110,11 +110,13 @@ def test_graph_equals_eager_bitwise():
     S.close()
 
 
-def test_one_group_in_two_branches():
-    """A handle of one size group of five members: its graph runs the group
-    as two halves (two and three members) on branches of their own, the
-    eager steps as one chain of launches; the two agree bit for bit."""
-    ms = [member(128, 64, "dleith", seed=s, init="spectrum") for s in range(11, 16)]
+@pytest.mark.parametrize("count", [2, 5])
+def test_one_group_in_two_branches(count):
+    """A handle of one size group of two or five members: its graph runs
+    the group as two halves (one and one, two and three members) on branches
+    of their own, the eager steps as one chain of launches; the two agree
+    bit for bit."""
+    ms = [member(128, 64, "dleith", seed=s, init="spectrum") for s in range(11, 11 + count)]
     S = solver_for(ms, 32)
     a = S.pack([m.omega0 for m in ms])
     b = a.clone()
