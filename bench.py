@@ -134,10 +134,11 @@ def time_kernels(S, om, nsteps, kinds=range(len(PHASE_NAMES))):
     return out
 
 
-def survey_bytes_per_point(closure, word):
-    """The scope table's byte model: per grid-point-step 4 [2/3 2 (F + P) + 4/3
-    (RK state) + 16/9 (dynamic split)] + 10 words (B sub-step), F inverse
-    fields and P forward products per right-hand side at full width."""
+def full_width_bytes_per_point(closure, word):
+    """Byte model with every inverse field and product at full width: per
+    grid-point-step 4 [2/3 2 (F + P) + 4/3 (RK state) + 16/9 (dynamic
+    split)] + 10 words (B sub-step), F inverse fields and P forward products
+    per right-hand side (388 B for dynamic Leith in FP32)."""
     F = {"none": 4, "smag": 6, "leith": 4, "dsmag": 12, "dleith": 8}[closure]
     P = {"none": 1, "smag": 3, "leith": 3, "dsmag": 6, "dleith": 6}[closure]
     dyn = 16.0 / 9.0 if closure in ("dsmag", "dleith") else 0.0
@@ -332,7 +333,7 @@ def main():
     wl = configs.config3(precision=32)
     nx, ny = wl.members[0].params["nx"], wl.members[0].params["ny"]
     pts = nx * ny
-    bpp32 = survey_bytes_per_point("dleith", 4)
+    bpp32 = full_width_bytes_per_point("dleith", 4)
 
     # ---- FP32, one 1024^2 member (value)
     S, om = make_solver(wl, 32)
@@ -389,7 +390,7 @@ def main():
         _, b64 = algorithmic_bytes(nx, ny, 8, "dleith")
         result["fp64"] = {"value": pts * k64 / sec64, "ms_per_step": sec64 / k64 * 1e3, "steps": k64,
                           "step_roofline_frac": b64 / (sec64 / k64) / 1e9 / HBM_PEAK_GBS,
-                          "step_roofline_frac_777B": survey_bytes_per_point("dleith", 8) * pts / (sec64 / k64)
+                          "step_roofline_frac_777B": full_width_bytes_per_point("dleith", 8) * pts / (sec64 / k64)
                           / 1e9 / HBM_PEAK_GBS}
         log(f"fp64 1024^2 dleith: {sec64 / k64 * 1e3:.4f} ms/step")
 
